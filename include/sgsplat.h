@@ -1,0 +1,223 @@
+/*
+ * sgsplat.h — C ABI of the MI355X SG-Splatting rasteriser (libsgsplat.so).
+ *
+ * The library renders 3D Gaussians whose view-dependent colour is low-degree
+ * spherical harmonics plus K spherical-Gaussian lobes (SG-Splatting, arXiv
+ * 2501.00342: Methods, eqs. 4-9) with the tile-based Gaussian-splatting
+ * rasteriser the method builds on (Preliminaries: EWA projection, then
+ * alpha blending of the depth-sorted splats), forward and backward, on one
+ * AMD gfx950 GPU.
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers marked "device" are HIP device pointers owned by the
+ *     caller.  The library allocates no device memory: every buffer it needs
+ *     lives in a caller-provided workspace sized by render_workspace_bytes().
+ *   - Arrays are component-major (SoA): component c of Gaussian g is at
+ *     [c * n + g].  SH coefficients are [(deg+1)^2][3][n], l-major then
+ *     m = -l..l, channel (r,g,b) inside; lobe arrays are [K][3][n] or [K][n].
+ *   - Quaternions are (w, x, y, z).  Raw parameters cross the ABI; the
+ *     library applies scale = exp(log_scale), opacity = sigmoid(logit),
+ *     sharpness = exp(log_sharpness) and normalises q and each lobe axis.
+ *   - Colour of a Gaussian seen along the unit direction d from the camera
+ *     centre to its mean: rgb = max(0, 0.5 + sum_lm sh_lm Y_lm(d)
+ *     + sum_k a_k exp(lambda_k (d . mu_k - 1)))   (eq. 5 per lobe, eq. 9).
+ *     Real SH with the Condon-Shortley phase.  K = 0 with degree 3 is the
+ *     plain degree-3 SH form (eq. 4).
+ *   - Cameras: pinhole, OpenCV axes, x_cam = R x_world + t, pixel (i, j)
+ *     sampled at integer coordinates (i, j).
+ *   - Several cameras render in one call ("batched views"): their pixels are
+ *     packed camera after camera.  Camera k's image is the (3, H_k, W_k)
+ *     block starting at float offset 3 * pix_base_k of `image`, and its
+ *     depth / final_T / n_contrib are the (H_k, W_k) blocks starting at
+ *     pix_base_k, with pix_base_k = sum_{j<k} W_j H_j.
+ *   - Every entry point returns an sgs_status; on a non-zero return
+ *     render_last_error() gives a message (thread-local).  No exception
+ *     crosses the ABI.  Work is enqueued on `stream` (a hipStream_t); the
+ *     calls do not synchronise unless stated.
+ */
+#ifndef SGSPLAT_H
+#define SGSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sgs_status {
+    SGS_OK = 0,
+    SGS_E_INVALID = 1,   /* bad argument: NULL pointer, size, degree, tile shape, workspace */
+    SGS_E_CAPACITY = 2,  /* more (tile, Gaussian) pairs than the workspace holds */
+    SGS_E_HIP = 3        /* a HIP runtime call failed */
+} sgs_status;
+
+#define SGS_MAX_SH_DEGREE 3
+#define SGS_MAX_LOBES 8
+#define SGS_MAX_CAMERAS 1024
+#define SGS_MAX_IMAGE_SIDE 32767
+
+/* Gaussian parameters (device, float32, SoA).  n may be 0. */
+typedef struct sgs_gaussians {
+    int64_t n;
+    int32_t sh_degree;               /* 0..3 */
+    int32_t n_lobes;                 /* K, 0..SGS_MAX_LOBES */
+    const float* means;              /* [3][n]   world position X (eq. 2)        */
+    const float* log_scales;         /* [3][n]   log of the scale vector s (eq. 3) */
+    const float* quats;              /* [4][n]   rotation q, (w,x,y,z) (eq. 3)     */
+    const float* opacity_logits;     /* [n]      logit of opacity sigma            */
+    const float* sh;                 /* [(deg+1)^2][3][n] SH coefficients (eq. 4)  */
+    const float* sg_axes;            /* [K][3][n] lobe axis mu, any length (eq. 5) */
+    const float* sg_log_sharpness;   /* [K][n]   log of lobe sharpness lambda      */
+    const float* sg_amplitudes;      /* [K][3][n] lobe RGB amplitude alpha          */
+} sgs_gaussians;
+
+/* Gradient outputs, same shapes as sgs_gaussians (device, float32).  Every
+ * array is overwritten (not accumulated).  Arrays of zero size may be NULL. */
+typedef struct sgs_grads {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+    float* sg_axes;
+    float* sg_log_sharpness;
+    float* sg_amplitudes;
+} sgs_grads;
+
+/* One pinhole camera (host and device copies share this layout). */
+typedef struct sgs_camera {
+    int32_t width, height;           /* 1..SGS_MAX_IMAGE_SIDE */
+    float R[9];                      /* world -> camera rotation, row-major */
+    float t[3];                      /* world -> camera translation */
+    float fx, fy, cx, cy;            /* focal lengths and principal point, pixels */
+    float znear;                     /* Gaussians with camera depth <= znear are culled */
+    float bg[3];                     /* background colour, added as T_final * bg */
+} sgs_camera;
+
+/* Rasteriser options.  Zero-initialised fields take the defaults given. */
+typedef struct sgs_options {
+    int32_t tile_w, tile_h;          /* 16x16 (default), 8x8, 16x8, 8x16, 32x8 */
+    int32_t batch;                   /* LDS batch depth: multiple of tile_w*tile_h, <= 1024; 0 = tile_w*tile_h */
+    float dilation;                  /* added to both diagonal entries of the 2D covariance (0.3) */
+    float guard;                     /* guard band on the projection Jacobian, x tan(fov/2) (1.3) */
+    float alpha_min;                 /* splats with alpha < alpha_min are skipped (1/255) */
+    float alpha_max;                 /* alpha is clamped to alpha_max (0.99) */
+    float t_min;                     /* blending stops before T would fall below t_min (1e-4) */
+} sgs_options;
+
+/* Forward outputs (device, packed over cameras as described above). */
+typedef struct sgs_outputs {
+    float* image;                    /* [3][H][W] per camera: C + T_final * bg */
+    float* depth;                    /* [H][W] sum alpha T z (may be NULL)     */
+    float* final_T;                  /* [H][W] transmittance after the last blended splat */
+    int32_t* n_contrib;              /* [H][W] 1 + position in the tile list of the last
+                                        blended splat, 0 if none */
+} sgs_outputs;
+
+/* Byte offsets of the workspace sections, for inspection by tests. */
+typedef struct sgs_layout {
+    size_t total_bytes;
+    size_t header;          /* u32[16]: [0] status bits, [1] pair count P, [2..] counters */
+    size_t cam_table;       /* per camera: int32 W,H,GX,GY,tile_base,pad; int64 pix_base */
+    size_t records;         /* per (camera, Gaussian) item: 64-byte splat record */
+    size_t depth_keys;      /* u32 per item: bits of float32 depth, 0xFFFFFFFF if culled */
+    size_t tile_rects;      /* u64 per item: tx0 | tx1<<16 | ty0<<32 | ty1<<48; 0 pairs if culled */
+    size_t sorted_items;    /* u32 per item: items in ascending (depth key, item) order */
+    size_t pair_offsets;    /* u32 per item: exclusive scan of pairs in sorted order */
+    size_t pair_tiles;      /* u32 per pair: global tile id, sorted ascending */
+    size_t pair_values;     /* u32 per pair: item = camera * n + g, in blend order */
+    size_t ranges;          /* u32[2] per global tile: [start, end), (0,0) if empty */
+    size_t grad2d;          /* f32[9][items]: d/d(u, v, Qa, Qb, Qc, opacity, r, g, b) */
+    int64_t n_items;        /* n_cams * n */
+    int64_t n_tiles;        /* total tiles over all cameras */
+    int64_t n_pixels;       /* total pixels over all cameras */
+    int64_t pair_capacity;
+} sgs_layout;
+
+#define SGS_STATUS_CAPACITY 1u   /* header[0] bit: P exceeded pair_capacity; pairs truncated */
+#define SGS_STATUS_CAMERAS  2u   /* header[0] bit: device cameras disagree with host sizes */
+
+#define SGS_FLAG_CHECK_CAPACITY 1 /* render_forward: read P on the host after binning */
+
+/*
+ * render_workspace_bytes / render_layout
+ *   Size (and section offsets) of the workspace for n Gaussians, the given
+ *   host cameras (only width/height are read) and options, holding up to
+ *   pair_capacity (tile, Gaussian) pairs (< 2^30).  Returns 0 (or
+ *   SGS_E_INVALID from render_layout) on invalid arguments.
+ */
+size_t render_workspace_bytes(const sgs_gaussians* g, const sgs_camera* host_cams,
+                              int32_t n_cams, const sgs_options* opts,
+                              int64_t pair_capacity);
+int render_layout(const sgs_gaussians* g, const sgs_camera* host_cams, int32_t n_cams,
+                  const sgs_options* opts, int64_t pair_capacity, sgs_layout* out);
+
+/*
+ * render_forward — the forward pass (preprocess, binning, sort, tile ranges,
+ * front-to-back compositing).  Paper: Preliminaries (eqs. 2-3 and the EWA
+ * projection; splats "accumulated and blended"), colour eqs. 4-9.
+ *   g           Gaussian parameters (device arrays).
+ *   host_cams   n_cams cameras in host memory: fix launch geometry/layout.
+ *   dev_cams    the same cameras in device memory: what the kernels read
+ *               (poses may change between calls without re-planning).
+ *   workspace   device buffer of workspace_bytes >= render_workspace_bytes().
+ *               Holds records, pairs and ranges that render_backward reuses:
+ *               keep it untouched between a forward and its backward.
+ *   outs        packed outputs (device).
+ *   flags       SGS_FLAG_CHECK_CAPACITY: synchronise after binning, and if
+ *               P > pair_capacity return SGS_E_CAPACITY with *pairs_needed
+ *               = P and no image written.  Without it nothing synchronises:
+ *               pairs beyond capacity are dropped on the device and status
+ *               bit SGS_STATUS_CAPACITY is set (read with render_status).
+ *   pairs_needed  optional host pointer, receives P when the flag is set.
+ * Camera counts 1..SGS_MAX_CAMERAS; n = 0 renders the background.
+ */
+int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams,
+                   const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                   void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                   const sgs_outputs* outs, int32_t flags, int64_t* pairs_needed,
+                   void* stream);
+
+/*
+ * render_backward — gradients of a scalar loss L w.r.t. every raw
+ * parameter, given dL/dimage (device, packed like `image`).  Walks each
+ * tile back to front from the saved final transmittance, recomputing each
+ * alpha, then applies the chain rule through the preprocess.  Arguments as
+ * render_forward; `workspace` and `fwd` must be those of the matching
+ * forward (same g, cameras, options, capacity).  Depth has no gradient.
+ */
+int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams,
+                    const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                    void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                    const sgs_outputs* fwd, const float* grad_image,
+                    const sgs_grads* grads, void* stream);
+
+/*
+ * render_l1 — L = sum over cameras of mean_{3 H W} |image - target| and
+ * dL/dimage = sign(image - target) / (3 H_k W_k) (sign(0) = 0).
+ * image, target, grad_image: packed like `image` (device).  loss: one
+ * device double.  Uses the camera table of the workspace of the forward.
+ */
+int render_l1(const sgs_camera* host_cams, int32_t n_cams, const void* workspace,
+              const float* image, const float* target, float* grad_image,
+              double* loss, void* stream);
+
+/* render_status — synchronises `stream` and returns header[0] of the
+ * workspace (SGS_STATUS_* bits); *pairs receives P when non-NULL. */
+int render_status(const void* workspace, uint32_t* status_bits, int64_t* pairs, void* stream);
+
+/* render_read_keys — writes the sorted 64-bit keys (tile << 32 | depth
+ * bits) of the first `count` pairs of a finished forward into keys_out
+ * (device u64[count]); for parity tests. */
+int render_read_keys(const void* workspace, const sgs_layout* layout, int64_t count,
+                     uint64_t* keys_out, void* stream);
+
+/* render_last_error — message for the last non-zero return on this thread. */
+const char* render_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGSPLAT_H */

@@ -1,0 +1,416 @@
+// Tile compositing, forward and backward, and the L1 loss.
+//
+// One workgroup per tile (TW x TH pixels, one pixel per thread).  The
+// tile's sorted Gaussians are streamed through LDS in batches: each thread
+// gathers one 64-byte record, turns it into a tile-relative entry and all
+// pixels of the tile read it back from LDS.  Forward (SG-Splatting
+// Preliminaries: splats "accumulated and blended" front to back):
+//   alpha = min(alpha_max, opacity * exp(-d^T Q d / 2)),  skip alpha < alpha_min,
+//   stop before T (1 - alpha) < T_min,  C += alpha T rgb,  T *= 1 - alpha.
+// exp(-d^T Q d / 2) is evaluated as exp2(-q), q = (w1.d)^2 + (w2.d)^2 with
+// whitening rows from the preprocess (one v_exp_f32, no conic cancellation).
+// Early exit: a wave skips the LDS loop once its 64 pixels are done and
+// the workgroup leaves when all pixels are done (__syncthreads_count).
+// Tile order: consecutive workgroup ids go to different XCDs, so block b is
+// mapped to a contiguous run of tiles per XCD to share L2 lines of records.
+//
+// Backward: the same tile walk back to front from the saved final T and
+// n_contrib, recomputing alpha with the same instructions, T_j =
+// T_{j+1} / (1 - alpha_j).  Per-Gaussian 2D gradients are summed across
+// the wave with DPP and added with one float atomic per value per wave.
+#include "common.hpp"
+
+namespace sgs {
+
+struct __align__(16) Entry {
+    float4 a;   // ux, vy, w1x, w1y   (ux = (x0 - u_hi) - u_lo, tile-relative)
+    float4 b;   // w2x, w2y, opacity, z
+    float4 c;   // r, g, b, item (as bits)
+    uint2 m;    // column mask, row mask of the pixel rectangle inside the tile
+};
+
+__device__ __forceinline__ uint32_t span_mask(int lo, int hi, int n) {
+    if (hi < 0 || lo > n - 1) return 0u;
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > n - 1 ? n - 1 : hi;
+    return (2u << hi) - (1u << lo);
+}
+
+__device__ __forceinline__ Entry make_entry(const Rec* __restrict__ recs, uint32_t item, int x0,
+                                            int y0, int TW, int TH) {
+    const float4* src = reinterpret_cast<const float4*>(recs + item);
+    const float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
+    Entry e;
+    e.a.x = ((float)x0 - r0.x) - r0.z;
+    e.a.y = ((float)y0 - r0.y) - r0.w;
+    e.a.z = r1.x;
+    e.a.w = r1.y;
+    e.b.x = r1.z;
+    e.b.y = r1.w;
+    e.b.z = r2.x;
+    e.b.w = r3.x;
+    e.c.x = r2.y;
+    e.c.y = r2.z;
+    e.c.z = r2.w;
+    e.c.w = __uint_as_float(item);
+    const uint32_t rx = __float_as_uint(r3.y), ry = __float_as_uint(r3.z);
+    e.m.x = span_mask((int)(rx & 0xFFFF) - x0, (int)(rx >> 16) - x0, TW);
+    e.m.y = span_mask((int)(ry & 0xFFFF) - y0, (int)(ry >> 16) - y0, TH);
+    return e;
+}
+
+// alpha of one splat at one pixel; identical instructions in both passes
+struct Eval {
+    float dx, dy, y1, y2, E, alpha;
+};
+
+__device__ __forceinline__ Eval eval_splat(const Entry& e, float lx, float ly, float amax) {
+    Eval v;
+    v.dx = lx + e.a.x;
+    v.dy = ly + e.a.y;
+    v.y1 = fmaf(e.a.w, v.dy, e.a.z * v.dx);
+    v.y2 = fmaf(e.b.y, v.dy, e.b.x * v.dx);
+    const float q = fmaf(v.y2, v.y2, v.y1 * v.y1);
+    v.E = __builtin_amdgcn_exp2f(-q);
+    v.alpha = fminf(amax, e.b.z * v.E);
+    return v;
+}
+
+// blockIdx -> tile: XCD x = b % 8 receives a contiguous run of tiles
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n_tiles) {
+    const int64_t q = n_tiles / 8, r = n_tiles % 8;
+    const int64_t x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ int find_camera(const CamTable* cams, int n_cams, int64_t tile) {
+    int lo = 0, hi = n_cams - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cams[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// entry for list position `pos`; an out-of-range item yields an empty mask
+__device__ __forceinline__ Entry load_entry(const Workspace& ws, int64_t pos, int x0, int y0, int TW,
+                                            int TH) {
+    const uint32_t item = ws.pair_values[pos];
+    if (item < (uint64_t)ws.n_items) return make_entry(ws.records, item, x0, y0, TW, TH);
+    Entry e = {};
+    e.c.w = __uint_as_float(0u);
+    return e;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
+            sgs_outputs out, int batch) {
+    constexpr int NT = TW * TH;
+    extern __shared__ Entry s_e[];
+    __shared__ int s_cam;
+    const int tid = threadIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, ws.n_tiles);
+    if (tid == 0) s_cam = find_camera(ws.cams, n_cams, tile);
+    __syncthreads();
+    const int cam = s_cam;
+    const CamTable ct = ws.cams[cam];
+    if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    const int lt = (int)(tile - ct.tile_base);
+    const int tx = lt % ct.GX, ty = lt / ct.GX;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int lx = tid % TW, ly = tid / TW;
+    const int px = x0 + lx, py = y0 + ly;
+    const bool inside = px < ct.W && py < ct.H;
+    const uint32_t start = ws.ranges[2 * tile];
+    const uint32_t end = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity ? ws.ranges[2 * tile + 1] : start;
+    const uint32_t colbit = 1u << lx, rowbit = 1u << ly;
+    const float lxf = (float)lx, lyf = (float)ly;
+    const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
+
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
+    int n = 0;
+    bool done = !inside;
+    for (uint32_t bs = start; bs < end; bs += batch) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int cnt = (int)((end - bs) < (uint32_t)batch ? (end - bs) : (uint32_t)batch);
+        for (int k = tid; k < cnt; k += NT)
+            s_e[k] = load_entry(ws, (int64_t)bs + k, x0, y0, TW, TH);
+        __syncthreads();
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                const Entry e = s_e[j];
+                if (!((e.m.x & colbit) && (e.m.y & rowbit))) continue;
+                const Eval v = eval_splat(e, lxf, lyf, amax);
+                if (v.alpha < amin) continue;
+                const float Tn = T * (1.0f - v.alpha);
+                if (Tn < tmin) {
+                    done = true;
+                    break;
+                }
+                const float w = v.alpha * T;
+                C0 = fmaf(w, e.c.x, C0);
+                C1 = fmaf(w, e.c.y, C1);
+                C2 = fmaf(w, e.c.z, C2);
+                D = fmaf(w, e.b.w, D);
+                T = Tn;
+                n = (int)(bs - start) + j + 1;
+            }
+        }
+    }
+    if (inside) {
+        const int64_t W = ct.W, H = ct.H;
+        const int64_t pix = (int64_t)py * W + px;
+        const sgs_camera& c = cams[cam];
+        float* img = out.image + 3 * ct.pix_base;
+        img[pix] = C0 + T * c.bg[0];
+        img[W * H + pix] = C1 + T * c.bg[1];
+        img[2 * W * H + pix] = C2 + T * c.bg[2];
+        if (out.depth) out.depth[ct.pix_base + pix] = D;
+        out.final_T[ct.pix_base + pix] = T;
+        out.n_contrib[ct.pix_base + pix] = n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    return v + __int_as_float(s);
+}
+
+// sum over the 64 lanes; the full sum ends in lane 63
+__device__ __forceinline__ float wave_sum63(float v) {
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x124, 0xF>(v);  // row_ror:4
+    v = dpp_add<0x128, 0xF>(v);  // row_ror:8
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
+            sgs_outputs fwd, const float* __restrict__ grad_image, int batch) {
+    constexpr int NT = TW * TH;
+    extern __shared__ Entry s_e[];
+    __shared__ int s_cam;
+    __shared__ int s_maxn;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t tile = xcd_tile(blockIdx.x, ws.n_tiles);
+    if (tid == 0) {
+        s_cam = find_camera(ws.cams, n_cams, tile);
+        s_maxn = 0;
+    }
+    __syncthreads();
+    const int cam = s_cam;
+    const CamTable ct = ws.cams[cam];
+    if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    const int lt = (int)(tile - ct.tile_base);
+    const int tx = lt % ct.GX, ty = lt / ct.GX;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int lx = tid % TW, ly = tid / TW;
+    const int px = x0 + lx, py = y0 + ly;
+    const bool inside = px < ct.W && py < ct.H;
+    const uint32_t start = ws.ranges[2 * tile];
+    const int64_t len = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity
+                            ? (int64_t)ws.ranges[2 * tile + 1] - start : 0;
+    const uint32_t colbit = 1u << lx, rowbit = 1u << ly;
+    const float lxf = (float)lx, lyf = (float)ly;
+    const float amin = o.alpha_min, amax = o.alpha_max;
+    const sgs_camera& c = cams[cam];
+
+    float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    int nc = 0;
+    if (inside) {
+        const int64_t W = ct.W, H = ct.H;
+        const int64_t pix = (int64_t)py * W + px;
+        T = fwd.final_T[ct.pix_base + pix];
+        nc = fwd.n_contrib[ct.pix_base + pix];
+        const float* gi = grad_image + 3 * ct.pix_base;
+        g0 = gi[pix];
+        g1 = gi[W * H + pix];
+        g2 = gi[2 * W * H + pix];
+    }
+    float S0 = T * c.bg[0], S1 = T * c.bg[1], S2 = T * c.bg[2];
+    if (nc > len) nc = (int)len;
+    if (nc > 0) atomicMax(&s_maxn, nc);
+    __syncthreads();
+    const int maxn = s_maxn;
+    const int64_t M = ws.n_items;
+    float* G = ws.grad2d;
+    const float inv_k = (float)(1.0 / kHalfLog2e);
+
+    for (int be = maxn; be > 0; be -= batch) {
+        const int bb = be - batch > 0 ? be - batch : 0;
+        const int cnt = be - bb;
+        __syncthreads();
+        for (int k = tid; k < cnt; k += NT)
+            s_e[k] = load_entry(ws, (int64_t)start + bb + k, x0, y0, TW, TH);
+        __syncthreads();
+        for (int k = cnt - 1; k >= 0; --k) {
+            const Entry e = s_e[k];
+            const int j = bb + k;
+            float v_u = 0.f, v_v = 0.f, v_qa = 0.f, v_qb = 0.f, v_qc = 0.f, v_s = 0.f;
+            float v_r = 0.f, v_g = 0.f, v_b = 0.f;
+            bool contrib = false;
+            if (j < nc && (e.m.x & colbit) && (e.m.y & rowbit)) {
+                const Eval v = eval_splat(e, lxf, lyf, amax);
+                if (v.alpha >= amin) {
+                    contrib = true;
+                    const float om = 1.0f - v.alpha;
+                    T = T / om;
+                    const float w = v.alpha * T;
+                    v_r = w * g0;
+                    v_g = w * g1;
+                    v_b = w * g2;
+                    const float cg = e.c.x * g0 + e.c.y * g1 + e.c.z * g2;
+                    const float sg = S0 * g0 + S1 * g1 + S2 * g2;
+                    const float dLda = T * cg - sg / om;
+                    S0 = fmaf(w, e.c.x, S0);
+                    S1 = fmaf(w, e.c.y, S1);
+                    S2 = fmaf(w, e.c.z, S2);
+                    if (e.b.z * v.E <= amax) {
+                        v_s = dLda * v.E;
+                        const float dLdp = dLda * v.alpha;
+                        // dp/du = (Q d)_x, Q d = (w1 y1 + w2 y2) / k
+                        v_u = dLdp * (e.a.z * v.y1 + e.b.x * v.y2) * inv_k;
+                        v_v = dLdp * (e.a.w * v.y1 + e.b.y * v.y2) * inv_k;
+                        v_qa = -0.5f * dLdp * v.dx * v.dx;
+                        v_qb = -dLdp * v.dx * v.dy;
+                        v_qc = -0.5f * dLdp * v.dy * v.dy;
+                    }
+                }
+            }
+            if (__any(contrib)) {
+                v_u = wave_sum63(v_u);
+                v_v = wave_sum63(v_v);
+                v_qa = wave_sum63(v_qa);
+                v_qb = wave_sum63(v_qb);
+                v_qc = wave_sum63(v_qc);
+                v_s = wave_sum63(v_s);
+                v_r = wave_sum63(v_r);
+                v_g = wave_sum63(v_g);
+                v_b = wave_sum63(v_b);
+                if (lane == 63) {
+                    const int64_t item = __float_as_uint(e.c.w);
+                    unsafeAtomicAdd(G + 0 * M + item, v_u);
+                    unsafeAtomicAdd(G + 1 * M + item, v_v);
+                    unsafeAtomicAdd(G + 2 * M + item, v_qa);
+                    unsafeAtomicAdd(G + 3 * M + item, v_qb);
+                    unsafeAtomicAdd(G + 4 * M + item, v_qc);
+                    unsafeAtomicAdd(G + 5 * M + item, v_s);
+                    unsafeAtomicAdd(G + 6 * M + item, v_r);
+                    unsafeAtomicAdd(G + 7 * M + item, v_g);
+                    unsafeAtomicAdd(G + 8 * M + item, v_b);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+template <int TW, int TH>
+static void launch_fwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
+                         const sgs_outputs& out, hipStream_t s) {
+    const size_t lds = (size_t)o.batch * sizeof(Entry);
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds, s, ws,
+                       cams, n_cams, o, out, o.batch);
+}
+
+template <int TW, int TH>
+static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
+                         const sgs_outputs& fwd, const float* gi, hipStream_t s) {
+    const size_t lds = (size_t)o.batch * sizeof(Entry);
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds, s, ws,
+                       cams, n_cams, o, fwd, gi, o.batch);
+}
+
+#define SGS_TILE_SWITCH(F, ...)                                                   \
+    if (o.tile_w == 16 && o.tile_h == 16) F<16, 16>(__VA_ARGS__);                 \
+    else if (o.tile_w == 8 && o.tile_h == 8) F<8, 8>(__VA_ARGS__);                \
+    else if (o.tile_w == 16 && o.tile_h == 8) F<16, 8>(__VA_ARGS__);              \
+    else if (o.tile_w == 8 && o.tile_h == 16) F<8, 16>(__VA_ARGS__);              \
+    else if (o.tile_w == 32 && o.tile_h == 8) F<32, 8>(__VA_ARGS__);
+
+void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                      const sgs_outputs& out, hipStream_t s) {
+    if (ws.n_tiles <= 0) return;
+    SGS_TILE_SWITCH(launch_fwd_t, ws, dev_cams, n_cams, o, out, s)
+}
+
+void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                      const sgs_outputs& fwd, const float* grad_image, hipStream_t s) {
+    if (ws.n_tiles <= 0) return;
+    SGS_TILE_SWITCH(launch_bwd_t, ws, dev_cams, n_cams, o, fwd, grad_image, s)
+}
+
+// ---------------------------------------------------------------------------
+// L1 loss: L = sum_k mean_{3 H_k W_k} |img - tgt|, grad = sign / (3 H_k W_k)
+// ---------------------------------------------------------------------------
+
+constexpr int kL1Blocks = 1024;
+
+__global__ void __launch_bounds__(256)
+k_l1(Workspace ws, int n_cams, const float* __restrict__ img, const float* __restrict__ tgt,
+     float* __restrict__ grad, double* partial) {
+    __shared__ double s_sum[256];
+    double acc = 0.0;
+    const int64_t total = ws.n_pixels;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_cams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ws.cams[mid].pix_base <= p) lo = mid; else hi = mid - 1;
+        }
+        const CamTable ct = ws.cams[lo];
+        const int64_t wh = (int64_t)ct.W * ct.H;
+        const int64_t local = p - ct.pix_base;
+        const float inv = (float)(1.0 / (3.0 * (double)wh));
+        double part = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            const int64_t idx = 3 * ct.pix_base + ch * wh + local;
+            const float d = img[idx] - tgt[idx];
+            grad[idx] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+            part += fabs((double)d);
+        }
+        acc += part / (3.0 * (double)wh);
+    }
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s_sum[0];
+}
+
+__global__ void __launch_bounds__(256) k_l1_final(const double* partial, int n, double* loss) {
+    __shared__ double s_sum[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = s_sum[0];
+}
+
+void launch_l1(const Workspace& ws, int n_cams, const float* image, const float* target,
+               float* grad, double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_l1, dim3(kL1Blocks), dim3(256), 0, s, ws, n_cams, image, target, grad,
+                       ws.loss_partial);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, s, ws.loss_partial, kL1Blocks, loss);
+}
+
+}  // namespace sgs

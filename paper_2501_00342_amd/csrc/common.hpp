@@ -1,0 +1,134 @@
+// Internal definitions shared by the HIP kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sgsplat.h"
+
+namespace sgs {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                       // per thread
+constexpr int kSortTile = kSortThreads * kSortItems; // items per onesweep partition
+constexpr int kDupChunk = 2048;                      // pairs per duplicate chunk
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kPreThreads = 256;
+constexpr int kHistBlocksMax = 1024;                 // partial-histogram rows (persistent grids)
+constexpr int kHistFold = 32;                        // second-level rows
+constexpr int kDepthPasses = 4;                      // 32-bit depth keys
+constexpr int kMaxTilePasses = 4;
+
+// header words (u32) at workspace offset 0
+enum Header : int {
+    kHdrStatus = 0,
+    kHdrPairs = 1,
+    kHdrTicketBase = 2,   // one ticket per sort/scan pass: [2, 2+12)
+    kHdrWords = 16
+};
+enum TicketSlot : int {
+    kTicketScan = 0,
+    kTicketDepth0 = 1,    // 1..4 depth passes
+    kTicketTile0 = 5,     // 5..8 tile passes
+};
+
+// per camera, computed on the device from the device cameras
+struct CamTable {
+    int32_t W, H, GX, GY, tile_base, pad;
+    int64_t pix_base;
+};
+
+// 64-byte splat record written by the preprocess, gathered by the blends
+struct __align__(16) Rec {
+    float u_hi, v_hi, u_lo, v_lo;     // projected mean as float32 hi + lo parts
+    float w1x, w1y, w2x, w2y;         // whitening rows: q = (w1.d)^2 + (w2.d)^2
+    float opacity, r, g, b;
+    float z;                          // camera depth
+    uint32_t rect_x;                  // px0 | px1 << 16 (inclusive pixel rectangle)
+    uint32_t rect_y;                  // py0 | py1 << 16
+    int32_t radius;
+};
+static_assert(sizeof(Rec) == 64, "record layout");
+
+// q = (log2 e / 2) d^T Q d, so that exp(-d^T Q d / 2) = exp2(-q)
+constexpr double kHalfLog2e = 0.72134752044448170368;
+
+struct Opts {
+    int tile_w, tile_h, batch;
+    float dilation, guard, alpha_min, alpha_max, t_min;
+};
+
+struct Params {
+    int64_t n;
+    int sh_degree, n_lobes;
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity_logits;
+    const float* sh;
+    const float* sg_axes;
+    const float* sg_log_sharpness;
+    const float* sg_amplitudes;
+};
+
+struct Workspace {
+    uint32_t* header;
+    CamTable* cams;
+    Rec* records;
+    uint32_t* depth_keys;
+    uint64_t* tile_rects;
+    uint32_t* sort_keys_alt;     // ping-pong for depth keys
+    uint32_t* sort_keys_alt2;
+    uint32_t* sorted_items;      // final depth order
+    uint32_t* sorted_items_alt;
+    uint32_t* pair_offsets;
+    uint32_t* chunk_start;       // first sorted position of every duplicate chunk
+    uint32_t* pair_tiles;
+    uint32_t* pair_values;
+    uint32_t* pair_tiles_alt;
+    uint32_t* pair_values_alt;
+    uint32_t* ranges;
+    float* grad2d;
+    uint32_t* hist_partial;      // [kHistBlocksMax][passes][256]
+    uint32_t* hist_fold;         // [kHistFold][passes][256]
+    uint32_t* digit_offsets;     // [kDepthPasses + kMaxTilePasses][256]
+    uint32_t* lookback;          // per pass: [partitions][256]
+    uint64_t* scan_lookback;     // [partitions]
+    double* loss_partial;
+    int64_t n_items, n_tiles, n_pixels, capacity;
+    int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
+    int dup_blocks;              // persistent grid of the duplicate kernel
+    int tile_passes, tile_bits;
+    int64_t lookback_pass_words;  // words per pass in `lookback`
+};
+
+// launchers (defined in the .hip files)
+void launch_clear(const Workspace& ws, hipStream_t s);
+void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, int tile_w, int tile_h,
+                  hipStream_t s);
+void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                       const Workspace& ws, int hist_blocks, hipStream_t s);
+void launch_hist_scan(const Workspace& ws, int passes, int digit_row0, int hist_rows, hipStream_t s);
+void launch_onesweep(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                     uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host,
+                     int shift, const uint32_t* digit_offsets, uint32_t* lookback,
+                     uint32_t* ticket, int64_t parts, hipStream_t s);
+void launch_scan_pairs(const Workspace& ws, hipStream_t s);
+void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
+void launch_ranges(const Workspace& ws, hipStream_t s);
+void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                      const sgs_outputs& out, hipStream_t s);
+void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                      const sgs_outputs& fwd, const float* grad_image, hipStream_t s);
+void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                           const Workspace& ws, const sgs_grads& gr, hipStream_t s);
+void launch_l1(const Workspace& ws, int n_cams, const float* image, const float* target,
+               float* grad, double* loss, hipStream_t s);
+void launch_read_keys(const Workspace& ws, int64_t count, uint64_t* keys, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+
+}  // namespace sgs

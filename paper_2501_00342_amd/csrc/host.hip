@@ -1,0 +1,404 @@
+// C-ABI entry points: argument checks, workspace layout, launch sequence.
+#include <string.h>
+
+#include <string>
+
+#include "common.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define SGS_HIP(x)                                                                       \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) return fail(SGS_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define SGS_LAUNCHED()                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = hipGetLastError();                                               \
+        if (e_ != hipSuccess) return fail(SGS_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Plan {
+    sgs_layout lay;
+    sgs::Opts o;
+    int64_t n;
+    int n_cams;
+    int tile_passes, tile_bits;
+    int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
+    int pre_blocks, dup_blocks;
+    int64_t pass_words;
+    // offsets not exported in sgs_layout
+    size_t sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
+        pair_values_alt, hist_partial, hist_fold, digit_offsets, lookback, scan_lookback,
+        loss_partial;
+};
+
+bool tile_shape_ok(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) ||
+           (tw == 8 && th == 16) || (tw == 32 && th == 8);
+}
+
+int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const sgs_options* oin,
+         int64_t cap, Plan* pl) {
+    if (!g) return fail(SGS_E_INVALID, "gaussians is NULL");
+    if (g->n < 0) return fail(SGS_E_INVALID, "n < 0");
+    if (g->sh_degree < 0 || g->sh_degree > SGS_MAX_SH_DEGREE)
+        return fail(SGS_E_INVALID, "sh_degree must be 0..3");
+    if (g->n_lobes < 0 || g->n_lobes > SGS_MAX_LOBES)
+        return fail(SGS_E_INVALID, "n_lobes must be 0..8");
+    if (!cams) return fail(SGS_E_INVALID, "host cameras are NULL");
+    if (n_cams < 1 || n_cams > SGS_MAX_CAMERAS) return fail(SGS_E_INVALID, "n_cams must be 1..1024");
+    if (cap < 0 || cap >= (int64_t(1) << 30)) return fail(SGS_E_INVALID, "pair_capacity must be in [0, 2^30)");
+    sgs::Opts o;
+    o.tile_w = oin && oin->tile_w ? oin->tile_w : 16;
+    o.tile_h = oin && oin->tile_h ? oin->tile_h : 16;
+    if (!tile_shape_ok(o.tile_w, o.tile_h))
+        return fail(SGS_E_INVALID, "tile shape must be 16x16, 8x8, 16x8, 8x16 or 32x8");
+    const int nt = o.tile_w * o.tile_h;
+    o.batch = oin && oin->batch ? oin->batch : nt;
+    if (o.batch < nt || o.batch % nt != 0 || o.batch > 1024)
+        return fail(SGS_E_INVALID, "batch must be a multiple of tile_w*tile_h, at most 1024");
+    o.dilation = oin && oin->dilation != 0.0f ? oin->dilation : 0.3f;
+    o.guard = oin && oin->guard != 0.0f ? oin->guard : 1.3f;
+    o.alpha_min = oin && oin->alpha_min != 0.0f ? oin->alpha_min : 1.0f / 255.0f;
+    o.alpha_max = oin && oin->alpha_max != 0.0f ? oin->alpha_max : 0.99f;
+    o.t_min = oin && oin->t_min != 0.0f ? oin->t_min : 1e-4f;
+    if (!(o.alpha_max > 0.0f && o.alpha_max < 1.0f))
+        return fail(SGS_E_INVALID, "alpha_max must be in (0, 1)");
+    int64_t tiles = 0, pixels = 0;
+    for (int c = 0; c < n_cams; ++c) {
+        const int W = cams[c].width, H = cams[c].height;
+        if (W < 1 || H < 1 || W > SGS_MAX_IMAGE_SIDE || H > SGS_MAX_IMAGE_SIDE)
+            return fail(SGS_E_INVALID, "camera width/height must be 1..32767");
+        tiles += cdiv(W, o.tile_w) * cdiv(H, o.tile_h);
+        pixels += (int64_t)W * H;
+    }
+    const int64_t n = g->n;
+    const int64_t items = n * n_cams;
+    if (items >= (int64_t(1) << 30)) return fail(SGS_E_INVALID, "n * n_cams must be < 2^30");
+    if (tiles >= (int64_t(1) << 31)) return fail(SGS_E_INVALID, "too many tiles");
+
+    pl->o = o;
+    pl->n = n;
+    pl->n_cams = n_cams;
+    int bits = 1;
+    while ((int64_t(1) << bits) < tiles) ++bits;
+    pl->tile_bits = bits;
+    pl->tile_passes = (bits + sgs::kRadixBits - 1) / sgs::kRadixBits;
+    pl->depth_parts = cdiv(items, sgs::kSortTile);
+    pl->pair_parts = cdiv(cap, sgs::kSortTile);
+    pl->scan_parts = cdiv(items, sgs::kScanTile);
+    pl->dup_chunks = cdiv(cap, sgs::kDupChunk);
+    int64_t pb = cdiv(n, sgs::kPreThreads);
+    pl->pre_blocks = (int)(pb < 1 ? 1 : (pb > sgs::kHistBlocksMax ? sgs::kHistBlocksMax : pb));
+    int64_t db = pl->dup_chunks;
+    pl->dup_blocks = (int)(db < 1 ? 1 : (db > sgs::kHistBlocksMax ? sgs::kHistBlocksMax : db));
+    pl->pass_words = (pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts) * sgs::kRadix;
+
+    sgs_layout& L = pl->lay;
+    memset(&L, 0, sizeof(L));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    // header, loss partials and camera table first: their offsets depend on
+    // n_cams only, so render_l1 can find them from the cameras alone
+    L.header = take(sgs::kHdrWords * 4);
+    pl->loss_partial = take(1024 * 8);
+    L.cam_table = take((size_t)n_cams * sizeof(sgs::CamTable));
+    L.records = take((size_t)items * sizeof(sgs::Rec));
+    L.depth_keys = take((size_t)items * 4);
+    L.tile_rects = take((size_t)items * 8);
+    pl->sort_keys_alt = take((size_t)items * 4);
+    pl->sort_keys_alt2 = take((size_t)items * 4);
+    L.sorted_items = take((size_t)items * 4);
+    pl->sorted_items_alt = take((size_t)items * 4);
+    L.pair_offsets = take((size_t)(items + 1) * 4);
+    pl->chunk_start = take((size_t)(pl->dup_chunks + 1) * 4);
+    L.pair_tiles = take((size_t)cap * 4);
+    L.pair_values = take((size_t)cap * 4);
+    pl->pair_tiles_alt = take((size_t)cap * 4);
+    pl->pair_values_alt = take((size_t)cap * 4);
+    L.ranges = take((size_t)tiles * 8);
+    L.grad2d = take((size_t)items * 9 * 4);
+    const int hpass = pl->tile_passes > sgs::kDepthPasses ? pl->tile_passes : sgs::kDepthPasses;
+    pl->hist_partial = take((size_t)sgs::kHistBlocksMax * hpass * sgs::kRadix * 4);
+    pl->hist_fold = take((size_t)sgs::kHistFold * hpass * sgs::kRadix * 4);
+    pl->digit_offsets = take((size_t)(sgs::kDepthPasses + sgs::kMaxTilePasses) * sgs::kRadix * 4);
+    pl->lookback = take((size_t)pl->pass_words * (sgs::kDepthPasses + pl->tile_passes) * 4);
+    pl->scan_lookback = take((size_t)pl->scan_parts * 8);
+    L.total_bytes = off;
+    L.n_items = items;
+    L.n_tiles = tiles;
+    L.n_pixels = pixels;
+    L.pair_capacity = cap;
+    return SGS_OK;
+}
+
+sgs::Workspace bind(const Plan& pl, void* base) {
+    char* b = static_cast<char*>(base);
+    const sgs_layout& L = pl.lay;
+    sgs::Workspace w;
+    w.header = reinterpret_cast<uint32_t*>(b + L.header);
+    w.cams = reinterpret_cast<sgs::CamTable*>(b + L.cam_table);
+    w.records = reinterpret_cast<sgs::Rec*>(b + L.records);
+    w.depth_keys = reinterpret_cast<uint32_t*>(b + L.depth_keys);
+    w.tile_rects = reinterpret_cast<uint64_t*>(b + L.tile_rects);
+    w.sort_keys_alt = reinterpret_cast<uint32_t*>(b + pl.sort_keys_alt);
+    w.sort_keys_alt2 = reinterpret_cast<uint32_t*>(b + pl.sort_keys_alt2);
+    w.sorted_items = reinterpret_cast<uint32_t*>(b + L.sorted_items);
+    w.sorted_items_alt = reinterpret_cast<uint32_t*>(b + pl.sorted_items_alt);
+    w.pair_offsets = reinterpret_cast<uint32_t*>(b + L.pair_offsets);
+    w.chunk_start = reinterpret_cast<uint32_t*>(b + pl.chunk_start);
+    w.pair_tiles = reinterpret_cast<uint32_t*>(b + L.pair_tiles);
+    w.pair_values = reinterpret_cast<uint32_t*>(b + L.pair_values);
+    w.pair_tiles_alt = reinterpret_cast<uint32_t*>(b + pl.pair_tiles_alt);
+    w.pair_values_alt = reinterpret_cast<uint32_t*>(b + pl.pair_values_alt);
+    w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
+    w.grad2d = reinterpret_cast<float*>(b + L.grad2d);
+    w.hist_partial = reinterpret_cast<uint32_t*>(b + pl.hist_partial);
+    w.hist_fold = reinterpret_cast<uint32_t*>(b + pl.hist_fold);
+    w.digit_offsets = reinterpret_cast<uint32_t*>(b + pl.digit_offsets);
+    w.lookback = reinterpret_cast<uint32_t*>(b + pl.lookback);
+    w.scan_lookback = reinterpret_cast<uint64_t*>(b + pl.scan_lookback);
+    w.loss_partial = reinterpret_cast<double*>(b + pl.loss_partial);
+    w.n_items = L.n_items;
+    w.n_tiles = L.n_tiles;
+    w.n_pixels = L.n_pixels;
+    w.capacity = L.pair_capacity;
+    w.depth_parts = pl.depth_parts;
+    w.pair_parts = pl.pair_parts;
+    w.scan_parts = pl.scan_parts;
+    w.dup_chunks = pl.dup_chunks;
+    w.dup_blocks = pl.dup_blocks;
+    w.tile_passes = pl.tile_passes;
+    w.tile_bits = pl.tile_bits;
+    w.lookback_pass_words = pl.pass_words;
+    return w;
+}
+
+sgs::Params params_of(const sgs_gaussians* g) {
+    sgs::Params p;
+    p.n = g->n;
+    p.sh_degree = g->sh_degree;
+    p.n_lobes = g->n_lobes;
+    p.means = g->means;
+    p.log_scales = g->log_scales;
+    p.quats = g->quats;
+    p.opacity_logits = g->opacity_logits;
+    p.sh = g->sh;
+    p.sg_axes = g->sg_axes;
+    p.sg_log_sharpness = g->sg_log_sharpness;
+    p.sg_amplitudes = g->sg_amplitudes;
+    return p;
+}
+
+int check_params(const sgs_gaussians* g) {
+    if (g->n == 0) return SGS_OK;
+    if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)
+        return fail(SGS_E_INVALID, "a Gaussian parameter array is NULL");
+    if (g->n_lobes > 0 && (!g->sg_axes || !g->sg_log_sharpness || !g->sg_amplitudes))
+        return fail(SGS_E_INVALID, "an SG lobe array is NULL");
+    return SGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t render_workspace_bytes(const sgs_gaussians* g, const sgs_camera* host_cams, int32_t n_cams,
+                              const sgs_options* opts, int64_t pair_capacity) {
+    Plan pl;
+    if (plan(g, host_cams, n_cams, opts, pair_capacity, &pl) != SGS_OK) return 0;
+    return pl.lay.total_bytes;
+}
+
+int render_layout(const sgs_gaussians* g, const sgs_camera* host_cams, int32_t n_cams,
+                  const sgs_options* opts, int64_t pair_capacity, sgs_layout* out) {
+    if (!out) return fail(SGS_E_INVALID, "layout output is NULL");
+    Plan pl;
+    const int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
+    if (rc != SGS_OK) return rc;
+    *out = pl.lay;
+    return SGS_OK;
+}
+
+int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
+                   int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
+                   int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
+                   int64_t* pairs_needed, void* stream) {
+    Plan pl;
+    int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
+    if (rc != SGS_OK) return rc;
+    if ((rc = check_params(g)) != SGS_OK) return rc;
+    if (!dev_cams) return fail(SGS_E_INVALID, "device cameras are NULL");
+    if (!workspace) return fail(SGS_E_INVALID, "workspace is NULL");
+    if (workspace_bytes < pl.lay.total_bytes) return fail(SGS_E_INVALID, "workspace too small");
+    if (!outs || !outs->image || !outs->final_T || !outs->n_contrib)
+        return fail(SGS_E_INVALID, "image, final_T and n_contrib outputs are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sgs::Workspace ws = bind(pl, workspace);
+    const sgs::Params p = params_of(g);
+    const sgs::Opts& o = pl.o;
+    (void)hipGetLastError();
+
+    sgs::launch_clear(ws, s);
+    sgs::launch_setup(ws, dev_cams, n_cams, o.tile_w, o.tile_h, s);
+    SGS_LAUNCHED();
+    if (pl.n > 0) {
+        sgs::launch_preprocess(p, dev_cams, n_cams, o, ws, pl.pre_blocks, s);
+        SGS_LAUNCHED();
+        // depth sort of the items: 4 passes, final order in sorted_items
+        sgs::launch_hist_scan(ws, sgs::kDepthPasses, 0, pl.pre_blocks, s);
+        const uint32_t* kin[4] = {ws.depth_keys, ws.sort_keys_alt, ws.sort_keys_alt2, ws.sort_keys_alt};
+        const uint32_t* vin[4] = {nullptr, ws.sorted_items_alt, ws.sorted_items, ws.sorted_items_alt};
+        uint32_t* kout[4] = {ws.sort_keys_alt, ws.sort_keys_alt2, ws.sort_keys_alt, nullptr};
+        uint32_t* vout[4] = {ws.sorted_items_alt, ws.sorted_items, ws.sorted_items_alt, ws.sorted_items};
+        for (int ps = 0; ps < sgs::kDepthPasses; ++ps) {
+            sgs::launch_onesweep(kin[ps], vin[ps], kout[ps], vout[ps], nullptr, ws.n_items,
+                                 ps * sgs::kRadixBits, ws.digit_offsets + ps * sgs::kRadix,
+                                 ws.lookback + ps * pl.pass_words,
+                                 ws.header + sgs::kHdrTicketBase + sgs::kTicketDepth0 + ps,
+                                 pl.depth_parts, s);
+        }
+        SGS_LAUNCHED();
+        sgs::launch_scan_pairs(ws, s);
+        SGS_LAUNCHED();
+    }
+    if (flags & SGS_FLAG_CHECK_CAPACITY) {
+        uint32_t h[2] = {0, 0};
+        SGS_HIP(hipMemcpyAsync(h, ws.header, 8, hipMemcpyDeviceToHost, s));
+        SGS_HIP(hipStreamSynchronize(s));
+        const uint32_t P = h[sgs::kHdrPairs];
+        if (pairs_needed) *pairs_needed = P;
+        if (h[sgs::kHdrStatus] & SGS_STATUS_CAMERAS)
+            return fail(SGS_E_INVALID, "device cameras disagree with the host cameras' sizes");
+        if ((int64_t)P > pair_capacity)
+            return fail(SGS_E_CAPACITY, "pair capacity " + std::to_string(pair_capacity) +
+                                            " < " + std::to_string(P) + " pairs");
+    }
+    if (pl.n > 0 && pair_capacity > 0) {
+        // the duplicate writes where the last tile pass leaves the primary buffers
+        sgs::Workspace wd = ws;
+        if (pl.tile_passes % 2 == 1) {
+            wd.pair_tiles = ws.pair_tiles_alt;
+            wd.pair_values = ws.pair_values_alt;
+        }
+        sgs::launch_duplicate(wd, pl.n, s);
+        SGS_LAUNCHED();
+        sgs::launch_hist_scan(ws, pl.tile_passes, sgs::kDepthPasses, pl.dup_blocks, s);
+        uint32_t* tk[2] = {wd.pair_tiles, wd.pair_tiles == ws.pair_tiles ? ws.pair_tiles_alt : ws.pair_tiles};
+        uint32_t* tv[2] = {wd.pair_values, wd.pair_values == ws.pair_values ? ws.pair_values_alt : ws.pair_values};
+        for (int ps = 0; ps < pl.tile_passes; ++ps) {
+            const int a = ps % 2, b = 1 - a;
+            sgs::launch_onesweep(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs, pair_capacity,
+                                 ps * sgs::kRadixBits,
+                                 ws.digit_offsets + (sgs::kDepthPasses + ps) * sgs::kRadix,
+                                 ws.lookback + (sgs::kDepthPasses + ps) * pl.pass_words,
+                                 ws.header + sgs::kHdrTicketBase + sgs::kTicketTile0 + ps,
+                                 pl.pair_parts, s);
+        }
+        SGS_LAUNCHED();
+        sgs::launch_ranges(ws, s);
+        SGS_LAUNCHED();
+    }
+    sgs::launch_blend_fwd(ws, dev_cams, n_cams, o, *outs, s);
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
+int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
+                    int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
+                    int64_t pair_capacity, const sgs_outputs* fwd, const float* grad_image,
+                    const sgs_grads* grads, void* stream) {
+    Plan pl;
+    int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
+    if (rc != SGS_OK) return rc;
+    if ((rc = check_params(g)) != SGS_OK) return rc;
+    if (!dev_cams || !workspace || !fwd || !fwd->final_T || !fwd->n_contrib || !grad_image || !grads)
+        return fail(SGS_E_INVALID, "a required backward argument is NULL");
+    if (workspace_bytes < pl.lay.total_bytes) return fail(SGS_E_INVALID, "workspace too small");
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats ||
+                     !grads->opacity_logits || !grads->sh))
+        return fail(SGS_E_INVALID, "a gradient output array is NULL");
+    if (g->n > 0 && g->n_lobes > 0 &&
+        (!grads->sg_axes || !grads->sg_log_sharpness || !grads->sg_amplitudes))
+        return fail(SGS_E_INVALID, "an SG gradient output array is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sgs::Workspace ws = bind(pl, workspace);
+    const sgs::Params p = params_of(g);
+    (void)hipGetLastError();
+    if (pl.n == 0) return SGS_OK;
+    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, 9 * ws.n_items, s);
+    sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, s);
+    SGS_LAUNCHED();
+    sgs::launch_preprocess_bwd(p, dev_cams, n_cams, pl.o, ws, *grads, s);
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
+int render_l1(const sgs_camera* host_cams, int32_t n_cams, const void* workspace, const float* image,
+              const float* target, float* grad_image, double* loss, void* stream) {
+    if (!host_cams || n_cams < 1 || n_cams > SGS_MAX_CAMERAS)
+        return fail(SGS_E_INVALID, "cameras");
+    if (!workspace || !image || !target || !grad_image || !loss)
+        return fail(SGS_E_INVALID, "a required L1 argument is NULL");
+    sgs_gaussians g0;
+    memset(&g0, 0, sizeof(g0));
+    Plan pl;
+    // only the camera table and the loss partials are used; their offsets do
+    // not depend on n, the options or the capacity
+    int rc = plan(&g0, host_cams, n_cams, nullptr, 0, &pl);
+    if (rc != SGS_OK) return rc;
+    sgs::Workspace ws = bind(pl, const_cast<void*>(workspace));
+    (void)hipGetLastError();
+    sgs::launch_l1(ws, n_cams, image, target, grad_image, loss, static_cast<hipStream_t>(stream));
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
+int render_status(const void* workspace, uint32_t* status_bits, int64_t* pairs, void* stream) {
+    if (!workspace) return fail(SGS_E_INVALID, "workspace is NULL");
+    uint32_t h[2];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SGS_HIP(hipStreamSynchronize(s));
+    SGS_HIP(hipMemcpy(h, workspace, 8, hipMemcpyDeviceToHost));
+    if (status_bits) *status_bits = h[0];
+    if (pairs) *pairs = h[1];
+    return SGS_OK;
+}
+
+int render_read_keys(const void* workspace, const sgs_layout* layout, int64_t count,
+                     uint64_t* keys_out, void* stream) {
+    if (!workspace || !layout || !keys_out) return fail(SGS_E_INVALID, "NULL argument");
+    if (count < 0 || count > layout->pair_capacity) return fail(SGS_E_INVALID, "count");
+    const char* b = static_cast<const char*>(workspace);
+    sgs::Workspace ws;
+    memset(&ws, 0, sizeof(ws));
+    ws.pair_tiles = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->pair_tiles);
+    ws.pair_values = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->pair_values);
+    ws.depth_keys = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->depth_keys);
+    ws.n_items = layout->n_items;
+    (void)hipGetLastError();
+    sgs::launch_read_keys(ws, count, keys_out, static_cast<hipStream_t>(stream));
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
+const char* render_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

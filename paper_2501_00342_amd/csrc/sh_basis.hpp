@@ -1,0 +1,88 @@
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase), as
+// polynomials of a unit direction (x, y, z), and their partial derivatives.
+// Colour model eq. 4 of SG-Splatting; normalisation
+// K_l^m = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!), times sqrt(2) for m != 0.
+// Order: l-major, m = -l..l.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sgs {
+
+#define SGS_PI 3.14159265358979323846
+
+template <int DEG>
+__device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y) {
+    Y[0] = 0.5 * sqrt(1.0 / SGS_PI);
+    if (DEG >= 1) {
+        const double c1 = sqrt(3.0 / (4.0 * SGS_PI));
+        Y[1] = -c1 * y;
+        Y[2] = c1 * z;
+        Y[3] = -c1 * x;
+    }
+    if (DEG >= 2) {
+        const double a = 0.5 * sqrt(15.0 / SGS_PI);
+        const double b = 0.25 * sqrt(5.0 / SGS_PI);
+        const double c = 0.25 * sqrt(15.0 / SGS_PI);
+        Y[4] = a * x * y;
+        Y[5] = -a * y * z;
+        Y[6] = b * (3.0 * z * z - 1.0);
+        Y[7] = -a * x * z;
+        Y[8] = c * (x * x - y * y);
+    }
+    if (DEG >= 3) {
+        const double a = 0.25 * sqrt(35.0 / (2.0 * SGS_PI));
+        const double b = 0.5 * sqrt(105.0 / SGS_PI);
+        const double c = 0.25 * sqrt(21.0 / (2.0 * SGS_PI));
+        const double d = 0.25 * sqrt(7.0 / SGS_PI);
+        const double e = 0.25 * sqrt(105.0 / SGS_PI);
+        const double z5 = 5.0 * z * z - 1.0;
+        Y[9] = -a * y * (3.0 * x * x - y * y);
+        Y[10] = b * x * y * z;
+        Y[11] = -c * y * z5;
+        Y[12] = d * z * (5.0 * z * z - 3.0);
+        Y[13] = -c * x * z5;
+        Y[14] = e * z * (x * x - y * y);
+        Y[15] = -a * x * (x * x - 3.0 * y * y);
+    }
+}
+
+// dY/dx, dY/dy, dY/dz of the polynomials above (x, y, z independent).
+template <int DEG>
+__device__ __forceinline__ void sh_grad(double x, double y, double z, double* gx, double* gy,
+                                        double* gz) {
+    gx[0] = gy[0] = gz[0] = 0.0;
+    if (DEG >= 1) {
+        const double c1 = sqrt(3.0 / (4.0 * SGS_PI));
+        gx[1] = 0.0; gy[1] = -c1; gz[1] = 0.0;
+        gx[2] = 0.0; gy[2] = 0.0; gz[2] = c1;
+        gx[3] = -c1; gy[3] = 0.0; gz[3] = 0.0;
+    }
+    if (DEG >= 2) {
+        const double a = 0.5 * sqrt(15.0 / SGS_PI);
+        const double b = 0.25 * sqrt(5.0 / SGS_PI);
+        const double c = 0.25 * sqrt(15.0 / SGS_PI);
+        gx[4] = a * y;   gy[4] = a * x;   gz[4] = 0.0;
+        gx[5] = 0.0;     gy[5] = -a * z;  gz[5] = -a * y;
+        gx[6] = 0.0;     gy[6] = 0.0;     gz[6] = 6.0 * b * z;
+        gx[7] = -a * z;  gy[7] = 0.0;     gz[7] = -a * x;
+        gx[8] = 2.0 * c * x; gy[8] = -2.0 * c * y; gz[8] = 0.0;
+    }
+    if (DEG >= 3) {
+        const double a = 0.25 * sqrt(35.0 / (2.0 * SGS_PI));
+        const double b = 0.5 * sqrt(105.0 / SGS_PI);
+        const double c = 0.25 * sqrt(21.0 / (2.0 * SGS_PI));
+        const double d = 0.25 * sqrt(7.0 / SGS_PI);
+        const double e = 0.25 * sqrt(105.0 / SGS_PI);
+        const double z5 = 5.0 * z * z - 1.0;
+        gx[9] = -a * 6.0 * x * y;            gy[9] = -a * (3.0 * x * x - 3.0 * y * y); gz[9] = 0.0;
+        gx[10] = b * y * z;                  gy[10] = b * x * z;                        gz[10] = b * x * y;
+        gx[11] = 0.0;                        gy[11] = -c * z5;                          gz[11] = -c * y * 10.0 * z;
+        gx[12] = 0.0;                        gy[12] = 0.0;                              gz[12] = d * (15.0 * z * z - 3.0);
+        gx[13] = -c * z5;                    gy[13] = 0.0;                              gz[13] = -c * x * 10.0 * z;
+        gx[14] = 2.0 * e * x * z;            gy[14] = -2.0 * e * y * z;                 gz[14] = e * (x * x - y * y);
+        gx[15] = -a * (3.0 * x * x - 3.0 * y * y); gy[15] = a * 6.0 * x * y;           gz[15] = 0.0;
+    }
+}
+
+}  // namespace sgs

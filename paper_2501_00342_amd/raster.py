@@ -1,0 +1,212 @@
+"""PyTorch front end of the HIP rasteriser.
+
+PyTorch supplies device memory and the stream; every step of the render
+runs in libsgsplat.so.  `Rasterizer` owns one workspace (records, pairs,
+ranges) that a backward reuses from its forward; `render` wraps it in a
+torch.autograd.Function.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .scenes import FIELDS, Options, Scene
+
+REC_FIELDS = ("u_hi", "v_hi", "u_lo", "v_lo", "w1x", "w1y", "w2x", "w2y", "opacity",
+              "r", "g", "b", "z", "rect_x", "rect_y", "radius")
+
+
+def params_to_device(scene: Scene, device="cuda") -> dict:
+    """Scene arrays -> contiguous float32 device tensors (same SoA layout)."""
+    return {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).to(device)
+            for k in FIELDS}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if (t is not None and t.numel() > 0) else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Outputs:
+    image: torch.Tensor      # packed (3 * sum W H,) float32
+    depth: torch.Tensor      # packed (sum W H,)
+    final_T: torch.Tensor
+    n_contrib: torch.Tensor  # int32
+
+    def camera(self, k: int, cams) -> tuple:
+        """(image (3,H,W), depth, final_T, n_contrib) views of camera k."""
+        base = sum(int(c.width) * int(c.height) for c in cams[:k])
+        W, H = int(cams[k].width), int(cams[k].height)
+        img = self.image[3 * base: 3 * (base + W * H)].view(3, H, W)
+        sl = slice(base, base + W * H)
+        return (img, self.depth[sl].view(H, W), self.final_T[sl].view(H, W),
+                self.n_contrib[sl].view(H, W))
+
+
+class Rasterizer:
+    """Plans and runs forward/backward passes for fixed cameras and options.
+
+    capacity: initial (tile, Gaussian) pair capacity; grown automatically
+    when `auto_grow` and a forward reports more pairs (one host sync).
+    """
+
+    def __init__(self, cams, opts: Options, n: int, sh_degree: int, n_lobes: int,
+                 device="cuda", capacity: int | None = None, auto_grow: bool = True):
+        self.cams = list(cams)
+        self.opts = opts
+        self.n, self.sh_degree, self.n_lobes = int(n), int(sh_degree), int(n_lobes)
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.host_cams = L.camera_array(self.cams)
+        raw = bytes(self.host_cams)
+        self.dev_cams = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        self.copts = L.options_struct(opts)
+        self.n_pixels = sum(int(c.width) * int(c.height) for c in self.cams)
+        self.auto_grow = auto_grow
+        self.capacity = int(capacity if capacity is not None else max(1 << 16, 8 * self.n))
+        self.capacity = min(self.capacity, (1 << 30) - 1)
+        self.ws = None
+        self.layout = None
+        self._alloc()
+
+    # -- planning ----------------------------------------------------------
+    def _gstruct(self, params: dict | None):
+        ptrs = {k: (params[k].data_ptr() if params[k].numel() else None) for k in FIELDS} \
+            if params else {}
+        return L.gaussians_struct(self.n, self.sh_degree, self.n_lobes, ptrs)
+
+    def _alloc(self):
+        g = self._gstruct(None)
+        lay = L.Layout()
+        L.check(L.LIB.render_layout(ctypes.byref(g), self.host_cams, len(self.cams),
+                                    ctypes.byref(self.copts), self.capacity, ctypes.byref(lay)))
+        self.layout = lay
+        self.ws = torch.empty(int(lay.total_bytes), dtype=torch.uint8, device=self.device)
+
+    def new_outputs(self) -> Outputs:
+        P = self.n_pixels
+        d = self.device
+        return Outputs(torch.empty(3 * P, dtype=torch.float32, device=d),
+                       torch.empty(P, dtype=torch.float32, device=d),
+                       torch.empty(P, dtype=torch.float32, device=d),
+                       torch.empty(P, dtype=torch.int32, device=d))
+
+    def _check_params(self, params):
+        for k in FIELDS:
+            t = params[k]
+            assert t.device == self.device and t.dtype == torch.float32 and t.is_contiguous(), k
+            assert t.shape[-1] == self.n or t.numel() == 0, k
+
+    # -- passes --------------------------------------------------------------
+    def forward(self, params: dict, out: Outputs | None = None, check: bool | None = None) -> Outputs:
+        self._check_params(params)
+        out = out or self.new_outputs()
+        check = self.auto_grow if check is None else check
+        g = self._gstruct(params)
+        o = L.Outputs(_ptr(out.image), _ptr(out.depth), _ptr(out.final_T), _ptr(out.n_contrib))
+        need = L.c_int64(0)
+        flags = L.SGS_FLAG_CHECK_CAPACITY if check else 0
+        while True:
+            rc = L.LIB.render_forward(ctypes.byref(g), self.host_cams, _ptr(self.dev_cams),
+                                      len(self.cams), ctypes.byref(self.copts), _ptr(self.ws),
+                                      self.ws.numel(), self.capacity, ctypes.byref(o), flags,
+                                      ctypes.byref(need), _stream())
+            if rc == L.SGS_E_CAPACITY and self.auto_grow:
+                self.capacity = min((1 << 30) - 1, int(need.value * 1.15) + 4096)
+                self.ws = None
+                torch.cuda.current_stream().synchronize()
+                self._alloc()
+                continue
+            L.check(rc)
+            return out
+
+    def backward(self, params: dict, out: Outputs, grad_image: torch.Tensor) -> dict:
+        self._check_params(params)
+        assert grad_image.dtype == torch.float32 and grad_image.is_contiguous()
+        assert grad_image.numel() == 3 * self.n_pixels
+        grads = {k: torch.empty_like(params[k]) for k in FIELDS}
+        g = self._gstruct(params)
+        gr = L.grads_struct({k: (grads[k].data_ptr() if grads[k].numel() else None)
+                             for k in FIELDS})
+        o = L.Outputs(_ptr(out.image), _ptr(out.depth), _ptr(out.final_T), _ptr(out.n_contrib))
+        L.check(L.LIB.render_backward(ctypes.byref(g), self.host_cams, _ptr(self.dev_cams),
+                                      len(self.cams), ctypes.byref(self.copts), _ptr(self.ws),
+                                      self.ws.numel(), self.capacity, ctypes.byref(o),
+                                      _ptr(grad_image), ctypes.byref(gr), _stream()))
+        return grads
+
+    def l1(self, image: torch.Tensor, target: torch.Tensor, grad_out: torch.Tensor | None = None):
+        """(loss as a device float64 scalar, dL/dimage)."""
+        grad = grad_out if grad_out is not None else torch.empty_like(image)
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        L.check(L.LIB.render_l1(self.host_cams, len(self.cams), _ptr(self.ws), _ptr(image),
+                                _ptr(target), _ptr(grad), _ptr(loss), _stream()))
+        return loss, grad
+
+    def status(self) -> tuple:
+        bits, pairs = L.c_uint32(0), L.c_int64(0)
+        L.check(L.LIB.render_status(_ptr(self.ws), ctypes.byref(bits), ctypes.byref(pairs),
+                                    _stream()))
+        return int(bits.value), int(pairs.value)
+
+    # -- inspection (tests) --------------------------------------------------
+    def _view(self, off, count, dtype):
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off: off + nbytes].view(dtype)
+
+    def records(self) -> torch.Tensor:
+        return self._view(self.layout.records, 16 * self.layout.n_items, torch.float32).view(-1, 16)
+
+    def depth_keys(self):
+        return self._view(self.layout.depth_keys, self.layout.n_items, torch.int32)
+
+    def tile_rects(self):
+        return self._view(self.layout.tile_rects, self.layout.n_items, torch.int64)
+
+    def ranges(self):
+        return self._view(self.layout.ranges, 2 * self.layout.n_tiles, torch.int32).view(-1, 2)
+
+    def pair_values(self, count):
+        return self._view(self.layout.pair_values, count, torch.int32)
+
+    def grad2d(self):
+        return self._view(self.layout.grad2d, 9 * self.layout.n_items, torch.float32).view(9, -1)
+
+    def sorted_keys(self, count) -> torch.Tensor:
+        keys = torch.empty(count, dtype=torch.int64, device=self.device)
+        L.check(L.LIB.render_read_keys(_ptr(self.ws), ctypes.byref(self.layout), count,
+                                       _ptr(keys), _stream()))
+        return keys
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, *params):
+        p = dict(zip(FIELDS, params))
+        out = rast.forward(p)
+        ctx.rast = rast
+        ctx.out = out
+        ctx.save_for_backward(*params)
+        ctx.mark_non_differentiable(out.depth, out.final_T, out.n_contrib)
+        return out.image, out.depth, out.final_T, out.n_contrib
+
+    @staticmethod
+    def backward(ctx, g_image, *_):
+        params = dict(zip(FIELDS, ctx.saved_tensors))
+        grads = ctx.rast.backward(params, ctx.out, g_image.contiguous())
+        return (None, *[grads[k] for k in FIELDS])
+
+
+def render(rast: Rasterizer, params: dict):
+    """Differentiable render: returns packed (image, depth, final_T,
+    n_contrib); only `image` carries gradients (to every parameter)."""
+    return _RenderFn.apply(rast, *[params[k] for k in FIELDS])

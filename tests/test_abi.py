@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every entry point include/sgsplat.h
+declares, and validates arguments on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2501_00342_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgsplat.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2501_00342_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_2501_00342_amd import _lib
+    return _lib
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(render_\w+)\s*\(", txt, re.M))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert names == set(lib.EXPORTS)
+    for nm in names:
+        assert hasattr(lib.LIB, nm), nm
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (render_\w+)", out))
+    assert names <= exported
+
+
+def test_ctypes_structs_match_the_c_layout(lib, tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sgsplat.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(sgs_gaussians), sizeof(sgs_grads), sizeof(sgs_camera),'
+                   'sizeof(sgs_options), sizeof(sgs_outputs), sizeof(sgs_layout),'
+                   'offsetof(sgs_camera, fx), offsetof(sgs_camera, bg),'
+                   'offsetof(sgs_layout, n_items));return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(lib.Gaussians), ctypes.sizeof(lib.Grads), ctypes.sizeof(lib.Camera),
+            ctypes.sizeof(lib.Options), ctypes.sizeof(lib.Outputs), ctypes.sizeof(lib.Layout),
+            lib.Camera.fx.offset, lib.Camera.bg.offset, lib.Layout.n_items.offset]
+    assert got == want
+
+
+def _args(lib, n=1000, sh=1, K=4, W=128, H=96, opts=None, cap=10000):
+    g = lib.gaussians_struct(n, sh, K, {})
+    cams = lib.camera_array([scenes.pinhole(W, H, np.eye(3), (0, 0, 4))])
+    o = lib.options_struct(opts or scenes.Options())
+    return g, cams, o, cap
+
+
+def test_workspace_size_and_layout(lib):
+    g, cams, o, cap = _args(lib)
+    nb = lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap)
+    assert nb > 1000 * 64 + cap * 16
+    lay = lib.Layout()
+    assert lib.LIB.render_layout(ctypes.byref(g), cams, 1, ctypes.byref(o), cap,
+                                 ctypes.byref(lay)) == 0
+    assert lay.total_bytes == nb and lay.n_items == 1000 and lay.pair_capacity == cap
+    assert lay.n_tiles == 8 * 6 and lay.n_pixels == 128 * 96
+    offs = [lay.header, lay.cam_table, lay.records, lay.depth_keys, lay.tile_rects,
+            lay.sorted_items, lay.pair_offsets, lay.pair_tiles, lay.pair_values, lay.ranges,
+            lay.grad2d]
+    assert all(x % 256 == 0 for x in offs) and offs == sorted(offs)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(sh=4), dict(K=9), dict(W=0), dict(H=40000), dict(cap=1 << 30), dict(n=-1),
+    dict(opts=scenes.Options(tile_w=12, tile_h=12)), dict(opts=scenes.Options(batch=300)),
+    dict(opts=scenes.Options(alpha_max=1.5))])
+def test_invalid_arguments_are_rejected_on_the_host(lib, bad):
+    g, cams, o, cap = _args(lib, **bad)
+    assert lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap) == 0
+    lay = lib.Layout()
+    rc = lib.LIB.render_layout(ctypes.byref(g), cams, 1, ctypes.byref(o), cap, ctypes.byref(lay))
+    assert rc == lib.SGS_E_INVALID and lib.last_error()
+
+
+def test_forward_rejects_null_arguments_before_any_launch(lib):
+    g, cams, o, cap = _args(lib)
+    outs = lib.Outputs()
+    rc = lib.LIB.render_forward(ctypes.byref(g), cams, None, 1, ctypes.byref(o), None, 0, cap,
+                                ctypes.byref(outs), 0, None, None)
+    assert rc == lib.SGS_E_INVALID
+    rc = lib.LIB.render_backward(ctypes.byref(g), cams, None, 1, ctypes.byref(o), None, 0, cap,
+                                 None, None, None, None)
+    assert rc == lib.SGS_E_INVALID

@@ -1,0 +1,168 @@
+"""Forward parity of the HIP path against the FP64 oracle (GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import forward as F
+from paper_2501_00342_amd import scenes
+from tests import parity
+from tests.gpu_util import camera_numpy, records_numpy, run_forward
+
+pytestmark = pytest.mark.gpu
+
+K_HALF_LOG2E = 0.5 / math.log(2.0)
+
+
+def _check_records(rast, pre, n, cam_index=0):
+    rec, ints = records_numpy(rast)
+    rects = rast.tile_rects().cpu().numpy().view(np.uint64)
+    keys = rast.depth_keys().cpu().numpy().view(np.uint32)
+    sl = slice(cam_index * n, (cam_index + 1) * n)
+    rec, ints, rects, keys = rec[sl], ints[sl], rects[sl], keys[sl]
+    tx0 = (rects & 0xFFFF).astype(np.int64)
+    tx1 = ((rects >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+    ty0 = ((rects >> np.uint64(32)) & np.uint64(0xFFFF)).astype(np.int64)
+    ty1 = ((rects >> np.uint64(48)) & np.uint64(0xFFFF)).astype(np.int64)
+    vis_gpu = tx1 >= tx0
+    # integers decided on the fixed-order float64 key path: bit-exact
+    assert np.array_equal(vis_gpu, pre.visible), "culling differs"
+    v = pre.visible
+    assert np.array_equal(keys[v], pre.depth_bits[v])
+    assert np.all(keys[~v] == 0xFFFFFFFF)
+    assert np.array_equal(np.stack([tx0, tx1, ty0, ty1])[:, v], pre.tile_rect[:, v])
+    px0 = (ints[:, 13] & 0xFFFF).astype(np.int64)
+    px1 = (ints[:, 13] >> 16).astype(np.int64)
+    py0 = (ints[:, 14] & 0xFFFF).astype(np.int64)
+    py1 = (ints[:, 14] >> 16).astype(np.int64)
+    assert np.array_equal(np.stack([px0, px1, py0, py1])[:, v], pre.rect[:, v])
+    assert np.array_equal(ints[v, 15].astype(np.int64), pre.radius[v])
+    # float fields
+    u = rec[v, 0].astype(np.float64) + rec[v, 2].astype(np.float64)
+    vv = rec[v, 1].astype(np.float64) + rec[v, 3].astype(np.float64)
+    assert np.abs(u - pre.u[v]).max() < 1e-9 * max(1.0, np.abs(pre.u[v]).max())
+    assert np.abs(vv - pre.v[v]).max() < 1e-9 * max(1.0, np.abs(pre.v[v]).max())
+    assert np.allclose(rec[v, 8], pre.opacity[v], rtol=1e-6, atol=1e-7)
+    assert np.abs(rec[v, 9:12].T - pre.rgb[:, v]).max() < 1e-6
+    assert np.allclose(rec[v, 12], pre.z[v], rtol=1e-7)
+    # whitening reproduces the conic: Q = (w1 w1^T + w2 w2^T) / k
+    w1 = rec[v, 4:6].astype(np.float64)
+    w2 = rec[v, 6:8].astype(np.float64)
+    Qa = (w1[:, 0] ** 2 + w2[:, 0] ** 2) / K_HALF_LOG2E
+    Qb = (w1[:, 0] * w1[:, 1] + w2[:, 0] * w2[:, 1]) / K_HALF_LOG2E
+    Qc = (w1[:, 1] ** 2 + w2[:, 1] ** 2) / K_HALF_LOG2E
+    scale = np.maximum(np.abs(pre.conic[0, v]), np.abs(pre.conic[2, v]))
+    for got, ref in ((Qa, pre.conic[0, v]), (Qb, pre.conic[1, v]), (Qc, pre.conic[2, v])):
+        assert np.all(np.abs(got - ref) <= 1e-5 * scale)
+
+
+def _check_pairs(rast, ref, ntiles):
+    bits, P = rast.status()
+    assert bits == 0
+    assert P == ref.keys.size
+    keys = rast.sorted_keys(P).cpu().numpy().view(np.uint64)
+    assert np.array_equal(keys, ref.keys), "sorted keys differ"
+    vals = rast.pair_values(P).cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal(vals, ref.values), "sorted values differ"
+    rng = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(rng, ref.ranges[:ntiles]), "tile ranges differ"
+
+
+def test_config0_records_pairs_and_image():
+    sc, cams, opts = scenes.workload("sg-1k-128")
+    rast, params, out = run_forward(sc, cams, opts)
+    pre = F.preprocess(sc, cams[0], opts)
+    ref = F.render(sc, cams[0], opts)
+    _check_records(rast, pre, sc.n)
+    _check_pairs(rast, ref, pre.grid[0] * pre.grid[1])
+    img, dep, T, n = camera_numpy(out, cams)
+    rep = parity.compare_image(img, dep, T, n, ref)
+    assert not rep["failures"], rep
+
+
+@pytest.mark.parametrize("tw,th,batch", [(16, 16, 0), (8, 8, 0), (32, 8, 512), (16, 8, 256),
+                                         (8, 16, 128)])
+def test_clustered_scene_tile_shapes(tw, th, batch):
+    """A few thousand clustered Gaussians (SH1 + 4 lobes) over a ragged
+    200x136 image: many tiles, partial edge tiles, deep lists."""
+    sc, cam = scenes.small_clustered(6000, 11, 200, 136)
+    opts = scenes.Options(tile_w=tw, tile_h=th, batch=batch)
+    rast, params, out = run_forward(sc, [cam], opts)
+    ref = F.render(sc, cam, opts)
+    pre = F.preprocess(sc, cam, opts)
+    _check_records(rast, pre, sc.n)
+    _check_pairs(rast, ref, pre.grid[0] * pre.grid[1])
+    img, dep, T, n = camera_numpy(out, [cam])
+    rep = parity.compare_image(img, dep, T, n, ref)
+    assert not rep["failures"], rep
+
+
+def test_sh3_form_parity():
+    sc = scenes.sh3_scene(4000, 12, n_clusters=20)
+    cam = scenes.config1_camera(160, 120)
+    opts = scenes.Options()
+    rast, params, out = run_forward(sc, [cam], opts)
+    ref = F.render(sc, cam, opts)
+    pre = F.preprocess(sc, cam, opts)
+    _check_records(rast, pre, sc.n)
+    img, dep, T, n = camera_numpy(out, [cam])
+    rep = parity.compare_image(img, dep, T, n, ref)
+    assert not rep["failures"], rep
+
+
+def test_forward_is_deterministic():
+    sc, cam = scenes.small_clustered(5000, 13, 180, 120)
+    opts = scenes.Options()
+    rast, params, out1 = run_forward(sc, [cam], opts)
+    out2 = rast.forward(params)
+    for a, b in zip((out1.image, out1.depth, out1.final_T, out1.n_contrib),
+                    (out2.image, out2.depth, out2.final_T, out2.n_contrib)):
+        assert bool((a == b).all())
+
+
+def test_empty_scene_renders_background():
+    sc = scenes.config0_scene(0, 5).subset(np.arange(0))
+    cam = scenes.config0_camera(40, 30)
+    cam.bg = np.array([0.2, 0.4, 0.6], np.float32)
+    rast, params, out = run_forward(sc, [cam], scenes.Options())
+    img, dep, T, n = camera_numpy(out, [cam])
+    assert np.all(img == cam.bg.astype(np.float64)[:, None, None])
+    assert np.all(T == 1.0) and np.all(n == 0) and np.all(dep == 0)
+
+
+def test_all_culled_and_nonfinite_inputs():
+    sc = scenes.config0_scene(0, 64)
+    sc.means[2, :32] = -10.0            # behind the camera
+    sc.quats[0, 32:40] = np.nan          # non-finite -> culled
+    sc.sg_amplitudes[0, 0, 40:48] = np.inf
+    cam = scenes.config0_camera(64, 64)
+    opts = scenes.Options()
+    rast, params, out = run_forward(sc, [cam], opts)
+    pre = F.preprocess(sc, cam, opts)
+    assert not pre.visible[:48].any()
+    _check_records(rast, pre, sc.n)
+    ref = F.render(sc, cam, opts)
+    img, dep, T, n = camera_numpy(out, [cam])
+    rep = parity.compare_image(img, dep, T, n, ref)
+    assert not rep["failures"], rep
+
+
+def test_batched_cameras_equal_single_renders():
+    sc, _ = scenes.small_clustered(3000, 14, 64, 48)
+    cams = scenes.ring_cameras(5, radius=6.0, seed=3, sizes=((96, 64), (64, 80), (130, 70)))
+    opts = scenes.Options()
+    rast, params, out = run_forward(sc, cams, opts)
+    pres, outs, keys, vals, ranges = F.render_batch(sc, cams, opts)
+    bits, P = rast.status()
+    assert bits == 0 and P == keys.size
+    gk = rast.sorted_keys(P).cpu().numpy().view(np.uint64)
+    assert np.array_equal(gk, keys)
+    for k, cam in enumerate(cams):
+        _check_records(rast, pres[k], sc.n, cam_index=k)
+        img, dep, T, n = camera_numpy(out, cams, k)
+        single_r, _, single_o = run_forward(sc, [cam], opts)
+        simg, sdep, sT, sn = camera_numpy(single_o, [cam])
+        assert np.array_equal(img, simg) and np.array_equal(n, sn) and np.array_equal(T, sT)
+        rep = parity.compare_image(img, dep, T, n, outs[k])
+        assert not rep["failures"], (k, rep)
