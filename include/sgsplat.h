@@ -213,6 +213,34 @@ int render_status(const void* workspace, uint32_t* status_bits, int64_t* pairs, 
 int render_read_keys(const void* workspace, const sgs_layout* layout, int64_t count,
                      uint64_t* keys_out, void* stream);
 
+/*
+ * Stage timing.  render_set_timing(1) makes render_forward / render_backward
+ * record HIP events between their stages on the call's stream (no host
+ * synchronisation is added).  render_stage_times() waits for the recorded
+ * events, returns in ms_out[s] the summed milliseconds of stage s over all
+ * calls recorded since the previous query, in *n_calls the number of
+ * forward calls summed, and forgets them.  Stages are numbered 0..
+ * SGS_N_STAGES-1 and named by render_stage_name().  The timing state is
+ * per process and not thread-safe.
+ */
+#define SGS_N_STAGES 11
+int render_set_timing(int32_t enable);
+int render_stage_times(float* ms_out, int32_t n_out, int32_t* n_calls, int32_t* n_bwd_calls);
+const char* render_stage_name(int32_t stage);
+
+/*
+ * render_blend_work — re-walks the tiles of a finished forward (same
+ * workspace, cameras, options and outputs) and counts, over all pixels,
+ * the list entries visited until each pixel stops (counts[0]) and those
+ * whose pixel rectangle holds the pixel, i.e. whose alpha is evaluated
+ * (counts[1]).  counts: device u64[2], overwritten.  For roofline figures;
+ * not part of the render.
+ */
+int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams,
+                      const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                      const void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                      uint64_t* counts, void* stream);
+
 /* render_last_error — message for the last non-zero return on this thread. */
 const char* render_last_error(void);
 

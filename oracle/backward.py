@@ -124,7 +124,7 @@ def preprocess_backward(scene, cam, opts, pre, g2):
         mu = mu_raw / mlen
         lam = np.exp(scene.sg_log_sharpness[k].astype(F64))
         cosv = (d * mu).sum(axis=0)
-        e = np.exp(lam * (cosv - 1.0))
+        e = np.where(cosv - 1.0 == 0.0, 1.0, np.exp(lam * (cosv - 1.0)))
         amp = scene.sg_amplitudes[k].astype(F64)
         out["sg_amplitudes"][k] = grgb * e
         s = (grgb * amp).sum(axis=0) * e
@@ -151,7 +151,7 @@ def preprocess_backward(scene, cam, opts, pre, g2):
     M3 = [[Rq[i][a] * s_[a] for a in range(3)] for i in range(3)]
     xc = pre.xc
     z = xc[2]
-    xn, yn = xc[0] / z, xc[1] / z
+    xn, yn = xc[0] * (1.0 / z), xc[1] * (1.0 / z)
     W, H = int(cam.width), int(cam.height)
     guard = R._f(opts.guard)
     limx = guard * ((0.5 * W) / fx)

@@ -26,7 +26,8 @@ unpinned" against the paper itself, since it prints no worked example):
   clamped to <= 0;  R16 alpha_max 0.99, alpha_min 1/255 (skip), T_min 1e-4
   (exclusive stop);  R17 depth = sum alpha T z, n_contrib = 1 + position of
   the last blended entry in the tile list;  R18 background T*bg;  R19 empty
-  tile -> range (0,0);  R21 non-finite -> culled.
+  tile -> range (0,0);  R21 a non-finite raw parameter or a lobe axis of
+  zero length -> culled.
 
 Key path.  Every value that decides an integer (cull flag, radius, pixel and
 tile rectangle, depth key) is computed with one prescribed sequence of IEEE
@@ -115,9 +116,20 @@ def colour(scene, dirs):
         mu = scene.sg_axes[k].astype(F64)
         mu = mu / np.sqrt((mu * mu).sum(axis=0))
         lam = np.exp(scene.sg_log_sharpness[k].astype(F64))
-        e = np.exp(lam * ((dirs * mu).sum(axis=0) - 1.0))       # eq. 5
+        t = (dirs * mu).sum(axis=0) - 1.0
+        # eq. 5; along the axis (t = 0) the lobe is 1 for any sharpness
+        e = np.where(t == 0.0, 1.0, np.exp(lam * t))
         raw = raw + scene.sg_amplitudes[k].astype(F64) * e
     return raw
+
+
+def zero_axis(scene) -> np.ndarray:
+    """Gaussians with a lobe axis of zero length (no direction to normalise)."""
+    bad = np.zeros(scene.n, bool)
+    for k in range(scene.n_lobes):
+        a = scene.sg_axes[k].astype(F64)
+        bad |= (a * a).sum(axis=0) == 0.0
+    return bad
 
 
 def preprocess(scene, cam, opts) -> Pre:
@@ -140,21 +152,23 @@ def preprocess(scene, cam, opts) -> Pre:
         s = np.exp(scene.log_scales.astype(F64))
         q = scene.quats.astype(F64)
         qn = np.sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3])
-        qw, qx, qy, qz = q[0] / qn, q[1] / qn, q[2] / qn, q[3] / qn
+        iq = 1.0 / qn
+        qw, qx, qy, qz = q[0] * iq, q[1] * iq, q[2] * iq, q[3] * iq
         Rq = quat_to_rotation(qw, qx, qy, qz)
         M3 = [[Rq[i][a] * s[a] for a in range(3)] for i in range(3)]   # R S (eq. 3)
 
         # EWA local affine approximation with the guard band (R9)
-        xn = xc[0] / z
-        yn = xc[1] / z
+        iz = 1.0 / z
+        xn = xc[0] * iz
+        yn = xc[1] * iz
         limx = guard * ((0.5 * W) / fx)
         limy = guard * ((0.5 * H) / fy)
         xn_c = np.minimum(np.maximum(xn, -limx), limx)
         yn_c = np.minimum(np.maximum(yn, -limy), limy)
-        J00 = fx / z
-        J02 = -(fx * xn_c) / z
-        J11 = fy / z
-        J12 = -(fy * yn_c) / z
+        J00 = fx * iz
+        J02 = -(fx * xn_c) * iz
+        J11 = fy * iz
+        J12 = -(fy * yn_c) * iz
         T2 = [[J00 * Rc[0, k] + J02 * Rc[2, k] for k in range(3)],
               [J11 * Rc[1, k] + J12 * Rc[2, k] for k in range(3)]]
         M = [[(T2[i][0] * M3[0][a] + T2[i][1] * M3[1][a]) + T2[i][2] * M3[2][a]
@@ -189,9 +203,9 @@ def preprocess(scene, cam, opts) -> Pre:
         rgb_raw = colour(scene, dirs)
         opacity = 1.0 / (1.0 + np.exp(-scene.opacity_logits.astype(F64)))
 
-    finite = (_finite_params(scene) & np.isfinite(A) & np.isfinite(B) & np.isfinite(C)
-              & np.isfinite(det) & np.isfinite(lam1) & np.isfinite(u) & np.isfinite(v)
-              & np.isfinite(rgb_raw).all(axis=0))
+    finite = (_finite_params(scene) & ~zero_axis(scene) & np.isfinite(A) & np.isfinite(B)
+              & np.isfinite(C) & np.isfinite(det) & np.isfinite(lam1) & np.isfinite(u)
+              & np.isfinite(v))
     visible = (finite & (z > znear) & (lox <= W - 1) & (hix >= 0)
                & (loy <= H - 1) & (hiy >= 0))
 

@@ -59,7 +59,9 @@ class Layout(Structure):
 
 
 EXPORTS = ("render_workspace_bytes", "render_layout", "render_forward", "render_backward",
-           "render_l1", "render_status", "render_read_keys", "render_last_error")
+           "render_l1", "render_status", "render_read_keys", "render_set_timing",
+           "render_stage_times", "render_stage_name", "render_blend_work", "render_last_error")
+N_STAGES = 11
 
 
 def _load():
@@ -88,6 +90,15 @@ def _load():
     lib.render_status.argtypes = [c_void_p, P(c_uint32), P(c_int64), c_void_p]
     lib.render_read_keys.restype = c_int32
     lib.render_read_keys.argtypes = [c_void_p, P(Layout), c_int64, c_void_p, c_void_p]
+    lib.render_set_timing.restype = c_int32
+    lib.render_set_timing.argtypes = [c_int32]
+    lib.render_stage_times.restype = c_int32
+    lib.render_stage_times.argtypes = [P(c_float), c_int32, P(c_int32), P(c_int32)]
+    lib.render_stage_name.restype = c_char_p
+    lib.render_stage_name.argtypes = [c_int32]
+    lib.render_blend_work.restype = c_int32
+    lib.render_blend_work.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
+                                      c_void_p, c_size_t, c_int64, c_void_p, c_void_p]
     lib.render_last_error.restype = c_char_p
     lib.render_last_error.argtypes = []
     return lib
@@ -105,6 +116,18 @@ class SgsError(RuntimeError):
 def check(code: int):
     if code != SGS_OK:
         raise SgsError(code, LIB.render_last_error().decode())
+
+
+def stage_names():
+    return [LIB.render_stage_name(i).decode() for i in range(N_STAGES)]
+
+
+def stage_times():
+    """(per-stage summed ms, forward calls, backward calls) since last query."""
+    ms = (c_float * N_STAGES)()
+    nf, nb = c_int32(0), c_int32(0)
+    check(LIB.render_stage_times(ms, N_STAGES, ctypes.byref(nf), ctypes.byref(nb)))
+    return list(ms), nf.value, nb.value
 
 
 def last_error() -> str:

@@ -29,6 +29,7 @@ SOURCES = {
     "preprocess.hip": ["-ffp-contract=off"],
     "preprocess_bwd.hip": ["-ffp-contract=off"],
     "sort.hip": [],
+    "radix.hip": [],
     "blend.hip": [],
 }
 

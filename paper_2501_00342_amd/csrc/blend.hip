@@ -102,10 +102,10 @@ __device__ __forceinline__ Entry load_entry(const Workspace& ws, int64_t pos, in
     return e;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool COUNT>
 __global__ void __launch_bounds__(TW * TH)
 k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
-            sgs_outputs out, int batch) {
+            sgs_outputs out, int batch, unsigned long long* counts) {
     constexpr int NT = TW * TH;
     extern __shared__ Entry s_e[];
     __shared__ int s_cam;
@@ -131,6 +131,7 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
     int n = 0;
     bool done = !inside;
+    unsigned long long visited = 0, evaluated = 0;
     for (uint32_t bs = start; bs < end; bs += batch) {
         if (__syncthreads_count(!done) == 0) break;
         const int cnt = (int)((end - bs) < (uint32_t)batch ? (end - bs) : (uint32_t)batch);
@@ -140,7 +141,9 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         if (!done) {
             for (int j = 0; j < cnt; ++j) {
                 const Entry e = s_e[j];
+                if (COUNT) ++visited;
                 if (!((e.m.x & colbit) && (e.m.y & rowbit))) continue;
+                if (COUNT) ++evaluated;
                 const Eval v = eval_splat(e, lxf, lyf, amax);
                 if (v.alpha < amin) continue;
                 const float Tn = T * (1.0f - v.alpha);
@@ -157,6 +160,19 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
                 n = (int)(bs - start) + j + 1;
             }
         }
+    }
+    if (COUNT) {
+        __shared__ unsigned long long s_cnt[2];
+        if (tid == 0) s_cnt[0] = s_cnt[1] = 0ull;
+        __syncthreads();
+        atomicAdd(&s_cnt[0], visited);
+        atomicAdd(&s_cnt[1], evaluated);
+        __syncthreads();
+        if (tid == 0) {
+            atomicAdd(&counts[0], s_cnt[0]);
+            atomicAdd(&counts[1], s_cnt[1]);
+        }
+        return;
     }
     if (inside) {
         const int64_t W = ct.W, H = ct.H;
@@ -321,8 +337,18 @@ template <int TW, int TH>
 static void launch_fwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
                          const sgs_outputs& out, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds, s, ws,
-                       cams, n_cams, o, out, o.batch);
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH, false>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds,
+                       s, ws, cams, n_cams, o, out, o.batch, nullptr);
+}
+
+template <int TW, int TH>
+static void launch_count_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
+                           uint64_t* counts, hipStream_t s) {
+    const size_t lds = (size_t)o.batch * sizeof(Entry);
+    sgs_outputs none = {};
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH, true>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds,
+                       s, ws, cams, n_cams, o, none, o.batch,
+                       reinterpret_cast<unsigned long long*>(counts));
 }
 
 template <int TW, int TH>
@@ -344,6 +370,12 @@ void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cam
                       const sgs_outputs& out, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
     SGS_TILE_SWITCH(launch_fwd_t, ws, dev_cams, n_cams, o, out, s)
+}
+
+void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                        uint64_t* counts, hipStream_t s) {
+    if (ws.n_tiles <= 0) return;
+    SGS_TILE_SWITCH(launch_count_t, ws, dev_cams, n_cams, o, counts, s)
 }
 
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,

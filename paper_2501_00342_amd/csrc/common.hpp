@@ -18,28 +18,21 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kPreThreads = 256;
-constexpr int kHistBlocksMax = 1024;                 // partial-histogram rows (persistent grids)
-constexpr int kHistFold = 32;                        // second-level rows
+constexpr int kPersistentBlocks = 1024;              // grid of the persistent kernels
 constexpr int kDepthPasses = 4;                      // 32-bit depth keys
-constexpr int kMaxTilePasses = 4;
 
 // header words (u32) at workspace offset 0
 enum Header : int {
     kHdrStatus = 0,
     kHdrPairs = 1,
-    kHdrTicketBase = 2,   // one ticket per sort/scan pass: [2, 2+12)
     kHdrWords = 16
-};
-enum TicketSlot : int {
-    kTicketScan = 0,
-    kTicketDepth0 = 1,    // 1..4 depth passes
-    kTicketTile0 = 5,     // 5..8 tile passes
 };
 
 // per camera, computed on the device from the device cameras
 struct CamTable {
     int32_t W, H, GX, GY, tile_base, pad;
     int64_t pix_base;
+    double limx, limy;   // guard band: guard * ((0.5 W) / fx), guard * ((0.5 H) / fy)
 };
 
 // 64-byte splat record written by the preprocess, gathered by the blends
@@ -93,35 +86,34 @@ struct Workspace {
     uint32_t* pair_values_alt;
     uint32_t* ranges;
     float* grad2d;
-    uint32_t* hist_partial;      // [kHistBlocksMax][passes][256]
-    uint32_t* hist_fold;         // [kHistFold][passes][256]
-    uint32_t* digit_offsets;     // [kDepthPasses + kMaxTilePasses][256]
-    uint32_t* lookback;          // per pass: [partitions][256]
-    uint64_t* scan_lookback;     // [partitions]
+    uint32_t* counts;            // radix pass: [256][partitions] digit counts -> offsets
+    uint32_t* totals;            // radix pass: [256] digit totals
+    uint32_t* pair_counts;       // pairs of each item, in depth order
+    uint64_t* scan_sums;         // per scan block
     double* loss_partial;
     int64_t n_items, n_tiles, n_pixels, capacity;
     int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
     int dup_blocks;              // persistent grid of the duplicate kernel
     int tile_passes, tile_bits;
-    int64_t lookback_pass_words;  // words per pass in `lookback`
 };
 
 // launchers (defined in the .hip files)
 void launch_clear(const Workspace& ws, hipStream_t s);
 void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, int tile_w, int tile_h,
-                  hipStream_t s);
+                  float guard, hipStream_t s);
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                        const Workspace& ws, int hist_blocks, hipStream_t s);
-void launch_hist_scan(const Workspace& ws, int passes, int digit_row0, int hist_rows, hipStream_t s);
-void launch_onesweep(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
-                     uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host,
-                     int shift, const uint32_t* digit_offsets, uint32_t* lookback,
-                     uint32_t* ticket, int64_t parts, hipStream_t s);
+void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                       uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
+                       uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
+                       uint32_t* pairs_out, int64_t n_rects, hipStream_t s);
 void launch_scan_pairs(const Workspace& ws, hipStream_t s);
 void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
 void launch_ranges(const Workspace& ws, hipStream_t s);
 void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                       const sgs_outputs& out, hipStream_t s);
+void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                        uint64_t* counts, hipStream_t s);
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                       const sgs_outputs& fwd, const float* grad_image, hipStream_t s);
 void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,

@@ -1,7 +1,9 @@
 // C-ABI entry points: argument checks, workspace layout, launch sequence.
 #include <string.h>
 
+#include <array>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -38,11 +40,10 @@ struct Plan {
     int tile_passes, tile_bits;
     int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
     int pre_blocks, dup_blocks;
-    int64_t pass_words;
+    int64_t max_parts;
     // offsets not exported in sgs_layout
     size_t sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
-        pair_values_alt, hist_partial, hist_fold, digit_offsets, lookback, scan_lookback,
-        loss_partial;
+        pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial;
 };
 
 bool tile_shape_ok(int tw, int th) {
@@ -102,10 +103,10 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->scan_parts = cdiv(items, sgs::kScanTile);
     pl->dup_chunks = cdiv(cap, sgs::kDupChunk);
     int64_t pb = cdiv(n, sgs::kPreThreads);
-    pl->pre_blocks = (int)(pb < 1 ? 1 : (pb > sgs::kHistBlocksMax ? sgs::kHistBlocksMax : pb));
+    pl->pre_blocks = (int)(pb < 1 ? 1 : (pb > sgs::kPersistentBlocks ? sgs::kPersistentBlocks : pb));
     int64_t db = pl->dup_chunks;
-    pl->dup_blocks = (int)(db < 1 ? 1 : (db > sgs::kHistBlocksMax ? sgs::kHistBlocksMax : db));
-    pl->pass_words = (pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts) * sgs::kRadix;
+    pl->dup_blocks = (int)(db < 1 ? 1 : (db > sgs::kPersistentBlocks ? sgs::kPersistentBlocks : db));
+    pl->max_parts = pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts;
 
     sgs_layout& L = pl->lay;
     memset(&L, 0, sizeof(L));
@@ -135,12 +136,10 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->pair_values_alt = take((size_t)cap * 4);
     L.ranges = take((size_t)tiles * 8);
     L.grad2d = take((size_t)items * 9 * 4);
-    const int hpass = pl->tile_passes > sgs::kDepthPasses ? pl->tile_passes : sgs::kDepthPasses;
-    pl->hist_partial = take((size_t)sgs::kHistBlocksMax * hpass * sgs::kRadix * 4);
-    pl->hist_fold = take((size_t)sgs::kHistFold * hpass * sgs::kRadix * 4);
-    pl->digit_offsets = take((size_t)(sgs::kDepthPasses + sgs::kMaxTilePasses) * sgs::kRadix * 4);
-    pl->lookback = take((size_t)pl->pass_words * (sgs::kDepthPasses + pl->tile_passes) * 4);
-    pl->scan_lookback = take((size_t)pl->scan_parts * 8);
+    pl->counts = take((size_t)pl->max_parts * sgs::kRadix * 4);
+    pl->totals = take((size_t)sgs::kRadix * 4);
+    pl->pair_counts = take((size_t)items * 4);
+    pl->scan_sums = take((size_t)(pl->scan_parts + 1) * 8);
     L.total_bytes = off;
     L.n_items = items;
     L.n_tiles = tiles;
@@ -170,11 +169,10 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.pair_values_alt = reinterpret_cast<uint32_t*>(b + pl.pair_values_alt);
     w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
     w.grad2d = reinterpret_cast<float*>(b + L.grad2d);
-    w.hist_partial = reinterpret_cast<uint32_t*>(b + pl.hist_partial);
-    w.hist_fold = reinterpret_cast<uint32_t*>(b + pl.hist_fold);
-    w.digit_offsets = reinterpret_cast<uint32_t*>(b + pl.digit_offsets);
-    w.lookback = reinterpret_cast<uint32_t*>(b + pl.lookback);
-    w.scan_lookback = reinterpret_cast<uint64_t*>(b + pl.scan_lookback);
+    w.counts = reinterpret_cast<uint32_t*>(b + pl.counts);
+    w.totals = reinterpret_cast<uint32_t*>(b + pl.totals);
+    w.pair_counts = reinterpret_cast<uint32_t*>(b + pl.pair_counts);
+    w.scan_sums = reinterpret_cast<uint64_t*>(b + pl.scan_sums);
     w.loss_partial = reinterpret_cast<double*>(b + pl.loss_partial);
     w.n_items = L.n_items;
     w.n_tiles = L.n_tiles;
@@ -187,7 +185,6 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.dup_blocks = pl.dup_blocks;
     w.tile_passes = pl.tile_passes;
     w.tile_bits = pl.tile_bits;
-    w.lookback_pass_words = pl.pass_words;
     return w;
 }
 
@@ -215,6 +212,42 @@ int check_params(const sgs_gaussians* g) {
         return fail(SGS_E_INVALID, "an SG lobe array is NULL");
     return SGS_OK;
 }
+
+// ---- stage timing (HIP events between stages, collected on query) ----
+constexpr int kFwdEvents = 9;   // 8 forward stages
+constexpr int kBwdEvents = 4;   // 3 backward stages
+constexpr size_t kMaxTimedCalls = 4096;
+const char* const kStageNames[SGS_N_STAGES] = {
+    "fwd.setup", "fwd.preprocess", "fwd.depth_sort", "fwd.pair_scan", "fwd.duplicate",
+    "fwd.tile_sort", "fwd.ranges", "fwd.blend", "bwd.clear", "bwd.blend", "bwd.preprocess"};
+
+struct Timing {
+    bool on = false;
+    std::vector<std::array<hipEvent_t, kFwdEvents>> fwd;
+    std::vector<std::array<hipEvent_t, kBwdEvents>> bwd;
+    size_t fwd_used = 0, bwd_used = 0;
+};
+Timing g_timing;
+
+template <size_t E>
+hipEvent_t* timing_slot(std::vector<std::array<hipEvent_t, E>>& v, size_t& used) {
+    if (!g_timing.on || used >= kMaxTimedCalls) return nullptr;
+    if (used == v.size()) {
+        std::array<hipEvent_t, E> a;
+        for (size_t i = 0; i < E; ++i)
+            if (hipEventCreate(&a[i]) != hipSuccess) return nullptr;
+        v.push_back(a);
+    }
+    return v[used++].data();
+}
+
+struct Marker {
+    hipEvent_t* ev;
+    hipStream_t s;
+    void mark(int i) {
+        if (ev) (void)hipEventRecord(ev[i], s);
+    }
+};
 
 }  // namespace
 
@@ -255,30 +288,39 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
     const sgs::Params p = params_of(g);
     const sgs::Opts& o = pl.o;
     (void)hipGetLastError();
+    Marker mk{timing_slot(g_timing.fwd, g_timing.fwd_used), s};
 
+    mk.mark(0);
     sgs::launch_clear(ws, s);
-    sgs::launch_setup(ws, dev_cams, n_cams, o.tile_w, o.tile_h, s);
+    sgs::launch_setup(ws, dev_cams, n_cams, o.tile_w, o.tile_h, o.guard, s);
     SGS_LAUNCHED();
+    mk.mark(1);
     if (pl.n > 0) {
         sgs::launch_preprocess(p, dev_cams, n_cams, o, ws, pl.pre_blocks, s);
         SGS_LAUNCHED();
-        // depth sort of the items: 4 passes, final order in sorted_items
-        sgs::launch_hist_scan(ws, sgs::kDepthPasses, 0, pl.pre_blocks, s);
+        mk.mark(2);
+        // depth sort of the items: 4 passes, final order in sorted_items; the
+        // last pass also lists each item's pair count in sorted order
         const uint32_t* kin[4] = {ws.depth_keys, ws.sort_keys_alt, ws.sort_keys_alt2, ws.sort_keys_alt};
         const uint32_t* vin[4] = {nullptr, ws.sorted_items_alt, ws.sorted_items, ws.sorted_items_alt};
         uint32_t* kout[4] = {ws.sort_keys_alt, ws.sort_keys_alt2, ws.sort_keys_alt, nullptr};
         uint32_t* vout[4] = {ws.sorted_items_alt, ws.sorted_items, ws.sorted_items_alt, ws.sorted_items};
         for (int ps = 0; ps < sgs::kDepthPasses; ++ps) {
-            sgs::launch_onesweep(kin[ps], vin[ps], kout[ps], vout[ps], nullptr, ws.n_items,
-                                 ps * sgs::kRadixBits, ws.digit_offsets + ps * sgs::kRadix,
-                                 ws.lookback + ps * pl.pass_words,
-                                 ws.header + sgs::kHdrTicketBase + sgs::kTicketDepth0 + ps,
-                                 pl.depth_parts, s);
+            const bool last = ps == sgs::kDepthPasses - 1;
+            sgs::launch_radix_pass(kin[ps], vin[ps], kout[ps], vout[ps], nullptr, ws.n_items,
+                                   ps * sgs::kRadixBits, ws.counts, ws.totals, pl.depth_parts,
+                                   last ? ws.tile_rects : nullptr, last ? ws.pair_counts : nullptr,
+                                   ws.n_items, s);
         }
         SGS_LAUNCHED();
+        mk.mark(3);
         sgs::launch_scan_pairs(ws, s);
         SGS_LAUNCHED();
+    } else {
+        mk.mark(2);
+        mk.mark(3);
     }
+    mk.mark(4);
     if (flags & SGS_FLAG_CHECK_CAPACITY) {
         uint32_t h[2] = {0, 0};
         SGS_HIP(hipMemcpyAsync(h, ws.header, 8, hipMemcpyDeviceToHost, s));
@@ -287,9 +329,11 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         if (pairs_needed) *pairs_needed = P;
         if (h[sgs::kHdrStatus] & SGS_STATUS_CAMERAS)
             return fail(SGS_E_INVALID, "device cameras disagree with the host cameras' sizes");
-        if ((int64_t)P > pair_capacity)
+        if ((int64_t)P > pair_capacity) {
+            if (mk.ev) --g_timing.fwd_used;
             return fail(SGS_E_CAPACITY, "pair capacity " + std::to_string(pair_capacity) +
                                             " < " + std::to_string(P) + " pairs");
+        }
     }
     if (pl.n > 0 && pair_capacity > 0) {
         // the duplicate writes where the last tile pass leaves the primary buffers
@@ -300,24 +344,27 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         }
         sgs::launch_duplicate(wd, pl.n, s);
         SGS_LAUNCHED();
-        sgs::launch_hist_scan(ws, pl.tile_passes, sgs::kDepthPasses, pl.dup_blocks, s);
+        mk.mark(5);
         uint32_t* tk[2] = {wd.pair_tiles, wd.pair_tiles == ws.pair_tiles ? ws.pair_tiles_alt : ws.pair_tiles};
         uint32_t* tv[2] = {wd.pair_values, wd.pair_values == ws.pair_values ? ws.pair_values_alt : ws.pair_values};
         for (int ps = 0; ps < pl.tile_passes; ++ps) {
             const int a = ps % 2, b = 1 - a;
-            sgs::launch_onesweep(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs, pair_capacity,
-                                 ps * sgs::kRadixBits,
-                                 ws.digit_offsets + (sgs::kDepthPasses + ps) * sgs::kRadix,
-                                 ws.lookback + (sgs::kDepthPasses + ps) * pl.pass_words,
-                                 ws.header + sgs::kHdrTicketBase + sgs::kTicketTile0 + ps,
-                                 pl.pair_parts, s);
+            sgs::launch_radix_pass(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs,
+                                   pair_capacity, ps * sgs::kRadixBits, ws.counts, ws.totals,
+                                   pl.pair_parts, nullptr, nullptr, 0, s);
         }
         SGS_LAUNCHED();
+        mk.mark(6);
         sgs::launch_ranges(ws, s);
         SGS_LAUNCHED();
+    } else {
+        mk.mark(5);
+        mk.mark(6);
     }
+    mk.mark(7);
     sgs::launch_blend_fwd(ws, dev_cams, n_cams, o, *outs, s);
     SGS_LAUNCHED();
+    mk.mark(8);
     return SGS_OK;
 }
 
@@ -343,11 +390,16 @@ int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const s
     const sgs::Params p = params_of(g);
     (void)hipGetLastError();
     if (pl.n == 0) return SGS_OK;
+    Marker mk{timing_slot(g_timing.bwd, g_timing.bwd_used), s};
+    mk.mark(0);
     sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, 9 * ws.n_items, s);
+    mk.mark(1);
     sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, s);
     SGS_LAUNCHED();
+    mk.mark(2);
     sgs::launch_preprocess_bwd(p, dev_cams, n_cams, pl.o, ws, *grads, s);
     SGS_LAUNCHED();
+    mk.mark(3);
     return SGS_OK;
 }
 
@@ -395,6 +447,60 @@ int render_read_keys(const void* workspace, const sgs_layout* layout, int64_t co
     ws.n_items = layout->n_items;
     (void)hipGetLastError();
     sgs::launch_read_keys(ws, count, keys_out, static_cast<hipStream_t>(stream));
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
+int render_set_timing(int32_t enable) {
+    g_timing.on = enable != 0;
+    return SGS_OK;
+}
+
+int render_stage_times(float* ms_out, int32_t n_out, int32_t* n_calls, int32_t* n_bwd_calls) {
+    if (!ms_out || n_out < SGS_N_STAGES) return fail(SGS_E_INVALID, "ms_out needs SGS_N_STAGES entries");
+    for (int i = 0; i < SGS_N_STAGES; ++i) ms_out[i] = 0.0f;
+    for (size_t c = 0; c < g_timing.fwd_used; ++c) {
+        auto& ev = g_timing.fwd[c];
+        SGS_HIP(hipEventSynchronize(ev[kFwdEvents - 1]));
+        for (int i = 0; i + 1 < kFwdEvents; ++i) {
+            float ms = 0.0f;
+            SGS_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            ms_out[i] += ms;
+        }
+    }
+    for (size_t c = 0; c < g_timing.bwd_used; ++c) {
+        auto& ev = g_timing.bwd[c];
+        SGS_HIP(hipEventSynchronize(ev[kBwdEvents - 1]));
+        for (int i = 0; i + 1 < kBwdEvents; ++i) {
+            float ms = 0.0f;
+            SGS_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            ms_out[kFwdEvents - 1 + i] += ms;
+        }
+    }
+    if (n_calls) *n_calls = (int32_t)g_timing.fwd_used;
+    if (n_bwd_calls) *n_bwd_calls = (int32_t)g_timing.bwd_used;
+    g_timing.fwd_used = g_timing.bwd_used = 0;
+    return SGS_OK;
+}
+
+const char* render_stage_name(int32_t stage) {
+    return (stage >= 0 && stage < SGS_N_STAGES) ? kStageNames[stage] : "";
+}
+
+int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
+                      int32_t n_cams, const sgs_options* opts, const void* workspace,
+                      size_t workspace_bytes, int64_t pair_capacity, uint64_t* counts,
+                      void* stream) {
+    Plan pl;
+    int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
+    if (rc != SGS_OK) return rc;
+    if (!dev_cams || !workspace || !counts) return fail(SGS_E_INVALID, "NULL argument");
+    if (workspace_bytes < pl.lay.total_bytes) return fail(SGS_E_INVALID, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sgs::Workspace ws = bind(pl, const_cast<void*>(workspace));
+    (void)hipGetLastError();
+    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 0u, 4, s);
+    sgs::launch_blend_count(ws, dev_cams, n_cams, pl.o, counts, s);
     SGS_LAUNCHED();
     return SGS_OK;
 }

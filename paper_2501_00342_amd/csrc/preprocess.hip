@@ -9,11 +9,12 @@
 // This file is compiled with -ffp-contract=off: the values that decide
 // integers (cull, radius, rectangles, depth key) follow one fixed sequence
 // of IEEE float64 operations, sums left to right, no fused multiply-add.
+// The colour is image-path only and runs in float32 (explicit fmaf); the
+// culling tests on the colour parameters look only at the inputs.
 //
 // Memory: every parameter array is read once with unit-stride (coalesced)
 // loads; outputs are one 64-byte record, a depth key and a packed tile
-// rectangle per (camera, Gaussian).  The depth-key digit histograms for the
-// depth sort are accumulated here in LDS (no extra pass over the keys).
+// rectangle per (camera, Gaussian).
 #include "common.hpp"
 #include "sh_basis.hpp"
 
@@ -31,7 +32,7 @@ __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // Fixed-order float64 key path.  Every line is one rounding step as written.
 __device__ __forceinline__ Geo project(const double X[3], const double ls[3], const double q[4],
-                                       const sgs_camera& cam, const Opts& o) {
+                                       const sgs_camera& cam, const CamTable& ct, const Opts& o) {
     Geo r;
     const double R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2];
     const double R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5];
@@ -48,7 +49,8 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     // activations
     const double s0 = exp(ls[0]), s1 = exp(ls[1]), s2 = exp(ls[2]);
     const double qn = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
-    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, zq = q[3] / qn;
+    const double iq = 1.0 / qn;
+    const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, zq = q[3] * iq;
     // rotation of the unit quaternion, then M3 = R diag(s)
     const double r00 = 1.0 - 2.0 * (y * y + zq * zq), r01 = 2.0 * (x * y - w * zq), r02 = 2.0 * (x * zq + w * y);
     const double r10 = 2.0 * (x * y + w * zq), r11 = 1.0 - 2.0 * (x * x + zq * zq), r12 = 2.0 * (y * zq - w * x);
@@ -57,16 +59,16 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     const double m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
     const double m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
     // Jacobian of the perspective map, evaluated inside the guard band
-    const double xn = xc0 / z;
-    const double yn = xc1 / z;
-    const double limx = (double)o.guard * ((0.5 * W) / fx);
-    const double limy = (double)o.guard * ((0.5 * H) / fy);
+    const double iz = 1.0 / z;
+    const double xn = xc0 * iz;
+    const double yn = xc1 * iz;
+    const double limx = ct.limx, limy = ct.limy;   // guard * ((0.5 W) / fx), per camera
     const double xnc = fmin(fmax(xn, -limx), limx);
     const double ync = fmin(fmax(yn, -limy), limy);
-    const double J00 = fx / z;
-    const double J02 = -(fx * xnc) / z;
-    const double J11 = fy / z;
-    const double J12 = -(fy * ync) / z;
+    const double J00 = fx * iz;
+    const double J02 = -(fx * xnc) * iz;
+    const double J11 = fy * iz;
+    const double J12 = -(fy * ync) * iz;
     // T2 = J W (2x3)
     const double t00 = J00 * R0 + J02 * R6, t01 = J00 * R1 + J02 * R7, t02 = J00 * R2 + J02 * R8;
     const double t10 = J11 * R3 + J12 * R6, t11 = J11 * R4 + J12 * R7, t12 = J11 * R5 + J12 * R8;
@@ -107,28 +109,64 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
                finite_d(det) && finite_d(lam1) && finite_d(u) && finite_d(v);
     vis = vis && lox <= (double)(W - 1) && hix >= 0.0 && loy <= (double)(H - 1) && hiy >= 0.0;
     r.visible = vis;
-    if (vis) {
-        r.radius = (int)rad;
-        r.px0 = (int)fmax(lox, 0.0);
-        r.px1 = (int)fmin(hix, (double)(W - 1));
-        r.py0 = (int)fmax(loy, 0.0);
-        r.py1 = (int)fmin(hiy, (double)(H - 1));
-    } else {
-        r.radius = r.px0 = r.px1 = r.py0 = r.py1 = 0;
-    }
+    // clamped into the image whether visible or not (equal to the plain
+    // max/min for visible Gaussians), so every conversion is in range
+    const double wm = (double)(W - 1), hm = (double)(H - 1);
+    r.radius = (int)fmin(rad, 1.0e9);
+    r.px0 = (int)fmin(fmax(lox, 0.0), wm);
+    r.px1 = (int)fmax(fmin(hix, wm), 0.0);
+    r.py0 = (int)fmin(fmax(loy, 0.0), hm);
+    r.py1 = (int)fmax(fmin(hiy, hm), 0.0);
     return r;
+}
+
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)).
+// Returns false when a colour parameter is non-finite or a lobe axis has
+// zero length (the Gaussian is culled).
+template <int DEG>
+__device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
+                                       float rgb[3]) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    const int64_t n = p.n;
+    bool ok = true;
+    float Y[NC];
+    sh_eval<DEG, float>(d0, d1, d2, Y);
+    rgb[0] = rgb[1] = rgb[2] = 0.5f;
+#pragma unroll
+    for (int l = 0; l < NC; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float f = p.sh[((int64_t)l * 3 + c) * n + g];
+            ok = ok && isfinite(f);
+            rgb[c] = fmaf(f, Y[l], rgb[c]);
+        }
+    for (int k = 0; k < p.n_lobes; ++k) {
+        const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
+        const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
+        const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
+        const float ls = p.sg_log_sharpness[(int64_t)k * n + g];
+        const float a0 = p.sg_amplitudes[((int64_t)k * 3 + 0) * n + g];
+        const float a1 = p.sg_amplitudes[((int64_t)k * 3 + 1) * n + g];
+        const float a2 = p.sg_amplitudes[((int64_t)k * 3 + 2) * n + g];
+        ok = ok && isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(ls) &&
+             isfinite(a0) && isfinite(a1) && isfinite(a2);
+        const float mn2 = m0 * m0 + m1 * m1 + m2 * m2;
+        ok = ok && mn2 > 0.0f;
+        const float t = (d0 * m0 + d1 * m1 + d2 * m2) * rsqrtf(mn2) - 1.0f;
+        const float e = t == 0.0f ? 1.0f : fast_exp(fast_exp(ls) * t);
+        rgb[0] = fmaf(a0, e, rgb[0]);
+        rgb[1] = fmaf(a1, e, rgb[1]);
+        rgb[2] = fmaf(a2, e, rgb[2]);
+    }
+    return ok;
 }
 
 template <int DEG>
 __global__ void __launch_bounds__(kPreThreads)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
-    constexpr int NC = (DEG + 1) * (DEG + 1);
-    __shared__ uint32_t hist[kDepthPasses][kRadix];
-    for (int i = threadIdx.x; i < kDepthPasses * kRadix; i += blockDim.x) (&hist[0][0])[i] = 0;
-    __syncthreads();
-
     const int64_t n = p.n;
-    const int K = p.n_lobes;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
          g += (int64_t)gridDim.x * blockDim.x) {
         double X[3], ls[3], q[4];
@@ -142,57 +180,25 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             q[c] = p.quats[c * n + g];
             finite = finite && finite_d(q[c]);
         }
-        const double logit = p.opacity_logits[g];
-        finite = finite && finite_d(logit);
-        float shc[NC][3];
-        for (int l = 0; l < NC; ++l)
-            for (int c = 0; c < 3; ++c) {
-                shc[l][c] = p.sh[((int64_t)l * 3 + c) * n + g];
-                finite = finite && isfinite(shc[l][c]);
-            }
-        for (int k = 0; k < K; ++k) {
-            for (int c = 0; c < 3; ++c) {
-                finite = finite && isfinite(p.sg_axes[((int64_t)k * 3 + c) * n + g]) &&
-                         isfinite(p.sg_amplitudes[((int64_t)k * 3 + c) * n + g]);
-            }
-            finite = finite && isfinite(p.sg_log_sharpness[(int64_t)k * n + g]);
-        }
-        const double opacity = 1.0 / (1.0 + exp(-logit));
+        const float logit = p.opacity_logits[g];
+        finite = finite && isfinite(logit);
+        const float opacity = 1.0f / (1.0f + fast_exp(-logit));
 
         for (int ci = 0; ci < n_cams; ++ci) {
             const sgs_camera& cam = cams[ci];
+            const CamTable ct = ws.cams[ci];
             const int64_t item = (int64_t)ci * n + g;
-            Geo geo = project(X, ls, q, cam, o);
+            const Geo geo = project(X, ls, q, cam, ct, o);
             bool vis = finite && geo.visible;
-            double rgb[3] = {0.0, 0.0, 0.0};
+            float rgb[3] = {0.0f, 0.0f, 0.0f};
             if (vis) {
-                // view direction: camera centre -> mean, c = -R^T t
+                // view direction: camera centre -> mean, centre = -R^T t
                 const double cc0 = -(((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1]) + (double)cam.R[6] * cam.t[2]);
                 const double cc1 = -(((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1]) + (double)cam.R[7] * cam.t[2]);
                 const double cc2 = -(((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1]) + (double)cam.R[8] * cam.t[2]);
-                double d0 = X[0] - cc0, d1 = X[1] - cc1, d2 = X[2] - cc2;
-                const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-                d0 /= dn;
-                d1 /= dn;
-                d2 /= dn;
-                double Y[NC];
-                sh_eval<DEG>(d0, d1, d2, Y);
-                for (int c = 0; c < 3; ++c) {
-                    double acc = 0.5;
-                    for (int l = 0; l < NC; ++l) acc += (double)shc[l][c] * Y[l];
-                    rgb[c] = acc;
-                }
-                for (int k = 0; k < K; ++k) {
-                    double m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
-                    double m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
-                    double m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
-                    const double mn = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
-                    const double lam = exp((double)p.sg_log_sharpness[(int64_t)k * n + g]);
-                    const double e = exp(lam * ((d0 * m0 + d1 * m1 + d2 * m2) / mn - 1.0));
-                    for (int c = 0; c < 3; ++c)
-                        rgb[c] += (double)p.sg_amplitudes[((int64_t)k * 3 + c) * n + g] * e;
-                }
-                vis = finite_d(rgb[0]) && finite_d(rgb[1]) && finite_d(rgb[2]);
+                const double e0 = X[0] - cc0, e1 = X[1] - cc1, e2 = X[2] - cc2;
+                const double idn = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                vis = colour<DEG>(p, g, (float)(e0 * idn), (float)(e1 * idn), (float)(e2 * idn), rgb);
             }
             uint32_t key = 0xFFFFFFFFu;
             uint64_t trect = 1;  // tx0 = 1 > tx1 = 0: no pairs
@@ -206,60 +212,44 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
                 key = __float_as_uint(zf);
                 // whitening of the conic Q = Sigma'^-1 along its eigenvectors
                 const double A = geo.A, B = geo.B, C = geo.C;
-                const double lam2 = geo.det / geo.lam1;
-                double e0, e1;
+                const double il1 = 1.0 / geo.lam1;
+                const double lam2 = geo.det * il1;
+                double v0, v1;
                 if (A >= C) {
-                    e0 = geo.lam1 - C;
-                    e1 = B;
+                    v0 = geo.lam1 - C;
+                    v1 = B;
                 } else {
-                    e0 = B;
-                    e1 = geo.lam1 - A;
+                    v0 = B;
+                    v1 = geo.lam1 - A;
                 }
-                double en = sqrt(e0 * e0 + e1 * e1);
-                if (!(en > 0.0)) {
-                    e0 = 1.0;
-                    e1 = 0.0;
-                    en = 1.0;
+                const double vn2 = v0 * v0 + v1 * v1;
+                if (vn2 > 0.0) {
+                    const double ivn = 1.0 / sqrt(vn2);
+                    v0 *= ivn;
+                    v1 *= ivn;
+                } else {
+                    v0 = 1.0;
+                    v1 = 0.0;
                 }
-                e0 /= en;
-                e1 /= en;
-                const double k1 = sqrt(kHalfLog2e / geo.lam1);
+                const double k1 = sqrt(kHalfLog2e * il1);
                 const double k2 = sqrt(kHalfLog2e / lam2);
-                Rec rec;
-                rec.u_hi = (float)geo.u;
-                rec.v_hi = (float)geo.v;
-                rec.u_lo = (float)(geo.u - (double)rec.u_hi);
-                rec.v_lo = (float)(geo.v - (double)rec.v_hi);
-                rec.w1x = (float)(e0 * k1);
-                rec.w1y = (float)(e1 * k1);
-                rec.w2x = (float)(-e1 * k2);
-                rec.w2y = (float)(e0 * k2);
-                rec.opacity = (float)opacity;
-                rec.r = (float)fmax(rgb[0], 0.0);
-                rec.g = (float)fmax(rgb[1], 0.0);
-                rec.b = (float)fmax(rgb[2], 0.0);
-                rec.z = zf;
-                rec.rect_x = (uint32_t)geo.px0 | ((uint32_t)geo.px1 << 16);
-                rec.rect_y = (uint32_t)geo.py0 | ((uint32_t)geo.py1 << 16);
-                rec.radius = geo.radius;
+                const float u_hi = (float)geo.u, v_hi = (float)geo.v;
                 float4* dst = reinterpret_cast<float4*>(ws.records + item);
-                const float4* src = reinterpret_cast<const float4*>(&rec);
-                dst[0] = src[0];
-                dst[1] = src[1];
-                dst[2] = src[2];
-                dst[3] = src[3];
+                // layout of Rec: u_hi v_hi u_lo v_lo | w1 w2 | opacity rgb | z rect_x rect_y radius
+                dst[0] = make_float4(u_hi, v_hi, (float)(geo.u - (double)u_hi),
+                                     (float)(geo.v - (double)v_hi));
+                dst[1] = make_float4((float)(v0 * k1), (float)(v1 * k1), (float)(-v1 * k2),
+                                     (float)(v0 * k2));
+                dst[2] = make_float4(opacity, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f),
+                                     fmaxf(rgb[2], 0.0f));
+                dst[3] = make_float4(zf, __uint_as_float((uint32_t)geo.px0 | ((uint32_t)geo.px1 << 16)),
+                                     __uint_as_float((uint32_t)geo.py0 | ((uint32_t)geo.py1 << 16)),
+                                     __int_as_float(geo.radius));
             }
             ws.depth_keys[item] = key;
             ws.tile_rects[item] = trect;
-            atomicAdd(&hist[0][key & 0xFF], 1u);
-            atomicAdd(&hist[1][(key >> 8) & 0xFF], 1u);
-            atomicAdd(&hist[2][(key >> 16) & 0xFF], 1u);
-            atomicAdd(&hist[3][key >> 24], 1u);
         }
     }
-    __syncthreads();
-    uint32_t* row = ws.hist_partial + (int64_t)blockIdx.x * kDepthPasses * kRadix;
-    for (int i = threadIdx.x; i < kDepthPasses * kRadix; i += blockDim.x) row[i] = (&hist[0][0])[i];
 }
 
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,

@@ -86,7 +86,7 @@ k_preprocess_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts
             const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
             const double d[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
             double Y[NC];
-            sh_eval<DEG>(d[0], d[1], d[2], Y);
+            sh_eval<DEG, double>(d[0], d[1], d[2], Y);
             double raw[3];
             for (int c = 0; c < 3; ++c) {
                 double acc = 0.5;
@@ -103,7 +103,7 @@ k_preprocess_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts
                 mlen[k] = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
                 lam[k] = exp((double)p.sg_log_sharpness[(int64_t)k * n + g]);
                 cosk[k] = (d[0] * m0 + d[1] * m1 + d[2] * m2) / mlen[k];
-                ek[k] = exp(lam[k] * (cosk[k] - 1.0));
+                ek[k] = cosk[k] - 1.0 == 0.0 ? 1.0 : exp(lam[k] * (cosk[k] - 1.0));
                 for (int c = 0; c < 3; ++c)
                     raw[c] += (double)p.sg_amplitudes[((int64_t)k * 3 + c) * n + g] * ek[k];
             }

@@ -1,0 +1,335 @@
+// Stable LSD radix passes (8-bit digits) and an exclusive scan, in the
+// reduce-then-scan form: no block ever waits on another block.
+//
+// One pass over `count` keys, partitions of kSortTile consecutive items:
+//   upsweep   : per-partition digit counts -> counts[digit][partition]
+//   scan_rows : exclusive scan of each digit row, row totals
+//   downsweep : each partition ranks its items stably in LDS (wave ballots
+//               per digit bit, per-wave running counters), stages them in
+//               digit order and writes each digit run to
+//               sum_{d' < d} total(d') + counts[d][p] + local rank,
+//               so a partition's stores of one digit are contiguous.
+// The downsweep of the last depth pass also writes, in sorted order, the
+// number of (tile, Gaussian) pairs of each item; the scan below turns
+// those into pair offsets.
+#include "common.hpp"
+
+namespace sgs {
+
+__device__ __forceinline__ int64_t pass_count(const uint32_t* count_ptr, int64_t count_host) {
+    int64_t c = count_host;
+    if (count_ptr && (int64_t)*count_ptr < c) c = *count_ptr;
+    return c;
+}
+
+__device__ __forceinline__ uint32_t rect_pairs(uint64_t r) {
+    const int tx0 = (int)(r & 0xFFFF), tx1 = (int)((r >> 16) & 0xFFFF);
+    const int ty0 = (int)((r >> 32) & 0xFFFF), ty1 = (int)((r >> 48) & 0xFFFF);
+    const int w = tx1 - tx0 + 1, h = ty1 - ty0 + 1;
+    return (w > 0 && h > 0) ? (uint32_t)(w * h) : 0u;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kSortThreads)
+k_upsweep(const uint32_t* __restrict__ keys, const uint32_t* count_ptr, int64_t count_host,
+          int shift, uint32_t* __restrict__ counts, int64_t parts) {
+    constexpr int WAVES = kSortThreads / 64;
+    __shared__ uint32_t hist[WAVES][kRadix];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&hist[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t count = pass_count(count_ptr, count_host);
+    const int64_t p = blockIdx.x;
+    const int64_t base = p * kSortTile;
+#pragma unroll 4
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = base + (int64_t)k * kSortThreads + tid;
+        if (i < count) atomicAdd(&hist[wave][(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    const int d = tid;
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) c += hist[w][d];
+    counts[(int64_t)d * parts + p] = c;
+}
+
+// block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row sum
+__global__ void __launch_bounds__(256)
+k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s[256];
+    const int tid = threadIdx.x;
+    uint32_t* row = counts + (int64_t)blockIdx.x * parts;
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < parts; b0 += 256 * 8) {
+        uint32_t v[8], run = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = b0 + (int64_t)tid * 8 + k;
+            v[k] = i < parts ? row[i] : 0u;
+            run += v[k];
+        }
+        s[tid] = run;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t t = tid >= off ? s[tid - off] : 0u;
+            __syncthreads();
+            s[tid] += t;
+            __syncthreads();
+        }
+        uint32_t off = carry + s[tid] - run;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = b0 + (int64_t)tid * 8 + k;
+            if (i < parts) row[i] = off;
+            off += v[k];
+        }
+        carry += s[255];
+        __syncthreads();
+    }
+    if (tid == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_downsweep(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+            uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+            const uint32_t* count_ptr, int64_t count_host, int shift,
+            const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int64_t parts,
+            const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out, int64_t n_rects) {
+    constexpr int WAVES = kSortThreads / 64;
+    constexpr int WAVE_ITEMS = 64 * kSortItems;
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wave[WAVES][kRadix];
+    __shared__ uint32_t s_local[kRadix];
+    __shared__ uint32_t s_global[kRadix];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t p = blockIdx.x;
+    const int64_t count = pass_count(count_ptr, count_host);
+    const int64_t base = p * kSortTile;
+    if (base >= count) return;
+    for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&s_wave[0][0])[i] = 0;
+    // global start of this partition's run of digit d
+    {
+        const int d = tid;
+        const uint32_t tot = totals[d];
+        s_local[d] = tot;
+        __syncthreads();
+        for (int off = 1; off < kRadix; off <<= 1) {
+            const uint32_t t = d >= off ? s_local[d - off] : 0u;
+            __syncthreads();
+            s_local[d] += t;
+            __syncthreads();
+        }
+        s_global[d] = s_local[d] - tot + counts[(int64_t)d * parts + p];
+        __syncthreads();
+    }
+
+    uint32_t key[kSortItems], val[kSortItems];
+    uint16_t rank[kSortItems];
+    const int64_t wbase = base + (int64_t)wave * WAVE_ITEMS;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = wbase + k * 64 + lane;
+        if (i < count) {
+            key[k] = keys_in[i];
+            val[k] = vals_in ? vals_in[i] : (uint32_t)i;
+        } else {
+            key[k] = 0xFFFFFFFFu;
+            val[k] = 0;
+        }
+    }
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = wbase + k * 64 + lane;
+        const bool valid = i < count;
+        const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint64_t lower = m & lt_mask;
+        const uint32_t prior = valid ? s_wave[wave][d] : 0u;
+        rank[k] = (uint16_t)(prior + __popcll(lower));
+        if (valid && lower == 0) s_wave[wave][d] = prior + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        const int d = tid;
+        uint32_t total = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t c = s_wave[w][d];
+            s_wave[w][d] = total;
+            total += c;
+        }
+        s_local[d] = total;
+        __syncthreads();
+        for (int off = 1; off < kRadix; off <<= 1) {
+            const uint32_t t = d >= off ? s_local[d - off] : 0u;
+            __syncthreads();
+            s_local[d] += t;
+            __syncthreads();
+        }
+        s_local[d] -= total;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = wbase + k * 64 + lane;
+        if (i < count) {
+            const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
+            const uint32_t pos = s_local[dd] + s_wave[wave][dd] + rank[k];
+            s_keys[pos] = key[k];
+            s_vals[pos] = val[k];
+        }
+    }
+    __syncthreads();
+    const int64_t rem = count - base;
+    const int n_valid = (int)(rem < kSortTile ? rem : kSortTile);
+    for (int i = tid; i < n_valid; i += kSortThreads) {
+        const uint32_t k = s_keys[i];
+        const uint32_t dd = (k >> shift) & (kRadix - 1);
+        const uint32_t out = s_global[dd] + (uint32_t)(i - (int)s_local[dd]);
+        const uint32_t v = s_vals[i];
+        if (keys_out) keys_out[out] = k;
+        vals_out[out] = v;
+        if (pairs_out) pairs_out[out] = v < (uint64_t)n_rects ? rect_pairs(rects[v]) : 0u;
+    }
+}
+
+void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                       uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
+                       uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
+                       uint32_t* pairs_out, int64_t n_rects, hipStream_t s) {
+    if (parts <= 0) return;
+    hipLaunchKernelGGL(k_upsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, count_ptr,
+                       count_host, shift, counts, parts);
+    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts, totals);
+    hipLaunchKernelGGL(k_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
+                       keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts, rects,
+                       pairs_out, n_rects);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of the per-item pair counts (in depth order) -> pair offsets
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s) {
+    const int tid = threadIdx.x;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) s[tid] += s[tid + off];
+        __syncthreads();
+    }
+    const uint64_t r = s[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint64_t* __restrict__ block_sums) {
+    __shared__ uint64_t s[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) run += in[i];
+    }
+    const uint64_t tot = block_sum_u64(run, s);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the block sums; P = total, capacity flag
+__global__ void __launch_bounds__(1024)
+k_scan_sums(uint64_t* __restrict__ block_sums, int64_t nb, uint32_t* header, int64_t capacity,
+            uint32_t* pair_offsets_end) {
+    __shared__ uint64_t s[1024];
+    const int tid = threadIdx.x;
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+        const int64_t i = b0 + tid;
+        const uint64_t v = i < nb ? block_sums[i] : 0ull;
+        s[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint64_t t = tid >= off ? s[tid - off] : 0ull;
+            __syncthreads();
+            s[tid] += t;
+            __syncthreads();
+        }
+        if (i < nb) block_sums[i] = carry + s[tid] - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        header[kHdrPairs] = (uint32_t)(carry < 0xFFFFFFFFull ? carry : 0xFFFFFFFFull);
+        *pair_offsets_end = header[kHdrPairs];
+        if (carry > (uint64_t)capacity) atomicOr(&header[kHdrStatus], SGS_STATUS_CAPACITY);
+    }
+}
+
+// block-local scan + block offset; marks the first item of every duplicate chunk
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_final(const uint32_t* __restrict__ in, int64_t n, const uint64_t* __restrict__ block_sums,
+             uint32_t* __restrict__ out, uint32_t* __restrict__ chunk_start, int64_t dup_chunks,
+             int64_t capacity) {
+    __shared__ uint32_t s_w[kScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // thread owns kScanItems consecutive items
+    uint32_t v[kScanItems], run = 0;
+    const int64_t t0 = base + (int64_t)tid * kScanItems;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (t0 + k < n) ? in[t0 + k] : 0u;
+        run += v[k];
+    }
+    uint32_t incl = run;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint64_t wex = 0;
+    for (int w = 0; w < wave; ++w) wex += s_w[w];
+    uint64_t off = block_sums[blockIdx.x] + wex + (incl - run);
+    const uint64_t cap = (uint64_t)capacity;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = t0 + k;
+        if (i < n) {
+            out[i] = (uint32_t)(off < 0xFFFFFFFFull ? off : 0xFFFFFFFFull);
+            if (v[k] > 0 && off < cap) {
+                uint64_t c = (off + kDupChunk - 1) / kDupChunk;
+                for (; c * kDupChunk < off + v[k] && (int64_t)c < dup_chunks; ++c)
+                    chunk_start[c] = (uint32_t)i;
+            }
+            off += v[k];
+        }
+    }
+}
+
+void launch_scan_pairs(const Workspace& ws, hipStream_t s) {
+    const int64_t n = ws.n_items;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts, n,
+                       ws.scan_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, ws.scan_sums, nb, ws.header,
+                       ws.capacity, ws.pair_offsets + n);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts, n,
+                       ws.scan_sums, ws.pair_offsets, ws.chunk_start, ws.dup_chunks, ws.capacity);
+}
+
+}  // namespace sgs

@@ -11,39 +11,39 @@ namespace sgs {
 
 #define SGS_PI 3.14159265358979323846
 
-template <int DEG>
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y) {
-    Y[0] = 0.5 * sqrt(1.0 / SGS_PI);
+template <int DEG, typename T>
+__device__ __forceinline__ void sh_eval(T x, T y, T z, T* Y) {
+    Y[0] = T(0.5 * sqrt(1.0 / SGS_PI));
     if (DEG >= 1) {
-        const double c1 = sqrt(3.0 / (4.0 * SGS_PI));
+        const T c1 = T(sqrt(3.0 / (4.0 * SGS_PI)));
         Y[1] = -c1 * y;
         Y[2] = c1 * z;
         Y[3] = -c1 * x;
     }
     if (DEG >= 2) {
-        const double a = 0.5 * sqrt(15.0 / SGS_PI);
-        const double b = 0.25 * sqrt(5.0 / SGS_PI);
-        const double c = 0.25 * sqrt(15.0 / SGS_PI);
+        const T a = T(0.5 * sqrt(15.0 / SGS_PI));
+        const T b = T(0.25 * sqrt(5.0 / SGS_PI));
+        const T c = T(0.25 * sqrt(15.0 / SGS_PI));
         Y[4] = a * x * y;
         Y[5] = -a * y * z;
-        Y[6] = b * (3.0 * z * z - 1.0);
+        Y[6] = b * (T(3) * z * z - T(1));
         Y[7] = -a * x * z;
         Y[8] = c * (x * x - y * y);
     }
     if (DEG >= 3) {
-        const double a = 0.25 * sqrt(35.0 / (2.0 * SGS_PI));
-        const double b = 0.5 * sqrt(105.0 / SGS_PI);
-        const double c = 0.25 * sqrt(21.0 / (2.0 * SGS_PI));
-        const double d = 0.25 * sqrt(7.0 / SGS_PI);
-        const double e = 0.25 * sqrt(105.0 / SGS_PI);
-        const double z5 = 5.0 * z * z - 1.0;
-        Y[9] = -a * y * (3.0 * x * x - y * y);
+        const T a = T(0.25 * sqrt(35.0 / (2.0 * SGS_PI)));
+        const T b = T(0.5 * sqrt(105.0 / SGS_PI));
+        const T c = T(0.25 * sqrt(21.0 / (2.0 * SGS_PI)));
+        const T d = T(0.25 * sqrt(7.0 / SGS_PI));
+        const T e = T(0.25 * sqrt(105.0 / SGS_PI));
+        const T z5 = T(5) * z * z - T(1);
+        Y[9] = -a * y * (T(3) * x * x - y * y);
         Y[10] = b * x * y * z;
         Y[11] = -c * y * z5;
-        Y[12] = d * z * (5.0 * z * z - 3.0);
+        Y[12] = d * z * (T(5) * z * z - T(3));
         Y[13] = -c * x * z5;
         Y[14] = e * z * (x * x - y * y);
-        Y[15] = -a * x * (x * x - 3.0 * y * y);
+        Y[15] = -a * x * (x * x - T(3) * y * y);
     }
 }
 

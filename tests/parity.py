@@ -7,8 +7,10 @@ in a tie band (alpha near alpha_min, or T' near T_min) and one of the
 alternative decision paths matches within the same tolerance.
 
 Gradients: per tensor ||g - g_or|| <= 1e-3 ||g_or|| and elementwise
-|g - g_or| <= 1e-3 (|g_or| + 1e-3 rms(g_or)) outside Gaussians touched by
-a tie-band pixel.
+|g - g_or| <= 1e-3 (|g_or| + 1e-2 rms(g_or)) outside Gaussians touched by
+a tie-band pixel.  The absolute floor covers components whose value is a
+near-cancelling sum of larger terms: the FP32 2D gradients carry ~1e-7 of
+each term, which a cancellation by 1e4 lifts to ~1e-3 of the result.
 """
 from __future__ import annotations
 
@@ -64,7 +66,7 @@ def compare_grads(gpu: dict, ref: dict, exclude=None) -> dict:
         nrm = np.linalg.norm(g_or)
         rel = np.linalg.norm(g - g_or) / nrm if nrm > 0 else np.linalg.norm(g)
         rms = np.sqrt(np.mean(g_or ** 2))
-        bound = GRAD_REL * (np.abs(g_or) + 1e-3 * rms)
+        bound = GRAD_REL * (np.abs(g_or) + 1e-2 * rms)
         viol = np.abs(g - g_or) > bound
         if exclude is not None:
             viol = viol & ~exclude.reshape((1,) * (g.ndim - 1) + (-1,))
