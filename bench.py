@@ -4,11 +4,12 @@
 
 Workload: 3M clustered Gaussians, 1600x1060, SG form (SH degree 1 + 4
 lobes) beside the degree-3 SH form on the same geometry.  Prints one JSON
-line: forward frames/s of the SG form (value), forward+backward ms (L1
-loss against a seeded target), the SH-3 form's frames/s, per-stage times
-from HIP events inside the timed loops, the roofline of the dominant
-kernel, and the FP64 oracle's throughput on a bounded sample of the same
-frame on the host CPU.
+line: forward frames/s of the SG form (value; the forward captured once in
+a HIP graph and replayed), forward+backward ms (L1 loss against a seeded
+target), the same passes launched eagerly, the SH-3 form's figures,
+per-stage times from HIP events inside the eager timed loops, the roofline
+of the dominant kernel, and the FP64 oracle's throughput on a bounded
+sample of the same frame on the host CPU.
 """
 from __future__ import annotations
 
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--no-sh3", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many forward+backward steps (for rocprofv3)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--tile", default=None, help="fixed launch shape tw,th,ppt,ppt_bwd,batch")
     return ap.parse_args()
 
 
@@ -68,6 +71,19 @@ def timed_loop(fn, steps, torch):
     t1.record()
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def capture(fn, torch):
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
 
 
 def cpu_baseline(scene, cam, opts, n_tiles_sample=24):
@@ -109,14 +125,25 @@ def main():
     from paper_2501_00342_amd import raster, scenes
 
     assert torch.cuda.is_available()
+    from paper_2501_00342_amd import autotune
     sc, cams, opts = scenes.workload(args.workload)
     cam = cams[0]
     W, H = cam.width, cam.height
-    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
     params = raster.params_to_device(sc)
-    target = torch.from_numpy(scenes.target_image(W, H, 1).reshape(-1)).cuda()
+    target = torch.from_numpy(np.concatenate(
+        [scenes.target_image(c.width, c.height, 1 + i).reshape(-1) for i, c in enumerate(cams)])).cuda()
+    tune_report = None
+    if args.tile:
+        tw, th, ppt, pptb, batch = (int(x) for x in args.tile.split(","))
+        opts = scenes.Options(tile_w=tw, tile_h=th, ppt=ppt, ppt_bwd=pptb, batch=batch)
+    elif not args.no_tune and not args.profile_steps:
+        opts, tune_report = autotune.tune(params, cams, opts, sc.n, sc.sh_degree, sc.n_lobes,
+                                          backward=False, reps=3, tiles=[(16, 16), (32, 8), (16, 8)],
+                                          batches=(128, 256), target=target)
+    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
     out = rast.forward(params, check=True)          # sizes the pair capacity
     grad_img = torch.empty_like(out.image)
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
 
     def fwd():
         rast.forward(params, out=out, check=False)
@@ -124,7 +151,7 @@ def main():
     def fwd_bwd():
         rast.forward(params, out=out, check=False)
         rast.l1(out.image, target, grad_out=grad_img)
-        rast.backward(params, out, grad_img)
+        rast.backward_into(params, out, grad_img, grads)
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
@@ -147,6 +174,12 @@ def main():
     st_fb, nf2, nb2 = L.stage_times()
     L.LIB.render_set_timing(0)
     names = L.stage_names()
+
+    # the same passes captured once in a HIP graph and replayed
+    g_fwd = capture(fwd, torch)
+    g_fb = capture(fwd_bwd, torch)
+    fwd_graph_ms = timed_loop(g_fwd.replay, args.steps, torch)
+    fb_graph_ms = timed_loop(g_fb.replay, args.steps, torch)
 
     visited, evaluated = rast.blend_work(params)
     n_vis = int(np.count_nonzero(rast.depth_keys().cpu().numpy().view(np.uint32) != 0xFFFFFFFF))
@@ -185,18 +218,35 @@ def main():
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
     result = {
-        "metric": "frames/s & fwd+bwd ms at 3M Gaussians 1600x1060, SG vs SH-3 form, same GPU",
-        "value": round(1000.0 / fwd_ms, 2), "unit": "frames/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fwd_ms, 4),
+        "metric": ("frames/s & fwd+bwd ms at 3M Gaussians 1600x1060, SG vs SH-3 form, same GPU"
+                   if args.workload == "sg-3m-1600" else f"frames/s & fwd+bwd ms, {args.workload}"),
+        "value": round(1000.0 / fwd_graph_ms, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fwd_graph_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "gaussians": sc.n, "width": W, "height": H,
-                   "colour": f"SH{sc.sh_degree}+{sc.n_lobes}SG", "tile": f"{opts.tile_w}x{opts.tile_h}"},
-        "fwd_bwd_ms": round(fb_ms, 4),
+        "config": {"workload": args.workload, "gaussians": sc.n, "cameras": len(cams),
+                   "width": W, "height": H, "colour": f"SH{sc.sh_degree}+{sc.n_lobes}SG",
+                   "tile": f"{opts.tile_w}x{opts.tile_h}", "ppt": rast.copts.pixels_per_thread,
+                   "ppt_bwd": rast.copts.pixels_per_thread_bwd, "batch": opts.batch},
+        "fwd_bwd_ms": round(fb_graph_ms, 4),
+        "eager": {"frames_per_s": round(1000.0 / fwd_ms, 2), "fwd_ms": round(fwd_ms, 4),
+                  "fwd_bwd_ms": round(fb_ms, 4)},
         "pairs": int(P), "visible": n_vis, "tiles": tiles,
         "blend_visited": visited, "blend_evaluated": evaluated,
         "stages": stages, "roofline": roof,
     }
+    if tune_report is not None:
+        result["autotune"] = sorted(tune_report, key=lambda r: r["ms"])[:5]
+    if len(cams) > 1:
+        result["views_per_s"] = round(len(cams) * 1000.0 / fwd_graph_ms, 2)
+    # per-tile load (list lengths), e.g. for the stress workload
+    rng = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
+    cnt = rng[:, 1] - rng[:, 0]
+    bins = np.bincount(np.ceil(np.log2(np.maximum(cnt, 1))).astype(np.int64))
+    result["tile_load"] = {"p50": float(np.percentile(cnt, 50)), "p90": float(np.percentile(cnt, 90)),
+                           "p99": float(np.percentile(cnt, 99)), "max": int(cnt.max()),
+                           "empty": int((cnt == 0).sum()),
+                           "log2_bins": {f"<=2^{i}": int(b) for i, b in enumerate(bins) if b}}
 
     if not args.no_sh3:
         sh3 = scenes.sh3_scene(sc.n, 1) if args.workload == "sg-3m-1600" else None
@@ -209,10 +259,12 @@ def main():
             def fwd3():
                 r3.forward(p3, out=o3, check=False)
 
+            gr3 = {k: torch.empty_like(v) for k, v in p3.items()}
+
             def fb3():
                 r3.forward(p3, out=o3, check=False)
                 r3.l1(o3.image, target, grad_out=g3)
-                r3.backward(p3, o3, g3)
+                r3.backward_into(p3, o3, g3, gr3)
 
             for _ in range(args.warmup):
                 fb3()
@@ -223,13 +275,19 @@ def main():
             sh3_fb = timed_loop(fb3, args.steps, torch)
             L.stage_times()
             L.LIB.render_set_timing(0)
-            result["sh3"] = {"frames_per_s": round(1000.0 / sh3_fwd, 2), "fwd_ms": round(sh3_fwd, 4),
-                             "fwd_bwd_ms": round(sh3_fb, 4),
+            gf3 = capture(fwd3, torch)
+            gb3 = capture(fb3, torch)
+            sh3_fwd_g = timed_loop(gf3.replay, args.steps, torch)
+            sh3_fb_g = timed_loop(gb3.replay, args.steps, torch)
+            result["sh3"] = {"frames_per_s": round(1000.0 / sh3_fwd_g, 2),
+                             "fwd_ms": round(sh3_fwd_g, 4), "fwd_bwd_ms": round(sh3_fb_g, 4),
+                             "eager_fwd_ms": round(sh3_fwd, 4), "eager_fwd_bwd_ms": round(sh3_fb, 4),
                              "preprocess_ms": round(st3[names.index("fwd.preprocess")] / max(n3, 1), 5)}
-            result["sg_over_sh3_fps"] = round(sh3_fwd / fwd_ms, 4)
-            del r3, p3, o3, g3
+            result["sg_over_sh3_fps"] = round(sh3_fwd_g / fwd_graph_ms, 4)
+            result["sg_over_sh3_fwd_bwd"] = round(sh3_fb_g / fb_graph_ms, 4)
+            del r3, p3, o3, g3, gf3, gb3
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and len(cams) == 1:
         result["cpu_baseline"] = cpu_baseline(sc, cam, opts)
     print(json.dumps(result), flush=True)
 

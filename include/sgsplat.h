@@ -98,12 +98,16 @@ typedef struct sgs_camera {
 /* Rasteriser options.  Zero-initialised fields take the defaults given. */
 typedef struct sgs_options {
     int32_t tile_w, tile_h;          /* 16x16 (default), 8x8, 16x8, 8x16, 32x8 */
-    int32_t batch;                   /* LDS batch depth: multiple of tile_w*tile_h, <= 1024; 0 = tile_w*tile_h */
+    int32_t batch;                   /* LDS batch depth: a multiple of the block size, <= 1024;
+                                        0 = 256 */
     float dilation;                  /* added to both diagonal entries of the 2D covariance (0.3) */
     float guard;                     /* guard band on the projection Jacobian, x tan(fov/2) (1.3) */
     float alpha_min;                 /* splats with alpha < alpha_min are skipped (1/255) */
     float alpha_max;                 /* alpha is clamped to alpha_max (0.99) */
     float t_min;                     /* blending stops before T would fall below t_min (1e-4) */
+    int32_t pixels_per_thread;       /* forward blend: 1, 2 or 4 pixels per thread (0 = 2); the
+                                        block, tile_w*tile_h/ppt threads, must be whole waves */
+    int32_t pixels_per_thread_bwd;   /* backward blend, same rule (0 = 4 where allowed) */
 } sgs_options;
 
 /* Forward outputs (device, packed over cameras as described above). */
@@ -125,7 +129,8 @@ typedef struct sgs_layout {
     size_t tile_rects;      /* u64 per item: tx0 | tx1<<16 | ty0<<32 | ty1<<48; 0 pairs if culled */
     size_t sorted_items;    /* u32 per item: items in ascending (depth key, item) order */
     size_t pair_offsets;    /* u32 per item: exclusive scan of pairs in sorted order */
-    size_t pair_tiles;      /* u32 per pair: global tile id, sorted ascending */
+    size_t pair_tiles;      /* per pair: global tile id, sorted ascending; u16 when
+                               n_tiles <= 65536, else u32 */
     size_t pair_values;     /* u32 per pair: item = camera * n + g, in blend order */
     size_t ranges;          /* u32[2] per global tile: [start, end), (0,0) if empty */
     size_t grad2d;          /* f32[9][items]: d/d(u, v, Qa, Qb, Qc, opacity, r, g, b) */

@@ -41,7 +41,8 @@ class Camera(Structure):
 class Options(Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32),
                 ("dilation", c_float), ("guard", c_float), ("alpha_min", c_float),
-                ("alpha_max", c_float), ("t_min", c_float)]
+                ("alpha_max", c_float), ("t_min", c_float), ("pixels_per_thread", c_int32),
+                ("pixels_per_thread_bwd", c_int32)]
 
 
 class Outputs(Structure):
@@ -158,6 +159,8 @@ def options_struct(opts) -> Options:
     o.tile_w, o.tile_h, o.batch = int(opts.tile_w), int(opts.tile_h), int(opts.batch)
     o.dilation, o.guard = opts.dilation, opts.guard
     o.alpha_min, o.alpha_max, o.t_min = opts.alpha_min, opts.alpha_max, opts.t_min
+    o.pixels_per_thread = int(getattr(opts, "ppt", 0))
+    o.pixels_per_thread_bwd = int(getattr(opts, "ppt_bwd", 0))
     return o
 
 

@@ -1,9 +1,10 @@
 // Tile compositing, forward and backward, and the L1 loss.
 //
-// One workgroup per tile (TW x TH pixels, one pixel per thread).  The
-// tile's sorted Gaussians are streamed through LDS in batches: each thread
-// gathers one 64-byte record, turns it into a tile-relative entry and all
-// pixels of the tile read it back from LDS.  Forward (SG-Splatting
+// One workgroup per tile (TW x TH pixels, PPT pixels per thread, stacked in
+// one column so that the column test and the x-terms of the power are
+// shared).  The tile's sorted Gaussians are streamed through LDS in
+// batches: each thread gathers 64-byte records, turns them into
+// tile-relative entries and all pixels of the tile read them back.  Forward (SG-Splatting
 // Preliminaries: splats "accumulated and blended" front to back):
 //   alpha = min(alpha_max, opacity * exp(-d^T Q d / 2)),  skip alpha < alpha_min,
 //   stop before T (1 - alpha) < T_min,  C += alpha T rgb,  T *= 1 - alpha.
@@ -16,8 +17,9 @@
 //
 // Backward: the same tile walk back to front from the saved final T and
 // n_contrib, recomputing alpha with the same instructions, T_j =
-// T_{j+1} / (1 - alpha_j).  Per-Gaussian 2D gradients are summed across
-// the wave with DPP and added with one float atomic per value per wave.
+// T_{j+1} / (1 - alpha_j).  Per-Gaussian 2D gradients are summed over a
+// thread's pixels, then across the wave with DPP, and added with one float
+// atomic per value per wave.
 #include "common.hpp"
 
 namespace sgs {
@@ -59,17 +61,17 @@ __device__ __forceinline__ Entry make_entry(const Rec* __restrict__ recs, uint32
     return e;
 }
 
-// alpha of one splat at one pixel; identical instructions in both passes
+// alpha of one splat at one pixel; identical instructions in both passes.
+// The x-terms w1x*dx and w2x*dx are shared by the pixels of one column.
 struct Eval {
-    float dx, dy, y1, y2, E, alpha;
+    float y1, y2, E, alpha;
 };
 
-__device__ __forceinline__ Eval eval_splat(const Entry& e, float lx, float ly, float amax) {
+__device__ __forceinline__ Eval eval_splat(const Entry& e, float t1, float t2, float dy,
+                                           float amax) {
     Eval v;
-    v.dx = lx + e.a.x;
-    v.dy = ly + e.a.y;
-    v.y1 = fmaf(e.a.w, v.dy, e.a.z * v.dx);
-    v.y2 = fmaf(e.b.y, v.dy, e.b.x * v.dx);
+    v.y1 = fmaf(e.a.w, dy, t1);
+    v.y2 = fmaf(e.b.y, dy, t2);
     const float q = fmaf(v.y2, v.y2, v.y1 * v.y1);
     v.E = __builtin_amdgcn_exp2f(-q);
     v.alpha = fminf(amax, e.b.z * v.E);
@@ -102,11 +104,14 @@ __device__ __forceinline__ Entry load_entry(const Workspace& ws, int64_t pos, in
     return e;
 }
 
-template <int TW, int TH, bool COUNT>
-__global__ void __launch_bounds__(TW * TH)
+// Thread t of a TW x TH tile with PPT pixels per thread owns column t % TW
+// and rows t / TW + k * (TH / PPT), k < PPT.
+template <int TW, int TH, int PPT, bool COUNT>
+__global__ void __launch_bounds__(TW * TH / PPT)
 k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs out, int batch, unsigned long long* counts) {
-    constexpr int NT = TW * TH;
+    constexpr int NT = TW * TH / PPT;
+    constexpr int RS = TH / PPT;   // row stride between a thread's pixels
     extern __shared__ Entry s_e[];
     __shared__ int s_cam;
     const int tid = threadIdx.x;
@@ -119,45 +124,58 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int lx = tid % TW, ly = tid / TW;
-    const int px = x0 + lx, py = y0 + ly;
-    const bool inside = px < ct.W && py < ct.H;
+    const int lx = tid % TW, ly0 = tid / TW;
     const uint32_t start = ws.ranges[2 * tile];
     const uint32_t end = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity ? ws.ranges[2 * tile + 1] : start;
-    const uint32_t colbit = 1u << lx, rowbit = 1u << ly;
-    const float lxf = (float)lx, lyf = (float)ly;
+    const uint32_t colbit = 1u << lx;
+    const float lxf = (float)lx;
     const float amin = o.alpha_min, amax = o.alpha_max, tmin = o.t_min;
 
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
-    int n = 0;
-    bool done = !inside;
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
+    int n[PPT];
+    uint32_t live = 0;   // bit k: pixel k still blending
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        T[k] = 1.0f;
+        C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
+        n[k] = 0;
+        if (x0 + lx < ct.W && y0 + ly0 + k * RS < ct.H) live |= 1u << k;
+    }
     unsigned long long visited = 0, evaluated = 0;
     for (uint32_t bs = start; bs < end; bs += batch) {
-        if (__syncthreads_count(!done) == 0) break;
+        if (__syncthreads_count(live != 0) == 0) break;
         const int cnt = (int)((end - bs) < (uint32_t)batch ? (end - bs) : (uint32_t)batch);
         for (int k = tid; k < cnt; k += NT)
             s_e[k] = load_entry(ws, (int64_t)bs + k, x0, y0, TW, TH);
         __syncthreads();
-        if (!done) {
+        if (live) {
             for (int j = 0; j < cnt; ++j) {
                 const Entry e = s_e[j];
-                if (COUNT) ++visited;
-                if (!((e.m.x & colbit) && (e.m.y & rowbit))) continue;
-                if (COUNT) ++evaluated;
-                const Eval v = eval_splat(e, lxf, lyf, amax);
-                if (v.alpha < amin) continue;
-                const float Tn = T * (1.0f - v.alpha);
-                if (Tn < tmin) {
-                    done = true;
-                    break;
+                if (COUNT) visited += __popc(live);
+                if (!(e.m.x & colbit)) continue;
+                const float dx = lxf + e.a.x;
+                const float t1 = e.a.z * dx, t2 = e.b.x * dx;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (!((live >> k) & 1u)) continue;
+                    if (!((e.m.y >> (ly0 + k * RS)) & 1u)) continue;
+                    if (COUNT) ++evaluated;
+                    const Eval v = eval_splat(e, t1, t2, (float)(ly0 + k * RS) + e.a.y, amax);
+                    if (v.alpha < amin) continue;
+                    const float Tn = T[k] * (1.0f - v.alpha);
+                    if (Tn < tmin) {
+                        live &= ~(1u << k);
+                        continue;
+                    }
+                    const float w = v.alpha * T[k];
+                    C0[k] = fmaf(w, e.c.x, C0[k]);
+                    C1[k] = fmaf(w, e.c.y, C1[k]);
+                    C2[k] = fmaf(w, e.c.z, C2[k]);
+                    D[k] = fmaf(w, e.b.w, D[k]);
+                    T[k] = Tn;
+                    n[k] = (int)(bs - start) + j + 1;
                 }
-                const float w = v.alpha * T;
-                C0 = fmaf(w, e.c.x, C0);
-                C1 = fmaf(w, e.c.y, C1);
-                C2 = fmaf(w, e.c.z, C2);
-                D = fmaf(w, e.b.w, D);
-                T = Tn;
-                n = (int)(bs - start) + j + 1;
+                if (!live) break;
             }
         }
     }
@@ -174,17 +192,20 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         }
         return;
     }
-    if (inside) {
-        const int64_t W = ct.W, H = ct.H;
+    const int64_t W = ct.W, H = ct.H;
+    const sgs_camera& c = cams[cam];
+    float* img = out.image + 3 * ct.pix_base;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int px = x0 + lx, py = y0 + ly0 + k * RS;
+        if (px >= ct.W || py >= ct.H) continue;
         const int64_t pix = (int64_t)py * W + px;
-        const sgs_camera& c = cams[cam];
-        float* img = out.image + 3 * ct.pix_base;
-        img[pix] = C0 + T * c.bg[0];
-        img[W * H + pix] = C1 + T * c.bg[1];
-        img[2 * W * H + pix] = C2 + T * c.bg[2];
-        if (out.depth) out.depth[ct.pix_base + pix] = D;
-        out.final_T[ct.pix_base + pix] = T;
-        out.n_contrib[ct.pix_base + pix] = n;
+        img[pix] = C0[k] + T[k] * c.bg[0];
+        img[W * H + pix] = C1[k] + T[k] * c.bg[1];
+        img[2 * W * H + pix] = C2[k] + T[k] * c.bg[2];
+        if (out.depth) out.depth[ct.pix_base + pix] = D[k];
+        out.final_T[ct.pix_base + pix] = T[k];
+        out.n_contrib[ct.pix_base + pix] = n[k];
     }
 }
 
@@ -209,11 +230,12 @@ __device__ __forceinline__ float wave_sum63(float v) {
     return v;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT)
 k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs fwd, const float* __restrict__ grad_image, int batch) {
-    constexpr int NT = TW * TH;
+    constexpr int NT = TW * TH / PPT;
+    constexpr int RS = TH / PPT;
     extern __shared__ Entry s_e[];
     __shared__ int s_cam;
     __shared__ int s_maxn;
@@ -231,32 +253,41 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int lx = tid % TW, ly = tid / TW;
-    const int px = x0 + lx, py = y0 + ly;
-    const bool inside = px < ct.W && py < ct.H;
+    const int lx = tid % TW, ly0 = tid / TW;
     const uint32_t start = ws.ranges[2 * tile];
     const int64_t len = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity
                             ? (int64_t)ws.ranges[2 * tile + 1] - start : 0;
-    const uint32_t colbit = 1u << lx, rowbit = 1u << ly;
-    const float lxf = (float)lx, lyf = (float)ly;
+    const uint32_t colbit = 1u << lx;
+    const float lxf = (float)lx;
     const float amin = o.alpha_min, amax = o.alpha_max;
     const sgs_camera& c = cams[cam];
+    const int64_t W = ct.W, H = ct.H;
+    const float* gi = grad_image + 3 * ct.pix_base;
 
-    float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-    int nc = 0;
-    if (inside) {
-        const int64_t W = ct.W, H = ct.H;
-        const int64_t pix = (int64_t)py * W + px;
-        T = fwd.final_T[ct.pix_base + pix];
-        nc = fwd.n_contrib[ct.pix_base + pix];
-        const float* gi = grad_image + 3 * ct.pix_base;
-        g0 = gi[pix];
-        g1 = gi[W * H + pix];
-        g2 = gi[2 * W * H + pix];
+    float T[PPT], g0[PPT], g1[PPT], g2[PPT], S0[PPT], S1[PPT], S2[PPT];
+    int nc[PPT];
+    int my_max = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int px = x0 + lx, py = y0 + ly0 + k * RS;
+        T[k] = 1.0f;
+        g0[k] = g1[k] = g2[k] = 0.0f;
+        nc[k] = 0;
+        if (px < ct.W && py < ct.H) {
+            const int64_t pix = (int64_t)py * W + px;
+            T[k] = fwd.final_T[ct.pix_base + pix];
+            nc[k] = fwd.n_contrib[ct.pix_base + pix];
+            g0[k] = gi[pix];
+            g1[k] = gi[W * H + pix];
+            g2[k] = gi[2 * W * H + pix];
+        }
+        if (nc[k] > len) nc[k] = (int)len;
+        S0[k] = T[k] * c.bg[0];
+        S1[k] = T[k] * c.bg[1];
+        S2[k] = T[k] * c.bg[2];
+        my_max = nc[k] > my_max ? nc[k] : my_max;
     }
-    float S0 = T * c.bg[0], S1 = T * c.bg[1], S2 = T * c.bg[2];
-    if (nc > len) nc = (int)len;
-    if (nc > 0) atomicMax(&s_maxn, nc);
+    if (my_max > 0) atomicMax(&s_maxn, my_max);
     __syncthreads();
     const int maxn = s_maxn;
     const int64_t M = ws.n_items;
@@ -270,37 +301,44 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         for (int k = tid; k < cnt; k += NT)
             s_e[k] = load_entry(ws, (int64_t)start + bb + k, x0, y0, TW, TH);
         __syncthreads();
-        for (int k = cnt - 1; k >= 0; --k) {
-            const Entry e = s_e[k];
-            const int j = bb + k;
+        for (int j = cnt - 1; j >= 0; --j) {
+            const Entry e = s_e[j];
+            const int pos = bb + j;
             float v_u = 0.f, v_v = 0.f, v_qa = 0.f, v_qb = 0.f, v_qc = 0.f, v_s = 0.f;
             float v_r = 0.f, v_g = 0.f, v_b = 0.f;
             bool contrib = false;
-            if (j < nc && (e.m.x & colbit) && (e.m.y & rowbit)) {
-                const Eval v = eval_splat(e, lxf, lyf, amax);
-                if (v.alpha >= amin) {
+            if (e.m.x & colbit) {
+                const float dx = lxf + e.a.x;
+                const float t1 = e.a.z * dx, t2 = e.b.x * dx;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (pos >= nc[k] || !((e.m.y >> (ly0 + k * RS)) & 1u)) continue;
+                    const float dy = (float)(ly0 + k * RS) + e.a.y;
+                    const Eval v = eval_splat(e, t1, t2, dy, amax);
+                    if (v.alpha < amin) continue;
                     contrib = true;
                     const float om = 1.0f - v.alpha;
-                    T = T / om;
-                    const float w = v.alpha * T;
-                    v_r = w * g0;
-                    v_g = w * g1;
-                    v_b = w * g2;
-                    const float cg = e.c.x * g0 + e.c.y * g1 + e.c.z * g2;
-                    const float sg = S0 * g0 + S1 * g1 + S2 * g2;
-                    const float dLda = T * cg - sg / om;
-                    S0 = fmaf(w, e.c.x, S0);
-                    S1 = fmaf(w, e.c.y, S1);
-                    S2 = fmaf(w, e.c.z, S2);
+                    T[k] = T[k] / om;
+                    const float w = v.alpha * T[k];
+                    v_r = fmaf(w, g0[k], v_r);
+                    v_g = fmaf(w, g1[k], v_g);
+                    v_b = fmaf(w, g2[k], v_b);
+                    const float cg = e.c.x * g0[k] + e.c.y * g1[k] + e.c.z * g2[k];
+                    const float sg = S0[k] * g0[k] + S1[k] * g1[k] + S2[k] * g2[k];
+                    const float dLda = T[k] * cg - sg / om;
+                    S0[k] = fmaf(w, e.c.x, S0[k]);
+                    S1[k] = fmaf(w, e.c.y, S1[k]);
+                    S2[k] = fmaf(w, e.c.z, S2[k]);
                     if (e.b.z * v.E <= amax) {
-                        v_s = dLda * v.E;
+                        v_s = fmaf(dLda, v.E, v_s);
                         const float dLdp = dLda * v.alpha;
                         // dp/du = (Q d)_x, Q d = (w1 y1 + w2 y2) / k
-                        v_u = dLdp * (e.a.z * v.y1 + e.b.x * v.y2) * inv_k;
-                        v_v = dLdp * (e.a.w * v.y1 + e.b.y * v.y2) * inv_k;
-                        v_qa = -0.5f * dLdp * v.dx * v.dx;
-                        v_qb = -dLdp * v.dx * v.dy;
-                        v_qc = -0.5f * dLdp * v.dy * v.dy;
+                        const float pk = dLdp * inv_k;
+                        v_u = fmaf(pk, e.a.z * v.y1 + e.b.x * v.y2, v_u);
+                        v_v = fmaf(pk, e.a.w * v.y1 + e.b.y * v.y2, v_v);
+                        v_qa = fmaf(-0.5f * dLdp * dx, dx, v_qa);
+                        v_qb = fmaf(-dLdp * dx, dy, v_qb);
+                        v_qc = fmaf(-0.5f * dLdp * dy, dy, v_qc);
                     }
                 }
             }
@@ -333,55 +371,62 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
 
 // ---------------------------------------------------------------------------
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 static void launch_fwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
                          const sgs_outputs& out, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH, false>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds,
-                       s, ws, cams, n_cams, o, out, o.batch, nullptr);
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, false>), dim3((unsigned)ws.n_tiles),
+                       dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, out, o.batch, nullptr);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 static void launch_count_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
                            uint64_t* counts, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     sgs_outputs none = {};
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH, true>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds,
-                       s, ws, cams, n_cams, o, none, o.batch,
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, true>), dim3((unsigned)ws.n_tiles),
+                       dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, none, o.batch,
                        reinterpret_cast<unsigned long long*>(counts));
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
                          const sgs_outputs& fwd, const float* gi, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH>), dim3((unsigned)ws.n_tiles), dim3(TW * TH), lds, s, ws,
-                       cams, n_cams, o, fwd, gi, o.batch);
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT>), dim3((unsigned)ws.n_tiles), dim3(TW * TH / PPT),
+                       lds, s, ws, cams, n_cams, o, fwd, gi, o.batch);
 }
 
-#define SGS_TILE_SWITCH(F, ...)                                                   \
-    if (o.tile_w == 16 && o.tile_h == 16) F<16, 16>(__VA_ARGS__);                 \
-    else if (o.tile_w == 8 && o.tile_h == 8) F<8, 8>(__VA_ARGS__);                \
-    else if (o.tile_w == 16 && o.tile_h == 8) F<16, 8>(__VA_ARGS__);              \
-    else if (o.tile_w == 8 && o.tile_h == 16) F<8, 16>(__VA_ARGS__);              \
-    else if (o.tile_w == 32 && o.tile_h == 8) F<32, 8>(__VA_ARGS__);
+// supported (tile, pixels per thread): the block is a whole number of waves
+#define SGS_TILE_SWITCH(F, PPT_FWD, ...)                                             \
+    if (o.tile_w == 16 && o.tile_h == 16 && PPT_FWD == 1) F<16, 16, 1>(__VA_ARGS__);   \
+    else if (o.tile_w == 16 && o.tile_h == 16 && PPT_FWD == 2) F<16, 16, 2>(__VA_ARGS__); \
+    else if (o.tile_w == 16 && o.tile_h == 16 && PPT_FWD == 4) F<16, 16, 4>(__VA_ARGS__); \
+    else if (o.tile_w == 8 && o.tile_h == 8) F<8, 8, 1>(__VA_ARGS__);                 \
+    else if (o.tile_w == 16 && o.tile_h == 8 && PPT_FWD == 2) F<16, 8, 2>(__VA_ARGS__);   \
+    else if (o.tile_w == 16 && o.tile_h == 8) F<16, 8, 1>(__VA_ARGS__);               \
+    else if (o.tile_w == 8 && o.tile_h == 16 && PPT_FWD == 2) F<8, 16, 2>(__VA_ARGS__);   \
+    else if (o.tile_w == 8 && o.tile_h == 16) F<8, 16, 1>(__VA_ARGS__);               \
+    else if (o.tile_w == 32 && o.tile_h == 8 && PPT_FWD == 2) F<32, 8, 2>(__VA_ARGS__);   \
+    else if (o.tile_w == 32 && o.tile_h == 8 && PPT_FWD == 4) F<32, 8, 4>(__VA_ARGS__);   \
+    else if (o.tile_w == 32 && o.tile_h == 8) F<32, 8, 1>(__VA_ARGS__);
 
 void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                       const sgs_outputs& out, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_fwd_t, ws, dev_cams, n_cams, o, out, s)
+    SGS_TILE_SWITCH(launch_fwd_t, o.ppt, ws, dev_cams, n_cams, o, out, s)
 }
 
 void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                         uint64_t* counts, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_count_t, ws, dev_cams, n_cams, o, counts, s)
+    SGS_TILE_SWITCH(launch_count_t, o.ppt, ws, dev_cams, n_cams, o, counts, s)
 }
 
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                       const sgs_outputs& fwd, const float* grad_image, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_bwd_t, ws, dev_cams, n_cams, o, fwd, grad_image, s)
+    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, grad_image, s)
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,134 @@
+// Colour of eq. 9 in float32 and its derivative, shared by the forward
+// preprocess and the colour backward: rgb = 0.5 + SH(d) + sum_k a_k
+// exp(lambda_k (d.mu_k - 1)) with lambda = exp(log-sharpness) and mu the
+// normalised lobe axis (eqs. 4, 5, 9).
+#pragma once
+
+#include "common.hpp"
+#include "sh_basis.hpp"
+
+namespace sgs {
+
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)).
+// Returns false when a colour parameter is non-finite or a lobe axis has
+// zero length (the Gaussian is culled).
+template <int DEG>
+__device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
+                                       float rgb[3]) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    const int64_t n = p.n;
+    bool ok = true;
+    float Y[NC];
+    sh_eval<DEG, float>(d0, d1, d2, Y);
+    rgb[0] = rgb[1] = rgb[2] = 0.5f;
+#pragma unroll
+    for (int l = 0; l < NC; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float f = p.sh[((int64_t)l * 3 + c) * n + g];
+            ok = ok && isfinite(f);
+            rgb[c] = fmaf(f, Y[l], rgb[c]);
+        }
+    for (int k = 0; k < p.n_lobes; ++k) {
+        const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
+        const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
+        const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
+        const float ls = p.sg_log_sharpness[(int64_t)k * n + g];
+        const float a0 = p.sg_amplitudes[((int64_t)k * 3 + 0) * n + g];
+        const float a1 = p.sg_amplitudes[((int64_t)k * 3 + 1) * n + g];
+        const float a2 = p.sg_amplitudes[((int64_t)k * 3 + 2) * n + g];
+        ok = ok && isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(ls) &&
+             isfinite(a0) && isfinite(a1) && isfinite(a2);
+        const float mn2 = m0 * m0 + m1 * m1 + m2 * m2;
+        ok = ok && mn2 > 0.0f;
+        const float t = (d0 * m0 + d1 * m1 + d2 * m2) * rsqrtf(mn2) - 1.0f;
+        const float e = t == 0.0f ? 1.0f : fast_exp(fast_exp(ls) * t);
+        rgb[0] = fmaf(a0, e, rgb[0]);
+        rgb[1] = fmaf(a1, e, rgb[1]);
+        rgb[2] = fmaf(a2, e, rgb[2]);
+    }
+    return ok;
+}
+
+// Unit view direction from the camera centre (-R^T t) to the mean X: the
+// difference in float64 (no cancellation near the camera), the
+// normalisation in float32.  *dist receives |X - centre|.
+__device__ __forceinline__ void view_dir(const double X[3], const sgs_camera& cam, float d[3],
+                                         float* dist) {
+    const double c0 = -(((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1]) + (double)cam.R[6] * cam.t[2]);
+    const double c1 = -(((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1]) + (double)cam.R[7] * cam.t[2]);
+    const double c2 = -(((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1]) + (double)cam.R[8] * cam.t[2]);
+    const float e0 = (float)(X[0] - c0), e1 = (float)(X[1] - c1), e2 = (float)(X[2] - c2);
+    const float n2 = e0 * e0 + e1 * e1 + e2 * e2;
+    const float inv = rsqrtf(n2);
+    d[0] = e0 * inv;
+    d[1] = e1 * inv;
+    d[2] = e2 * inv;
+    *dist = n2 * inv;
+}
+
+// Backward of the colour.  grgb: dL/d(clamped rgb).  Adds the parameter
+// gradients into the accumulators and returns dL/dd (the view direction,
+// before the normalisation Jacobian).
+template <int DEG, int KMAX>
+__device__ __forceinline__ void colour_bwd(const Params& p, int64_t g, float d0, float d1, float d2,
+                                           const float grgb[3], float gsh[][3],
+                                           float gamp[][3], float gax[][3], float glsh[],
+                                           float gd[3]) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    const int64_t n = p.n;
+    float raw[3];
+    colour<DEG>(p, g, d0, d1, d2, raw);
+    // max(0, .): derivative 1 where the raw colour is >= 0
+    const float gc[3] = {raw[0] >= 0.0f ? grgb[0] : 0.0f, raw[1] >= 0.0f ? grgb[1] : 0.0f,
+                         raw[2] >= 0.0f ? grgb[2] : 0.0f};
+    float Y[NC], gx[NC], gy[NC], gz[NC];
+    sh_eval<DEG, float>(d0, d1, d2, Y);
+    sh_grad<DEG, float>(d0, d1, d2, gx, gy, gz);
+    gd[0] = gd[1] = gd[2] = 0.0f;
+#pragma unroll
+    for (int l = 0; l < NC; ++l) {
+        float cl = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gsh[l][c] = fmaf(gc[c], Y[l], gsh[l][c]);
+            cl = fmaf(gc[c], p.sh[((int64_t)l * 3 + c) * n + g], cl);
+        }
+        gd[0] = fmaf(cl, gx[l], gd[0]);
+        gd[1] = fmaf(cl, gy[l], gd[1]);
+        gd[2] = fmaf(cl, gz[l], gd[2]);
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k >= p.n_lobes) break;
+        const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
+        const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
+        const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
+        const float imn = rsqrtf(m0 * m0 + m1 * m1 + m2 * m2);
+        const float mu0 = m0 * imn, mu1 = m1 * imn, mu2 = m2 * imn;
+        const float lam = fast_exp(p.sg_log_sharpness[(int64_t)k * n + g]);
+        const float t = (d0 * m0 + d1 * m1 + d2 * m2) * imn - 1.0f;
+        const float e = t == 0.0f ? 1.0f : fast_exp(lam * t);
+        float sk = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gamp[k][c] = fmaf(gc[c], e, gamp[k][c]);
+            sk = fmaf(gc[c], p.sg_amplitudes[((int64_t)k * 3 + c) * n + g], sk);
+        }
+        sk *= e;
+        glsh[k] = fmaf(sk * t, lam, glsh[k]);
+        // d/dmu_hat = sk lam d, then (I - mu mu^T) / |m|
+        const float sl = sk * lam;
+        const float dot = sl * (mu0 * d0 + mu1 * d1 + mu2 * d2);
+        gax[k][0] += (sl * d0 - mu0 * dot) * imn;
+        gax[k][1] += (sl * d1 - mu1 * dot) * imn;
+        gax[k][2] += (sl * d2 - mu2 * dot) * imn;
+        gd[0] = fmaf(sl, mu0, gd[0]);
+        gd[1] = fmaf(sl, mu1, gd[1]);
+        gd[2] = fmaf(sl, mu2, gd[2]);
+    }
+}
+
+}  // namespace sgs

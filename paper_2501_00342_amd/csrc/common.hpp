@@ -25,6 +25,7 @@ constexpr int kDepthPasses = 4;                      // 32-bit depth keys
 enum Header : int {
     kHdrStatus = 0,
     kHdrPairs = 1,
+    kHdrVisible = 2,      // items left after culling (length of the depth order)
     kHdrWords = 16
 };
 
@@ -52,6 +53,7 @@ constexpr double kHalfLog2e = 0.72134752044448170368;
 
 struct Opts {
     int tile_w, tile_h, batch;
+    int ppt, ppt_bwd;
     float dilation, guard, alpha_min, alpha_max, t_min;
 };
 
@@ -86,6 +88,7 @@ struct Workspace {
     uint32_t* pair_values_alt;
     uint32_t* ranges;
     float* grad2d;
+    float* gx_colour;            // [3][n]: mean gradient through the view direction
     uint32_t* counts;            // radix pass: [256][partitions] digit counts -> offsets
     uint32_t* totals;            // radix pass: [256] digit totals
     uint32_t* pair_counts;       // pairs of each item, in depth order
@@ -95,6 +98,7 @@ struct Workspace {
     int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
     int dup_blocks;              // persistent grid of the duplicate kernel
     int tile_passes, tile_bits;
+    bool key16;                  // pair tile ids stored as u16 (at most 65536 tiles)
 };
 
 // launchers (defined in the .hip files)
@@ -103,10 +107,16 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
                   float guard, hipStream_t s);
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                        const Workspace& ws, int hist_blocks, hipStream_t s);
+// One stable pass.  With `drop_culled`, keys equal to 0xFFFFFFFF are removed
+// and the number of kept items is written to *kept_out.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
-                       uint32_t* pairs_out, int64_t n_rects, hipStream_t s);
+                       uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
+                       hipStream_t s);
+void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
+                         uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
+                         uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s);
 void launch_scan_pairs(const Workspace& ws, hipStream_t s);
 void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
 void launch_ranges(const Workspace& ws, hipStream_t s);

@@ -43,7 +43,7 @@ struct Plan {
     int64_t max_parts;
     // offsets not exported in sgs_layout
     size_t sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
-        pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial;
+        pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial, gx_colour;
 };
 
 bool tile_shape_ok(int tw, int th) {
@@ -68,9 +68,23 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     if (!tile_shape_ok(o.tile_w, o.tile_h))
         return fail(SGS_E_INVALID, "tile shape must be 16x16, 8x8, 16x8, 8x16 or 32x8");
     const int nt = o.tile_w * o.tile_h;
-    o.batch = oin && oin->batch ? oin->batch : nt;
-    if (o.batch < nt || o.batch % nt != 0 || o.batch > 1024)
-        return fail(SGS_E_INVALID, "batch must be a multiple of tile_w*tile_h, at most 1024");
+    // pixels per thread: the block (nt / ppt threads) must be whole waves
+    auto ppt_ok = [&](int ppt) {
+        if (ppt != 1 && ppt != 2 && ppt != 4) return false;
+        if (o.tile_h % ppt != 0 || (nt / ppt) % 64 != 0) return false;
+        return !(o.tile_w == 8 && o.tile_h == 8 && ppt != 1) &&
+               !((o.tile_w == 16 && o.tile_h == 8) && ppt == 4) &&
+               !((o.tile_w == 8 && o.tile_h == 16) && ppt == 4);
+    };
+    o.ppt = oin && oin->pixels_per_thread ? oin->pixels_per_thread : (ppt_ok(2) ? 2 : 1);
+    o.ppt_bwd = oin && oin->pixels_per_thread_bwd ? oin->pixels_per_thread_bwd
+                                                   : (ppt_ok(4) ? 4 : (ppt_ok(2) ? 2 : 1));
+    if (!ppt_ok(o.ppt) || !ppt_ok(o.ppt_bwd))
+        return fail(SGS_E_INVALID, "pixels_per_thread must be 1, 2 or 4 with tile_w*tile_h/ppt a "
+                                   "multiple of 64");
+    o.batch = oin && oin->batch ? oin->batch : 256;
+    if (o.batch < 64 || o.batch % 64 != 0 || o.batch > 1024)
+        return fail(SGS_E_INVALID, "batch must be a multiple of 64 in [64, 1024]");
     o.dilation = oin && oin->dilation != 0.0f ? oin->dilation : 0.3f;
     o.guard = oin && oin->guard != 0.0f ? oin->guard : 1.3f;
     o.alpha_min = oin && oin->alpha_min != 0.0f ? oin->alpha_min : 1.0f / 255.0f;
@@ -136,6 +150,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->pair_values_alt = take((size_t)cap * 4);
     L.ranges = take((size_t)tiles * 8);
     L.grad2d = take((size_t)items * 9 * 4);
+    pl->gx_colour = take((size_t)n * 3 * 4);
     pl->counts = take((size_t)pl->max_parts * sgs::kRadix * 4);
     pl->totals = take((size_t)sgs::kRadix * 4);
     pl->pair_counts = take((size_t)items * 4);
@@ -169,6 +184,7 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.pair_values_alt = reinterpret_cast<uint32_t*>(b + pl.pair_values_alt);
     w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
     w.grad2d = reinterpret_cast<float*>(b + L.grad2d);
+    w.gx_colour = reinterpret_cast<float*>(b + pl.gx_colour);
     w.counts = reinterpret_cast<uint32_t*>(b + pl.counts);
     w.totals = reinterpret_cast<uint32_t*>(b + pl.totals);
     w.pair_counts = reinterpret_cast<uint32_t*>(b + pl.pair_counts);
@@ -185,6 +201,7 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.dup_blocks = pl.dup_blocks;
     w.tile_passes = pl.tile_passes;
     w.tile_bits = pl.tile_bits;
+    w.key16 = L.n_tiles <= 65536;
     return w;
 }
 
@@ -306,11 +323,12 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         uint32_t* kout[4] = {ws.sort_keys_alt, ws.sort_keys_alt2, ws.sort_keys_alt, nullptr};
         uint32_t* vout[4] = {ws.sorted_items_alt, ws.sorted_items, ws.sorted_items_alt, ws.sorted_items};
         for (int ps = 0; ps < sgs::kDepthPasses; ++ps) {
-            const bool last = ps == sgs::kDepthPasses - 1;
-            sgs::launch_radix_pass(kin[ps], vin[ps], kout[ps], vout[ps], nullptr, ws.n_items,
+            const bool first = ps == 0, last = ps == sgs::kDepthPasses - 1;
+            sgs::launch_radix_pass(kin[ps], vin[ps], kout[ps], vout[ps],
+                                   first ? nullptr : ws.header + sgs::kHdrVisible, ws.n_items,
                                    ps * sgs::kRadixBits, ws.counts, ws.totals, pl.depth_parts,
                                    last ? ws.tile_rects : nullptr, last ? ws.pair_counts : nullptr,
-                                   ws.n_items, s);
+                                   ws.n_items, first, ws.header + sgs::kHdrVisible, s);
         }
         SGS_LAUNCHED();
         mk.mark(3);
@@ -349,9 +367,15 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         uint32_t* tv[2] = {wd.pair_values, wd.pair_values == ws.pair_values ? ws.pair_values_alt : ws.pair_values};
         for (int ps = 0; ps < pl.tile_passes; ++ps) {
             const int a = ps % 2, b = 1 - a;
-            sgs::launch_radix_pass(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs,
-                                   pair_capacity, ps * sgs::kRadixBits, ws.counts, ws.totals,
-                                   pl.pair_parts, nullptr, nullptr, 0, s);
+            if (ws.key16)
+                sgs::launch_radix_pass16(reinterpret_cast<const uint16_t*>(tk[a]), tv[a],
+                                         reinterpret_cast<uint16_t*>(tk[b]), tv[b],
+                                         ws.header + sgs::kHdrPairs, pair_capacity,
+                                         ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts, s);
+            else
+                sgs::launch_radix_pass(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs,
+                                       pair_capacity, ps * sgs::kRadixBits, ws.counts, ws.totals,
+                                       pl.pair_parts, nullptr, nullptr, 0, false, nullptr, s);
         }
         SGS_LAUNCHED();
         mk.mark(6);
@@ -445,6 +469,7 @@ int render_read_keys(const void* workspace, const sgs_layout* layout, int64_t co
     ws.pair_values = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->pair_values);
     ws.depth_keys = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->depth_keys);
     ws.n_items = layout->n_items;
+    ws.key16 = layout->n_tiles <= 65536;
     (void)hipGetLastError();
     sgs::launch_read_keys(ws, count, keys_out, static_cast<hipStream_t>(stream));
     SGS_LAUNCHED();

@@ -16,7 +16,7 @@
 // loads; outputs are one 64-byte record, a depth key and a packed tile
 // rectangle per (camera, Gaussian).
 #include "common.hpp"
-#include "sh_basis.hpp"
+#include "colour.hpp"
 
 namespace sgs {
 
@@ -120,49 +120,6 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     return r;
 }
 
-__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
-
-// colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)).
-// Returns false when a colour parameter is non-finite or a lobe axis has
-// zero length (the Gaussian is culled).
-template <int DEG>
-__device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
-                                       float rgb[3]) {
-    constexpr int NC = (DEG + 1) * (DEG + 1);
-    const int64_t n = p.n;
-    bool ok = true;
-    float Y[NC];
-    sh_eval<DEG, float>(d0, d1, d2, Y);
-    rgb[0] = rgb[1] = rgb[2] = 0.5f;
-#pragma unroll
-    for (int l = 0; l < NC; ++l)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float f = p.sh[((int64_t)l * 3 + c) * n + g];
-            ok = ok && isfinite(f);
-            rgb[c] = fmaf(f, Y[l], rgb[c]);
-        }
-    for (int k = 0; k < p.n_lobes; ++k) {
-        const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
-        const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
-        const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
-        const float ls = p.sg_log_sharpness[(int64_t)k * n + g];
-        const float a0 = p.sg_amplitudes[((int64_t)k * 3 + 0) * n + g];
-        const float a1 = p.sg_amplitudes[((int64_t)k * 3 + 1) * n + g];
-        const float a2 = p.sg_amplitudes[((int64_t)k * 3 + 2) * n + g];
-        ok = ok && isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(ls) &&
-             isfinite(a0) && isfinite(a1) && isfinite(a2);
-        const float mn2 = m0 * m0 + m1 * m1 + m2 * m2;
-        ok = ok && mn2 > 0.0f;
-        const float t = (d0 * m0 + d1 * m1 + d2 * m2) * rsqrtf(mn2) - 1.0f;
-        const float e = t == 0.0f ? 1.0f : fast_exp(fast_exp(ls) * t);
-        rgb[0] = fmaf(a0, e, rgb[0]);
-        rgb[1] = fmaf(a1, e, rgb[1]);
-        rgb[2] = fmaf(a2, e, rgb[2]);
-    }
-    return ok;
-}
-
 template <int DEG>
 __global__ void __launch_bounds__(kPreThreads)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
@@ -192,13 +149,9 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             bool vis = finite && geo.visible;
             float rgb[3] = {0.0f, 0.0f, 0.0f};
             if (vis) {
-                // view direction: camera centre -> mean, centre = -R^T t
-                const double cc0 = -(((double)cam.R[0] * cam.t[0] + (double)cam.R[3] * cam.t[1]) + (double)cam.R[6] * cam.t[2]);
-                const double cc1 = -(((double)cam.R[1] * cam.t[0] + (double)cam.R[4] * cam.t[1]) + (double)cam.R[7] * cam.t[2]);
-                const double cc2 = -(((double)cam.R[2] * cam.t[0] + (double)cam.R[5] * cam.t[1]) + (double)cam.R[8] * cam.t[2]);
-                const double e0 = X[0] - cc0, e1 = X[1] - cc1, e2 = X[2] - cc2;
-                const double idn = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                vis = colour<DEG>(p, g, (float)(e0 * idn), (float)(e1 * idn), (float)(e2 * idn), rgb);
+                float d[3], dist;
+                view_dir(X, cam, d, &dist);
+                vis = colour<DEG>(p, g, d[0], d[1], d[2], rgb);
             }
             uint32_t key = 0xFFFFFFFFu;
             uint64_t trect = 1;  // tx0 = 1 > tx1 = 0: no pairs
@@ -222,24 +175,25 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
                     v0 = B;
                     v1 = geo.lam1 - A;
                 }
-                const double vn2 = v0 * v0 + v1 * v1;
-                if (vn2 > 0.0) {
-                    const double ivn = 1.0 / sqrt(vn2);
-                    v0 *= ivn;
-                    v1 *= ivn;
+                // eigenvector of lambda_1 (difference in float64, normalised in float32)
+                float f0 = (float)v0, f1 = (float)v1;
+                const float fn2 = f0 * f0 + f1 * f1;
+                if (fn2 > 0.0f) {
+                    const float ivn = rsqrtf(fn2);
+                    f0 *= ivn;
+                    f1 *= ivn;
                 } else {
-                    v0 = 1.0;
-                    v1 = 0.0;
+                    f0 = 1.0f;
+                    f1 = 0.0f;
                 }
-                const double k1 = sqrt(kHalfLog2e * il1);
-                const double k2 = sqrt(kHalfLog2e / lam2);
+                const float k1 = sqrtf((float)(kHalfLog2e * il1));
+                const float k2 = sqrtf((float)(kHalfLog2e / lam2));
                 const float u_hi = (float)geo.u, v_hi = (float)geo.v;
                 float4* dst = reinterpret_cast<float4*>(ws.records + item);
                 // layout of Rec: u_hi v_hi u_lo v_lo | w1 w2 | opacity rgb | z rect_x rect_y radius
                 dst[0] = make_float4(u_hi, v_hi, (float)(geo.u - (double)u_hi),
                                      (float)(geo.v - (double)v_hi));
-                dst[1] = make_float4((float)(v0 * k1), (float)(v1 * k1), (float)(-v1 * k2),
-                                     (float)(v0 * k2));
+                dst[1] = make_float4(f0 * k1, f1 * k1, -f1 * k2, f0 * k2);
                 dst[2] = make_float4(opacity, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f),
                                      fmaxf(rgb[2], 0.0f));
                 dst[3] = make_float4(zf, __uint_as_float((uint32_t)geo.px0 | ((uint32_t)geo.px1 << 16)),

@@ -1,172 +1,136 @@
-// Backward preprocess: one thread per Gaussian, summing over cameras.
+// Backward preprocess: chain rule from the per-item 2D gradients to every
+// raw parameter, one thread per Gaussian summing over cameras, in two
+// kernels so that neither holds both live sets (no register spills):
 //
-// Input: the 2D gradients of each (camera, Gaussian) item w.r.t. the
-// projected mean (u, v), the conic Q = Sigma'^-1 (Qa, Qb, Qc), the opacity
-// and the clamped colour.  Output: gradients of every raw parameter,
-// written once (no atomics).  The chain rule runs through
-//   conic -> Sigma' (dQ = -Q dSigma' Q),
-//   Sigma' = M M^T + dilation I, M = J W R S   (eq. 3 and the EWA step),
-//   J and (u, v) -> camera-space mean (no derivative through the guard
-//   clamp where it is active),
-//   colour eq. 9 -> SH coefficients (eq. 4), SG amplitude, sharpness and
-//   axis (eq. 5), and the view direction -> mean,
-//   activations exp / sigmoid and the normalisations of q and mu.
-// Float64 arithmetic: the kernel is bound by memory traffic.
-#include "common.hpp"
-#include "sh_basis.hpp"
+//   k_colour_bwd<DEG> (float32): colour eq. 9 -> SH coefficients (eq. 4),
+//     SG amplitude, log-sharpness and axis (eq. 5), and the part of the
+//     mean's gradient that flows through the view direction; the latter is
+//     left in a [3][n] scratch row of the workspace.
+//   k_geom_bwd (float64): conic Q = Sigma'^-1 -> Sigma' (dQ = -Q dSigma' Q),
+//     Sigma' = M M^T + dilation I with M = J W R S (eq. 3 and the EWA step),
+//     J and the projected mean -> camera-space mean (no derivative through
+//     the guard clamp where it is active), opacity sigmoid, scale exp and
+//     quaternion normalisation; adds the colour part of the mean gradient.
+// Both write their outputs once (no atomics, no accumulation across calls).
+#include "colour.hpp"
 
 namespace sgs {
 
-template <int DEG>
+__device__ __forceinline__ bool item_visible(const Workspace& ws, int64_t item) {
+    const uint64_t tr = ws.tile_rects[item];
+    return (int)((tr >> 16) & 0xFFFF) >= (int)(tr & 0xFFFF);
+}
+
+template <int DEG, int KMAX>
 __global__ void __launch_bounds__(kPreThreads)
-k_preprocess_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws,
-                 sgs_grads gr) {
+k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspace ws,
+             sgs_grads gr, float* __restrict__ gx_colour) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     const int64_t n = p.n;
-    const int K = p.n_lobes;
     const int64_t M = ws.n_items;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
          g += (int64_t)gridDim.x * blockDim.x) {
-        double X[3], ls[3], q[4];
-        for (int c = 0; c < 3; ++c) {
-            X[c] = p.means[c * n + g];
-            ls[c] = p.log_scales[c * n + g];
+        float gsh[NC][3];
+        float gamp[KMAX + 1][3], gax[KMAX + 1][3], glsh[KMAX + 1];
+#pragma unroll
+        for (int l = 0; l < NC; ++l) gsh[l][0] = gsh[l][1] = gsh[l][2] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KMAX + 1; ++k) {
+            glsh[k] = 0.0f;
+            gamp[k][0] = gamp[k][1] = gamp[k][2] = 0.0f;
+            gax[k][0] = gax[k][1] = gax[k][2] = 0.0f;
         }
-        for (int c = 0; c < 4; ++c) q[c] = p.quats[c * n + g];
-        const double logit = p.opacity_logits[g];
-        const double sig = 1.0 / (1.0 + exp(-logit));
-        const double s[3] = {exp(ls[0]), exp(ls[1]), exp(ls[2])};
-        const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        float gX[3] = {0.0f, 0.0f, 0.0f};
+        const double X[3] = {p.means[g], p.means[n + g], p.means[2 * n + g]};
+        for (int ci = 0; ci < n_cams; ++ci) {
+            const int64_t item = (int64_t)ci * n + g;
+            if (!item_visible(ws, item)) continue;
+            const float grgb[3] = {ws.grad2d[6 * M + item], ws.grad2d[7 * M + item],
+                                   ws.grad2d[8 * M + item]};
+            float d[3], dist;
+            view_dir(X, cams[ci], d, &dist);
+            float gd[3];
+            colour_bwd<DEG, KMAX>(p, g, d[0], d[1], d[2], grgb, gsh, gamp, gax, glsh, gd);
+            // through d = (X - c) / |X - c|: (I - d d^T) / |X - c|
+            const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+            const float inv = 1.0f / dist;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gX[c] += (gd[c] - d[c] * dd) * inv;
+        }
+#pragma unroll
+        for (int l = 0; l < NC; ++l)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gr.sh[((int64_t)l * 3 + c) * n + g] = gsh[l][c];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k >= p.n_lobes) break;
+            for (int c = 0; c < 3; ++c) {
+                gr.sg_axes[((int64_t)k * 3 + c) * n + g] = gax[k][c];
+                gr.sg_amplitudes[((int64_t)k * 3 + c) * n + g] = gamp[k][c];
+            }
+            gr.sg_log_sharpness[(int64_t)k * n + g] = glsh[k];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gx_colour[c * n + g] = gX[c];
+    }
+}
+
+__global__ void __launch_bounds__(kPreThreads)
+k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws,
+           sgs_grads gr, const float* __restrict__ gx_colour) {
+    const int64_t n = p.n;
+    const int64_t M = ws.n_items;
+    const double dil = o.dilation;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        double gX[3] = {0.0, 0.0, 0.0}, gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
+        double glogit = 0.0;
+        const double X[3] = {p.means[g], p.means[n + g], p.means[2 * n + g]};
+        const double s[3] = {exp((double)p.log_scales[g]), exp((double)p.log_scales[n + g]),
+                             exp((double)p.log_scales[2 * n + g])};
+        const double q[4] = {p.quats[g], p.quats[n + g], p.quats[2 * n + g], p.quats[3 * n + g]};
+        const double iq = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
         const double Rq[3][3] = {
             {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
             {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
             {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-        double M3[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int a = 0; a < 3; ++a) M3[i][a] = Rq[i][a] * s[a];
-
-        // accumulators (sum over cameras)
-        double gX[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
-        float gsh[NC][3];
-        for (int l = 0; l < NC; ++l) gsh[l][0] = gsh[l][1] = gsh[l][2] = 0.0f;
-        float gamp[SGS_MAX_LOBES][3], gax[SGS_MAX_LOBES][3], glsh[SGS_MAX_LOBES];
-#pragma unroll
-        for (int k = 0; k < SGS_MAX_LOBES; ++k) {
-            glsh[k] = 0.0f;
-            for (int c = 0; c < 3; ++c) gamp[k][c] = gax[k][c] = 0.0f;
-        }
-
+        const double sig = 1.0 / (1.0 + exp(-(double)p.opacity_logits[g]));
+        bool any = false;
         for (int ci = 0; ci < n_cams; ++ci) {
             const int64_t item = (int64_t)ci * n + g;
-            const uint64_t tr = ws.tile_rects[item];
-            if ((int)((tr >> 16) & 0xFFFF) < (int)(tr & 0xFFFF)) continue;   // culled
+            if (!item_visible(ws, item)) continue;
+            any = true;
             const sgs_camera& cam = cams[ci];
-            const double g2[9] = {ws.grad2d[0 * M + item], ws.grad2d[1 * M + item],
-                                  ws.grad2d[2 * M + item], ws.grad2d[3 * M + item],
-                                  ws.grad2d[4 * M + item], ws.grad2d[5 * M + item],
-                                  ws.grad2d[6 * M + item], ws.grad2d[7 * M + item],
-                                  ws.grad2d[8 * M + item]};
-            double Rc[3][3];
-            for (int i = 0; i < 3; ++i)
-                for (int k = 0; k < 3; ++k) Rc[i][k] = cam.R[3 * i + k];
+            const CamTable ct = ws.cams[ci];
+            const double gu = ws.grad2d[item], gv = ws.grad2d[M + item];
+            const double gQa = ws.grad2d[2 * M + item], gQb = ws.grad2d[3 * M + item];
+            const double gQc = ws.grad2d[4 * M + item];
+            glogit += (double)ws.grad2d[5 * M + item] * sig * (1.0 - sig);
             const double fx = cam.fx, fy = cam.fy;
             double xc[3];
             for (int i = 0; i < 3; ++i)
-                xc[i] = Rc[i][0] * X[0] + Rc[i][1] * X[1] + Rc[i][2] * X[2] + (double)cam.t[i];
-
-            // ---- opacity
-            glogit += g2[5] * sig * (1.0 - sig);
-
-            // ---- colour
-            double cc[3];
-            for (int j = 0; j < 3; ++j)
-                cc[j] = -(Rc[0][j] * cam.t[0] + Rc[1][j] * cam.t[1] + Rc[2][j] * cam.t[2]);
-            double dv[3] = {X[0] - cc[0], X[1] - cc[1], X[2] - cc[2]};
-            const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-            const double d[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
-            double Y[NC];
-            sh_eval<DEG, double>(d[0], d[1], d[2], Y);
-            double raw[3];
-            for (int c = 0; c < 3; ++c) {
-                double acc = 0.5;
-                for (int l = 0; l < NC; ++l) acc += (double)p.sh[((int64_t)l * 3 + c) * n + g] * Y[l];
-                raw[c] = acc;
+                xc[i] = (double)cam.R[3 * i] * X[0] + (double)cam.R[3 * i + 1] * X[1] +
+                        (double)cam.R[3 * i + 2] * X[2] + (double)cam.t[i];
+            const double iz = 1.0 / xc[2];
+            const double xn = xc[0] * iz, yn = xc[1] * iz;
+            const bool clx = xn < -ct.limx || xn > ct.limx;
+            const bool cly = yn < -ct.limy || yn > ct.limy;
+            const double xnc = fmin(fmax(xn, -ct.limx), ct.limx);
+            const double ync = fmin(fmax(yn, -ct.limy), ct.limy);
+            const double J00 = fx * iz, J02 = -(fx * xnc) * iz;
+            const double J11 = fy * iz, J12 = -(fy * ync) * iz;
+            // T2 = J W
+            double T2[2][3];
+            for (int k = 0; k < 3; ++k) {
+                T2[0][k] = J00 * (double)cam.R[k] + J02 * (double)cam.R[6 + k];
+                T2[1][k] = J11 * (double)cam.R[3 + k] + J12 * (double)cam.R[6 + k];
             }
-            double lam[SGS_MAX_LOBES], ek[SGS_MAX_LOBES], cosk[SGS_MAX_LOBES], mlen[SGS_MAX_LOBES];
-#pragma unroll
-            for (int k = 0; k < SGS_MAX_LOBES; ++k) {
-                if (k >= K) break;
-                const double m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
-                const double m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
-                const double m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
-                mlen[k] = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
-                lam[k] = exp((double)p.sg_log_sharpness[(int64_t)k * n + g]);
-                cosk[k] = (d[0] * m0 + d[1] * m1 + d[2] * m2) / mlen[k];
-                ek[k] = cosk[k] - 1.0 == 0.0 ? 1.0 : exp(lam[k] * (cosk[k] - 1.0));
-                for (int c = 0; c < 3; ++c)
-                    raw[c] += (double)p.sg_amplitudes[((int64_t)k * 3 + c) * n + g] * ek[k];
-            }
-            const double grgb[3] = {raw[0] >= 0.0 ? g2[6] : 0.0, raw[1] >= 0.0 ? g2[7] : 0.0,
-                                    raw[2] >= 0.0 ? g2[8] : 0.0};
-            for (int l = 0; l < NC; ++l)
-                for (int c = 0; c < 3; ++c) gsh[l][c] += (float)(grgb[c] * Y[l]);
-            double gd[3] = {0, 0, 0};
-            {
-                double gx[NC], gy[NC], gz[NC];
-                sh_grad<DEG>(d[0], d[1], d[2], gx, gy, gz);
-                for (int l = 0; l < NC; ++l) {
-                    double cl = 0.0;
-                    for (int c = 0; c < 3; ++c) cl += grgb[c] * (double)p.sh[((int64_t)l * 3 + c) * n + g];
-                    gd[0] += cl * gx[l];
-                    gd[1] += cl * gy[l];
-                    gd[2] += cl * gz[l];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < SGS_MAX_LOBES; ++k) {
-                if (k >= K) break;
-                double sk = 0.0;
-                for (int c = 0; c < 3; ++c) {
-                    const int64_t ia = ((int64_t)k * 3 + c) * n + g;
-                    gamp[k][c] += (float)(grgb[c] * ek[k]);
-                    sk += grgb[c] * (double)p.sg_amplitudes[ia];
-                }
-                sk *= ek[k];
-                glsh[k] += (float)(sk * (cosk[k] - 1.0) * lam[k]);
-                const double mu[3] = {p.sg_axes[((int64_t)k * 3 + 0) * n + g] / mlen[k],
-                                      p.sg_axes[((int64_t)k * 3 + 1) * n + g] / mlen[k],
-                                      p.sg_axes[((int64_t)k * 3 + 2) * n + g] / mlen[k]};
-                const double gm[3] = {sk * lam[k] * d[0], sk * lam[k] * d[1], sk * lam[k] * d[2]};
-                const double dot = mu[0] * gm[0] + mu[1] * gm[1] + mu[2] * gm[2];
-                for (int c = 0; c < 3; ++c) {
-                    gax[k][c] += (float)((gm[c] - mu[c] * dot) / mlen[k]);
-                    gd[c] += sk * lam[k] * mu[c];
-                }
-            }
-            {
-                const double dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
-                for (int c = 0; c < 3; ++c) gX[c] += (gd[c] - d[c] * dd) / dist;
-            }
-
-            // ---- geometry: recompute the forward chain
-            const double zc = xc[2];
-            const double xn = xc[0] / zc, yn = xc[1] / zc;
-            const double limx = (double)o.guard * ((0.5 * cam.width) / fx);
-            const double limy = (double)o.guard * ((0.5 * cam.height) / fy);
-            const bool clx = xn < -limx || xn > limx;
-            const bool cly = yn < -limy || yn > limy;
-            const double xnc = fmin(fmax(xn, -limx), limx);
-            const double ync = fmin(fmax(yn, -limy), limy);
-            const double J[2][3] = {{fx / zc, 0.0, -(fx * xnc) / zc}, {0.0, fy / zc, -(fy * ync) / zc}};
-            double T2[2][3], Mm[2][3];
-            for (int i = 0; i < 2; ++i)
-                for (int k = 0; k < 3; ++k)
-                    T2[i][k] = J[i][0] * Rc[0][k] + J[i][1] * Rc[1][k] + J[i][2] * Rc[2][k];
+            // M = T2 R diag(s)
+            double Mm[2][3];
             for (int i = 0; i < 2; ++i)
                 for (int a = 0; a < 3; ++a)
-                    Mm[i][a] = T2[i][0] * M3[0][a] + T2[i][1] * M3[1][a] + T2[i][2] * M3[2][a];
-            const double dil = o.dilation;
+                    Mm[i][a] = (T2[i][0] * Rq[0][a] + T2[i][1] * Rq[1][a] + T2[i][2] * Rq[2][a]) * s[a];
             const double pp = Mm[0][0] * Mm[0][0] + Mm[0][1] * Mm[0][1] + Mm[0][2] * Mm[0][2];
             const double qq = Mm[1][0] * Mm[1][0] + Mm[1][1] * Mm[1][1] + Mm[1][2] * Mm[1][2];
             const double A = pp + dil, C = qq + dil;
@@ -175,91 +139,71 @@ k_preprocess_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts
             const double cry = Mm[0][2] * Mm[1][0] - Mm[0][0] * Mm[1][2];
             const double crz = Mm[0][0] * Mm[1][1] - Mm[0][1] * Mm[1][0];
             const double det = crx * crx + cry * cry + crz * crz + dil * (pp + qq) + dil * dil;
+            const double id2 = 1.0 / (det * det);
             // conic -> Sigma'
-            const double gQa = g2[2], gQb = g2[3], gQc = g2[4];
-            const double d2 = det * det;
-            const double gA = (-C * C * gQa + B * C * gQb - B * B * gQc) / d2;
-            const double gC = (-B * B * gQa + A * B * gQb - A * A * gQc) / d2;
-            const double gB = (2.0 * B * C * gQa - (A * C + B * B) * gQb + 2.0 * A * B * gQc) / d2;
-            // Sigma' = M M^T + dil I
+            const double gA = (-C * C * gQa + B * C * gQb - B * B * gQc) * id2;
+            const double gC = (-B * B * gQa + A * B * gQb - A * A * gQc) * id2;
+            const double gB = (2.0 * B * C * gQa - (A * C + B * B) * gQb + 2.0 * A * B * gQc) * id2;
+            // Sigma' = M M^T + dil I -> M
             double gM[2][3];
             for (int a = 0; a < 3; ++a) {
                 gM[0][a] = 2.0 * gA * Mm[0][a] + gB * Mm[1][a];
                 gM[1][a] = gB * Mm[0][a] + 2.0 * gC * Mm[1][a];
             }
-            // M = T2 M3
-            double gT2[2][3], gM3[3][3];
-            for (int i = 0; i < 2; ++i)
-                for (int k = 0; k < 3; ++k)
-                    gT2[i][k] = gM[i][0] * M3[k][0] + gM[i][1] * M3[k][1] + gM[i][2] * M3[k][2];
-            for (int k = 0; k < 3; ++k)
-                for (int a = 0; a < 3; ++a) gM3[k][a] = T2[0][k] * gM[0][a] + T2[1][k] * gM[1][a];
-            // M3 = Rq diag(s)
-            double gR[3][3];
-            for (int i = 0; i < 3; ++i)
-                for (int a = 0; a < 3; ++a) gR[i][a] = gM3[i][a] * s[a];
-            for (int a = 0; a < 3; ++a)
-                gls[a] += (gM3[0][a] * Rq[0][a] + gM3[1][a] * Rq[1][a] + gM3[2][a] * Rq[2][a]) * s[a];
-            const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] -
-                                     y * gR[2][0] + x * gR[2][1]);
-            const double gxq = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] -
-                                      w * gR[1][2] + z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
-            const double gyq = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] +
-                                      z * gR[1][2] - w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
-            const double gzq = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] -
-                                      2.0 * z * gR[1][1] + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
-            gq[0] += gw;
-            gq[1] += gxq;
-            gq[2] += gyq;
-            gq[3] += gzq;
-            // T2 = J W -> J
-            double gJ[2][3];
-            for (int i = 0; i < 2; ++i)
-                for (int m = 0; m < 3; ++m)
-                    gJ[i][m] = gT2[i][0] * Rc[m][0] + gT2[i][1] * Rc[m][1] + gT2[i][2] * Rc[m][2];
-            // J, (u, v) -> camera-space mean
-            const double z2 = zc * zc;
-            double gxc[3] = {0.0, 0.0, 0.0};
-            gxc[2] += gJ[0][0] * (-fx / z2) + gJ[1][1] * (-fy / z2);
+            // M[i][a] = (T2 R)[i][a] s[a]: to log s, to R (then q), to T2 (then J)
+            double gR[3][3], gT2[2][3] = {{0, 0, 0}, {0, 0, 0}};
+            for (int a = 0; a < 3; ++a) {
+                gls[a] += gM[0][a] * Mm[0][a] + gM[1][a] * Mm[1][a];
+                const double ga0 = gM[0][a] * s[a], ga1 = gM[1][a] * s[a];
+                for (int m = 0; m < 3; ++m) {
+                    gR[m][a] = T2[0][m] * ga0 + T2[1][m] * ga1;
+                    gT2[0][m] += ga0 * Rq[m][a];
+                    gT2[1][m] += ga1 * Rq[m][a];
+                }
+            }
+            gq[0] += 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] -
+                            y * gR[2][0] + x * gR[2][1]);
+            gq[1] += 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] -
+                            w * gR[1][2] + z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
+            gq[2] += 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] +
+                            z * gR[1][2] - w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
+            gq[3] += 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] -
+                            2.0 * z * gR[1][1] + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+            // T2 = J W -> J entries
+            double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+            for (int k = 0; k < 3; ++k) {
+                gJ00 += gT2[0][k] * (double)cam.R[k];
+                gJ02 += gT2[0][k] * (double)cam.R[6 + k];
+                gJ11 += gT2[1][k] * (double)cam.R[3 + k];
+                gJ12 += gT2[1][k] * (double)cam.R[6 + k];
+            }
+            // J and (u, v) -> camera-space mean
+            const double iz2 = iz * iz;
+            double g0 = gu * fx * iz, g1 = gv * fy * iz;
+            double g2 = -(gJ00 * fx + gJ11 * fy) * iz2 - (gu * fx * xc[0] + gv * fy * xc[1]) * iz2;
             if (clx) {
-                gxc[2] += gJ[0][2] * (fx * xnc / z2);
+                g2 += gJ02 * fx * xnc * iz2;
             } else {
-                gxc[0] += gJ[0][2] * (-fx / z2);
-                gxc[2] += gJ[0][2] * (2.0 * fx * xc[0] / (z2 * zc));
+                g0 += -gJ02 * fx * iz2;
+                g2 += 2.0 * gJ02 * fx * xc[0] * iz2 * iz;
             }
             if (cly) {
-                gxc[2] += gJ[1][2] * (fy * ync / z2);
+                g2 += gJ12 * fy * ync * iz2;
             } else {
-                gxc[1] += gJ[1][2] * (-fy / z2);
-                gxc[2] += gJ[1][2] * (2.0 * fy * xc[1] / (z2 * zc));
+                g1 += -gJ12 * fy * iz2;
+                g2 += 2.0 * gJ12 * fy * xc[1] * iz2 * iz;
             }
-            const double gu = g2[0], gv = g2[1];
-            gxc[0] += gu * fx / zc;
-            gxc[1] += gv * fy / zc;
-            gxc[2] += -gu * fx * xc[0] / z2 - gv * fy * xc[1] / z2;
-            for (int j = 0; j < 3; ++j) gX[j] += Rc[0][j] * gxc[0] + Rc[1][j] * gxc[1] + Rc[2][j] * gxc[2];
+            for (int j = 0; j < 3; ++j)
+                gX[j] += (double)cam.R[j] * g0 + (double)cam.R[3 + j] * g1 + (double)cam.R[6 + j] * g2;
         }
-
-        // quaternion normalisation: (I - q q^T) / |q|
+        const double dq = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
         const double qh[4] = {w, x, y, z};
-        const double dq = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
         for (int c = 0; c < 3; ++c) {
-            gr.means[c * n + g] = (float)gX[c];
+            gr.means[c * n + g] = (float)(gX[c] + (any ? (double)gx_colour[c * n + g] : 0.0));
             gr.log_scales[c * n + g] = (float)gls[c];
         }
-        for (int c = 0; c < 4; ++c) gr.quats[c * n + g] = (float)((gq[c] - qh[c] * dq) / qn);
+        for (int c = 0; c < 4; ++c) gr.quats[c * n + g] = (float)((gq[c] - qh[c] * dq) * iq);
         gr.opacity_logits[g] = (float)glogit;
-        for (int l = 0; l < NC; ++l)
-            for (int c = 0; c < 3; ++c) gr.sh[((int64_t)l * 3 + c) * n + g] = gsh[l][c];
-#pragma unroll
-        for (int k = 0; k < SGS_MAX_LOBES; ++k) {
-            if (k >= K) break;
-            for (int c = 0; c < 3; ++c) {
-                gr.sg_axes[((int64_t)k * 3 + c) * n + g] = gax[k][c];
-                gr.sg_amplitudes[((int64_t)k * 3 + c) * n + g] = gamp[k][c];
-            }
-            gr.sg_log_sharpness[(int64_t)k * n + g] = glsh[k];
-        }
     }
 }
 
@@ -269,12 +213,18 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     int64_t blocks = (p.n + kPreThreads - 1) / kPreThreads;
     if (blocks > 4096) blocks = 4096;
     dim3 grid((unsigned)blocks), block(kPreThreads);
+    float* gxc = ws.gx_colour;
+#define SGS_COLOUR_BWD(D, K)                                                                   \
+    hipLaunchKernelGGL((k_colour_bwd<D, K>), grid, block, 0, s, p, dev_cams, n_cams, ws, gr, gxc)
+    const bool few = p.n_lobes <= 4;
     switch (p.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr); break;
-        case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr); break;
-        case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr); break;
-        default: hipLaunchKernelGGL(k_preprocess_bwd<3>, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr); break;
+        case 0: if (few) SGS_COLOUR_BWD(0, 4); else SGS_COLOUR_BWD(0, 8); break;
+        case 1: if (few) SGS_COLOUR_BWD(1, 4); else SGS_COLOUR_BWD(1, 8); break;
+        case 2: if (few) SGS_COLOUR_BWD(2, 4); else SGS_COLOUR_BWD(2, 8); break;
+        default: if (few) SGS_COLOUR_BWD(3, 4); else SGS_COLOUR_BWD(3, 8); break;
     }
+#undef SGS_COLOUR_BWD
+    hipLaunchKernelGGL(k_geom_bwd, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr, gxc);
 }
 
 }  // namespace sgs

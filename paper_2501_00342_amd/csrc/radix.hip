@@ -9,7 +9,9 @@
 //               digit order and writes each digit run to
 //               sum_{d' < d} total(d') + counts[d][p] + local rank,
 //               so a partition's stores of one digit are contiguous.
-// The downsweep of the last depth pass also writes, in sorted order, the
+// The first depth pass drops culled items (depth key 0xFFFFFFFF), so the
+// later passes and everything after them see only the visible items.  The
+// downsweep of the last depth pass also writes, in sorted order, the
 // number of (tile, Gaussian) pairs of each item; the scan below turns
 // those into pair offsets.
 #include "common.hpp"
@@ -31,9 +33,10 @@ __device__ __forceinline__ uint32_t rect_pairs(uint64_t r) {
 
 // ---------------------------------------------------------------------------
 
+template <typename KeyT>
 __global__ void __launch_bounds__(kSortThreads)
-k_upsweep(const uint32_t* __restrict__ keys, const uint32_t* count_ptr, int64_t count_host,
-          int shift, uint32_t* __restrict__ counts, int64_t parts) {
+k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t count_host,
+          int shift, uint32_t* __restrict__ counts, int64_t parts, bool drop) {
     constexpr int WAVES = kSortThreads / 64;
     __shared__ uint32_t hist[WAVES][kRadix];
     const int tid = threadIdx.x, wave = tid >> 6;
@@ -45,7 +48,10 @@ k_upsweep(const uint32_t* __restrict__ keys, const uint32_t* count_ptr, int64_t 
 #pragma unroll 4
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = base + (int64_t)k * kSortThreads + tid;
-        if (i < count) atomicAdd(&hist[wave][(keys[i] >> shift) & (kRadix - 1)], 1u);
+        if (i < count) {
+            const uint32_t key = keys[i];
+            if (!drop || key != 0xFFFFFFFFu) atomicAdd(&hist[wave][(key >> shift) & (kRadix - 1)], 1u);
+        }
     }
     __syncthreads();
     const int d = tid;
@@ -57,7 +63,8 @@ k_upsweep(const uint32_t* __restrict__ keys, const uint32_t* count_ptr, int64_t 
 
 // block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row sum
 __global__ void __launch_bounds__(256)
-k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__ totals) {
+k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__ totals,
+            uint32_t* kept_out) {
     __shared__ uint32_t s[256];
     const int tid = threadIdx.x;
     uint32_t* row = counts + (int64_t)blockIdx.x * parts;
@@ -88,15 +95,20 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
         carry += s[255];
         __syncthreads();
     }
-    if (tid == 0) totals[blockIdx.x] = carry;
+    if (tid == 0) {
+        totals[blockIdx.x] = carry;
+        if (kept_out) atomicAdd(kept_out, carry);
+    }
 }
 
+template <typename KeyT>
 __global__ void __launch_bounds__(kSortThreads)
-k_downsweep(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-            uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+            KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
             const uint32_t* count_ptr, int64_t count_host, int shift,
             const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int64_t parts,
-            const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out, int64_t n_rects) {
+            const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out, int64_t n_rects,
+            bool drop) {
     constexpr int WAVES = kSortThreads / 64;
     constexpr int WAVE_ITEMS = 64 * kSortItems;
     __shared__ uint32_t s_keys[kSortTile];
@@ -104,6 +116,7 @@ k_downsweep(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ v
     __shared__ uint32_t s_wave[WAVES][kRadix];
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_global[kRadix];
+    __shared__ uint32_t s_kept;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t p = blockIdx.x;
@@ -145,7 +158,7 @@ k_downsweep(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ v
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + k * 64 + lane;
-        const bool valid = i < count;
+        const bool valid = i < count && !(drop && key[k] == 0xFFFFFFFFu);
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -178,13 +191,14 @@ k_downsweep(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ v
             s_local[d] += t;
             __syncthreads();
         }
+        if (d == kRadix - 1) s_kept = s_local[d];
         s_local[d] -= total;
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = wbase + k * 64 + lane;
-        if (i < count) {
+        if (i < count && !(drop && key[k] == 0xFFFFFFFFu)) {
             const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
             const uint32_t pos = s_local[dd] + s_wave[wave][dd] + rank[k];
             s_keys[pos] = key[k];
@@ -192,30 +206,48 @@ k_downsweep(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ v
         }
     }
     __syncthreads();
-    const int64_t rem = count - base;
-    const int n_valid = (int)(rem < kSortTile ? rem : kSortTile);
+    const int n_valid = (int)s_kept;
     for (int i = tid; i < n_valid; i += kSortThreads) {
         const uint32_t k = s_keys[i];
         const uint32_t dd = (k >> shift) & (kRadix - 1);
         const uint32_t out = s_global[dd] + (uint32_t)(i - (int)s_local[dd]);
         const uint32_t v = s_vals[i];
-        if (keys_out) keys_out[out] = k;
+        if (keys_out) keys_out[out] = (KeyT)k;
         vals_out[out] = v;
         if (pairs_out) pairs_out[out] = v < (uint64_t)n_rects ? rect_pairs(rects[v]) : 0u;
     }
 }
 
+template <typename KeyT>
+static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* keys_out,
+                         uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
+                         uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
+                         uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
+                         hipStream_t s) {
+    if (parts <= 0) return;
+    hipLaunchKernelGGL(k_upsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
+                       count_ptr, count_host, shift, counts, parts, drop_culled);
+    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts, totals,
+                       drop_culled ? kept_out : nullptr);
+    hipLaunchKernelGGL(k_downsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
+                       vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts,
+                       rects, pairs_out, n_rects, drop_culled);
+}
+
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
-                       uint32_t* pairs_out, int64_t n_rects, hipStream_t s) {
-    if (parts <= 0) return;
-    hipLaunchKernelGGL(k_upsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, count_ptr,
-                       count_host, shift, counts, parts);
-    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts, totals);
-    hipLaunchKernelGGL(k_downsweep, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in, vals_in,
-                       keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts, rects,
-                       pairs_out, n_rects);
+                       uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
+                       hipStream_t s) {
+    radix_pass_t<uint32_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
+                           totals, parts, rects, pairs_out, n_rects, drop_culled, kept_out, s);
+}
+
+void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
+                         uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
+                         uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s) {
+    radix_pass_t<uint16_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
+                           totals, parts, nullptr, nullptr, 0, false, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,8 +268,10 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s) {
 }
 
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint64_t* __restrict__ block_sums) {
+k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* n_ptr, int64_t n_max,
+              uint64_t* __restrict__ block_sums) {
     __shared__ uint64_t s[kScanThreads];
+    const int64_t n = pass_count(n_ptr, n_max);
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint64_t run = 0;
 #pragma unroll
@@ -252,7 +286,7 @@ k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint64_t* __restrict__
 // one block: exclusive scan of the block sums; P = total, capacity flag
 __global__ void __launch_bounds__(1024)
 k_scan_sums(uint64_t* __restrict__ block_sums, int64_t nb, uint32_t* header, int64_t capacity,
-            uint32_t* pair_offsets_end) {
+            uint32_t* pair_offsets) {
     __shared__ uint64_t s[1024];
     const int tid = threadIdx.x;
     uint64_t carry = 0;
@@ -273,17 +307,19 @@ k_scan_sums(uint64_t* __restrict__ block_sums, int64_t nb, uint32_t* header, int
     }
     if (tid == 0) {
         header[kHdrPairs] = (uint32_t)(carry < 0xFFFFFFFFull ? carry : 0xFFFFFFFFull);
-        *pair_offsets_end = header[kHdrPairs];
+        pair_offsets[header[kHdrVisible]] = header[kHdrPairs];
         if (carry > (uint64_t)capacity) atomicOr(&header[kHdrStatus], SGS_STATUS_CAPACITY);
     }
 }
 
 // block-local scan + block offset; marks the first item of every duplicate chunk
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_final(const uint32_t* __restrict__ in, int64_t n, const uint64_t* __restrict__ block_sums,
-             uint32_t* __restrict__ out, uint32_t* __restrict__ chunk_start, int64_t dup_chunks,
-             int64_t capacity) {
+k_scan_final(const uint32_t* __restrict__ in, const uint32_t* n_ptr, int64_t n_max,
+             const uint64_t* __restrict__ block_sums, uint32_t* __restrict__ out,
+             uint32_t* __restrict__ chunk_start, int64_t dup_chunks, int64_t capacity) {
     __shared__ uint32_t s_w[kScanThreads / 64];
+    const int64_t n = pass_count(n_ptr, n_max);
+    if ((int64_t)blockIdx.x * kScanTile >= n) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     // thread owns kScanItems consecutive items
@@ -324,12 +360,14 @@ void launch_scan_pairs(const Workspace& ws, hipStream_t s) {
     const int64_t n = ws.n_items;
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts, n,
-                       ws.scan_sums);
+    const uint32_t* nv = ws.header + kHdrVisible;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts,
+                       nv, n, ws.scan_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, ws.scan_sums, nb, ws.header,
-                       ws.capacity, ws.pair_offsets + n);
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts, n,
-                       ws.scan_sums, ws.pair_offsets, ws.chunk_start, ws.dup_chunks, ws.capacity);
+                       ws.capacity, ws.pair_offsets);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts,
+                       nv, n, ws.scan_sums, ws.pair_offsets, ws.chunk_start, ws.dup_chunks,
+                       ws.capacity);
 }
 
 }  // namespace sgs

@@ -48,40 +48,39 @@ __device__ __forceinline__ void sh_eval(T x, T y, T z, T* Y) {
 }
 
 // dY/dx, dY/dy, dY/dz of the polynomials above (x, y, z independent).
-template <int DEG>
-__device__ __forceinline__ void sh_grad(double x, double y, double z, double* gx, double* gy,
-                                        double* gz) {
-    gx[0] = gy[0] = gz[0] = 0.0;
+template <int DEG, typename T>
+__device__ __forceinline__ void sh_grad(T x, T y, T z, T* gx, T* gy, T* gz) {
+    gx[0] = gy[0] = gz[0] = T(0);
     if (DEG >= 1) {
-        const double c1 = sqrt(3.0 / (4.0 * SGS_PI));
-        gx[1] = 0.0; gy[1] = -c1; gz[1] = 0.0;
-        gx[2] = 0.0; gy[2] = 0.0; gz[2] = c1;
-        gx[3] = -c1; gy[3] = 0.0; gz[3] = 0.0;
+        const T c1 = T(sqrt(3.0 / (4.0 * SGS_PI)));
+        gx[1] = T(0); gy[1] = -c1; gz[1] = T(0);
+        gx[2] = T(0); gy[2] = T(0); gz[2] = c1;
+        gx[3] = -c1; gy[3] = T(0); gz[3] = T(0);
     }
     if (DEG >= 2) {
-        const double a = 0.5 * sqrt(15.0 / SGS_PI);
-        const double b = 0.25 * sqrt(5.0 / SGS_PI);
-        const double c = 0.25 * sqrt(15.0 / SGS_PI);
-        gx[4] = a * y;   gy[4] = a * x;   gz[4] = 0.0;
-        gx[5] = 0.0;     gy[5] = -a * z;  gz[5] = -a * y;
-        gx[6] = 0.0;     gy[6] = 0.0;     gz[6] = 6.0 * b * z;
-        gx[7] = -a * z;  gy[7] = 0.0;     gz[7] = -a * x;
-        gx[8] = 2.0 * c * x; gy[8] = -2.0 * c * y; gz[8] = 0.0;
+        const T a = T(0.5 * sqrt(15.0 / SGS_PI));
+        const T b = T(0.25 * sqrt(5.0 / SGS_PI));
+        const T c = T(0.25 * sqrt(15.0 / SGS_PI));
+        gx[4] = a * y;       gy[4] = a * x;        gz[4] = T(0);
+        gx[5] = T(0);        gy[5] = -a * z;       gz[5] = -a * y;
+        gx[6] = T(0);        gy[6] = T(0);         gz[6] = T(6) * b * z;
+        gx[7] = -a * z;      gy[7] = T(0);         gz[7] = -a * x;
+        gx[8] = T(2) * c * x; gy[8] = T(-2) * c * y; gz[8] = T(0);
     }
     if (DEG >= 3) {
-        const double a = 0.25 * sqrt(35.0 / (2.0 * SGS_PI));
-        const double b = 0.5 * sqrt(105.0 / SGS_PI);
-        const double c = 0.25 * sqrt(21.0 / (2.0 * SGS_PI));
-        const double d = 0.25 * sqrt(7.0 / SGS_PI);
-        const double e = 0.25 * sqrt(105.0 / SGS_PI);
-        const double z5 = 5.0 * z * z - 1.0;
-        gx[9] = -a * 6.0 * x * y;            gy[9] = -a * (3.0 * x * x - 3.0 * y * y); gz[9] = 0.0;
-        gx[10] = b * y * z;                  gy[10] = b * x * z;                        gz[10] = b * x * y;
-        gx[11] = 0.0;                        gy[11] = -c * z5;                          gz[11] = -c * y * 10.0 * z;
-        gx[12] = 0.0;                        gy[12] = 0.0;                              gz[12] = d * (15.0 * z * z - 3.0);
-        gx[13] = -c * z5;                    gy[13] = 0.0;                              gz[13] = -c * x * 10.0 * z;
-        gx[14] = 2.0 * e * x * z;            gy[14] = -2.0 * e * y * z;                 gz[14] = e * (x * x - y * y);
-        gx[15] = -a * (3.0 * x * x - 3.0 * y * y); gy[15] = a * 6.0 * x * y;           gz[15] = 0.0;
+        const T a = T(0.25 * sqrt(35.0 / (2.0 * SGS_PI)));
+        const T b = T(0.5 * sqrt(105.0 / SGS_PI));
+        const T c = T(0.25 * sqrt(21.0 / (2.0 * SGS_PI)));
+        const T d = T(0.25 * sqrt(7.0 / SGS_PI));
+        const T e = T(0.25 * sqrt(105.0 / SGS_PI));
+        const T z5 = T(5) * z * z - T(1);
+        gx[9] = -a * T(6) * x * y;           gy[9] = -a * (T(3) * x * x - T(3) * y * y); gz[9] = T(0);
+        gx[10] = b * y * z;                  gy[10] = b * x * z;                          gz[10] = b * x * y;
+        gx[11] = T(0);                       gy[11] = -c * z5;                            gz[11] = -c * y * T(10) * z;
+        gx[12] = T(0);                       gy[12] = T(0);                               gz[12] = d * (T(15) * z * z - T(3));
+        gx[13] = -c * z5;                    gy[13] = T(0);                               gz[13] = -c * x * T(10) * z;
+        gx[14] = T(2) * e * x * z;           gy[14] = T(-2) * e * y * z;                  gz[14] = e * (x * x - y * y);
+        gx[15] = -a * (T(3) * x * x - T(3) * y * y); gy[15] = a * T(6) * x * y;          gz[15] = T(0);
     }
 }
 

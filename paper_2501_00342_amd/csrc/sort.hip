@@ -83,13 +83,14 @@ k_duplicate(Workspace ws, int64_t n) {
     const uint32_t P = ws.header[kHdrPairs];
     const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
     const uint32_t nn = (uint32_t)n;
+    const int64_t n_vis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
     for (int64_t chunk = blockIdx.x; chunk * kDupChunk < Pc; chunk += gridDim.x) {
         const int64_t p0 = chunk * kDupChunk;
         const int64_t p1 = (p0 + kDupChunk < Pc) ? p0 + kDupChunk : Pc;
         const int64_t i0 = ws.chunk_start[chunk];
-        if (i0 >= ws.n_items) continue;   // uniform: no chunk start was recorded
-        // items i0 .. cover [p0, p1); each has >= 1 pair until the culled tail
-        int64_t i_end = ws.n_items;
+        if (i0 >= n_vis) continue;   // uniform: no chunk start was recorded
+        // visible items i0 .. cover [p0, p1); every visible item has >= 1 pair
+        int64_t i_end = n_vis;
         if (chunk + 1 < ws.dup_chunks && p1 < Pc) i_end = (int64_t)ws.chunk_start[chunk + 1] + 1;
         int64_t nloc = i_end - i0;
         if (nloc > kDupChunk + 1) nloc = kDupChunk + 1;
@@ -123,7 +124,10 @@ k_duplicate(Workspace ws, int64_t n) {
             int tx = j - ty * w;
             if (tx < 0) { --ty; tx += w; } else if (tx >= w) { ++ty; tx -= w; }
             const uint32_t tile = s_origin[lo] + (uint32_t)(ty * gx + tx);
-            ws.pair_tiles[p] = tile;
+            if (ws.key16)
+                reinterpret_cast<uint16_t*>(ws.pair_tiles)[p] = (uint16_t)tile;
+            else
+                ws.pair_tiles[p] = tile;
             ws.pair_values[p] = s_item[lo];
         }
     }
@@ -137,23 +141,38 @@ void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s) {
 // tile ranges from the sorted tile ids
 // --------------------------------------------------------------------------
 
-__global__ void k_ranges(Workspace ws) {
+// a tile starts where the sorted tile id changes; a block covers
+// 256 * kRangeItems consecutive pairs with lane-strided (coalesced) loads
+constexpr int kRangeItems = 16;
+
+template <typename KeyT>
+__global__ void __launch_bounds__(256) k_ranges(Workspace ws) {
     const uint32_t P = ws.header[kHdrPairs];
     const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Pc;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = ws.pair_tiles[i];
-        if ((int64_t)t >= ws.n_tiles) continue;
-        if (i == 0 || ws.pair_tiles[i - 1] != t) ws.ranges[2 * (int64_t)t] = (uint32_t)i;
-        if (i == Pc - 1 || ws.pair_tiles[i + 1] != t) ws.ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    const int64_t base = (int64_t)blockIdx.x * 256 * kRangeItems;
+    if (base >= Pc) return;
+    const KeyT* tiles = reinterpret_cast<const KeyT*>(ws.pair_tiles);
+#pragma unroll 4
+    for (int k = 0; k < kRangeItems; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
+        if (i >= Pc) break;
+        const uint32_t t = tiles[i];
+        const uint32_t prev = i > 0 ? (uint32_t)tiles[i - 1] : 0xFFFFFFFFu;
+        if (t != prev) {
+            if ((int64_t)t < ws.n_tiles) ws.ranges[2 * (int64_t)t] = (uint32_t)i;
+            if (i > 0 && (int64_t)prev < ws.n_tiles) ws.ranges[2 * (int64_t)prev + 1] = (uint32_t)i;
+        }
+        if (i == Pc - 1 && (int64_t)t < ws.n_tiles) ws.ranges[2 * (int64_t)t + 1] = (uint32_t)Pc;
     }
 }
 
 void launch_ranges(const Workspace& ws, hipStream_t s) {
-    int64_t blocks = (ws.capacity + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, ws);
+    const int64_t blocks = (ws.capacity + 256 * kRangeItems - 1) / (256 * kRangeItems);
+    if (blocks < 1) return;
+    if (ws.key16)
+        hipLaunchKernelGGL(k_ranges<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, ws);
+    else
+        hipLaunchKernelGGL(k_ranges<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, ws);
 }
 
 // --------------------------------------------------------------------------
@@ -165,7 +184,9 @@ __global__ void k_read_keys(Workspace ws, int64_t count, uint64_t* keys) {
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t item = ws.pair_values[i];
         const uint32_t dk = item < (uint64_t)ws.n_items ? ws.depth_keys[item] : 0xFFFFFFFFu;
-        keys[i] = ((uint64_t)ws.pair_tiles[i] << 32) | dk;
+        const uint32_t t = ws.key16 ? (uint32_t)reinterpret_cast<const uint16_t*>(ws.pair_tiles)[i]
+                                    : ws.pair_tiles[i];
+        keys[i] = ((uint64_t)t << 32) | dk;
     }
 }
 

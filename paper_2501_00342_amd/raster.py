@@ -130,10 +130,17 @@ class Rasterizer:
             return out
 
     def backward(self, params: dict, out: Outputs, grad_image: torch.Tensor) -> dict:
+        grads = {k: torch.empty_like(params[k]) for k in FIELDS}
+        self.backward_into(params, out, grad_image, grads)
+        return grads
+
+    def backward_into(self, params: dict, out: Outputs, grad_image: torch.Tensor,
+                      grads: dict) -> dict:
+        """Backward writing into preallocated gradient tensors (no allocation:
+        usable under stream capture)."""
         self._check_params(params)
         assert grad_image.dtype == torch.float32 and grad_image.is_contiguous()
         assert grad_image.numel() == 3 * self.n_pixels
-        grads = {k: torch.empty_like(params[k]) for k in FIELDS}
         g = self._gstruct(params)
         gr = L.grads_struct({k: (grads[k].data_ptr() if grads[k].numel() else None)
                              for k in FIELDS})

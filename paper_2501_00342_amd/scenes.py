@@ -98,6 +98,8 @@ class Options:
     tile_w: int = 16
     tile_h: int = 16
     batch: int = 0              # LDS batch depth, 0 = library default
+    ppt: int = 0                # pixels per thread, forward blend (0 = library default)
+    ppt_bwd: int = 0            # pixels per thread, backward blend
     dilation: float = 0.3
     guard: float = 1.3
     alpha_min: float = 1.0 / 255.0

@@ -67,9 +67,11 @@ def test_backward_sh3_form():
     _assert_grads({k: grads[k].cpu().numpy() for k in FIELDS}, grads_ref, ex, "raw")
 
 
-def test_backward_other_tile_shape_and_batch():
+@pytest.mark.parametrize("tw,th,batch,ppt_bwd", [(32, 8, 512, 4), (16, 16, 256, 1),
+                                                 (16, 16, 64, 2), (8, 8, 128, 1)])
+def test_backward_other_tile_shape_and_batch(tw, th, batch, ppt_bwd):
     sc, cam = scenes.small_clustered(4000, 24, 120, 80)
-    opts = scenes.Options(tile_w=32, tile_h=8, batch=512)
+    opts = scenes.Options(tile_w=tw, tile_h=th, batch=batch, ppt_bwd=ppt_bwd)
     rast, grads, g2_gpu, g2_ref, grads_ref, ex = _backward_case(sc, cam, opts, 24)
     _assert_grads({k: grads[k].cpu().numpy() for k in FIELDS}, grads_ref, ex, "raw")
 

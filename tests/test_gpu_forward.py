@@ -81,13 +81,14 @@ def test_config0_records_pairs_and_image():
     assert not rep["failures"], rep
 
 
-@pytest.mark.parametrize("tw,th,batch", [(16, 16, 0), (8, 8, 0), (32, 8, 512), (16, 8, 256),
-                                         (8, 16, 128)])
-def test_clustered_scene_tile_shapes(tw, th, batch):
+@pytest.mark.parametrize("tw,th,batch,ppt", [(16, 16, 0, 1), (16, 16, 0, 2), (16, 16, 128, 4),
+                                             (8, 8, 64, 1), (32, 8, 512, 4), (16, 8, 256, 2),
+                                             (8, 16, 128, 1)])
+def test_clustered_scene_tile_shapes(tw, th, batch, ppt):
     """A few thousand clustered Gaussians (SH1 + 4 lobes) over a ragged
     200x136 image: many tiles, partial edge tiles, deep lists."""
     sc, cam = scenes.small_clustered(6000, 11, 200, 136)
-    opts = scenes.Options(tile_w=tw, tile_h=th, batch=batch)
+    opts = scenes.Options(tile_w=tw, tile_h=th, batch=batch, ppt=ppt)
     rast, params, out = run_forward(sc, [cam], opts)
     ref = F.render(sc, cam, opts)
     pre = F.preprocess(sc, cam, opts)
@@ -166,3 +167,47 @@ def test_batched_cameras_equal_single_renders():
         assert np.array_equal(img, simg) and np.array_equal(n, sn) and np.array_equal(T, sT)
         rep = parity.compare_image(img, dep, T, n, outs[k])
         assert not rep["failures"], (k, rep)
+
+
+def test_graph_replay_matches_eager():
+    """The whole forward and backward captured in one HIP graph: every replay,
+    with eager work and synchronisation in between, equals the eager pass."""
+    import torch
+    from paper_2501_00342_amd import raster
+    sc, cam = scenes.small_clustered(5000, 31, 150, 100)
+    opts = scenes.Options()
+    rast, params, out_e = run_forward(sc, [cam], opts)
+    tgt = torch.from_numpy(scenes.target_image(150, 100, 4).reshape(-1)).cuda()
+    _, g_e = rast.l1(out_e.image, tgt)
+    grads_e = rast.backward(params, out_e, g_e)
+    grads_e = {k: v.clone() for k, v in grads_e.items()}
+    img_e = out_e.image.clone()
+    T_e = out_e.final_T.clone()
+    n_e = out_e.n_contrib.clone()
+
+    out = rast.new_outputs()
+    gimg = torch.empty_like(out.image)
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):           # warm-up outside capture
+        rast.forward(params, out=out, check=False)
+    torch.cuda.current_stream().wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rast.forward(params, out=out, check=False)
+        rast.l1(out.image, tgt, grad_out=gimg)
+        rast.backward_into(params, out, gimg, grads)
+    other_sc, other_cam = scenes.small_clustered(2000, 32, 64, 48)
+    for rep in range(3):
+        for t in (out.image, out.final_T, gimg):
+            t.fill_(-7.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.image, img_e) and torch.equal(out.final_T, T_e), rep
+        assert torch.equal(out.n_contrib, n_e), rep
+        for k in grads:
+            a, b = grads[k], grads_e[k]
+            assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(b.abs().max() + 1e-30)), (rep, k)
+        run_forward(other_sc, [other_cam], opts)   # unrelated eager work between replays
+        torch.cuda.synchronize()
