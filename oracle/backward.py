@@ -82,6 +82,45 @@ def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile
     return out
 
 
+def pixel_backward(pre, cam, opts, px, py, gC):
+    """2D-gradient contributions of one pixel (brute-force list, as in
+    `forward.render_pixel`) for upstream gradient gC (3,): dict g -> 9-vector
+    ordered as GRAD2D."""
+    amax = R._f(opts.alpha_max)
+    bg = cam.bg.astype(F64)
+    entries = R.pixel_list(pre, px, py)
+    pxa, pya = np.array([px]), np.array([py])
+    C, D, Tf, nn, fl, trace = R._blend_tile(pre, entries, pxa, pya, opts, bg, want_trace=True)
+    gC = np.asarray(gC, F64).reshape(3, 1)
+    S = Tf[None, :] * bg[:, None]
+    out = {}
+    for (j, g, blend, a, T) in reversed(trace):
+        if not blend[0]:
+            continue
+        w = a * T
+        c = pre.rgb[:, g][:, None]
+        grgb = (gC * w).sum(axis=1)
+        dLda = float((gC * (T * c - S / (1.0 - a))).sum())
+        S = S + w * c
+        dx = px - pre.u[g]
+        dy = py - pre.v[g]
+        Qa, Qb, Qc = pre.conic[:, g]
+        power = -0.5 * (Qa * dx * dx + 2.0 * Qb * dx * dy + Qc * dy * dy)
+        E = np.exp(min(power, 0.0))
+        v = np.zeros(9)
+        if pre.opacity[g] * E <= amax:
+            dLdp = dLda * float(a[0]) if power <= 0.0 else 0.0
+            v[5] = dLda * E
+            v[2] = dLdp * (-0.5 * dx * dx)
+            v[3] = dLdp * (-dx * dy)
+            v[4] = dLdp * (-0.5 * dy * dy)
+            v[0] = dLdp * (Qa * dx + Qb * dy)
+            v[1] = dLdp * (Qb * dx + Qc * dy)
+        v[6:9] = grgb
+        out[int(g)] = out.get(int(g), 0.0) + v
+    return out, bool(fl[0])
+
+
 def _quat_rotation_grad(w, x, y, z, gR):
     """Gradient of the rotation matrix entries w.r.t. (w, x, y, z)."""
     gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2]

@@ -85,3 +85,21 @@ def test_l1_loss_definition():
     loss, g = G.l1_loss(img, tgt)
     assert loss == pytest.approx((0.1 + 0.2 + 0.5) / 6)
     assert np.array_equal(g * 6, np.sign(img - tgt))
+
+
+def test_pixel_backward_matches_tiled_backward():
+    """Per-pixel brute-force backward summed over pixels = tiled backward."""
+    sc, cam, tgt = fd_subcase()
+    img = F.render(sc, cam, OPTS)
+    pre = F.preprocess(sc, cam, OPTS)
+    _, gimg = G.l1_loss(img.image, tgt)
+    tiled = G.blend_backward(pre, cam, OPTS, img.values, img.ranges, gimg)
+    acc = {}
+    for py in range(32):
+        for px in range(32):
+            contrib, _ = G.pixel_backward(pre, cam, OPTS, px, py, gimg[:, py, px])
+            for g, v in contrib.items():
+                acc[g] = acc.get(g, 0.0) + v
+    for g, v in acc.items():
+        ref = np.array([tiled[k][g] for k in G.GRAD2D])
+        assert np.allclose(v, ref, rtol=1e-9, atol=1e-15), g
