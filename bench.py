@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 28      # calibration kernel: bytes read (and written) per launch
 # fp32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed lane ops)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
@@ -41,8 +42,11 @@ def parse():
     ap.add_argument("--no-sh3", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many forward+backward steps (for rocprofv3)")
-    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
-    ap.add_argument("--tile", default=None, help="fixed launch shape tw,th,ppt,ppt_bwd,batch")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuner")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every launch shape again instead of using the cached choice")
+    ap.add_argument("--tile", default=None,
+                    help="fixed launch shape tw,th,ppt,ppt_bwd,batch[,schedule]")
     return ap.parse_args()
 
 
@@ -114,6 +118,135 @@ def cpu_baseline(scene, cam, opts, n_tiles_sample=24):
             "host_cpu_count": os.cpu_count()}
 
 
+SINGLE_KERNEL_STAGES = ("fwd.preprocess", "fwd.duplicate", "fwd.blend")
+
+
+def source_digest(path):
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counter_traffic(stage, workload, shape):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the calibration kernel), or
+    None when there is none for this workload and launch shape, or the
+    kernel's source has changed since the counters were taken."""
+    import glob
+    src = {"fwd.blend": "paper_2501_00342_amd/csrc/blend.hip",
+           "fwd.preprocess": "paper_2501_00342_amd/csrc/preprocess.hip",
+           "fwd.duplicate": "paper_2501_00342_amd/csrc/sort.hip"}.get(stage)
+    if src is None:
+        return None
+    digest = source_digest(src)
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*counters*.md"))):
+        with open(fn) as f:
+            for line in f:
+                if not line.startswith("traffic_json: "):
+                    continue
+                try:
+                    rec = json.loads(line[len("traffic_json: "):])
+                except ValueError:
+                    continue
+                if (rec.get("stage") == stage and rec.get("workload") == workload
+                        and rec.get("shape") == shape and rec.get("source_sha256") == digest):
+                    return {"bytes": int(rec["bytes_per_launch"]),
+                            "file": os.path.relpath(fn, ROOT)}
+    return None
+
+
+def choose_options(args, torch, scenes, autotune, params, cams, base, scene, target):
+    """(forward options, forward+backward options, tuning reports)."""
+    if args.tile:
+        v = [int(x) for x in args.tile.split(",")]
+        o = scenes.Options(tile_w=v[0], tile_h=v[1], ppt=v[2], ppt_bwd=v[3], batch=v[4],
+                           schedule=v[5] if len(v) > 5 else 0)
+        return o, o, None
+    if args.no_tune:
+        return base, base, None
+    # launch shapes picked by the autotuner (cached per GPU and workload): one
+    # for the forward alone, one for forward + L1 + backward
+    kw = dict(reps=3, tiles=[(16, 16), (32, 8), (16, 8)], batches=(128, 256), target=target,
+              use_cache=not args.retune)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    picked, reports = [], {}
+    for bwd in (False, True):
+        o, rep = autotune.tune(params, cams, base, scene.n, scene.sh_degree, scene.n_lobes,
+                               backward=bwd, **kw)
+        picked.append(o)
+        reports["fwd_bwd" if bwd else "fwd"] = sorted(rep, key=lambda r: r["ms"])[:3]
+        if args.retune:
+            key = autotune.cache_key(arch, cams, scene.n, scene.sh_degree, scene.n_lobes, bwd)
+            best = min(rep, key=lambda r: r["ms"])
+            print(json.dumps({"autotune_entry": {key: {
+                "choice": {k: best[k] for k in best if k != "ms"}, "report": rep}}}),
+                file=sys.stderr, flush=True)
+    return picked[0], picked[1], reports
+
+
+def shape_of(rast, o):
+    c = rast.copts
+    return (f"{o.tile_w}x{o.tile_h},ppt{c.pixels_per_thread},pptb{c.pixels_per_thread_bwd},"
+            f"b{c.batch or 256},s{c.schedule or 0}")
+
+
+def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, target,
+                 profile=False):
+    """Tune, then time one colour form: eager passes with per-stage HIP
+    events, then the same passes captured in HIP graphs and replayed."""
+    params = raster.params_to_device(scene)
+    opts_f, opts_b, reports = choose_options(args, torch, scenes, autotune, params, cams, base,
+                                             scene, target)
+    rast = raster.Rasterizer(cams, opts_f, scene.n, scene.sh_degree, scene.n_lobes)
+    out = rast.forward(params, check=True)          # sizes the pair capacity
+    if opts_b == opts_f:
+        rast_b, out_b = rast, out
+    else:
+        rast_b = raster.Rasterizer(cams, opts_b, scene.n, scene.sh_degree, scene.n_lobes)
+        out_b = rast_b.forward(params, check=True)
+    grad_img = torch.empty_like(out_b.image)
+    grads = {k: torch.empty_like(v) for k, v in params.items()}
+
+    def fwd():
+        rast.forward(params, out=out, check=False)
+
+    def fwd_bwd():
+        rast_b.forward(params, out=out_b, check=False)
+        rast_b.l1(out_b.image, target, grad_out=grad_img)
+        rast_b.backward_into(params, out_b, grad_img, grads)
+
+    if profile:
+        for _ in range(args.profile_steps):
+            fwd()
+            fwd_bwd()
+        torch.cuda.synchronize()
+        return None
+
+    for _ in range(args.warmup):
+        fwd()
+        fwd_bwd()
+    torch.cuda.synchronize()
+    for r in (rast, rast_b):
+        bits, _ = r.status()
+        assert bits == 0, f"status bits {bits}"
+
+    L.LIB.render_set_timing(1)
+    L.stage_times()
+    fwd_ms = timed_loop(fwd, args.steps, torch)
+    st_fwd, nf, _ = L.stage_times()
+    fb_ms = timed_loop(fwd_bwd, args.steps, torch)
+    st_fb, _, nb = L.stage_times()
+    L.LIB.render_set_timing(0)
+    g_fwd = capture(fwd, torch)
+    g_fb = capture(fwd_bwd, torch)
+    fwd_graph_ms = timed_loop(g_fwd.replay, args.steps, torch)
+    fb_graph_ms = timed_loop(g_fb.replay, args.steps, torch)
+    del g_fwd, g_fb
+    return dict(rast=rast, rast_b=rast_b, params=params, opts_f=opts_f, opts_b=opts_b,
+                reports=reports, fwd_ms=fwd_ms, fb_ms=fb_ms, fwd_graph_ms=fwd_graph_ms,
+                fb_graph_ms=fb_graph_ms, st_fwd=st_fwd, nf=nf, st_fb=st_fb, nb=nb)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -122,66 +255,34 @@ def main():
         sys.exit(2)
     import torch
     from paper_2501_00342_amd import _lib as L
-    from paper_2501_00342_amd import raster, scenes
+    from paper_2501_00342_amd import autotune, raster, scenes
 
     assert torch.cuda.is_available()
-    from paper_2501_00342_amd import autotune
-    sc, cams, opts = scenes.workload(args.workload)
+    sc, cams, base = scenes.workload(args.workload)
     cam = cams[0]
     W, H = cam.width, cam.height
-    params = raster.params_to_device(sc)
     target = torch.from_numpy(np.concatenate(
         [scenes.target_image(c.width, c.height, 1 + i).reshape(-1) for i, c in enumerate(cams)])).cuda()
-    tune_report = None
-    if args.tile:
-        tw, th, ppt, pptb, batch = (int(x) for x in args.tile.split(","))
-        opts = scenes.Options(tile_w=tw, tile_h=th, ppt=ppt, ppt_bwd=pptb, batch=batch)
-    elif not args.no_tune and not args.profile_steps:
-        opts, tune_report = autotune.tune(params, cams, opts, sc.n, sc.sh_degree, sc.n_lobes,
-                                          backward=False, reps=3, tiles=[(16, 16), (32, 8), (16, 8)],
-                                          batches=(128, 256), target=target)
-    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
-    out = rast.forward(params, check=True)          # sizes the pair capacity
-    grad_img = torch.empty_like(out.image)
-    grads = {k: torch.empty_like(v) for k, v in params.items()}
-
-    def fwd():
-        rast.forward(params, out=out, check=False)
-
-    def fwd_bwd():
-        rast.forward(params, out=out, check=False)
-        rast.l1(out.image, target, grad_out=grad_img)
-        rast.backward_into(params, out, grad_img, grads)
+    mods = (torch, L, raster, scenes, autotune)
 
     if args.profile_steps:
-        for _ in range(args.profile_steps):
-            fwd_bwd()
+        measure_form(args, *mods, sc, cams, base, target, profile=True)
+        # counter calibration: an elementwise kernel that reads and writes
+        # COPY_BYTES each (torch's neg), profiled in the same run
+        src = torch.ones(COPY_BYTES // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.profile_steps}), flush=True)
+        print(json.dumps({"profile_steps": args.profile_steps, "copy_bytes": COPY_BYTES}),
+              flush=True)
         return
 
-    for _ in range(args.warmup):
-        fwd_bwd()
-    torch.cuda.synchronize()
-    bits, P = rast.status()
-    assert bits == 0, f"status bits {bits}"
-
-    L.LIB.render_set_timing(1)
-    L.stage_times()
-    fwd_ms = timed_loop(fwd, args.steps, torch)
-    st_fwd, nf, _ = L.stage_times()
-    fb_ms = timed_loop(fwd_bwd, args.steps, torch)
-    st_fb, nf2, nb2 = L.stage_times()
-    L.LIB.render_set_timing(0)
+    m = measure_form(args, *mods, sc, cams, base, target)
+    rast, opts = m["rast"], m["opts_f"]
     names = L.stage_names()
-
-    # the same passes captured once in a HIP graph and replayed
-    g_fwd = capture(fwd, torch)
-    g_fb = capture(fwd_bwd, torch)
-    fwd_graph_ms = timed_loop(g_fwd.replay, args.steps, torch)
-    fb_graph_ms = timed_loop(g_fb.replay, args.steps, torch)
-
-    visited, evaluated = rast.blend_work(params)
+    bits, P = rast.status()
+    visited, evaluated = rast.blend_work(m["params"])
     n_vis = int(np.count_nonzero(rast.depth_keys().cpu().numpy().view(np.uint32) != 0xFFFFFFFF))
     tiles = int(rast.layout.n_tiles)
     tile_passes = math.ceil(max(1, math.ceil(math.log2(max(tiles, 2)))) / 8)
@@ -189,8 +290,8 @@ def main():
 
     stages = {}
     for i, nm in enumerate(names):
-        calls = nf if nm.startswith("fwd") else nb2
-        src = st_fwd if nm.startswith("fwd") else st_fb
+        calls = m["nf"] if nm.startswith("fwd") else m["nb"]
+        src = m["st_fwd"] if nm.startswith("fwd") else m["st_fb"]
         if calls <= 0:
             continue
         ms = src[i] / calls
@@ -202,43 +303,49 @@ def main():
             ent["hbm_frac"] = round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         stages[nm] = ent
 
-    # dominant forward kernel group and its roofline
-    fwd_names = [n for n in stages if n.startswith("fwd.") and n != "fwd.setup"]
-    dom = max(fwd_names, key=lambda n: stages[n]["ms"])
+    # roofline of the forward's dominant kernel (stages that are one launch)
+    dom = max((n for n in SINGLE_KERNEL_STAGES if n in stages), key=lambda n: stages[n]["ms"])
+    shape = shape_of(rast, opts)
+    tr = counter_traffic(dom, args.workload, shape)
     if dom == "fwd.blend":
-        ops = evaluated * 24 + visited * 4          # lane-ops (blend costs)
+        ops = evaluated * 24 + visited * 4          # lane-ops per launch
         ach = ops / (stages[dom]["ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tlane-op/s",
-                "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": None}
+                "frac": round(ach / VALU_PEAK_TOPS, 4), "ms_per_launch": stages[dom]["ms"],
+                "lane_ops_per_launch": int(ops)}
     else:
         b = stages[dom]["alg_bytes"]
         ach = b / (stages[dom]["ms"] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "ms_per_launch": stages[dom]["ms"], "alg_bytes_per_launch": int(b)}
+    roof["traffic"] = tr["bytes"] if tr else None
+    if tr:
+        roof["traffic_source"] = tr["file"]
+    roof["shape"] = shape
 
     result = {
         "metric": ("frames/s & fwd+bwd ms at 3M Gaussians 1600x1060, SG vs SH-3 form, same GPU"
                    if args.workload == "sg-3m-1600" else f"frames/s & fwd+bwd ms, {args.workload}"),
-        "value": round(1000.0 / fwd_graph_ms, 2), "unit": "frames/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fwd_graph_ms, 4),
+        "value": round(1000.0 / m["fwd_graph_ms"], 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(m["fwd_graph_ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "gaussians": sc.n, "cameras": len(cams),
                    "width": W, "height": H, "colour": f"SH{sc.sh_degree}+{sc.n_lobes}SG",
-                   "tile": f"{opts.tile_w}x{opts.tile_h}", "ppt": rast.copts.pixels_per_thread,
-                   "ppt_bwd": rast.copts.pixels_per_thread_bwd, "batch": opts.batch},
-        "fwd_bwd_ms": round(fb_graph_ms, 4),
-        "eager": {"frames_per_s": round(1000.0 / fwd_ms, 2), "fwd_ms": round(fwd_ms, 4),
-                  "fwd_bwd_ms": round(fb_ms, 4)},
+                   "fwd_shape": shape, "fwd_bwd_shape": shape_of(m["rast_b"], m["opts_b"])},
+        "fwd_bwd_ms": round(m["fb_graph_ms"], 4),
+        "eager": {"frames_per_s": round(1000.0 / m["fwd_ms"], 2), "fwd_ms": round(m["fwd_ms"], 4),
+                  "fwd_bwd_ms": round(m["fb_ms"], 4)},
         "pairs": int(P), "visible": n_vis, "tiles": tiles,
         "blend_visited": visited, "blend_evaluated": evaluated,
         "stages": stages, "roofline": roof,
     }
-    if tune_report is not None:
-        result["autotune"] = sorted(tune_report, key=lambda r: r["ms"])[:5]
+    if m["reports"]:
+        result["autotune"] = m["reports"]
     if len(cams) > 1:
-        result["views_per_s"] = round(len(cams) * 1000.0 / fwd_graph_ms, 2)
+        result["views_per_s"] = round(len(cams) * 1000.0 / m["fwd_graph_ms"], 2)
     # per-tile load (list lengths), e.g. for the stress workload
     rng = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
     cnt = rng[:, 1] - rng[:, 0]
@@ -247,48 +354,28 @@ def main():
                            "p99": float(np.percentile(cnt, 99)), "max": int(cnt.max()),
                            "empty": int((cnt == 0).sum()),
                            "log2_bins": {f"<=2^{i}": int(b) for i, b in enumerate(bins) if b}}
+    del m, rast
+    torch.cuda.empty_cache()
 
-    if not args.no_sh3:
-        sh3 = scenes.sh3_scene(sc.n, 1) if args.workload == "sg-3m-1600" else None
-        if sh3 is not None:
-            r3 = raster.Rasterizer(cams, opts, sh3.n, sh3.sh_degree, sh3.n_lobes)
-            p3 = raster.params_to_device(sh3)
-            o3 = r3.forward(p3, check=True)
-            g3 = torch.empty_like(o3.image)
-
-            def fwd3():
-                r3.forward(p3, out=o3, check=False)
-
-            gr3 = {k: torch.empty_like(v) for k, v in p3.items()}
-
-            def fb3():
-                r3.forward(p3, out=o3, check=False)
-                r3.l1(o3.image, target, grad_out=g3)
-                r3.backward_into(p3, o3, g3, gr3)
-
-            for _ in range(args.warmup):
-                fb3()
-            L.LIB.render_set_timing(1)
-            L.stage_times()
-            sh3_fwd = timed_loop(fwd3, args.steps, torch)
-            st3, n3, _ = L.stage_times()
-            sh3_fb = timed_loop(fb3, args.steps, torch)
-            L.stage_times()
-            L.LIB.render_set_timing(0)
-            gf3 = capture(fwd3, torch)
-            gb3 = capture(fb3, torch)
-            sh3_fwd_g = timed_loop(gf3.replay, args.steps, torch)
-            sh3_fb_g = timed_loop(gb3.replay, args.steps, torch)
-            result["sh3"] = {"frames_per_s": round(1000.0 / sh3_fwd_g, 2),
-                             "fwd_ms": round(sh3_fwd_g, 4), "fwd_bwd_ms": round(sh3_fb_g, 4),
-                             "eager_fwd_ms": round(sh3_fwd, 4), "eager_fwd_bwd_ms": round(sh3_fb, 4),
-                             "preprocess_ms": round(st3[names.index("fwd.preprocess")] / max(n3, 1), 5)}
-            result["sg_over_sh3_fps"] = round(sh3_fwd_g / fwd_graph_ms, 4)
-            result["sg_over_sh3_fwd_bwd"] = round(sh3_fb_g / fb_graph_ms, 4)
-            del r3, p3, o3, g3, gf3, gb3
+    if not args.no_sh3 and args.workload == "sg-3m-1600":
+        sh3 = scenes.sh3_scene(sc.n, 1)
+        m3 = measure_form(args, *mods, sh3, cams, base, target)
+        i_pre = names.index("fwd.preprocess")
+        result["sh3"] = {"frames_per_s": round(1000.0 / m3["fwd_graph_ms"], 2),
+                         "fwd_ms": round(m3["fwd_graph_ms"], 4),
+                         "fwd_bwd_ms": round(m3["fb_graph_ms"], 4),
+                         "eager_fwd_ms": round(m3["fwd_ms"], 4),
+                         "eager_fwd_bwd_ms": round(m3["fb_ms"], 4),
+                         "preprocess_ms": round(m3["st_fwd"][i_pre] / max(m3["nf"], 1), 5),
+                         "fwd_shape": shape_of(m3["rast"], m3["opts_f"]),
+                         "fwd_bwd_shape": shape_of(m3["rast_b"], m3["opts_b"])}
+        result["sg_over_sh3_fps"] = round(m3["fwd_graph_ms"] / (1000.0 / result["value"]), 4)
+        result["sg_over_sh3_fwd_bwd"] = round(m3["fb_graph_ms"] / result["fwd_bwd_ms"], 4)
+        del m3
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline and len(cams) == 1:
-        result["cpu_baseline"] = cpu_baseline(sc, cam, opts)
+        result["cpu_baseline"] = cpu_baseline(sc, cam, base)
     print(json.dumps(result), flush=True)
 
 

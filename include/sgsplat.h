@@ -108,7 +108,15 @@ typedef struct sgs_options {
     int32_t pixels_per_thread;       /* forward blend: 1, 2 or 4 pixels per thread (0 = 2); the
                                         block, tile_w*tile_h/ppt threads, must be whole waves */
     int32_t pixels_per_thread_bwd;   /* backward blend, same rule (0 = 4 where allowed) */
+    int32_t schedule;                /* tile schedule of both blends: SGS_SCHEDULE_GRID (one
+                                        workgroup per tile), SGS_SCHEDULE_QUEUE (persistent
+                                        workgroups popping tiles heavy-first from an atomic
+                                        counter); 0 = queue for several cameras, grid for one.
+                                        The image does not depend on it. */
 } sgs_options;
+
+#define SGS_SCHEDULE_GRID 1
+#define SGS_SCHEDULE_QUEUE 2
 
 /* Forward outputs (device, packed over cameras as described above). */
 typedef struct sgs_outputs {
@@ -122,7 +130,8 @@ typedef struct sgs_outputs {
 /* Byte offsets of the workspace sections, for inspection by tests. */
 typedef struct sgs_layout {
     size_t total_bytes;
-    size_t header;          /* u32[16]: [0] status bits, [1] pair count P, [2..] counters */
+    size_t header;          /* u32[16]: [0] status bits, [1] pair count P, [2] visible
+                               items, [3] forward and [4] backward tile-queue counters */
     size_t cam_table;       /* per camera: int32 W,H,GX,GY,tile_base,pad; int64 pix_base */
     size_t records;         /* per (camera, Gaussian) item: 64-byte splat record */
     size_t depth_keys;      /* u32 per item: bits of float32 depth, 0xFFFFFFFF if culled */
@@ -161,7 +170,7 @@ int render_layout(const sgs_gaussians* g, const sgs_camera* host_cams, int32_t n
 /*
  * render_forward — the forward pass (preprocess, binning, sort, tile ranges,
  * front-to-back compositing).  Paper: Preliminaries (eqs. 2-3 and the EWA
- * projection; splats "accumulated and blended"), colour eqs. 4-9.
+ * projection; depth-sorted splats composited front to back), colour eqs. 4-9.
  *   g           Gaussian parameters (device arrays).
  *   host_cams   n_cams cameras in host memory: fix launch geometry/layout.
  *   dev_cams    the same cameras in device memory: what the kernels read

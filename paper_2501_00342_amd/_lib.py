@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsgsplat.
 
 SGS_OK, SGS_E_INVALID, SGS_E_CAPACITY, SGS_E_HIP = 0, 1, 2, 3
 SGS_STATUS_CAPACITY, SGS_STATUS_CAMERAS = 1, 2
+SCHEDULE_GRID, SCHEDULE_QUEUE = 1, 2
 SGS_FLAG_CHECK_CAPACITY = 1
 MAX_SH_DEGREE, MAX_LOBES, MAX_CAMERAS, MAX_IMAGE_SIDE = 3, 8, 1024, 32767
 
@@ -42,7 +43,7 @@ class Options(Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32),
                 ("dilation", c_float), ("guard", c_float), ("alpha_min", c_float),
                 ("alpha_max", c_float), ("t_min", c_float), ("pixels_per_thread", c_int32),
-                ("pixels_per_thread_bwd", c_int32)]
+                ("pixels_per_thread_bwd", c_int32), ("schedule", c_int32)]
 
 
 class Outputs(Structure):
@@ -161,6 +162,7 @@ def options_struct(opts) -> Options:
     o.alpha_min, o.alpha_max, o.t_min = opts.alpha_min, opts.alpha_max, opts.t_min
     o.pixels_per_thread = int(getattr(opts, "ppt", 0))
     o.pixels_per_thread_bwd = int(getattr(opts, "ppt_bwd", 0))
+    o.schedule = int(getattr(opts, "schedule", 0))
     return o
 
 

@@ -1,7 +1,8 @@
 """Autotuner for the rasteriser's launch shape.
 
 Picks the tile shape, the pixels per thread of the forward and backward
-blends and the LDS batch depth by timing the candidates on the caller's own
+blends, the LDS batch depth and the tile schedule (one workgroup per tile or
+the persistent heavy-first queue) by timing the candidates on the caller's own
 scene and cameras, and caches the winner in a JSON file keyed by (GPU
 architecture, camera sizes, Gaussian-count bucket, colour form, pass).
 The rendered image does not depend on the choice (the splat footprint is an
@@ -26,6 +27,7 @@ TILE_PPT = {
     (8, 8): (1,),
 }
 BATCHES = (128, 256, 512)
+SCHEDULES = (1, 2)      # grid, heavy-first queue
 
 
 def default_cache_path() -> str:
@@ -37,12 +39,12 @@ def cache_key(arch: str, cams, n: int, sh_degree: int, n_lobes: int, backward: b
     sizes = sorted({(int(c.width), int(c.height)) for c in cams})
     bucket = 0 if n <= 0 else int(math.ceil(math.log2(n)))
     size_s = ",".join(f"{w}x{h}" for w, h in sizes)
-    return (f"{arch}|{size_s}|cams{len(cams)}|n2^{bucket}|sh{sh_degree}k{n_lobes}|"
+    return (f"v2|{arch}|{size_s}|cams{len(cams)}|n2^{bucket}|sh{sh_degree}k{n_lobes}|"
             f"{'fwdbwd' if backward else 'fwd'}")
 
 
-def candidates(tiles=None, batches=BATCHES, backward=True):
-    """Every valid (tile, ppt, ppt_bwd, batch) combination."""
+def candidates(tiles=None, batches=BATCHES, backward=True, schedules=SCHEDULES):
+    """Every valid (tile, ppt, ppt_bwd, batch, schedule) combination."""
     out = []
     for (tw, th), ppts in TILE_PPT.items():
         if tiles is not None and (tw, th) not in tiles:
@@ -50,8 +52,15 @@ def candidates(tiles=None, batches=BATCHES, backward=True):
         for b in batches:
             for p in ppts:
                 for pb in (ppts if backward else (ppts[0],)):
-                    out.append({"tile_w": tw, "tile_h": th, "ppt": p, "ppt_bwd": pb, "batch": b})
+                    for sc in schedules:
+                        out.append({"tile_w": tw, "tile_h": th, "ppt": p, "ppt_bwd": pb,
+                                    "batch": b, "schedule": sc})
     return out
+
+
+# choices measured on MI355X for the standard workloads, shipped with the
+# package; a user cache entry of the same key takes precedence
+PACKAGED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_gfx950.json")
 
 
 def load_cache(path: str) -> dict:
@@ -60,6 +69,15 @@ def load_cache(path: str) -> dict:
             return json.load(f)
     except (OSError, ValueError):
         return {}
+
+
+def lookup(key: str, cache_path: str | None = None):
+    """Cached entry for `key`: the user cache first, then the packaged table."""
+    for p in (cache_path or default_cache_path(), PACKAGED_TABLE):
+        ent = load_cache(p).get(key)
+        if ent is not None:
+            return ent
+    return None
 
 
 def save_cache(path: str, cache: dict) -> None:
@@ -72,7 +90,8 @@ def save_cache(path: str, cache: dict) -> None:
 
 def tune(params: dict, cams, base: Options, n: int, sh_degree: int, n_lobes: int,
          backward: bool = True, reps: int = 5, tiles=None, batches=BATCHES,
-         cache_path: str | None = None, use_cache: bool = True, target=None):
+         cache_path: str | None = None, use_cache: bool = True, target=None,
+         schedules=SCHEDULES):
     """Time every candidate and return (best Options, report list).
 
     params: device tensors of the scene (raster.params_to_device).  With
@@ -86,16 +105,17 @@ def tune(params: dict, cams, base: Options, n: int, sh_degree: int, n_lobes: int
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
     key = cache_key(arch, cams, n, sh_degree, n_lobes, backward)
     cache_path = cache_path or default_cache_path()
-    cache = load_cache(cache_path) if use_cache else {}
-    if use_cache and key in cache:
-        return replace(base, **cache[key]["choice"]), cache[key]["report"]
+    if use_cache:
+        ent = lookup(key, cache_path)
+        if ent is not None:
+            return replace(base, **ent["choice"]), ent["report"]
 
     if target is None and backward:
         target = torch.rand(3 * sum(int(c.width) * int(c.height) for c in cams),
                             device=next(iter(params.values())).device)
     report = []
     best, best_ms = None, float("inf")
-    for cand in candidates(tiles, batches, backward):
+    for cand in candidates(tiles, batches, backward, schedules):
         opts = replace(base, **cand)
         rast = raster.Rasterizer(cams, opts, n, sh_degree, n_lobes)
         out = rast.forward(params, check=True)
@@ -124,10 +144,12 @@ def tune(params: dict, cams, base: Options, n: int, sh_degree: int, n_lobes: int
         del rast, out, gimg, grads
     torch.cuda.empty_cache()
     if use_cache:
+        cache = load_cache(cache_path)
         cache[key] = {"choice": best, "report": report}
         save_cache(cache_path, cache)
     return replace(base, **best), report
 
 
 __all__ = ["tune", "candidates", "cache_key", "load_cache", "save_cache", "default_cache_path",
-           "TILE_PPT", "BATCHES", "asdict"]
+           "lookup", "PACKAGED_TABLE",
+           "TILE_PPT", "BATCHES", "SCHEDULES", "asdict"]

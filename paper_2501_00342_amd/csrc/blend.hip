@@ -4,22 +4,32 @@
 // one column so that the column test and the x-terms of the power are
 // shared).  The tile's sorted Gaussians are streamed through LDS in
 // batches: each thread gathers 64-byte records, turns them into
-// tile-relative entries and all pixels of the tile read them back.  Forward (SG-Splatting
-// Preliminaries: splats "accumulated and blended" front to back):
+// tile-relative entries and all pixels of the tile read them back.  Forward
+// (the compositing of the Preliminaries section, front to back in depth):
 //   alpha = min(alpha_max, opacity * exp(-d^T Q d / 2)),  skip alpha < alpha_min,
 //   stop before T (1 - alpha) < T_min,  C += alpha T rgb,  T *= 1 - alpha.
 // exp(-d^T Q d / 2) is evaluated as exp2(-q), q = (w1.d)^2 + (w2.d)^2 with
 // whitening rows from the preprocess (one v_exp_f32, no conic cancellation).
 // Early exit: a wave skips the LDS loop once its 64 pixels are done and
 // the workgroup leaves when all pixels are done (__syncthreads_count).
-// Tile order: consecutive workgroup ids go to different XCDs, so block b is
-// mapped to a contiguous run of tiles per XCD to share L2 lines of records.
+// Tile order, two schedules:
+//   grid   one workgroup per tile; consecutive workgroup ids go to different
+//          XCDs, so block b is mapped to a contiguous run of tiles per XCD
+//          to share L2 lines of records;
+//   queue  a persistent grid (as many workgroups as fit on the chip at once)
+//          pops tiles from an atomic counter over a heavy-first tile order
+//          (tiles sorted by decreasing list length), so that the longest
+//          tiles start first and the short ones fill the tail.
 //
 // Backward: the same tile walk back to front from the saved final T and
 // n_contrib, recomputing alpha with the same instructions, T_j =
 // T_{j+1} / (1 - alpha_j).  Per-Gaussian 2D gradients are summed over a
 // thread's pixels, then across the wave with DPP, and added with one float
 // atomic per value per wave.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "common.hpp"
 
 namespace sgs {
@@ -107,20 +117,18 @@ __device__ __forceinline__ Entry load_entry(const Workspace& ws, int64_t pos, in
 // Thread t of a TW x TH tile with PPT pixels per thread owns column t % TW
 // and rows t / TW + k * (TH / PPT), k < PPT.
 template <int TW, int TH, int PPT, bool COUNT>
-__global__ void __launch_bounds__(TW * TH / PPT)
-k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
-            sgs_outputs out, int batch, unsigned long long* counts) {
+__device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
+                                         int n_cams, const Opts& o, const sgs_outputs& out,
+                                         int batch, int64_t tile, Entry* s_e, int* s_cam,
+                                         unsigned long long& visited,
+                                         unsigned long long& evaluated) {
     constexpr int NT = TW * TH / PPT;
     constexpr int RS = TH / PPT;   // row stride between a thread's pixels
-    extern __shared__ Entry s_e[];
-    __shared__ int s_cam;
     const int tid = threadIdx.x;
-    const int64_t tile = xcd_tile(blockIdx.x, ws.n_tiles);
-    if (tid == 0) s_cam = find_camera(ws.cams, n_cams, tile);
+    if (tid == 0) *s_cam = find_camera(ws.cams, n_cams, tile);
     __syncthreads();
-    const int cam = s_cam;
+    const int cam = *s_cam;
     const CamTable ct = ws.cams[cam];
-    if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
@@ -141,7 +149,6 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         n[k] = 0;
         if (x0 + lx < ct.W && y0 + ly0 + k * RS < ct.H) live |= 1u << k;
     }
-    unsigned long long visited = 0, evaluated = 0;
     for (uint32_t bs = start; bs < end; bs += batch) {
         if (__syncthreads_count(live != 0) == 0) break;
         const int cnt = (int)((end - bs) < (uint32_t)batch ? (end - bs) : (uint32_t)batch);
@@ -179,19 +186,7 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
             }
         }
     }
-    if (COUNT) {
-        __shared__ unsigned long long s_cnt[2];
-        if (tid == 0) s_cnt[0] = s_cnt[1] = 0ull;
-        __syncthreads();
-        atomicAdd(&s_cnt[0], visited);
-        atomicAdd(&s_cnt[1], evaluated);
-        __syncthreads();
-        if (tid == 0) {
-            atomicAdd(&counts[0], s_cnt[0]);
-            atomicAdd(&counts[1], s_cnt[1]);
-        }
-        return;
-    }
+    if (COUNT) return;
     const int64_t W = ct.W, H = ct.H;
     const sgs_camera& c = cams[cam];
     float* img = out.image + 3 * ct.pix_base;
@@ -206,6 +201,56 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         if (out.depth) out.depth[ct.pix_base + pix] = D[k];
         out.final_T[ct.pix_base + pix] = T[k];
         out.n_contrib[ct.pix_base + pix] = n[k];
+    }
+}
+
+// next tile of the queue schedule, or -1 once the queue is drained; every
+// thread of the workgroup gets the same answer.  The leading barrier keeps
+// the previous tile's LDS reads ahead of the next tile's writes.
+__device__ __forceinline__ int64_t pop_tile(const Workspace& ws, uint32_t* counter,
+                                            uint32_t* s_next) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_next = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t pos = *s_next;
+    if ((int64_t)pos >= ws.n_tiles) return -1;
+    const uint32_t t = ws.tile_order[pos];
+    return (int64_t)t < ws.n_tiles ? (int64_t)t : -1;
+}
+
+template <int TW, int TH, int PPT, bool COUNT, bool QUEUE>
+__global__ void __launch_bounds__(TW * TH / PPT)
+k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
+            sgs_outputs out, int batch, unsigned long long* counts) {
+    extern __shared__ Entry s_e[];
+    __shared__ int s_cam;
+    __shared__ uint32_t s_next;
+    if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    unsigned long long visited = 0, evaluated = 0;
+    if (QUEUE) {
+        for (;;) {
+            const int64_t tile = pop_tile(ws, ws.header + kHdrQueueFwd, &s_next);
+            if (tile < 0) break;
+            fwd_tile<TW, TH, PPT, COUNT>(ws, cams, n_cams, o, out, batch, tile, s_e, &s_cam,
+                                         visited, evaluated);
+        }
+    } else {
+        fwd_tile<TW, TH, PPT, COUNT>(ws, cams, n_cams, o, out, batch,
+                                     xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, visited,
+                                     evaluated);
+    }
+    if (COUNT) {
+        __shared__ unsigned long long s_cnt[2];
+        __syncthreads();
+        if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0ull;
+        __syncthreads();
+        atomicAdd(&s_cnt[0], visited);
+        atomicAdd(&s_cnt[1], evaluated);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            atomicAdd(&counts[0], s_cnt[0]);
+            atomicAdd(&counts[1], s_cnt[1]);
+        }
     }
 }
 
@@ -231,25 +276,21 @@ __device__ __forceinline__ float wave_sum63(float v) {
 }
 
 template <int TW, int TH, int PPT>
-__global__ void __launch_bounds__(TW * TH / PPT)
-k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
-            sgs_outputs fwd, const float* __restrict__ grad_image, int batch) {
+__device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
+                                         int n_cams, const Opts& o, const sgs_outputs& fwd,
+                                         const float* __restrict__ grad_image, int batch,
+                                         int64_t tile, Entry* s_e, int* s_cam, int* s_maxn) {
     constexpr int NT = TW * TH / PPT;
     constexpr int RS = TH / PPT;
-    extern __shared__ Entry s_e[];
-    __shared__ int s_cam;
-    __shared__ int s_maxn;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t tile = xcd_tile(blockIdx.x, ws.n_tiles);
     if (tid == 0) {
-        s_cam = find_camera(ws.cams, n_cams, tile);
-        s_maxn = 0;
+        *s_cam = find_camera(ws.cams, n_cams, tile);
+        *s_maxn = 0;
     }
     __syncthreads();
-    const int cam = s_cam;
+    const int cam = *s_cam;
     const CamTable ct = ws.cams[cam];
-    if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
@@ -287,9 +328,9 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         S2[k] = T[k] * c.bg[2];
         my_max = nc[k] > my_max ? nc[k] : my_max;
     }
-    if (my_max > 0) atomicMax(&s_maxn, my_max);
+    if (my_max > 0) atomicMax(s_maxn, my_max);
     __syncthreads();
-    const int maxn = s_maxn;
+    const int maxn = *s_maxn;
     const int64_t M = ws.n_items;
     float* G = ws.grad2d;
     const float inv_k = (float)(1.0 / kHalfLog2e);
@@ -369,14 +410,69 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
     }
 }
 
+template <int TW, int TH, int PPT, bool QUEUE>
+__global__ void __launch_bounds__(TW * TH / PPT)
+k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
+            sgs_outputs fwd, const float* __restrict__ grad_image, int batch) {
+    extern __shared__ Entry s_e[];
+    __shared__ int s_cam;
+    __shared__ int s_maxn;
+    __shared__ uint32_t s_next;
+    if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    if (QUEUE) {
+        for (;;) {
+            const int64_t tile = pop_tile(ws, ws.header + kHdrQueueBwd, &s_next);
+            if (tile < 0) break;
+            bwd_tile<TW, TH, PPT>(ws, cams, n_cams, o, fwd, grad_image, batch, tile, s_e, &s_cam,
+                                  &s_maxn);
+        }
+    } else {
+        bwd_tile<TW, TH, PPT>(ws, cams, n_cams, o, fwd, grad_image, batch,
+                              xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, &s_maxn);
+    }
+}
+
 // ---------------------------------------------------------------------------
+
+// workgroups of `kernel` resident on the whole chip at once (cached per
+// device, kernel and LDS size): the grid of the queue schedule
+template <typename K>
+static int64_t resident_blocks(K kernel, int threads, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, int64_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    const auto key = std::make_tuple(dev, reinterpret_cast<const void*>(kernel), lds);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int64_t r = (int64_t)(per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
+    cache[key] = r;
+    return r;
+}
+
+static unsigned grid_of(int64_t resident, int64_t n_tiles) {
+    const int64_t g = resident < 1 || resident > n_tiles ? n_tiles : resident;
+    return (unsigned)g;
+}
 
 template <int TW, int TH, int PPT>
 static void launch_fwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
-                         const sgs_outputs& out, hipStream_t s) {
+                         const sgs_outputs& out, bool queue, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, false>), dim3((unsigned)ws.n_tiles),
-                       dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, out, o.batch, nullptr);
+    constexpr int NT = TW * TH / PPT;
+    if (queue) {
+        auto k = k_blend_fwd<TW, TH, PPT, false, true>;
+        hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, NT, lds), ws.n_tiles)), dim3(NT), lds,
+                           s, ws, cams, n_cams, o, out, o.batch, nullptr);
+    } else {
+        hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, false, false>), dim3((unsigned)ws.n_tiles),
+                           dim3(NT), lds, s, ws, cams, n_cams, o, out, o.batch, nullptr);
+    }
 }
 
 template <int TW, int TH, int PPT>
@@ -384,17 +480,24 @@ static void launch_count_t(const Workspace& ws, const sgs_camera* cams, int n_ca
                            uint64_t* counts, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     sgs_outputs none = {};
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, true>), dim3((unsigned)ws.n_tiles),
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, true, false>), dim3((unsigned)ws.n_tiles),
                        dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, none, o.batch,
                        reinterpret_cast<unsigned long long*>(counts));
 }
 
 template <int TW, int TH, int PPT>
 static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
-                         const sgs_outputs& fwd, const float* gi, hipStream_t s) {
+                         const sgs_outputs& fwd, const float* gi, bool queue, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT>), dim3((unsigned)ws.n_tiles), dim3(TW * TH / PPT),
-                       lds, s, ws, cams, n_cams, o, fwd, gi, o.batch);
+    constexpr int NT = TW * TH / PPT;
+    if (queue) {
+        auto k = k_blend_bwd<TW, TH, PPT, true>;
+        hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, NT, lds), ws.n_tiles)), dim3(NT), lds,
+                           s, ws, cams, n_cams, o, fwd, gi, o.batch);
+    } else {
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false>), dim3((unsigned)ws.n_tiles), dim3(NT),
+                           lds, s, ws, cams, n_cams, o, fwd, gi, o.batch);
+    }
 }
 
 // supported (tile, pixels per thread): the block is a whole number of waves
@@ -412,9 +515,9 @@ static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams
     else if (o.tile_w == 32 && o.tile_h == 8) F<32, 8, 1>(__VA_ARGS__);
 
 void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                      const sgs_outputs& out, hipStream_t s) {
+                      const sgs_outputs& out, bool queue, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_fwd_t, o.ppt, ws, dev_cams, n_cams, o, out, s)
+    SGS_TILE_SWITCH(launch_fwd_t, o.ppt, ws, dev_cams, n_cams, o, out, queue, s)
 }
 
 void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
@@ -424,9 +527,9 @@ void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_c
 }
 
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                      const sgs_outputs& fwd, const float* grad_image, hipStream_t s) {
+                      const sgs_outputs& fwd, const float* grad_image, bool queue, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, grad_image, s)
+    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, grad_image, queue, s)
 }
 
 // ---------------------------------------------------------------------------

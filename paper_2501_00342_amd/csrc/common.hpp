@@ -26,6 +26,8 @@ enum Header : int {
     kHdrStatus = 0,
     kHdrPairs = 1,
     kHdrVisible = 2,      // items left after culling (length of the depth order)
+    kHdrQueueFwd = 3,     // next heavy-first tile position of the forward blend queue
+    kHdrQueueBwd = 4,     // same for the backward blend
     kHdrWords = 16
 };
 
@@ -54,6 +56,7 @@ constexpr double kHalfLog2e = 0.72134752044448170368;
 struct Opts {
     int tile_w, tile_h, batch;
     int ppt, ppt_bwd;
+    int schedule;        // SGS_SCHEDULE_GRID or SGS_SCHEDULE_QUEUE (resolved)
     float dilation, guard, alpha_min, alpha_max, t_min;
 };
 
@@ -87,6 +90,8 @@ struct Workspace {
     uint32_t* pair_tiles_alt;
     uint32_t* pair_values_alt;
     uint32_t* ranges;
+    uint32_t* tile_keys;         // heavy-first sort key of every tile
+    uint32_t* tile_order;        // tiles by decreasing list length (stable)
     float* grad2d;
     float* gx_colour;            // [3][n]: mean gradient through the view direction
     uint32_t* counts;            // radix pass: [256][partitions] digit counts -> offsets
@@ -120,12 +125,17 @@ void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint1
 void launch_scan_pairs(const Workspace& ws, hipStream_t s);
 void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
 void launch_ranges(const Workspace& ws, hipStream_t s);
+// tile_order = tiles sorted by decreasing list length (one stable 8-bit pass
+// over a log-scale length bucket)
+void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s);
+// `queue`: persistent workgroups over tile_order (requires launch_tile_order
+// after the ranges of the same forward); otherwise one workgroup per tile
 void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                      const sgs_outputs& out, hipStream_t s);
+                      const sgs_outputs& out, bool queue, hipStream_t s);
 void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                         uint64_t* counts, hipStream_t s);
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                      const sgs_outputs& fwd, const float* grad_image, hipStream_t s);
+                      const sgs_outputs& fwd, const float* grad_image, bool queue, hipStream_t s);
 void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                            const Workspace& ws, const sgs_grads& gr, hipStream_t s);
 void launch_l1(const Workspace& ws, int n_cams, const float* image, const float* target,

@@ -43,7 +43,12 @@ struct Plan {
     int64_t max_parts;
     // offsets not exported in sgs_layout
     size_t sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
-        pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial, gx_colour;
+        pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial, gx_colour,
+        tile_keys, tile_order;
+    int64_t tile_parts;   // partitions of the heavy-first tile sort
+    // the blends run the queue schedule: requested, and the forward builds
+    // the tile order (it does when there are Gaussians and pair capacity)
+    bool queue;
 };
 
 bool tile_shape_ok(int tw, int th) {
@@ -85,6 +90,10 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     o.batch = oin && oin->batch ? oin->batch : 256;
     if (o.batch < 64 || o.batch % 64 != 0 || o.batch > 1024)
         return fail(SGS_E_INVALID, "batch must be a multiple of 64 in [64, 1024]");
+    o.schedule = oin && oin->schedule ? oin->schedule
+                                      : (n_cams > 1 ? SGS_SCHEDULE_QUEUE : SGS_SCHEDULE_GRID);
+    if (o.schedule != SGS_SCHEDULE_GRID && o.schedule != SGS_SCHEDULE_QUEUE)
+        return fail(SGS_E_INVALID, "schedule must be 0, SGS_SCHEDULE_GRID or SGS_SCHEDULE_QUEUE");
     o.dilation = oin && oin->dilation != 0.0f ? oin->dilation : 0.3f;
     o.guard = oin && oin->guard != 0.0f ? oin->guard : 1.3f;
     o.alpha_min = oin && oin->alpha_min != 0.0f ? oin->alpha_min : 1.0f / 255.0f;
@@ -120,7 +129,10 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->pre_blocks = (int)(pb < 1 ? 1 : (pb > sgs::kPersistentBlocks ? sgs::kPersistentBlocks : pb));
     int64_t db = pl->dup_chunks;
     pl->dup_blocks = (int)(db < 1 ? 1 : (db > sgs::kPersistentBlocks ? sgs::kPersistentBlocks : db));
+    pl->tile_parts = cdiv(tiles, sgs::kSortTile);
     pl->max_parts = pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts;
+    if (pl->tile_parts > pl->max_parts) pl->max_parts = pl->tile_parts;
+    pl->queue = o.schedule == SGS_SCHEDULE_QUEUE && n > 0 && cap > 0;
 
     sgs_layout& L = pl->lay;
     memset(&L, 0, sizeof(L));
@@ -149,6 +161,8 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->pair_tiles_alt = take((size_t)cap * 4);
     pl->pair_values_alt = take((size_t)cap * 4);
     L.ranges = take((size_t)tiles * 8);
+    pl->tile_keys = take((size_t)tiles * 4);
+    pl->tile_order = take((size_t)tiles * 4);
     L.grad2d = take((size_t)items * 9 * 4);
     pl->gx_colour = take((size_t)n * 3 * 4);
     pl->counts = take((size_t)pl->max_parts * sgs::kRadix * 4);
@@ -183,6 +197,8 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.pair_tiles_alt = reinterpret_cast<uint32_t*>(b + pl.pair_tiles_alt);
     w.pair_values_alt = reinterpret_cast<uint32_t*>(b + pl.pair_values_alt);
     w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
+    w.tile_keys = reinterpret_cast<uint32_t*>(b + pl.tile_keys);
+    w.tile_order = reinterpret_cast<uint32_t*>(b + pl.tile_order);
     w.grad2d = reinterpret_cast<float*>(b + L.grad2d);
     w.gx_colour = reinterpret_cast<float*>(b + pl.gx_colour);
     w.counts = reinterpret_cast<uint32_t*>(b + pl.counts);
@@ -380,13 +396,14 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         SGS_LAUNCHED();
         mk.mark(6);
         sgs::launch_ranges(ws, s);
+        if (pl.queue) sgs::launch_tile_order(ws, pl.tile_parts, s);
         SGS_LAUNCHED();
     } else {
         mk.mark(5);
         mk.mark(6);
     }
     mk.mark(7);
-    sgs::launch_blend_fwd(ws, dev_cams, n_cams, o, *outs, s);
+    sgs::launch_blend_fwd(ws, dev_cams, n_cams, o, *outs, pl.queue, s);
     SGS_LAUNCHED();
     mk.mark(8);
     return SGS_OK;
@@ -417,8 +434,9 @@ int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const s
     Marker mk{timing_slot(g_timing.bwd, g_timing.bwd_used), s};
     mk.mark(0);
     sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, 9 * ws.n_items, s);
+    if (pl.queue) sgs::launch_fill_u32(ws.header + sgs::kHdrQueueBwd, 0u, 1, s);
     mk.mark(1);
-    sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, s);
+    sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, pl.queue, s);
     SGS_LAUNCHED();
     mk.mark(2);
     sgs::launch_preprocess_bwd(p, dev_cams, n_cams, pl.o, ws, *grads, s);

@@ -176,6 +176,36 @@ void launch_ranges(const Workspace& ws, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
+// heavy-first tile order for the queue schedule: key = 255 - bucket, bucket =
+// 0 for an empty tile, else 1 + 8 e + m with e = floor(log2(length)) and m the
+// three bits below the leading one (eight buckets per octave), so one stable
+// 8-bit pass puts long tiles first and keeps tile order within a bucket
+// --------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_tile_keys(Workspace ws) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ws.n_tiles) return;
+    const uint32_t a = ws.ranges[2 * t], b = ws.ranges[2 * t + 1];
+    const uint32_t len = b > a ? b - a : 0u;
+    uint32_t bucket = 0;
+    if (len > 0) {
+        const int e = 31 - __clz((int)len);
+        const uint32_t m = (e >= 3 ? len >> (e - 3) : len << (3 - e)) & 7u;
+        const uint32_t lb = 8u * (uint32_t)e + m;
+        bucket = 1u + (lb > 254u ? 254u : lb);
+    }
+    ws.tile_keys[t] = 255u - bucket;
+}
+
+void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s) {
+    if (ws.n_tiles <= 0) return;
+    const int64_t blocks = (ws.n_tiles + 255) / 256;
+    hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)blocks), dim3(256), 0, s, ws);
+    launch_radix_pass(ws.tile_keys, nullptr, nullptr, ws.tile_order, nullptr, ws.n_tiles, 0,
+                      ws.counts, ws.totals, parts, nullptr, nullptr, 0, false, nullptr, s);
+}
+
+// --------------------------------------------------------------------------
 // sorted 64-bit keys for inspection
 // --------------------------------------------------------------------------
 

@@ -121,6 +121,9 @@ class Rasterizer:
                                       self.ws.numel(), self.capacity, ctypes.byref(o), flags,
                                       ctypes.byref(need), _stream())
             if rc == L.SGS_E_CAPACITY and self.auto_grow:
+                if need.value > (1 << 30) - 1:
+                    raise L.SgsError(L.SGS_E_CAPACITY, f"{need.value} pairs exceed the 2^30 - 1 "
+                                     "pair limit of one call; render fewer cameras per call")
                 self.capacity = min((1 << 30) - 1, int(need.value * 1.15) + 4096)
                 self.ws = None
                 torch.cuda.current_stream().synchronize()

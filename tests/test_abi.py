@@ -82,7 +82,7 @@ def test_workspace_size_and_layout(lib):
     dict(sh=4), dict(K=9), dict(W=0), dict(H=40000), dict(cap=1 << 30), dict(n=-1),
     dict(opts=scenes.Options(tile_w=12, tile_h=12)), dict(opts=scenes.Options(batch=300)),
     dict(opts=scenes.Options(tile_w=8, tile_h=8, ppt=2)), dict(opts=scenes.Options(ppt=3)),
-    dict(opts=scenes.Options(alpha_max=1.5))])
+    dict(opts=scenes.Options(alpha_max=1.5)), dict(opts=scenes.Options(schedule=3))])
 def test_invalid_arguments_are_rejected_on_the_host(lib, bad):
     g, cams, o, cap = _args(lib, **bad)
     assert lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap) == 0

@@ -12,7 +12,8 @@ def test_candidates_are_all_accepted_by_the_library():
     g = L.gaussians_struct(1000, 1, 4, {})
     cams = L.camera_array([scenes.pinhole(200, 120, np.eye(3), (0, 0, 4))])
     cands = autotune.candidates()
-    assert len(cands) == sum(len(p) ** 2 for p in autotune.TILE_PPT.values()) * len(autotune.BATCHES)
+    assert len(cands) == (sum(len(p) ** 2 for p in autotune.TILE_PPT.values()) * len(autotune.BATCHES)
+                          * len(autotune.SCHEDULES))
     for c in cands:
         o = L.options_struct(scenes.Options(**c))
         assert L.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), 4096) > 0, c

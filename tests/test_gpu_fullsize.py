@@ -114,3 +114,72 @@ def test_full_frame_1m_sampled_gradients():
         want = ref[..., mask]
         nrm = np.linalg.norm(want)
         assert np.linalg.norm(got - want) <= 2e-3 * nrm + 1e-12, k
+
+
+def _check_sampled_camera(rast, sc, cam, opts, k, tile_base, img_dev, rng, n_tiles=12, n_pix=24):
+    """Camera k of a batched frame: depth keys and tile rectangles of its
+    items, the length of every one of its tile lists, sampled tile lists and
+    sampled pixels against the oracle."""
+    from tests.sampling import sample_tiles, tile_counts, tile_list
+    pre = F.preprocess(sc, cam, opts)
+    n = sc.n
+    keys = rast.depth_keys()[k * n:(k + 1) * n].cpu().numpy().view(np.uint32)
+    v = pre.visible
+    assert np.array_equal(keys != 0xFFFFFFFF, v), ("culling", k)
+    assert np.array_equal(keys[v], pre.depth_bits[v]), ("depth keys", k)
+    GX, GY = pre.grid
+    rng_gpu = rast.ranges()[tile_base:tile_base + GX * GY].cpu().numpy().view(np.uint32).astype(np.int64)
+    cnt = tile_counts(pre)
+    assert np.array_equal(rng_gpu[:, 1] - rng_gpu[:, 0], cnt), ("tile list lengths", k)
+    vals_dev = rast.pair_values(int(rng_gpu[:, 1].max()) if cnt.any() else 0)
+    for t in sample_tiles(cnt, n_tiles, rng):
+        a, b = rng_gpu[t]
+        got = vals_dev[a:b].cpu().numpy().view(np.uint32).astype(np.uint64)
+        assert np.array_equal(got, tile_list(pre, t, k * n)), ("tile list", k, t)
+    bad = []
+    for (py, px) in _sample_pixels(cam.width, cam.height, n_pix, rng):
+        ref = F.render_pixel(pre, cam, opts, px, py)
+        gpu = (img_dev[0][:, py, px], img_dev[1][py, px], img_dev[2][py, px], int(img_dev[3][py, px]))
+        if not parity.compare_pixel(gpu, ref):
+            bad.append((k, py, px, np.abs(gpu[0] - ref[0]).max(), gpu[3], ref[3]))
+    assert not bad, bad
+    return int(cnt.sum())
+
+
+def test_batched_64_cameras_sampled():
+    """2M Gaussians, 64 cameras of mixed size in one call (queue schedule):
+    four cameras (each size) are checked against the oracle, and every tile
+    range of the frame must tile [0, P) in order."""
+    sc, cams, opts = scenes.workload("sg-2m-64cam")
+    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
+    params = raster.params_to_device(sc)
+    out = rast.forward(params, check=True)
+    bits, P = rast.status()
+    assert bits == 0
+    rng_all = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
+    nz = rng_all[rng_all[:, 1] > rng_all[:, 0]]
+    assert nz[0, 0] == 0 and nz[-1, 1] == P and np.array_equal(nz[1:, 0], nz[:-1, 1])
+    sizes = {}
+    for k, c in enumerate(cams):
+        sizes.setdefault((c.width, c.height), k)
+    picks = sorted(set(sizes.values()) | {len(cams) - 1})
+    rng = np.random.default_rng(3)
+    for k in picks:
+        base = sum(-(-c.width // opts.tile_w) * -(-c.height // opts.tile_h) for c in cams[:k])
+        img = camera_numpy(out, cams, k)
+        _check_sampled_camera(rast, sc, cams[k], opts, k, base, img, rng)
+
+
+def test_stress_6m_sampled():
+    """6M Gaussians in tight clusters at 1920x1080: every tile list length,
+    the heaviest and sampled tile lists, and sampled pixels."""
+    sc, cams, opts = scenes.workload("sg-6m-1920")
+    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
+    params = raster.params_to_device(sc)
+    out = rast.forward(params, check=True)
+    bits, P = rast.status()
+    assert bits == 0
+    img = camera_numpy(out, cams, 0)
+    total = _check_sampled_camera(rast, sc, cams[0], opts, 0, 0, img, np.random.default_rng(4),
+                                  n_tiles=16, n_pix=48)
+    assert total == P
