@@ -16,4 +16,5 @@ from .sh import sh_basis, sh_basis_grad
 __all__ = ["Pre", "Image", "preprocess", "emit_pairs", "sort_pairs", "tile_ranges",
            "render", "render_batch", "render_pixel", "pixel_list", "blend_image",
            "ALPHA_BAND", "T_BAND", "blend_backward", "preprocess_backward", "l1_loss",
-           "render_and_grad", "fd_grad", "signature", "pixel_backward", "sh_basis", "sh_basis_grad"]
+           "render_and_grad", "fd_grad", "signature", "pixel_backward", "sh_basis",
+           "sh_basis_grad"]

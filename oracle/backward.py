@@ -32,9 +32,12 @@ F64 = np.float64
 GRAD2D = ("u", "v", "Qa", "Qb", "Qc", "sigma", "r", "g", "b")
 
 
-def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile_base=0):
+def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile_base=0,
+                   tiles=None):
     """Per-Gaussian gradients of sum(grad_image * image) w.r.t. the 2D
-    quantities (u, v, Qa, Qb, Qc, sigma, rgb) -> dict of (N,) arrays."""
+    quantities (u, v, Qa, Qb, Qc, sigma, rgb) -> dict of (N,) arrays.  With
+    `tiles`, only those local tiles' pixels are summed (the exact gradient
+    when grad_image is zero elsewhere)."""
     W, H = int(cam.width), int(cam.height)
     amax = R._f(opts.alpha_max)
     bg = cam.bg.astype(F64)
@@ -42,7 +45,7 @@ def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile
     n = pre.z.shape[0]
     out = {k: np.zeros(n) for k in GRAD2D}
     gimg = grad_image.astype(F64)
-    for t in range(GX * GY):
+    for t in (range(GX * GY) if tiles is None else tiles):
         tx, ty = t % GX, t // GX
         lo, hi = ranges[tile_base + t]
         if hi <= lo:
@@ -82,24 +85,17 @@ def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile
     return out
 
 
-def pixel_backward(pre, cam, opts, px, py, gC):
-    """2D-gradient contributions of one pixel (brute-force list, as in
-    `forward.render_pixel`) for upstream gradient gC (3,): dict g -> 9-vector
-    ordered as GRAD2D."""
+def _pixel_contributions(pre, opts, px, py, gC, blended, T_final, bg):
+    """Back-to-front walk of one pixel's blended splats [(g, alpha, T before
+    it)] ending at T_final: dict g -> 9-vector ordered as GRAD2D."""
     amax = R._f(opts.alpha_max)
-    bg = cam.bg.astype(F64)
-    entries = R.pixel_list(pre, px, py)
-    pxa, pya = np.array([px]), np.array([py])
-    C, D, Tf, nn, fl, trace = R._blend_tile(pre, entries, pxa, pya, opts, bg, want_trace=True)
-    gC = np.asarray(gC, F64).reshape(3, 1)
-    S = Tf[None, :] * bg[:, None]
+    gC = np.asarray(gC, F64)
+    S = T_final * bg
     out = {}
-    for (j, g, blend, a, T) in reversed(trace):
-        if not blend[0]:
-            continue
+    for (g, a, T) in reversed(blended):
         w = a * T
-        c = pre.rgb[:, g][:, None]
-        grgb = (gC * w).sum(axis=1)
+        c = pre.rgb[:, g]
+        grgb = gC * w
         dLda = float((gC * (T * c - S / (1.0 - a))).sum())
         S = S + w * c
         dx = px - pre.u[g]
@@ -109,7 +105,7 @@ def pixel_backward(pre, cam, opts, px, py, gC):
         E = np.exp(min(power, 0.0))
         v = np.zeros(9)
         if pre.opacity[g] * E <= amax:
-            dLdp = dLda * float(a[0]) if power <= 0.0 else 0.0
+            dLdp = dLda * a if power <= 0.0 else 0.0
             v[5] = dLda * E
             v[2] = dLdp * (-0.5 * dx * dx)
             v[3] = dLdp * (-dx * dy)
@@ -118,7 +114,19 @@ def pixel_backward(pre, cam, opts, px, py, gC):
             v[1] = dLdp * (Qb * dx + Qc * dy)
         v[6:9] = grgb
         out[int(g)] = out.get(int(g), 0.0) + v
-    return out, bool(fl[0])
+    return out
+
+
+def pixel_backward(pre, cam, opts, px, py, gC):
+    """2D-gradient contributions of one pixel (brute-force list, as in
+    `forward.render_pixel`) for upstream gradient gC (3,): (dict g ->
+    9-vector ordered as GRAD2D, tie flag) on the FP64 decision path."""
+    bg = cam.bg.astype(F64)
+    entries = R.pixel_list(pre, px, py)
+    pxa, pya = np.array([px]), np.array([py])
+    C, D, Tf, nn, fl, trace = R._blend_tile(pre, entries, pxa, pya, opts, bg, want_trace=True)
+    blended = [(g, float(a[0]), float(T[0])) for (j, g, blend, a, T) in trace if blend[0]]
+    return _pixel_contributions(pre, opts, px, py, gC, blended, float(Tf[0]), bg), bool(fl[0])
 
 
 def _quat_rotation_grad(w, x, y, z, gR):

@@ -2,9 +2,10 @@
 //
 // One workgroup per tile (TW x TH pixels, PPT pixels per thread, stacked in
 // one column so that the column test and the x-terms of the power are
-// shared).  The tile's sorted Gaussians are streamed through LDS in
-// batches: each thread gathers 64-byte records, turns them into
-// tile-relative entries and all pixels of the tile read them back.  Forward
+// shared; a wave owns a compact block of rows).  The tile's sorted
+// Gaussians are streamed through LDS in batches: each thread gathers 64-byte
+// records, turns them into tile-relative entries and all pixels of the tile
+// read them back.  Forward
 // (the compositing of the Preliminaries section, front to back in depth):
 //   alpha = min(alpha_max, opacity * exp(-d^T Q d / 2)),  skip alpha < alpha_min,
 //   stop before T (1 - alpha) < T_min,  C += alpha T rgb,  T *= 1 - alpha.
@@ -115,7 +116,8 @@ __device__ __forceinline__ Entry load_entry(const Workspace& ws, int64_t pos, in
 }
 
 // Thread t of a TW x TH tile with PPT pixels per thread owns column t % TW
-// and rows t / TW + k * (TH / PPT), k < PPT.
+// and the PPT consecutive rows from (t / TW) * PPT, so that a wave covers a
+// compact TW x (64 / TW) * PPT block and small splats touch few waves.
 template <int TW, int TH, int PPT, bool COUNT>
 __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
                                          int n_cams, const Opts& o, const sgs_outputs& out,
@@ -123,7 +125,6 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
                                          unsigned long long& visited,
                                          unsigned long long& evaluated) {
     constexpr int NT = TW * TH / PPT;
-    constexpr int RS = TH / PPT;   // row stride between a thread's pixels
     const int tid = threadIdx.x;
     if (tid == 0) *s_cam = find_camera(ws.cams, n_cams, tile);
     __syncthreads();
@@ -132,7 +133,7 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int lx = tid % TW, ly0 = tid / TW;
+    const int lx = tid % TW, ry = (tid / TW) * PPT;   // rows ry .. ry + PPT - 1
     const uint32_t start = ws.ranges[2 * tile];
     const uint32_t end = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity ? ws.ranges[2 * tile + 1] : start;
     const uint32_t colbit = 1u << lx;
@@ -147,7 +148,7 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
         n[k] = 0;
-        if (x0 + lx < ct.W && y0 + ly0 + k * RS < ct.H) live |= 1u << k;
+        if (x0 + lx < ct.W && y0 + ry + k < ct.H) live |= 1u << k;
     }
     for (uint32_t bs = start; bs < end; bs += batch) {
         if (__syncthreads_count(live != 0) == 0) break;
@@ -165,9 +166,9 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     if (!((live >> k) & 1u)) continue;
-                    if (!((e.m.y >> (ly0 + k * RS)) & 1u)) continue;
+                    if (!((e.m.y >> (ry + k)) & 1u)) continue;
                     if (COUNT) ++evaluated;
-                    const Eval v = eval_splat(e, t1, t2, (float)(ly0 + k * RS) + e.a.y, amax);
+                    const Eval v = eval_splat(e, t1, t2, (float)(ry + k) + e.a.y, amax);
                     if (v.alpha < amin) continue;
                     const float Tn = T[k] * (1.0f - v.alpha);
                     if (Tn < tmin) {
@@ -192,7 +193,7 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
     float* img = out.image + 3 * ct.pix_base;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int px = x0 + lx, py = y0 + ly0 + k * RS;
+        const int px = x0 + lx, py = y0 + ry + k;
         if (px >= ct.W || py >= ct.H) continue;
         const int64_t pix = (int64_t)py * W + px;
         img[pix] = C0[k] + T[k] * c.bg[0];
@@ -281,7 +282,6 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                                          const float* __restrict__ grad_image, int batch,
                                          int64_t tile, Entry* s_e, int* s_cam, int* s_maxn) {
     constexpr int NT = TW * TH / PPT;
-    constexpr int RS = TH / PPT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     if (tid == 0) {
@@ -294,7 +294,7 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int lx = tid % TW, ly0 = tid / TW;
+    const int lx = tid % TW, ry = (tid / TW) * PPT;   // rows ry .. ry + PPT - 1
     const uint32_t start = ws.ranges[2 * tile];
     const int64_t len = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity
                             ? (int64_t)ws.ranges[2 * tile + 1] - start : 0;
@@ -310,7 +310,7 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     int my_max = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int px = x0 + lx, py = y0 + ly0 + k * RS;
+        const int px = x0 + lx, py = y0 + ry + k;
         T[k] = 1.0f;
         g0[k] = g1[k] = g2[k] = 0.0f;
         nc[k] = 0;
@@ -353,8 +353,8 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                 const float t1 = e.a.z * dx, t2 = e.b.x * dx;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    if (pos >= nc[k] || !((e.m.y >> (ly0 + k * RS)) & 1u)) continue;
-                    const float dy = (float)(ly0 + k * RS) + e.a.y;
+                    if (pos >= nc[k] || !((e.m.y >> (ry + k)) & 1u)) continue;
+                    const float dy = (float)(ry + k) + e.a.y;
                     const Eval v = eval_splat(e, t1, t2, dy, amax);
                     if (v.alpha < amin) continue;
                     contrib = true;

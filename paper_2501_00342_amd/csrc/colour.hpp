@@ -13,8 +13,9 @@ __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp
 
 // colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)).
 // Returns false when a colour parameter is non-finite or a lobe axis has
-// zero length (the Gaussian is culled).
-template <int DEG>
+// zero length (the Gaussian is culled).  KMAX >= n_lobes bounds the unrolled
+// lobe loop (constant array offsets).
+template <int DEG, int KMAX>
 __device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
                                        float rgb[3]) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
@@ -31,7 +32,9 @@ __device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, flo
             ok = ok && isfinite(f);
             rgb[c] = fmaf(f, Y[l], rgb[c]);
         }
-    for (int k = 0; k < p.n_lobes; ++k) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k >= p.n_lobes) break;
         const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
         const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
         const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
@@ -80,7 +83,7 @@ __device__ __forceinline__ void colour_bwd(const Params& p, int64_t g, float d0,
     constexpr int NC = (DEG + 1) * (DEG + 1);
     const int64_t n = p.n;
     float raw[3];
-    colour<DEG>(p, g, d0, d1, d2, raw);
+    colour<DEG, KMAX>(p, g, d0, d1, d2, raw);
     // max(0, .): derivative 1 where the raw colour is >= 0
     const float gc[3] = {raw[0] >= 0.0f ? grgb[0] : 0.0f, raw[1] >= 0.0f ? grgb[1] : 0.0f,
                          raw[2] >= 0.0f ? grgb[2] : 0.0f};

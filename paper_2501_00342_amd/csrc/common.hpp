@@ -112,16 +112,19 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
                   float guard, hipStream_t s);
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                        const Workspace& ws, int hist_blocks, hipStream_t s);
-// One stable pass.  With `drop_culled`, keys equal to 0xFFFFFFFF are removed
-// and the number of kept items is written to *kept_out.
+// One stable pass over the digit (key >> shift) & 255.  With `drop_culled`,
+// keys equal to 0xFFFFFFFF are removed and the number of kept items is
+// written to *kept_out.  digit_bits < 8 declares that the key has no set
+// bits above shift + digit_bits (fewer ballots in the ranking).
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
                        uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                       hipStream_t s);
+                       hipStream_t s, int digit_bits = kRadixBits);
 void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
-                         uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s);
+                         uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s,
+                         int digit_bits = kRadixBits);
 void launch_scan_pairs(const Workspace& ws, hipStream_t s);
 void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
 void launch_ranges(const Workspace& ws, hipStream_t s);

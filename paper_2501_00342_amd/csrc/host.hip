@@ -383,15 +383,19 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         uint32_t* tv[2] = {wd.pair_values, wd.pair_values == ws.pair_values ? ws.pair_values_alt : ws.pair_values};
         for (int ps = 0; ps < pl.tile_passes; ++ps) {
             const int a = ps % 2, b = 1 - a;
+            // tile ids are below 2^tile_bits: the last pass has fewer digit bits
+            const int left = pl.tile_bits - ps * sgs::kRadixBits;
+            const int nb = left < sgs::kRadixBits ? left : sgs::kRadixBits;
             if (ws.key16)
                 sgs::launch_radix_pass16(reinterpret_cast<const uint16_t*>(tk[a]), tv[a],
                                          reinterpret_cast<uint16_t*>(tk[b]), tv[b],
                                          ws.header + sgs::kHdrPairs, pair_capacity,
-                                         ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts, s);
+                                         ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts, s,
+                                         nb);
             else
                 sgs::launch_radix_pass(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs,
                                        pair_capacity, ps * sgs::kRadixBits, ws.counts, ws.totals,
-                                       pl.pair_parts, nullptr, nullptr, 0, false, nullptr, s);
+                                       pl.pair_parts, nullptr, nullptr, 0, false, nullptr, s, nb);
         }
         SGS_LAUNCHED();
         mk.mark(6);

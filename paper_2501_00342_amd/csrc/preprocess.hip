@@ -120,7 +120,7 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     return r;
 }
 
-template <int DEG>
+template <int DEG, int KMAX>
 __global__ void __launch_bounds__(kPreThreads)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
     const int64_t n = p.n;
@@ -151,7 +151,7 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             if (vis) {
                 float d[3], dist;
                 view_dir(X, cam, d, &dist);
-                vis = colour<DEG>(p, g, d[0], d[1], d[2], rgb);
+                vis = colour<DEG, KMAX>(p, g, d[0], d[1], d[2], rgb);
             }
             uint32_t key = 0xFFFFFFFFu;
             uint64_t trect = 1;  // tx0 = 1 > tx1 = 0: no pairs
@@ -206,15 +206,24 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
     }
 }
 
+template <int KMAX>
+static void launch_pre_k(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
+                         const Workspace& ws, dim3 grid, hipStream_t s) {
+    const dim3 block(kPreThreads);
+    switch (p.sh_degree) {
+        case 0: hipLaunchKernelGGL((k_preprocess<0, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        case 1: hipLaunchKernelGGL((k_preprocess<1, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        case 2: hipLaunchKernelGGL((k_preprocess<2, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        default: hipLaunchKernelGGL((k_preprocess<3, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+    }
+}
+
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                        const Workspace& ws, int hist_blocks, hipStream_t s) {
-    dim3 grid(hist_blocks), block(kPreThreads);
-    switch (p.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        default: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-    }
+    const dim3 grid(hist_blocks);
+    if (p.n_lobes == 0) launch_pre_k<0>(p, dev_cams, n_cams, o, ws, grid, s);
+    else if (p.n_lobes <= 4) launch_pre_k<4>(p, dev_cams, n_cams, o, ws, grid, s);
+    else launch_pre_k<SGS_MAX_LOBES>(p, dev_cams, n_cams, o, ws, grid, s);
 }
 
 }  // namespace sgs

@@ -101,7 +101,9 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
     }
 }
 
-template <typename KeyT>
+// NB: significant bits of the digit (the key has no bits above shift + NB),
+// so ranking needs NB ballots instead of kRadixBits
+template <typename KeyT, int NB>
 __global__ void __launch_bounds__(kSortThreads)
 k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
             KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -162,7 +164,7 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         uint64_t m = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < NB; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t bb = __ballot(bit);
             m &= bit ? bb : ~bb;
@@ -218,36 +220,61 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     }
 }
 
+template <typename KeyT, int NB>
+static void downsweep_t(dim3 grid, hipStream_t s, const KeyT* keys_in, const uint32_t* vals_in,
+                        KeyT* keys_out, uint32_t* vals_out, const uint32_t* count_ptr,
+                        int64_t count_host, int shift, const uint32_t* counts,
+                        const uint32_t* totals, int64_t parts, const uint64_t* rects,
+                        uint32_t* pairs_out, int64_t n_rects, bool drop) {
+    hipLaunchKernelGGL((k_downsweep<KeyT, NB>), grid, dim3(kSortThreads), 0, s, keys_in, vals_in,
+                       keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts,
+                       rects, pairs_out, n_rects, drop);
+}
+
 template <typename KeyT>
 static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                          uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
                          uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                         hipStream_t s) {
+                         int digit_bits, hipStream_t s) {
     if (parts <= 0) return;
     hipLaunchKernelGGL(k_upsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
                        count_ptr, count_host, shift, counts, parts, drop_culled);
     hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts, totals,
                        drop_culled ? kept_out : nullptr);
-    hipLaunchKernelGGL(k_downsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
-                       vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts,
-                       rects, pairs_out, n_rects, drop_culled);
+    const dim3 g((unsigned)parts);
+#define SGS_DOWNSWEEP(NB)                                                                      \
+    downsweep_t<KeyT, NB>(g, s, keys_in, vals_in, keys_out, vals_out, count_ptr, count_host,   \
+                          shift, counts, totals, parts, rects, pairs_out, n_rects, drop_culled)
+    switch (digit_bits) {
+        case 1: SGS_DOWNSWEEP(1); break;
+        case 2: SGS_DOWNSWEEP(2); break;
+        case 3: SGS_DOWNSWEEP(3); break;
+        case 4: SGS_DOWNSWEEP(4); break;
+        case 5: SGS_DOWNSWEEP(5); break;
+        case 6: SGS_DOWNSWEEP(6); break;
+        case 7: SGS_DOWNSWEEP(7); break;
+        default: SGS_DOWNSWEEP(8); break;
+    }
+#undef SGS_DOWNSWEEP
 }
 
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
                        uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                       hipStream_t s) {
+                       hipStream_t s, int digit_bits) {
     radix_pass_t<uint32_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
-                           totals, parts, rects, pairs_out, n_rects, drop_culled, kept_out, s);
+                           totals, parts, rects, pairs_out, n_rects, drop_culled, kept_out,
+                           digit_bits, s);
 }
 
 void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
-                         uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s) {
+                         uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s,
+                         int digit_bits) {
     radix_pass_t<uint16_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
-                           totals, parts, nullptr, nullptr, 0, false, nullptr, s);
+                           totals, parts, nullptr, nullptr, 0, false, nullptr, digit_bits, s);
 }
 
 // ---------------------------------------------------------------------------
