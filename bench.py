@@ -90,7 +90,7 @@ def capture(fn, torch):
     return g
 
 
-def cpu_baseline(scene, cam, opts, n_tiles_sample=24):
+def cpu_baseline(scene, cam, opts, n_tiles_sample=800):
     """The FP64 oracle on a bounded sample of the same frame: full
     preprocess, key emission and stable sort, and the blend of a random
     sample of tiles, scaled to the frame's tile count."""
@@ -121,10 +121,13 @@ def cpu_baseline(scene, cam, opts, n_tiles_sample=24):
 SINGLE_KERNEL_STAGES = ("fwd.preprocess", "fwd.duplicate", "fwd.blend")
 
 
-def source_digest(path):
+def source_digest(paths):
     import hashlib
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_traffic(stage, workload, shape):
@@ -133,9 +136,11 @@ def counter_traffic(stage, workload, shape):
     None when there is none for this workload and launch shape, or the
     kernel's source has changed since the counters were taken."""
     import glob
-    src = {"fwd.blend": "paper_2501_00342_amd/csrc/blend.hip",
-           "fwd.preprocess": "paper_2501_00342_amd/csrc/preprocess.hip",
-           "fwd.duplicate": "paper_2501_00342_amd/csrc/sort.hip"}.get(stage)
+    c = "paper_2501_00342_amd/csrc/"
+    src = {"fwd.blend": [c + "blend.hip", c + "common.hpp"],
+           "fwd.preprocess": [c + "preprocess.hip", c + "colour.hpp", c + "sh_basis.hpp",
+                              c + "common.hpp"],
+           "fwd.duplicate": [c + "sort.hip", c + "common.hpp"]}.get(stage)
     if src is None:
         return None
     digest = source_digest(src)
