@@ -52,13 +52,16 @@ def parse():
 
 def stage_bytes(name, n, nvis, P, tiles, fpg, tile_passes, npix):
     """Algorithmic HBM bytes of each stage for one frame."""
+    kb = 2 if tiles <= 65536 else 4   # bytes per tile key
     return {
         "fwd.preprocess": n * (4 * fpg) + n * (4 + 8) + nvis * 64,
         "fwd.depth_sort": 56 * n,
         "fwd.pair_scan": n * (4 + 8 + 4),
         "fwd.duplicate": nvis * (4 + 4 + 8) + 8 * P,
-        "fwd.tile_sort": 16 * P * tile_passes,
-        "fwd.ranges": 4 * P + 8 * tiles,
+        # per pass: the downsweep reads and writes (key, value); every pass but
+        # the first (counted by the duplicate) reads the keys once more
+        "fwd.tile_sort": (2 * (kb + 4) * tile_passes + kb * (tile_passes - 1)) * P,
+        "fwd.tile_order": None,  # heavy-first order of the queue schedule
         "fwd.blend": None,
         "bwd.blend": None,
         "bwd.preprocess": nvis * 36 + 2 * n * (4 * fpg),

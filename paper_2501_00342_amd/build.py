@@ -30,7 +30,10 @@ SOURCES = {
     "preprocess_bwd.hip": ["-ffp-contract=off"],
     "sort.hip": [],
     "radix.hip": [],
-    "blend.hip": [],
+    # the blends' atomics come from one lane with a wave-uniform address
+    # (already reduced with DPP): LLVM's atomic optimizer would only wrap
+    # each of them in a second, redundant wave reduction
+    "blend.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
 }
 
 COMMON = [

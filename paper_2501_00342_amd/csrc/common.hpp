@@ -115,19 +115,24 @@ void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, 
 // One stable pass over the digit (key >> shift) & 255.  With `drop_culled`,
 // keys equal to 0xFFFFFFFF are removed and the number of kept items is
 // written to *kept_out.  digit_bits < 8 declares that the key has no set
-// bits above shift + digit_bits (fewer ballots in the ranking).
+// bits above shift + digit_bits (fewer ballots in the ranking).  counted:
+// the digit counts of every half partition (kSortTile / 2 items) are already
+// in counts[d * 2 parts + h]; the pass then skips its upsweep.  ranges: the
+// pass is the last of a tile sort; the tile ranges (cleared beforehand) are
+// written from the key changes of its sorted output.
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
                        uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                       hipStream_t s, int digit_bits = kRadixBits);
+                       hipStream_t s, int digit_bits = kRadixBits, bool counted = false,
+                       uint32_t* ranges = nullptr, int64_t n_tiles = 0);
 void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                          uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s,
-                         int digit_bits = kRadixBits);
+                         int digit_bits = kRadixBits, bool counted = false,
+                         uint32_t* ranges = nullptr, int64_t n_tiles = 0);
 void launch_scan_pairs(const Workspace& ws, hipStream_t s);
 void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
-void launch_ranges(const Workspace& ws, hipStream_t s);
 // tile_order = tiles sorted by decreasing list length (one stable 8-bit pass
 // over a log-scale length bucket)
 void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s);

@@ -132,6 +132,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->tile_parts = cdiv(tiles, sgs::kSortTile);
     pl->max_parts = pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts;
     if (pl->tile_parts > pl->max_parts) pl->max_parts = pl->tile_parts;
+    if (2 * pl->pair_parts > pl->max_parts) pl->max_parts = 2 * pl->pair_parts;   // duplicate's counts
     pl->queue = o.schedule == SGS_SCHEDULE_QUEUE && n > 0 && cap > 0;
 
     sgs_layout& L = pl->lay;
@@ -252,7 +253,7 @@ constexpr int kBwdEvents = 4;   // 3 backward stages
 constexpr size_t kMaxTimedCalls = 4096;
 const char* const kStageNames[SGS_N_STAGES] = {
     "fwd.setup", "fwd.preprocess", "fwd.depth_sort", "fwd.pair_scan", "fwd.duplicate",
-    "fwd.tile_sort", "fwd.ranges", "fwd.blend", "bwd.clear", "bwd.blend", "bwd.preprocess"};
+    "fwd.tile_sort", "fwd.tile_order", "fwd.blend", "bwd.clear", "bwd.blend", "bwd.preprocess"};
 
 struct Timing {
     bool on = false;
@@ -386,20 +387,24 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
             // tile ids are below 2^tile_bits: the last pass has fewer digit bits
             const int left = pl.tile_bits - ps * sgs::kRadixBits;
             const int nb = left < sgs::kRadixBits ? left : sgs::kRadixBits;
+            // the duplicate counted the first pass's digits; the last pass
+            // writes the tile ranges
+            const bool counted = ps == 0;
+            uint32_t* rng = ps == pl.tile_passes - 1 ? ws.ranges : nullptr;
             if (ws.key16)
                 sgs::launch_radix_pass16(reinterpret_cast<const uint16_t*>(tk[a]), tv[a],
                                          reinterpret_cast<uint16_t*>(tk[b]), tv[b],
                                          ws.header + sgs::kHdrPairs, pair_capacity,
                                          ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts, s,
-                                         nb);
+                                         nb, counted, rng, ws.n_tiles);
             else
                 sgs::launch_radix_pass(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs,
                                        pair_capacity, ps * sgs::kRadixBits, ws.counts, ws.totals,
-                                       pl.pair_parts, nullptr, nullptr, 0, false, nullptr, s, nb);
+                                       pl.pair_parts, nullptr, nullptr, 0, false, nullptr, s, nb,
+                                       counted, rng, ws.n_tiles);
         }
         SGS_LAUNCHED();
         mk.mark(6);
-        sgs::launch_ranges(ws, s);
         if (pl.queue) sgs::launch_tile_order(ws, pl.tile_parts, s);
         SGS_LAUNCHED();
     } else {

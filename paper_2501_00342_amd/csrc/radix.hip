@@ -110,7 +110,7 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
             const uint32_t* count_ptr, int64_t count_host, int shift,
             const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int64_t parts,
             const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out, int64_t n_rects,
-            bool drop) {
+            bool drop, int cstride, uint32_t* __restrict__ ranges, int64_t n_tiles) {
     constexpr int WAVES = kSortThreads / 64;
     constexpr int WAVE_ITEMS = 64 * kSortItems;
     __shared__ uint32_t s_keys[kSortTile];
@@ -138,19 +138,25 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
             s_local[d] += t;
             __syncthreads();
         }
-        s_global[d] = s_local[d] - tot + counts[(int64_t)d * parts + p];
+        s_global[d] = s_local[d] - tot + counts[((int64_t)d * parts + p) * cstride];
         __syncthreads();
     }
 
     uint32_t key[kSortItems], val[kSortItems];
     uint16_t rank[kSortItems];
+    // this wave's items in 32-bit offsets from a wave-uniform base pointer
+    // (counts stay below 2^30)
     const int64_t wbase = base + (int64_t)wave * WAVE_ITEMS;
+    const int64_t left = count - wbase;
+    const int lim = left <= 0 ? 0 : (left >= WAVE_ITEMS ? WAVE_ITEMS : (int)left);
+    const KeyT* __restrict__ kin = keys_in + wbase;
+    const uint32_t* __restrict__ vin = vals_in ? vals_in + wbase : nullptr;
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = wbase + k * 64 + lane;
-        if (i < count) {
-            key[k] = keys_in[i];
-            val[k] = vals_in ? vals_in[i] : (uint32_t)i;
+        const int li = k * 64 + lane;
+        if (li < lim) {
+            key[k] = kin[li];
+            val[k] = vin ? vin[li] : (uint32_t)wbase + (uint32_t)li;
         } else {
             key[k] = 0xFFFFFFFFu;
             val[k] = 0;
@@ -159,8 +165,8 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = wbase + k * 64 + lane;
-        const bool valid = i < count && !(drop && key[k] == 0xFFFFFFFFu);
+        const int li = k * 64 + lane;
+        const bool valid = li < lim && !(drop && key[k] == 0xFFFFFFFFu);
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -199,8 +205,8 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     }
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = wbase + k * 64 + lane;
-        if (i < count && !(drop && key[k] == 0xFFFFFFFFu)) {
+        const int li = k * 64 + lane;
+        if (li < lim && !(drop && key[k] == 0xFFFFFFFFu)) {
             const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
             const uint32_t pos = s_local[dd] + s_wave[wave][dd] + rank[k];
             s_keys[pos] = key[k];
@@ -213,10 +219,58 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
         const uint32_t k = s_keys[i];
         const uint32_t dd = (k >> shift) & (kRadix - 1);
         const uint32_t out = s_global[dd] + (uint32_t)(i - (int)s_local[dd]);
+        __builtin_assume(out < (1u << 30));
         const uint32_t v = s_vals[i];
         if (keys_out) keys_out[out] = (KeyT)k;
         vals_out[out] = v;
         if (pairs_out) pairs_out[out] = v < (uint64_t)n_rects ? rect_pairs(rects[v]) : 0u;
+        // last tile pass: a key change between neighbours of this block's run
+        // is a tile boundary (run starts are checked by k_range_edges)
+        if (ranges && i > (int)s_local[dd]) {
+            const uint32_t pk = s_keys[i - 1];
+            if (pk != k) {
+                if (k < (uint64_t)n_tiles) ranges[2 * (int64_t)k] = out;
+                if (pk < (uint64_t)n_tiles) ranges[2 * (int64_t)pk + 1] = out;
+            }
+        }
+    }
+}
+
+// Tile boundaries at the start of each (digit, partition) run of the last
+// tile pass, where the previous element was written by another block, and
+// the end of the last tile.  Block (x, d) checks partitions x * 256 + t.
+template <typename KeyT>
+__global__ void __launch_bounds__(256)
+k_range_edges(const KeyT* __restrict__ keys, const uint32_t* __restrict__ counts,
+              const uint32_t* __restrict__ totals, int64_t parts, int cstride,
+              const uint32_t* count_ptr, int64_t count_host, uint32_t* __restrict__ ranges,
+              int64_t n_tiles) {
+    __shared__ uint32_t s_base;
+    const int d = blockIdx.y;
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int e = 0; e < d; ++e) b += totals[e];
+        s_base = b;
+    }
+    __syncthreads();
+    const int64_t count = pass_count(count_ptr, count_host);
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < parts) {
+        const uint32_t off = counts[((int64_t)d * parts + p) * cstride];
+        const uint32_t next =
+            p + 1 < parts ? counts[((int64_t)d * parts + p + 1) * cstride] : totals[d];
+        const int64_t at = (int64_t)s_base + off;
+        if (next > off && at > 0 && at < count) {
+            const uint32_t a = keys[at - 1], b = keys[at];
+            if (a != b) {
+                if (b < (uint64_t)n_tiles) ranges[2 * (int64_t)b] = (uint32_t)at;
+                if (a < (uint64_t)n_tiles) ranges[2 * (int64_t)a + 1] = (uint32_t)at;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && d == 0 && threadIdx.x == 0 && count > 0) {
+        const uint32_t last = keys[count - 1];
+        if (last < (uint64_t)n_tiles) ranges[2 * (int64_t)last + 1] = (uint32_t)count;
     }
 }
 
@@ -225,10 +279,11 @@ static void downsweep_t(dim3 grid, hipStream_t s, const KeyT* keys_in, const uin
                         KeyT* keys_out, uint32_t* vals_out, const uint32_t* count_ptr,
                         int64_t count_host, int shift, const uint32_t* counts,
                         const uint32_t* totals, int64_t parts, const uint64_t* rects,
-                        uint32_t* pairs_out, int64_t n_rects, bool drop) {
+                        uint32_t* pairs_out, int64_t n_rects, bool drop, int cstride,
+                        uint32_t* ranges, int64_t n_tiles) {
     hipLaunchKernelGGL((k_downsweep<KeyT, NB>), grid, dim3(kSortThreads), 0, s, keys_in, vals_in,
                        keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts,
-                       rects, pairs_out, n_rects, drop);
+                       rects, pairs_out, n_rects, drop, cstride, ranges, n_tiles);
 }
 
 template <typename KeyT>
@@ -236,16 +291,22 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                          uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
                          uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                         int digit_bits, hipStream_t s) {
+                         int digit_bits, bool counted, uint32_t* ranges, int64_t n_tiles,
+                         hipStream_t s) {
     if (parts <= 0) return;
-    hipLaunchKernelGGL(k_upsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
-                       count_ptr, count_host, shift, counts, parts, drop_culled);
-    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts, totals,
+    // counted: the digit counts of every half partition are already in
+    // counts[d][2 parts] (written by the pass's producer)
+    const int cstride = counted ? 2 : 1;
+    if (!counted)
+        hipLaunchKernelGGL(k_upsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
+                           count_ptr, count_host, shift, counts, parts, drop_culled);
+    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts * cstride, totals,
                        drop_culled ? kept_out : nullptr);
     const dim3 g((unsigned)parts);
 #define SGS_DOWNSWEEP(NB)                                                                      \
     downsweep_t<KeyT, NB>(g, s, keys_in, vals_in, keys_out, vals_out, count_ptr, count_host,   \
-                          shift, counts, totals, parts, rects, pairs_out, n_rects, drop_culled)
+                          shift, counts, totals, parts, rects, pairs_out, n_rects, drop_culled,  \
+                          cstride, ranges, n_tiles)
     switch (digit_bits) {
         case 1: SGS_DOWNSWEEP(1); break;
         case 2: SGS_DOWNSWEEP(2); break;
@@ -257,24 +318,34 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
         default: SGS_DOWNSWEEP(8); break;
     }
 #undef SGS_DOWNSWEEP
+    if (ranges) {
+        // the pass's output keys are sorted; its counts hold each partition's
+        // exclusive offset within its digit (the key has digit_bits bits here)
+        const int digits = 1 << (digit_bits < kRadixBits ? digit_bits : kRadixBits);
+        const dim3 eg((unsigned)((parts + 255) / 256), (unsigned)digits);
+        hipLaunchKernelGGL(k_range_edges<KeyT>, eg, dim3(256), 0, s, keys_out, counts, totals, parts,
+                           cstride, count_ptr, count_host, ranges, n_tiles);
+    }
 }
 
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
                        uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                       hipStream_t s, int digit_bits) {
+                       hipStream_t s, int digit_bits, bool counted, uint32_t* ranges,
+                       int64_t n_tiles) {
     radix_pass_t<uint32_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
                            totals, parts, rects, pairs_out, n_rects, drop_culled, kept_out,
-                           digit_bits, s);
+                           digit_bits, counted, ranges, n_tiles, s);
 }
 
 void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                          uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s,
-                         int digit_bits) {
+                         int digit_bits, bool counted, uint32_t* ranges, int64_t n_tiles) {
     radix_pass_t<uint16_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
-                           totals, parts, nullptr, nullptr, 0, false, nullptr, digit_bits, s);
+                           totals, parts, nullptr, nullptr, 0, false, nullptr, digit_bits, counted,
+                           ranges, n_tiles, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,29 +73,40 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
 // duplicate: one block per 4096-pair chunk, one thread per pair (balanced)
 // --------------------------------------------------------------------------
 
+// Also the first tile-sort pass's digit histogram: chunk c's counts of the
+// low 8 bits of its tile ids go to counts[d * 2 * pair_parts + c] (two
+// chunks per radix partition, so that pass needs no upsweep of its own);
+// chunks past the pair count get zero rows.
+static_assert(2 * kDupChunk == kSortTile, "two duplicate chunks per radix partition");
+
 __global__ void __launch_bounds__(256)
 k_duplicate(Workspace ws, int64_t n) {
     __shared__ uint32_t s_off[kDupChunk + 1];
     __shared__ uint32_t s_origin[kDupChunk + 1];   // global tile id of the rectangle origin
     __shared__ uint32_t s_wgx[kDupChunk + 1];      // width | GX << 16
     __shared__ uint32_t s_item[kDupChunk + 1];
+    __shared__ uint32_t s_hist[kRadix];
     const int tid = threadIdx.x;
     const uint32_t P = ws.header[kHdrPairs];
     const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
     const uint32_t nn = (uint32_t)n;
     const int64_t n_vis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
+    const int64_t row = 2 * ws.pair_parts;   // histogram row length
     for (int64_t chunk = blockIdx.x; chunk * kDupChunk < Pc; chunk += gridDim.x) {
         const int64_t p0 = chunk * kDupChunk;
         const int64_t p1 = (p0 + kDupChunk < Pc) ? p0 + kDupChunk : Pc;
         const int64_t i0 = ws.chunk_start[chunk];
-        if (i0 >= n_vis) continue;   // uniform: no chunk start was recorded
+        __syncthreads();   // previous chunk done with LDS
+        s_hist[tid] = 0;
         // visible items i0 .. cover [p0, p1); every visible item has >= 1 pair
         int64_t i_end = n_vis;
         if (chunk + 1 < ws.dup_chunks && p1 < Pc) i_end = (int64_t)ws.chunk_start[chunk + 1] + 1;
-        int64_t nloc = i_end - i0;
+        int64_t nloc = i0 < n_vis ? i_end - i0 : 0;   // 0: no chunk start was recorded
         if (nloc > kDupChunk + 1) nloc = kDupChunk + 1;
-        if (nloc < 1) continue;
-        __syncthreads();   // previous chunk done with LDS
+        if (nloc < 1) {
+            ws.counts[tid * row + chunk] = 0;
+            continue;   // uniform
+        }
         for (int j = tid; j < nloc; j += 256) {
             const int64_t i = i0 + j;
             uint32_t item = ws.sorted_items[i];
@@ -129,50 +140,19 @@ k_duplicate(Workspace ws, int64_t n) {
             else
                 ws.pair_tiles[p] = tile;
             ws.pair_values[p] = s_item[lo];
+            atomicAdd(&s_hist[tile & (kRadix - 1)], 1u);
         }
+        __syncthreads();
+        ws.counts[tid * row + chunk] = s_hist[tid];
     }
+    // zero rows for the chunks past the pair count
+    for (int64_t chunk = (Pc + kDupChunk - 1) / kDupChunk + blockIdx.x; chunk < row;
+         chunk += gridDim.x)
+        ws.counts[tid * row + chunk] = 0;
 }
 
 void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_duplicate, dim3((unsigned)ws.dup_blocks), dim3(256), 0, s, ws, n);
-}
-
-// --------------------------------------------------------------------------
-// tile ranges from the sorted tile ids
-// --------------------------------------------------------------------------
-
-// a tile starts where the sorted tile id changes; a block covers
-// 256 * kRangeItems consecutive pairs with lane-strided (coalesced) loads
-constexpr int kRangeItems = 16;
-
-template <typename KeyT>
-__global__ void __launch_bounds__(256) k_ranges(Workspace ws) {
-    const uint32_t P = ws.header[kHdrPairs];
-    const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
-    const int64_t base = (int64_t)blockIdx.x * 256 * kRangeItems;
-    if (base >= Pc) return;
-    const KeyT* tiles = reinterpret_cast<const KeyT*>(ws.pair_tiles);
-#pragma unroll 4
-    for (int k = 0; k < kRangeItems; ++k) {
-        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
-        if (i >= Pc) break;
-        const uint32_t t = tiles[i];
-        const uint32_t prev = i > 0 ? (uint32_t)tiles[i - 1] : 0xFFFFFFFFu;
-        if (t != prev) {
-            if ((int64_t)t < ws.n_tiles) ws.ranges[2 * (int64_t)t] = (uint32_t)i;
-            if (i > 0 && (int64_t)prev < ws.n_tiles) ws.ranges[2 * (int64_t)prev + 1] = (uint32_t)i;
-        }
-        if (i == Pc - 1 && (int64_t)t < ws.n_tiles) ws.ranges[2 * (int64_t)t + 1] = (uint32_t)Pc;
-    }
-}
-
-void launch_ranges(const Workspace& ws, hipStream_t s) {
-    const int64_t blocks = (ws.capacity + 256 * kRangeItems - 1) / (256 * kRangeItems);
-    if (blocks < 1) return;
-    if (ws.key16)
-        hipLaunchKernelGGL(k_ranges<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, ws);
-    else
-        hipLaunchKernelGGL(k_ranges<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, ws);
 }
 
 // --------------------------------------------------------------------------
