@@ -174,7 +174,7 @@ def choose_options(args, torch, scenes, autotune, params, cams, base, scene, tar
         return base, base, None
     # launch shapes picked by the autotuner (cached per GPU and workload): one
     # for the forward alone, one for forward + L1 + backward
-    kw = dict(reps=3, tiles=[(16, 16), (32, 8), (16, 8)], batches=(128, 256), target=target,
+    kw = dict(reps=3, tiles=[(16, 16), (32, 8), (16, 8)], batches=(64, 128, 256), target=target,
               use_cache=not args.retune)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     picked, reports = [], {}
@@ -195,7 +195,7 @@ def choose_options(args, torch, scenes, autotune, params, cams, base, scene, tar
 def shape_of(rast, o):
     c = rast.copts
     return (f"{o.tile_w}x{o.tile_h},ppt{c.pixels_per_thread},pptb{c.pixels_per_thread_bwd},"
-            f"b{c.batch or 256},s{c.schedule or 0}")
+            f"b{c.batch or 128},s{c.schedule or 0}")
 
 
 def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, target,

@@ -99,7 +99,7 @@ typedef struct sgs_camera {
 typedef struct sgs_options {
     int32_t tile_w, tile_h;          /* 16x16 (default), 8x8, 16x8, 8x16, 32x8 */
     int32_t batch;                   /* LDS batch depth: a multiple of the block size, <= 1024;
-                                        0 = 256 */
+                                        0 = 128 */
     float dilation;                  /* added to both diagonal entries of the 2D covariance (0.3) */
     float guard;                     /* guard band on the projection Jacobian, x tan(fov/2) (1.3) */
     float alpha_min;                 /* splats with alpha < alpha_min are skipped (1/255) */

@@ -11,15 +11,15 @@ namespace sgs {
 
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
-// colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)).
-// Returns false when a colour parameter is non-finite or a lobe axis has
-// zero length (the Gaussian is culled).  KMAX >= n_lobes bounds the unrolled
-// lobe loop (constant array offsets).
-template <int DEG, int KMAX>
-__device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
-                                       float rgb[3]) {
+// colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)),
+// reading the parameters through accessors: sh(l, c), axis(k, j),
+// lsh(k) (log-sharpness) and amp(k, c).  Returns false when a colour
+// parameter is non-finite or a lobe axis has zero length (the Gaussian is
+// culled).  KMAX >= n_lobes bounds the unrolled lobe loop.
+template <int DEG, int KMAX, typename SH, typename AX, typename LS, typename AM>
+__device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int n_lobes, float d0,
+                                            float d1, float d2, float rgb[3]) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    const int64_t n = p.n;
     bool ok = true;
     float Y[NC];
     sh_eval<DEG, float>(d0, d1, d2, Y);
@@ -28,20 +28,16 @@ __device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, flo
     for (int l = 0; l < NC; ++l)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float f = p.sh[((int64_t)l * 3 + c) * n + g];
+            const float f = sh(l, c);
             ok = ok && isfinite(f);
             rgb[c] = fmaf(f, Y[l], rgb[c]);
         }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        if (k >= p.n_lobes) break;
-        const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
-        const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
-        const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
-        const float ls = p.sg_log_sharpness[(int64_t)k * n + g];
-        const float a0 = p.sg_amplitudes[((int64_t)k * 3 + 0) * n + g];
-        const float a1 = p.sg_amplitudes[((int64_t)k * 3 + 1) * n + g];
-        const float a2 = p.sg_amplitudes[((int64_t)k * 3 + 2) * n + g];
+        if (k >= n_lobes) break;
+        const float m0 = axis(k, 0), m1 = axis(k, 1), m2 = axis(k, 2);
+        const float ls = lsh(k);
+        const float a0 = amp(k, 0), a1 = amp(k, 1), a2 = amp(k, 2);
         ok = ok && isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(ls) &&
              isfinite(a0) && isfinite(a1) && isfinite(a2);
         const float mn2 = m0 * m0 + m1 * m1 + m2 * m2;
@@ -53,6 +49,19 @@ __device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, flo
         rgb[2] = fmaf(a2, e, rgb[2]);
     }
     return ok;
+}
+
+// the colour of Gaussian g read from the global (component-major) arrays
+template <int DEG, int KMAX>
+__device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
+                                       float rgb[3]) {
+    const int64_t n = p.n;
+    return colour_eval<DEG, KMAX>(
+        [&](int l, int c) { return p.sh[((int64_t)l * 3 + c) * n + g]; },
+        [&](int k, int j) { return p.sg_axes[((int64_t)k * 3 + j) * n + g]; },
+        [&](int k) { return p.sg_log_sharpness[(int64_t)k * n + g]; },
+        [&](int k, int c) { return p.sg_amplitudes[((int64_t)k * 3 + c) * n + g]; }, p.n_lobes,
+        d0, d1, d2, rgb);
 }
 
 // Unit view direction from the camera centre (-R^T t) to the mean X: the

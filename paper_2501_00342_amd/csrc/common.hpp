@@ -18,6 +18,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kPreThreads = 256;
+constexpr int kPreTile = 128;                        // Gaussians per forward-preprocess block
 constexpr int kPersistentBlocks = 1024;              // grid of the persistent kernels
 constexpr int kDepthPasses = 4;                      // 32-bit depth keys
 

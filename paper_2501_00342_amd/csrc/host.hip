@@ -87,7 +87,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     if (!ppt_ok(o.ppt) || !ppt_ok(o.ppt_bwd))
         return fail(SGS_E_INVALID, "pixels_per_thread must be 1, 2 or 4 with tile_w*tile_h/ppt a "
                                    "multiple of 64");
-    o.batch = oin && oin->batch ? oin->batch : 256;
+    o.batch = oin && oin->batch ? oin->batch : 128;
     if (o.batch < 64 || o.batch % 64 != 0 || o.batch > 1024)
         return fail(SGS_E_INVALID, "batch must be a multiple of 64 in [64, 1024]");
     o.schedule = oin && oin->schedule ? oin->schedule

@@ -120,12 +120,65 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     return r;
 }
 
-template <int DEG, int KMAX>
-__global__ void __launch_bounds__(kPreThreads)
-k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
+// pointer to colour parameter row r of the component-major arrays: SH
+// coefficient (l, c) is row 3 l + c, then per lobe k the axis (3 rows), then
+// the log-sharpness rows, then the amplitudes (3 rows per lobe)
+__device__ __forceinline__ const float* colour_row(const Params& p, int nc3, int r) {
+    const int K = p.n_lobes;
     const int64_t n = p.n;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    if (r < nc3) return p.sh + (int64_t)r * n;
+    r -= nc3;
+    if (r < 3 * K) return p.sg_axes + (int64_t)r * n;
+    r -= 3 * K;
+    if (r < K) return p.sg_log_sharpness + (int64_t)r * n;
+    return p.sg_amplitudes + (int64_t)(r - K) * n;
+}
+
+// A block takes tiles of kPreTile consecutive Gaussians.  At the start of a
+// tile each wave issues direct global->LDS loads of its half of every colour
+// row (no registers held), then runs the float64 geometry while they are in
+// flight; the colour is evaluated from LDS afterwards.  The geometry's and
+// the colour's registers are then never live together.
+template <int DEG, int KMAX>
+__global__ void __launch_bounds__(kPreTile)
+k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    constexpr int MAXROWS = 3 * NC + 7 * KMAX;
+    // an even number of rows: the 16-byte loads fill rows in pairs
+    __shared__ float s_col[(MAXROWS + 1) & ~1][kPreTile];
+    const int64_t n = p.n;
+    const int rows = 3 * NC + 7 * p.n_lobes;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // rows start 16-byte aligned when n is a multiple of 4 (the arrays are)
+    const bool vec4 = (n & 3) == 0;
+    for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
+         base += (int64_t)gridDim.x * kPreTile) {
+        __syncthreads();   // the previous tile's colour rows are no longer read
+        if (vec4) {
+            // 16 bytes per lane: one instruction fills two rows (lanes 0-31 row
+            // r, lanes 32-63 row r + 1); wave w takes row pairs 2 w, 2 w + 4, ...
+            // Lanes past the end read the last aligned quad (in bounds, unused).
+            int64_t src = base + 4 * (lane & 31);
+            src = src + 4 <= n ? src : n - 4;
+            for (int r = 2 * wave; r < rows; r += 4) {
+                const int rr = r + (lane >> 5) < rows ? r + (lane >> 5) : r;
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void*)(colour_row(p, 3 * NC, rr) + src),
+                    (__attribute__((address_space(3))) void*)&s_col[r][0], 16, 0, 0);
+            }
+        } else {
+            // 4 bytes per lane: wave w loads floats [64 w, 64 w + 64) of every
+            // row; lanes past the end read the last Gaussian (in bounds, unused)
+            int64_t src = base + wave * 64 + lane;
+            src = src < n ? src : n - 1;
+            for (int r = 0; r < rows; ++r)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void*)(colour_row(p, 3 * NC, r) + src),
+                    (__attribute__((address_space(3))) void*)&s_col[r][wave * 64], 4, 0, 0);
+        }
+        const int64_t g0 = base + tid;
+        const bool active = g0 < n;
+        const int64_t g = active ? g0 : n - 1;
         double X[3], ls[3], q[4];
         bool finite = true;
         for (int c = 0; c < 3; ++c) {
@@ -146,13 +199,24 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             const CamTable ct = ws.cams[ci];
             const int64_t item = (int64_t)ci * n + g;
             const Geo geo = project(X, ls, q, cam, ct, o);
-            bool vis = finite && geo.visible;
+            bool vis = active && finite && geo.visible;
+            if (ci == 0) {
+                // this wave's LDS loads, then every wave's, have landed
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+            }
             float rgb[3] = {0.0f, 0.0f, 0.0f};
             if (vis) {
                 float d[3], dist;
                 view_dir(X, cam, d, &dist);
-                vis = colour<DEG, KMAX>(p, g, d[0], d[1], d[2], rgb);
+                vis = colour_eval<DEG, KMAX>(
+                    [&](int l, int c) { return s_col[3 * l + c][tid]; },
+                    [&](int k, int j) { return s_col[3 * NC + 3 * k + j][tid]; },
+                    [&](int k) { return s_col[3 * NC + 3 * p.n_lobes + k][tid]; },
+                    [&](int k, int c) { return s_col[3 * NC + 4 * p.n_lobes + 3 * k + c][tid]; },
+                    p.n_lobes, d[0], d[1], d[2], rgb);
             }
+            if (!active) continue;
             uint32_t key = 0xFFFFFFFFu;
             uint64_t trect = 1;  // tx0 = 1 > tx1 = 0: no pairs
             if (vis) {
@@ -209,7 +273,7 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
 template <int KMAX>
 static void launch_pre_k(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                          const Workspace& ws, dim3 grid, hipStream_t s) {
-    const dim3 block(kPreThreads);
+    const dim3 block(kPreTile);
     switch (p.sh_degree) {
         case 0: hipLaunchKernelGGL((k_preprocess<0, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
         case 1: hipLaunchKernelGGL((k_preprocess<1, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
@@ -220,7 +284,10 @@ static void launch_pre_k(const Params& p, const sgs_camera* dev_cams, int n_cams
 
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                        const Workspace& ws, int hist_blocks, hipStream_t s) {
-    const dim3 grid(hist_blocks);
+    (void)hist_blocks;
+    // persistent: up to 16 blocks of two waves per CU
+    const int64_t tiles = (p.n + kPreTile - 1) / kPreTile;
+    const dim3 grid((unsigned)(tiles < 4096 ? (tiles < 1 ? 1 : tiles) : 4096));
     if (p.n_lobes == 0) launch_pre_k<0>(p, dev_cams, n_cams, o, ws, grid, s);
     else if (p.n_lobes <= 4) launch_pre_k<4>(p, dev_cams, n_cams, o, ws, grid, s);
     else launch_pre_k<SGS_MAX_LOBES>(p, dev_cams, n_cams, o, ws, grid, s);
