@@ -64,6 +64,53 @@ __device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, flo
         d0, d1, d2, rgb);
 }
 
+// pointer to colour parameter row r of the component-major arrays: SH
+// coefficient (l, c) is row 3 l + c, then per lobe k the axis (3 rows), then
+// the log-sharpness rows, then the amplitudes (3 rows per lobe)
+__device__ __forceinline__ const float* colour_row(const Params& p, int nc3, int r) {
+    const int K = p.n_lobes;
+    const int64_t n = p.n;
+    if (r < nc3) return p.sh + (int64_t)r * n;
+    r -= nc3;
+    if (r < 3 * K) return p.sg_axes + (int64_t)r * n;
+    r -= 3 * K;
+    if (r < K) return p.sg_log_sharpness + (int64_t)r * n;
+    return p.sg_amplitudes + (int64_t)(r - K) * n;
+}
+
+// Direct global->LDS loads (no registers) of the colour rows of the
+// kPreTile Gaussians from `base` into s_col[rows][kPreTile] (a block of
+// kPreTile threads; s_col holds an even number of rows).  vec4: the rows
+// start 16-byte aligned (n a multiple of 4), one instruction fills two
+// rows; otherwise 4 bytes per lane.  Lanes past the end read in-bounds
+// data that nothing uses.  The caller waits (s_waitcnt) and synchronises
+// before reading s_col.
+__device__ __forceinline__ void stage_colour_rows(const Params& p, int nc3, int rows, int64_t base,
+                                                  bool vec4, float* s_col) {
+    const int64_t n = p.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (vec4) {
+        // lanes 0-31 row r, lanes 32-63 row r + 1; wave w takes rows 2 w, 2 w + 4, ...
+        int64_t src = base + 4 * (lane & 31);
+        src = src + 4 <= n ? src : n - 4;
+        for (int r = 2 * wave; r < rows; r += 4) {
+            const int rr = r + (lane >> 5) < rows ? r + (lane >> 5) : r;
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void*)(colour_row(p, nc3, rr) + src),
+                (__attribute__((address_space(3))) void*)(s_col + r * kPreTile), 16, 0, 0);
+        }
+    } else {
+        // wave w loads floats [64 w, 64 w + 64) of every row
+        int64_t src = base + wave * 64 + lane;
+        src = src < n ? src : n - 1;
+        for (int r = 0; r < rows; ++r)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void*)(colour_row(p, nc3, r) + src),
+                (__attribute__((address_space(3))) void*)(s_col + r * kPreTile + wave * 64), 4, 0,
+                0);
+    }
+}
+
 // Unit view direction from the camera centre (-R^T t) to the mean X: the
 // difference in float64 (no cancellation near the camera), the
 // normalisation in float32.  *dist receives |X - centre|.
@@ -83,16 +130,16 @@ __device__ __forceinline__ void view_dir(const double X[3], const sgs_camera& ca
 
 // Backward of the colour.  grgb: dL/d(clamped rgb).  Adds the parameter
 // gradients into the accumulators and returns dL/dd (the view direction,
-// before the normalisation Jacobian).
-template <int DEG, int KMAX>
-__device__ __forceinline__ void colour_bwd(const Params& p, int64_t g, float d0, float d1, float d2,
-                                           const float grgb[3], float gsh[][3],
-                                           float gamp[][3], float gax[][3], float glsh[],
-                                           float gd[3]) {
+// before the normalisation Jacobian).  Parameters are read through the same
+// accessors as colour_eval.
+template <int DEG, int KMAX, typename SH, typename AX, typename LS, typename AM>
+__device__ __forceinline__ void colour_bwd_eval(SH sh, AX axis, LS lsh, AM amp, int n_lobes,
+                                                float d0, float d1, float d2, const float grgb[3],
+                                                float gsh[][3], float gamp[][3], float gax[][3],
+                                                float glsh[], float gd[3]) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    const int64_t n = p.n;
     float raw[3];
-    colour<DEG, KMAX>(p, g, d0, d1, d2, raw);
+    colour_eval<DEG, KMAX>(sh, axis, lsh, amp, n_lobes, d0, d1, d2, raw);
     // max(0, .): derivative 1 where the raw colour is >= 0
     const float gc[3] = {raw[0] >= 0.0f ? grgb[0] : 0.0f, raw[1] >= 0.0f ? grgb[1] : 0.0f,
                          raw[2] >= 0.0f ? grgb[2] : 0.0f};
@@ -106,7 +153,7 @@ __device__ __forceinline__ void colour_bwd(const Params& p, int64_t g, float d0,
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             gsh[l][c] = fmaf(gc[c], Y[l], gsh[l][c]);
-            cl = fmaf(gc[c], p.sh[((int64_t)l * 3 + c) * n + g], cl);
+            cl = fmaf(gc[c], sh(l, c), cl);
         }
         gd[0] = fmaf(cl, gx[l], gd[0]);
         gd[1] = fmaf(cl, gy[l], gd[1]);
@@ -114,20 +161,18 @@ __device__ __forceinline__ void colour_bwd(const Params& p, int64_t g, float d0,
     }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        if (k >= p.n_lobes) break;
-        const float m0 = p.sg_axes[((int64_t)k * 3 + 0) * n + g];
-        const float m1 = p.sg_axes[((int64_t)k * 3 + 1) * n + g];
-        const float m2 = p.sg_axes[((int64_t)k * 3 + 2) * n + g];
+        if (k >= n_lobes) break;
+        const float m0 = axis(k, 0), m1 = axis(k, 1), m2 = axis(k, 2);
         const float imn = rsqrtf(m0 * m0 + m1 * m1 + m2 * m2);
         const float mu0 = m0 * imn, mu1 = m1 * imn, mu2 = m2 * imn;
-        const float lam = fast_exp(p.sg_log_sharpness[(int64_t)k * n + g]);
+        const float lam = fast_exp(lsh(k));
         const float t = (d0 * m0 + d1 * m1 + d2 * m2) * imn - 1.0f;
         const float e = t == 0.0f ? 1.0f : fast_exp(lam * t);
         float sk = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             gamp[k][c] = fmaf(gc[c], e, gamp[k][c]);
-            sk = fmaf(gc[c], p.sg_amplitudes[((int64_t)k * 3 + c) * n + g], sk);
+            sk = fmaf(gc[c], amp(k, c), sk);
         }
         sk *= e;
         glsh[k] = fmaf(sk * t, lam, glsh[k]);

@@ -120,20 +120,6 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     return r;
 }
 
-// pointer to colour parameter row r of the component-major arrays: SH
-// coefficient (l, c) is row 3 l + c, then per lobe k the axis (3 rows), then
-// the log-sharpness rows, then the amplitudes (3 rows per lobe)
-__device__ __forceinline__ const float* colour_row(const Params& p, int nc3, int r) {
-    const int K = p.n_lobes;
-    const int64_t n = p.n;
-    if (r < nc3) return p.sh + (int64_t)r * n;
-    r -= nc3;
-    if (r < 3 * K) return p.sg_axes + (int64_t)r * n;
-    r -= 3 * K;
-    if (r < K) return p.sg_log_sharpness + (int64_t)r * n;
-    return p.sg_amplitudes + (int64_t)(r - K) * n;
-}
-
 // A block takes tiles of kPreTile consecutive Gaussians.  At the start of a
 // tile each wave issues direct global->LDS loads of its half of every colour
 // row (no registers held), then runs the float64 geometry while they are in
@@ -154,28 +140,7 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
     for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
          base += (int64_t)gridDim.x * kPreTile) {
         __syncthreads();   // the previous tile's colour rows are no longer read
-        if (vec4) {
-            // 16 bytes per lane: one instruction fills two rows (lanes 0-31 row
-            // r, lanes 32-63 row r + 1); wave w takes row pairs 2 w, 2 w + 4, ...
-            // Lanes past the end read the last aligned quad (in bounds, unused).
-            int64_t src = base + 4 * (lane & 31);
-            src = src + 4 <= n ? src : n - 4;
-            for (int r = 2 * wave; r < rows; r += 4) {
-                const int rr = r + (lane >> 5) < rows ? r + (lane >> 5) : r;
-                __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void*)(colour_row(p, 3 * NC, rr) + src),
-                    (__attribute__((address_space(3))) void*)&s_col[r][0], 16, 0, 0);
-            }
-        } else {
-            // 4 bytes per lane: wave w loads floats [64 w, 64 w + 64) of every
-            // row; lanes past the end read the last Gaussian (in bounds, unused)
-            int64_t src = base + wave * 64 + lane;
-            src = src < n ? src : n - 1;
-            for (int r = 0; r < rows; ++r)
-                __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void*)(colour_row(p, 3 * NC, r) + src),
-                    (__attribute__((address_space(3))) void*)&s_col[r][wave * 64], 4, 0, 0);
-        }
+        stage_colour_rows(p, 3 * NC, rows, base, vec4, &s_col[0][0]);
         const int64_t g0 = base + tid;
         const bool active = g0 < n;
         const int64_t g = active ? g0 : n - 1;

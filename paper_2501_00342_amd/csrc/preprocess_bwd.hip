@@ -2,7 +2,7 @@
 // raw parameter, one thread per Gaussian summing over cameras, in two
 // kernels so that neither holds both live sets (no register spills):
 //
-//   k_colour_bwd<DEG> (float32): colour eq. 9 -> SH coefficients (eq. 4),
+//   k_colour_bwd<DEG, KMAX> (float32): colour eq. 9 -> SH coefficients (eq. 4),
 //     SG amplitude, log-sharpness and axis (eq. 5), and the part of the
 //     mean's gradient that flows through the view direction; the latter is
 //     left in a [3][n] scratch row of the workspace.
@@ -21,15 +21,28 @@ __device__ __forceinline__ bool item_visible(const Workspace& ws, int64_t item) 
     return (int)((tr >> 16) & 0xFFFF) >= (int)(tr & 0xFFFF);
 }
 
+// A block takes tiles of kPreTile consecutive Gaussians and stages their
+// colour rows in LDS with direct loads (as the forward preprocess does); the
+// gradients are written from registers, one coalesced row at a time.
 template <int DEG, int KMAX>
-__global__ void __launch_bounds__(kPreThreads)
+__global__ void __launch_bounds__(kPreTile)
 k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspace ws,
              sgs_grads gr, float* __restrict__ gx_colour) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
+    constexpr int MAXROWS = 3 * NC + 7 * KMAX;
+    __shared__ float s_col[(MAXROWS + 1) & ~1][kPreTile];
     const int64_t n = p.n;
     const int64_t M = ws.n_items;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    const int K = p.n_lobes;
+    const int rows = 3 * NC + 7 * K;
+    const int tid = threadIdx.x;
+    const bool vec4 = (n & 3) == 0;
+    for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
+         base += (int64_t)gridDim.x * kPreTile) {
+        __syncthreads();   // the previous tile's colour rows are no longer read
+        stage_colour_rows(p, 3 * NC, rows, base, vec4, &s_col[0][0]);
+        const int64_t g = base + tid;
+        const bool active = g < n;
         float gsh[NC][3];
         float gamp[KMAX + 1][3], gax[KMAX + 1][3], glsh[KMAX + 1];
 #pragma unroll
@@ -41,29 +54,38 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
             gax[k][0] = gax[k][1] = gax[k][2] = 0.0f;
         }
         float gX[3] = {0.0f, 0.0f, 0.0f};
-        const double X[3] = {p.means[g], p.means[n + g], p.means[2 * n + g]};
+        const int64_t gc = active ? g : n - 1;
+        const double X[3] = {p.means[gc], p.means[n + gc], p.means[2 * n + gc]};
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         for (int ci = 0; ci < n_cams; ++ci) {
-            const int64_t item = (int64_t)ci * n + g;
-            if (!item_visible(ws, item)) continue;
+            const int64_t item = (int64_t)ci * n + gc;
+            if (!active || !item_visible(ws, item)) continue;
             const float grgb[3] = {ws.grad2d[6 * M + item], ws.grad2d[7 * M + item],
                                    ws.grad2d[8 * M + item]};
             float d[3], dist;
             view_dir(X, cams[ci], d, &dist);
             float gd[3];
-            colour_bwd<DEG, KMAX>(p, g, d[0], d[1], d[2], grgb, gsh, gamp, gax, glsh, gd);
+            colour_bwd_eval<DEG, KMAX>(
+                [&](int l, int c) { return s_col[3 * l + c][tid]; },
+                [&](int k, int j) { return s_col[3 * NC + 3 * k + j][tid]; },
+                [&](int k) { return s_col[3 * NC + 3 * K + k][tid]; },
+                [&](int k, int c) { return s_col[3 * NC + 4 * K + 3 * k + c][tid]; }, K, d[0],
+                d[1], d[2], grgb, gsh, gamp, gax, glsh, gd);
             // through d = (X - c) / |X - c|: (I - d d^T) / |X - c|
             const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
             const float inv = 1.0f / dist;
 #pragma unroll
             for (int c = 0; c < 3; ++c) gX[c] += (gd[c] - d[c] * dd) * inv;
         }
+        if (!active) continue;
 #pragma unroll
         for (int l = 0; l < NC; ++l)
 #pragma unroll
             for (int c = 0; c < 3; ++c) gr.sh[((int64_t)l * 3 + c) * n + g] = gsh[l][c];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            if (k >= p.n_lobes) break;
+            if (k >= K) break;
             for (int c = 0; c < 3; ++c) {
                 gr.sg_axes[((int64_t)k * 3 + c) * n + g] = gax[k][c];
                 gr.sg_amplitudes[((int64_t)k * 3 + c) * n + g] = gamp[k][c];
@@ -214,15 +236,21 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     if (blocks > 4096) blocks = 4096;
     dim3 grid((unsigned)blocks), block(kPreThreads);
     float* gxc = ws.gx_colour;
+    const int64_t tiles = (p.n + kPreTile - 1) / kPreTile;
+    const dim3 cgrid((unsigned)(tiles < 4096 ? tiles : 4096)), cblock(kPreTile);
 #define SGS_COLOUR_BWD(D, K)                                                                   \
-    hipLaunchKernelGGL((k_colour_bwd<D, K>), grid, block, 0, s, p, dev_cams, n_cams, ws, gr, gxc)
-    const bool few = p.n_lobes <= 4;
+    hipLaunchKernelGGL((k_colour_bwd<D, K>), cgrid, cblock, 0, s, p, dev_cams, n_cams, ws, gr, gxc)
+#define SGS_COLOUR_BWD_K(D)                                                                    \
+    if (p.n_lobes == 0) SGS_COLOUR_BWD(D, 0);                                                  \
+    else if (p.n_lobes <= 4) SGS_COLOUR_BWD(D, 4);                                             \
+    else SGS_COLOUR_BWD(D, 8)
     switch (p.sh_degree) {
-        case 0: if (few) SGS_COLOUR_BWD(0, 4); else SGS_COLOUR_BWD(0, 8); break;
-        case 1: if (few) SGS_COLOUR_BWD(1, 4); else SGS_COLOUR_BWD(1, 8); break;
-        case 2: if (few) SGS_COLOUR_BWD(2, 4); else SGS_COLOUR_BWD(2, 8); break;
-        default: if (few) SGS_COLOUR_BWD(3, 4); else SGS_COLOUR_BWD(3, 8); break;
+        case 0: SGS_COLOUR_BWD_K(0); break;
+        case 1: SGS_COLOUR_BWD_K(1); break;
+        case 2: SGS_COLOUR_BWD_K(2); break;
+        default: SGS_COLOUR_BWD_K(3); break;
     }
+#undef SGS_COLOUR_BWD_K
 #undef SGS_COLOUR_BWD
     hipLaunchKernelGGL(k_geom_bwd, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr, gxc);
 }

@@ -33,6 +33,7 @@ __device__ __forceinline__ uint32_t rect_pairs(uint64_t r) {
 
 // ---------------------------------------------------------------------------
 
+// Digit histogram of one partition (per-wave LDS rows, atomics).
 template <typename KeyT>
 __global__ void __launch_bounds__(kSortThreads)
 k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t count_host,
@@ -297,9 +298,11 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
     // counted: the digit counts of every half partition are already in
     // counts[d][2 parts] (written by the pass's producer)
     const int cstride = counted ? 2 : 1;
-    if (!counted)
-        hipLaunchKernelGGL(k_upsweep<KeyT>, dim3((unsigned)parts), dim3(kSortThreads), 0, s, keys_in,
-                           count_ptr, count_host, shift, counts, parts, drop_culled);
+    if (!counted) {
+        const dim3 ug((unsigned)parts), ub(kSortThreads);
+        hipLaunchKernelGGL(k_upsweep<KeyT>, ug, ub, 0, s, keys_in, count_ptr, count_host, shift,
+                           counts, parts, drop_culled);
+    }
     hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts * cstride, totals,
                        drop_culled ? kept_out : nullptr);
     const dim3 g((unsigned)parts);
