@@ -182,13 +182,14 @@ def choose_options(args, torch, scenes, autotune, params, cams, base, scene, tar
         o, rep = autotune.tune(params, cams, base, scene.n, scene.sh_degree, scene.n_lobes,
                                backward=bwd, **kw)
         picked.append(o)
-        reports["fwd_bwd" if bwd else "fwd"] = sorted(rep, key=lambda r: r["ms"])[:3]
+        timed = [r for r in rep if r.get("ms") is not None]
+        reports["fwd_bwd" if bwd else "fwd"] = sorted(timed, key=lambda r: r["ms"])[:3]
         if args.retune:
             key = autotune.cache_key(arch, cams, scene.n, scene.sh_degree, scene.n_lobes, bwd)
-            best = min(rep, key=lambda r: r["ms"])
+            best = min(timed, key=lambda r: r["ms"])
             print(json.dumps({"autotune_entry": {key: {
-                "choice": {k: best[k] for k in best if k != "ms"}, "report": rep}}}),
-                file=sys.stderr, flush=True)
+                "choice": {k: best[k] for k in best if k not in ("ms", "error")},
+                "report": rep}}}), file=sys.stderr, flush=True)
     return picked[0], picked[1], reports
 
 

@@ -115,10 +115,16 @@ def tune(params: dict, cams, base: Options, n: int, sh_degree: int, n_lobes: int
                             device=next(iter(params.values())).device)
     report = []
     best, best_ms = None, float("inf")
+    from ._lib import SgsError
     for cand in candidates(tiles, batches, backward, schedules):
         opts = replace(base, **cand)
         rast = raster.Rasterizer(cams, opts, n, sh_degree, n_lobes)
-        out = rast.forward(params, check=True)
+        try:
+            out = rast.forward(params, check=True)
+        except SgsError as e:     # e.g. more pairs than one call may hold
+            report.append(dict(cand, ms=None, error=str(e)))
+            del rast
+            continue
         gimg = torch.empty_like(out.image)
         grads = {k: torch.empty_like(v) for k, v in params.items()}
 

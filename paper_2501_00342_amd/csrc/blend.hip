@@ -159,7 +159,7 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
         if (live) {
             for (int j = 0; j < cnt; ++j) {
                 const Entry e = s_e[j];
-                if (COUNT) visited += __popc(live);
+                if (COUNT) ++visited;   // per thread: its pixels share the column work
                 if (!(e.m.x & colbit)) continue;
                 const float dx = lxf + e.a.x;
                 const float t1 = e.a.z * dx, t2 = e.b.x * dx;
