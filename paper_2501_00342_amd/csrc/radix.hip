@@ -62,15 +62,20 @@ k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t coun
     counts[(int64_t)d * parts + p] = c;
 }
 
-// block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row sum
-__global__ void __launch_bounds__(256)
+// block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row
+// sum.  1024 threads x 8 consecutive entries per round, wave scans with
+// lane shuffles, then a scan of the 16 wave totals.
+constexpr int kScanRowThreads = 1024;
+
+__global__ void __launch_bounds__(kScanRowThreads)
 k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__ totals,
             uint32_t* kept_out) {
-    __shared__ uint32_t s[256];
-    const int tid = threadIdx.x;
+    constexpr int WAVES = kScanRowThreads / 64;
+    __shared__ uint32_t s_w[WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t* row = counts + (int64_t)blockIdx.x * parts;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < parts; b0 += 256 * 8) {
+    for (int64_t b0 = 0; b0 < parts; b0 += kScanRowThreads * 8) {
         uint32_t v[8], run = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -78,22 +83,32 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
             v[k] = i < parts ? row[i] : 0u;
             run += v[k];
         }
-        s[tid] = run;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const uint32_t t = tid >= off ? s[tid - off] : 0u;
-            __syncthreads();
-            s[tid] += t;
-            __syncthreads();
+        uint32_t x = run;   // inclusive scan over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
         }
-        uint32_t off = carry + s[tid] - run;
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            uint32_t t = lane < WAVES ? s_w[lane] : 0u;
+#pragma unroll
+            for (int off = 1; off < WAVES; off <<= 1) {
+                const uint32_t y = __shfl_up(t, off);
+                if (lane >= off) t += y;
+            }
+            if (lane < WAVES) s_w[lane] = t;   // inclusive over waves
+        }
+        __syncthreads();
+        uint32_t off = carry + (w > 0 ? s_w[w - 1] : 0u) + x - run;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int64_t i = b0 + (int64_t)tid * 8 + k;
             if (i < parts) row[i] = off;
             off += v[k];
         }
-        carry += s[255];
+        carry += s_w[WAVES - 1];
         __syncthreads();
     }
     if (tid == 0) {
@@ -303,8 +318,8 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
         hipLaunchKernelGGL(k_upsweep<KeyT>, ug, ub, 0, s, keys_in, count_ptr, count_host, shift,
                            counts, parts, drop_culled);
     }
-    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(256), 0, s, counts, parts * cstride, totals,
-                       drop_culled ? kept_out : nullptr);
+    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kScanRowThreads), 0, s, counts,
+                       parts * cstride, totals, drop_culled ? kept_out : nullptr);
     const dim3 g((unsigned)parts);
 #define SGS_DOWNSWEEP(NB)                                                                      \
     downsweep_t<KeyT, NB>(g, s, keys_in, vals_in, keys_out, vals_out, count_ptr, count_host,   \
