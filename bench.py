@@ -376,6 +376,10 @@ def main():
                          "eager_fwd_ms": round(m3["fwd_ms"], 4),
                          "eager_fwd_bwd_ms": round(m3["fb_ms"], 4),
                          "preprocess_ms": round(m3["st_fwd"][i_pre] / max(m3["nf"], 1), 5),
+                         "stages_ms": {nm: round((m3["st_fwd"] if nm.startswith("fwd") else
+                                                  m3["st_fb"])[i] /
+                                                 max(m3["nf"] if nm.startswith("fwd") else m3["nb"], 1), 5)
+                                       for i, nm in enumerate(names)},
                          "fwd_shape": shape_of(m3["rast"], m3["opts_f"]),
                          "fwd_bwd_shape": shape_of(m3["rast_b"], m3["opts_b"])}
         result["sg_over_sh3_fps"] = round(m3["fwd_graph_ms"] / (1000.0 / result["value"]), 4)

@@ -129,9 +129,14 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
             bool drop, int cstride, uint32_t* __restrict__ ranges, int64_t n_tiles) {
     constexpr int WAVES = kSortThreads / 64;
     constexpr int WAVE_ITEMS = 64 * kSortItems;
-    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ __align__(16) uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wave[WAVES][kRadix];
+    // full 8-bit digits: lanes with equal digits are found through a per-wave
+    // table of lane masks (one LDS OR and one read per item) instead of eight
+    // ballots; the table lives in s_keys, which the ranking does not use yet
+    constexpr bool kLdsMatch = NB >= kRadixBits;
+    unsigned long long* s_match = reinterpret_cast<unsigned long long*>(s_keys);
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_global[kRadix];
     __shared__ uint32_t s_kept;
@@ -142,6 +147,8 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     const int64_t base = p * kSortTile;
     if (base >= count) return;
     for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&s_wave[0][0])[i] = 0;
+    if (kLdsMatch)
+        for (int i = tid; i < WAVES * kRadix; i += kSortThreads) s_match[i] = 0ull;
     // global start of this partition's run of digit d
     {
         const int d = tid;
@@ -184,12 +191,22 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
         const int li = k * 64 + lane;
         const bool valid = li < lim && !(drop && key[k] == 0xFFFFFFFFu);
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
-        uint64_t m = __ballot(valid);
+        uint64_t m;
+        if constexpr (kLdsMatch) {
+            // a wave's LDS instructions execute in order: every lane's OR
+            // lands before any lane reads, every read before the clear
+            unsigned long long* slot = s_match + wave * kRadix + d;
+            if (valid) atomicOr(slot, 1ull << lane);
+            m = valid ? *slot : 0ull;
+            if (valid) *slot = 0ull;
+        } else {
+            m = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+            for (int b = 0; b < NB; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
         }
         const uint64_t lower = m & lt_mask;
         const uint32_t prior = valid ? s_wave[wave][d] : 0u;
