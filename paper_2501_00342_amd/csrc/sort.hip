@@ -70,7 +70,8 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
 }
 
 // --------------------------------------------------------------------------
-// duplicate: one block per 4096-pair chunk, one thread per pair (balanced)
+// duplicate: one block per 2048-pair chunk, eight consecutive pairs per
+// thread (balanced: pairs, not Gaussians, are split between threads)
 // --------------------------------------------------------------------------
 
 // Also the first tile-sort pass's digit histogram: chunk c's counts of the
@@ -78,6 +79,8 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
 // chunks per radix partition, so that pass needs no upsweep of its own);
 // chunks past the pair count get zero rows.
 static_assert(2 * kDupChunk == kSortTile, "two duplicate chunks per radix partition");
+constexpr int kDupRun = kDupChunk / 256;   // consecutive pairs per thread
+static_assert(kDupRun == 8, "vector stores of eight pairs");
 
 __global__ void __launch_bounds__(256)
 k_duplicate(Workspace ws, int64_t n) {
@@ -121,26 +124,74 @@ k_duplicate(Workspace ws, int64_t n) {
             s_wgx[j] = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)ct.GX << 16);
         }
         __syncthreads();
-        for (int64_t p = p0 + tid; p < p1; p += 256) {
-            int lo = 0, hi = (int)nloc - 1;     // last local item with offset <= p
+        // thread t emits the kDupRun consecutive pairs from p0 + kDupRun t:
+        // one search for the first, then a walk along the rectangles
+        const int64_t q0 = p0 + (int64_t)tid * kDupRun;
+        if (q0 < p1) {
+            int lo = 0, hi = (int)nloc - 1;     // last local item with offset <= q0
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if ((int64_t)s_off[mid] <= p) lo = mid; else hi = mid - 1;
+                if ((int64_t)s_off[mid] <= q0) lo = mid; else hi = mid - 1;
             }
-            const uint32_t wgx = s_wgx[lo];
-            const int w = (int)(wgx & 0xFFFF), gx = (int)(wgx >> 16);
-            const int j = (int)(p - s_off[lo]);
+            uint32_t wgx = s_wgx[lo];
+            int w = (int)(wgx & 0xFFFF), gx = (int)(wgx >> 16);
+            const int j = (int)(q0 - s_off[lo]);
             // j / w in float: the quotient is at least 0.5/w from an integer
             int ty = (int)(((float)j + 0.5f) * (1.0f / (float)w));
             int tx = j - ty * w;
             if (tx < 0) { --ty; tx += w; } else if (tx >= w) { ++ty; tx -= w; }
-            const uint32_t tile = s_origin[lo] + (uint32_t)(ty * gx + tx);
-            if (ws.key16)
-                reinterpret_cast<uint16_t*>(ws.pair_tiles)[p] = (uint16_t)tile;
-            else
-                ws.pair_tiles[p] = tile;
-            ws.pair_values[p] = s_item[lo];
-            atomicAdd(&s_hist[tile & (kRadix - 1)], 1u);
+            uint32_t origin = s_origin[lo], item = s_item[lo];
+            int64_t next = lo + 1 < nloc ? (int64_t)s_off[lo + 1] : INT64_MAX;
+            const int cnt = p1 - q0 < kDupRun ? (int)(p1 - q0) : kDupRun;
+            uint32_t tl[kDupRun], vl[kDupRun];
+#pragma unroll
+            for (int e = 0; e < kDupRun; ++e) {
+                if (e < cnt) {
+                    if (q0 + e >= next) {   // the next item (every item has >= 1 pair)
+                        ++lo;
+                        wgx = s_wgx[lo];
+                        w = (int)(wgx & 0xFFFF);
+                        gx = (int)(wgx >> 16);
+                        origin = s_origin[lo];
+                        item = s_item[lo];
+                        next = lo + 1 < nloc ? (int64_t)s_off[lo + 1] : INT64_MAX;
+                        tx = ty = 0;
+                    }
+                    tl[e] = origin + (uint32_t)(ty * gx + tx);
+                    vl[e] = item;
+                    atomicAdd(&s_hist[tl[e] & (kRadix - 1)], 1u);
+                    if (++tx == w) {
+                        tx = 0;
+                        ++ty;
+                    }
+                }
+            }
+            if (cnt == kDupRun) {
+                // q0 is a multiple of 8: 16-byte aligned vector stores
+                if (ws.key16) {
+                    uint4 t;
+                    t.x = (tl[0] & 0xFFFF) | (tl[1] << 16);
+                    t.y = (tl[2] & 0xFFFF) | (tl[3] << 16);
+                    t.z = (tl[4] & 0xFFFF) | (tl[5] << 16);
+                    t.w = (tl[6] & 0xFFFF) | (tl[7] << 16);
+                    *reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(ws.pair_tiles) + q0) = t;
+                } else {
+                    uint4* t = reinterpret_cast<uint4*>(ws.pair_tiles + q0);
+                    t[0] = make_uint4(tl[0], tl[1], tl[2], tl[3]);
+                    t[1] = make_uint4(tl[4], tl[5], tl[6], tl[7]);
+                }
+                uint4* v = reinterpret_cast<uint4*>(ws.pair_values + q0);
+                v[0] = make_uint4(vl[0], vl[1], vl[2], vl[3]);
+                v[1] = make_uint4(vl[4], vl[5], vl[6], vl[7]);
+            } else {
+                for (int e = 0; e < cnt; ++e) {
+                    if (ws.key16)
+                        reinterpret_cast<uint16_t*>(ws.pair_tiles)[q0 + e] = (uint16_t)tl[e];
+                    else
+                        ws.pair_tiles[q0 + e] = tl[e];
+                    ws.pair_values[q0 + e] = vl[e];
+                }
+            }
         }
         __syncthreads();
         ws.counts[tid * row + chunk] = s_hist[tid];
