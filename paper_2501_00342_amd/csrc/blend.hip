@@ -223,7 +223,7 @@ template <int TW, int TH, int PPT, bool COUNT, bool QUEUE>
 __global__ void __launch_bounds__(TW * TH / PPT)
 k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs out, int batch, unsigned long long* counts) {
-    extern __shared__ Entry s_e[];
+    extern __shared__ __align__(16) Entry s_e[];
     __shared__ int s_cam;
     __shared__ uint32_t s_next;
     if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
@@ -440,7 +440,7 @@ template <int TW, int TH, int PPT, bool QUEUE>
 __global__ void __launch_bounds__(TW * TH / PPT)
 k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs fwd, const float* __restrict__ grad_image, int batch) {
-    extern __shared__ Entry s_e[];
+    extern __shared__ __align__(16) Entry s_e[];
     __shared__ int s_cam;
     __shared__ int s_maxn;
     __shared__ uint32_t s_next;
