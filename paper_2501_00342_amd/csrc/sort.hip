@@ -85,8 +85,9 @@ static_assert(kDupRun == 8, "vector stores of eight pairs");
 __global__ void __launch_bounds__(256)
 k_duplicate(Workspace ws, int64_t n) {
     __shared__ uint32_t s_off[kDupChunk + 1];
-    __shared__ uint32_t s_origin[kDupChunk + 1];   // global tile id of the rectangle origin
-    __shared__ uint32_t s_wgx[kDupChunk + 1];      // width | GX << 16
+    // after the walk these two stage the chunk's output (16-byte reads)
+    __shared__ __align__(16) uint32_t s_origin[kDupChunk + 1];   // global tile id of the rectangle origin
+    __shared__ __align__(16) uint32_t s_wgx[kDupChunk + 1];      // width | GX << 16
     __shared__ uint32_t s_item[kDupChunk + 1];
     __shared__ uint32_t s_hist[kRadix];
     const int tid = threadIdx.x;
@@ -127,6 +128,7 @@ k_duplicate(Workspace ws, int64_t n) {
         // thread t emits the kDupRun consecutive pairs from p0 + kDupRun t:
         // one search for the first, then a walk along the rectangles
         const int64_t q0 = p0 + (int64_t)tid * kDupRun;
+        uint32_t tl[kDupRun], vl[kDupRun];
         if (q0 < p1) {
             int lo = 0, hi = (int)nloc - 1;     // last local item with offset <= q0
             while (lo < hi) {
@@ -143,7 +145,6 @@ k_duplicate(Workspace ws, int64_t n) {
             uint32_t origin = s_origin[lo], item = s_item[lo];
             int64_t next = lo + 1 < nloc ? (int64_t)s_off[lo + 1] : INT64_MAX;
             const int cnt = p1 - q0 < kDupRun ? (int)(p1 - q0) : kDupRun;
-            uint32_t tl[kDupRun], vl[kDupRun];
 #pragma unroll
             for (int e = 0; e < kDupRun; ++e) {
                 if (e < cnt) {
@@ -166,31 +167,58 @@ k_duplicate(Workspace ws, int64_t n) {
                     }
                 }
             }
-            if (cnt == kDupRun) {
-                // q0 is a multiple of 8: 16-byte aligned vector stores
-                if (ws.key16) {
-                    uint4 t;
-                    t.x = (tl[0] & 0xFFFF) | (tl[1] << 16);
-                    t.y = (tl[2] & 0xFFFF) | (tl[3] << 16);
-                    t.z = (tl[4] & 0xFFFF) | (tl[5] << 16);
-                    t.w = (tl[6] & 0xFFFF) | (tl[7] << 16);
-                    *reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(ws.pair_tiles) + q0) = t;
-                } else {
-                    uint4* t = reinterpret_cast<uint4*>(ws.pair_tiles + q0);
-                    t[0] = make_uint4(tl[0], tl[1], tl[2], tl[3]);
-                    t[1] = make_uint4(tl[4], tl[5], tl[6], tl[7]);
-                }
-                uint4* v = reinterpret_cast<uint4*>(ws.pair_values + q0);
-                v[0] = make_uint4(vl[0], vl[1], vl[2], vl[3]);
-                v[1] = make_uint4(vl[4], vl[5], vl[6], vl[7]);
+        }
+        // stage the chunk's pairs in LDS (the rectangle arrays are done), then
+        // write them with whole-wave contiguous 16-byte stores
+        __syncthreads();
+        uint32_t* st_val = s_origin;                              // 2048 values
+        uint16_t* st_tile = reinterpret_cast<uint16_t*>(s_wgx);   // 2048 tile ids (u16 keys)
+        uint32_t* st_tile32 = s_wgx;                              // or (u32 keys)
+        if (q0 + kDupRun <= p1) {
+            uint4* v4 = reinterpret_cast<uint4*>(st_val) + 2 * tid;
+            v4[0] = make_uint4(vl[0], vl[1], vl[2], vl[3]);
+            v4[1] = make_uint4(vl[4], vl[5], vl[6], vl[7]);
+            if (ws.key16) {
+                reinterpret_cast<uint4*>(st_tile)[tid] =
+                    make_uint4((tl[0] & 0xFFFF) | (tl[1] << 16), (tl[2] & 0xFFFF) | (tl[3] << 16),
+                               (tl[4] & 0xFFFF) | (tl[5] << 16), (tl[6] & 0xFFFF) | (tl[7] << 16));
             } else {
-                for (int e = 0; e < cnt; ++e) {
-                    if (ws.key16)
-                        reinterpret_cast<uint16_t*>(ws.pair_tiles)[q0 + e] = (uint16_t)tl[e];
-                    else
-                        ws.pair_tiles[q0 + e] = tl[e];
-                    ws.pair_values[q0 + e] = vl[e];
-                }
+                uint4* t4 = reinterpret_cast<uint4*>(st_tile32) + 2 * tid;
+                t4[0] = make_uint4(tl[0], tl[1], tl[2], tl[3]);
+                t4[1] = make_uint4(tl[4], tl[5], tl[6], tl[7]);
+            }
+        } else if (q0 < p1) {
+            const int cnt = (int)(p1 - q0);
+            for (int e = 0; e < cnt; ++e) {
+                const int at = tid * kDupRun + e;
+                st_val[at] = vl[e];
+                if (ws.key16) st_tile[at] = (uint16_t)tl[e];
+                else st_tile32[at] = tl[e];
+            }
+        }
+        __syncthreads();
+        const int n_here = (int)(p1 - p0);
+        if (n_here == kDupChunk) {
+            // p0 is a multiple of 2048: every vector store is aligned
+            uint4* vdst = reinterpret_cast<uint4*>(ws.pair_values + p0);
+            const uint4* vsrc = reinterpret_cast<const uint4*>(st_val);
+            vdst[tid] = vsrc[tid];
+            vdst[256 + tid] = vsrc[256 + tid];
+            if (ws.key16) {
+                reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(ws.pair_tiles) + p0)[tid] =
+                    reinterpret_cast<const uint4*>(st_tile)[tid];
+            } else {
+                uint4* tdst = reinterpret_cast<uint4*>(ws.pair_tiles + p0);
+                tdst[tid] = reinterpret_cast<const uint4*>(st_tile32)[tid];
+                tdst[256 + tid] = reinterpret_cast<const uint4*>(st_tile32)[256 + tid];
+            }
+        } else {
+            for (int e = tid; e < n_here; e += 256) {
+                ws.pair_values[p0 + e] = st_val[e];
+                if (ws.key16)
+                    reinterpret_cast<uint16_t*>(ws.pair_tiles)[p0 + e] = st_tile[e];
+                else
+                    ws.pair_tiles[p0 + e] = st_tile32[e];
             }
         }
         __syncthreads();
