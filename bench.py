@@ -6,7 +6,8 @@ Workload: 3M clustered Gaussians, 1600x1060, SG form (SH degree 1 + 4
 lobes) beside the degree-3 SH form on the same geometry.  Prints one JSON
 line: forward frames/s of the SG form (value; the forward captured once in
 a HIP graph and replayed), forward+backward ms (L1 loss against a seeded
-target), the same passes launched eagerly, the SH-3 form's figures,
+target), the same passes launched eagerly, the SH-3 form's figures (and a
+paired comparison: both forms' graphs replayed in alternation),
 per-stage times from HIP events inside the eager timed loops, the roofline
 of the dominant kernel, and the FP64 oracle's throughput on a bounded
 sample of the same frame on the host CPU.
@@ -250,10 +251,28 @@ def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, ta
     g_fb = capture(fwd_bwd, torch)
     fwd_graph_ms = timed_loop(g_fwd.replay, args.steps, torch)
     fb_graph_ms = timed_loop(g_fb.replay, args.steps, torch)
-    del g_fwd, g_fb
     return dict(rast=rast, rast_b=rast_b, params=params, opts_f=opts_f, opts_b=opts_b,
                 reports=reports, fwd_ms=fwd_ms, fb_ms=fb_ms, fwd_graph_ms=fwd_graph_ms,
-                fb_graph_ms=fb_graph_ms, st_fwd=st_fwd, nf=nf, st_fb=st_fb, nb=nb)
+                fb_graph_ms=fb_graph_ms, st_fwd=st_fwd, nf=nf, st_fb=st_fb, nb=nb,
+                g_fwd=g_fwd, g_fb=g_fb)
+
+
+def paired_comparison(m, m3, steps, torch, rounds=5):
+    """SG and SH-3 graphs replayed in alternation (same clocks and
+    temperature for both), K steps per timing; medians over the rounds."""
+    t = {"sg_fwd": [], "sh3_fwd": [], "sg_fb": [], "sh3_fb": []}
+    for _ in range(rounds):
+        t["sg_fwd"].append(timed_loop(m["g_fwd"].replay, steps, torch))
+        t["sh3_fwd"].append(timed_loop(m3["g_fwd"].replay, steps, torch))
+        t["sg_fb"].append(timed_loop(m["g_fb"].replay, steps, torch))
+        t["sh3_fb"].append(timed_loop(m3["g_fb"].replay, steps, torch))
+    med = {k: float(np.median(v)) for k, v in t.items()}
+    return {"rounds": rounds, "steps_per_round": steps,
+            "sg_fwd_ms": round(med["sg_fwd"], 4), "sh3_fwd_ms": round(med["sh3_fwd"], 4),
+            "sg_fwd_bwd_ms": round(med["sg_fb"], 4), "sh3_fwd_bwd_ms": round(med["sh3_fb"], 4),
+            "sg_over_sh3_fps": round(med["sh3_fwd"] / med["sg_fwd"], 4),
+            "sg_over_sh3_fwd_bwd": round(med["sh3_fb"] / med["sg_fb"], 4),
+            "per_round_fps_ratio": [round(b / a, 4) for a, b in zip(t["sg_fwd"], t["sh3_fwd"])]}
 
 
 def main():
@@ -363,8 +382,6 @@ def main():
                            "p99": float(np.percentile(cnt, 99)), "max": int(cnt.max()),
                            "empty": int((cnt == 0).sum()),
                            "log2_bins": {f"<=2^{i}": int(b) for i, b in enumerate(bins) if b}}
-    del m, rast
-    torch.cuda.empty_cache()
 
     if not args.no_sh3 and args.workload == "sg-3m-1600":
         sh3 = scenes.sh3_scene(sc.n, 1)
@@ -384,8 +401,10 @@ def main():
                          "fwd_bwd_shape": shape_of(m3["rast_b"], m3["opts_b"])}
         result["sg_over_sh3_fps"] = round(m3["fwd_graph_ms"] / (1000.0 / result["value"]), 4)
         result["sg_over_sh3_fwd_bwd"] = round(m3["fb_graph_ms"] / result["fwd_bwd_ms"], 4)
+        result["sg_vs_sh3_paired"] = paired_comparison(m, m3, args.steps, torch)
         del m3
-        torch.cuda.empty_cache()
+    del m, rast
+    torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline and len(cams) == 1:
         result["cpu_baseline"] = cpu_baseline(sc, cam, base)

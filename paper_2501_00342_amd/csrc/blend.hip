@@ -335,7 +335,9 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     const int64_t W = ct.W, H = ct.H;
     const float* gi = grad_image + 3 * ct.pix_base;
 
-    float T[PPT], g0[PPT], g1[PPT], g2[PPT], S0[PPT], S1[PPT], S2[PPT];
+    // SG: dL/dC . S, S = colour composited behind the current splat (only its
+    // product with the pixel's upstream gradient is needed)
+    float T[PPT], g0[PPT], g1[PPT], g2[PPT], SG[PPT];
     int nc[PPT];
     int my_max = 0;
 #pragma unroll
@@ -353,9 +355,7 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
             g2[k] = gi[2 * W * H + pix];
         }
         if (nc[k] > len) nc[k] = (int)len;
-        S0[k] = T[k] * c.bg[0];
-        S1[k] = T[k] * c.bg[1];
-        S2[k] = T[k] * c.bg[2];
+        SG[k] = T[k] * (c.bg[0] * g0[k] + c.bg[1] * g1[k] + c.bg[2] * g2[k]);
         my_max = nc[k] > my_max ? nc[k] : my_max;
     }
     if (my_max > 0) atomicMax(s_maxn, my_max);
@@ -396,11 +396,9 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                     v_g = fmaf(w, g1[k], v_g);
                     v_b = fmaf(w, g2[k], v_b);
                     const float cg = e.c.x * g0[k] + e.c.y * g1[k] + e.c.z * g2[k];
-                    const float sg = S0[k] * g0[k] + S1[k] * g1[k] + S2[k] * g2[k];
+                    const float sg = SG[k];
                     const float dLda = T[k] * cg - sg * iom;
-                    S0[k] = fmaf(w, e.c.x, S0[k]);
-                    S1[k] = fmaf(w, e.c.y, S1[k]);
-                    S2[k] = fmaf(w, e.c.z, S2[k]);
+                    SG[k] = fmaf(w, cg, SG[k]);
                     if (e.b.z * v.E <= amax) {
                         v_s = fmaf(dLda, v.E, v_s);
                         const float dLdp = dLda * v.alpha;
