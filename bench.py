@@ -251,10 +251,12 @@ def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, ta
     g_fb = capture(fwd_bwd, torch)
     fwd_graph_ms = timed_loop(g_fwd.replay, args.steps, torch)
     fb_graph_ms = timed_loop(g_fb.replay, args.steps, torch)
+    # the graphs replay into out, out_b, grad_img and grads: they are kept
+    # with the graphs, so no replay ever writes memory the allocator reused
     return dict(rast=rast, rast_b=rast_b, params=params, opts_f=opts_f, opts_b=opts_b,
                 reports=reports, fwd_ms=fwd_ms, fb_ms=fb_ms, fwd_graph_ms=fwd_graph_ms,
                 fb_graph_ms=fb_graph_ms, st_fwd=st_fwd, nf=nf, st_fb=st_fb, nb=nb,
-                g_fwd=g_fwd, g_fb=g_fb)
+                g_fwd=g_fwd, g_fb=g_fb, buffers=(out, out_b, grad_img, grads, target))
 
 
 def paired_comparison(m, m3, steps, torch, rounds=5):

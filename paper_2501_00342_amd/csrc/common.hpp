@@ -21,6 +21,20 @@ constexpr int kPreThreads = 256;
 constexpr int kPreTile = 128;                        // Gaussians per forward-preprocess block
 constexpr int kPersistentBlocks = 1024;              // grid of the persistent kernels
 constexpr int kDepthPasses = 4;                      // 32-bit depth keys
+constexpr int kXcds = 8;                             // dies; blocks go to them round-robin
+
+// Renumbers block b of a grid whose first `active` blocks carry work so that
+// the live blocks one XCD runs (b = x, x + 8, x + 16, ... < active) take a
+// contiguous range of ids; blocks from `active` on keep their ids.
+// Neighbouring partitions then share that die's L2, where their partial-line
+// writes (strided digit counts, short scatter runs) merge, and the live work
+// stays spread over all dies.  A bijection of [0, grid size).
+__device__ __forceinline__ int64_t xcd_part(uint32_t b, int64_t active) {
+    if ((int64_t)b >= active) return b;
+    const uint32_t A = (uint32_t)active;
+    const uint32_t x = b % kXcds, i = b / kXcds, q = A / kXcds, r = A % kXcds;
+    return (int64_t)x * q + (x < r ? x : r) + i;
+}
 
 // header words (u32) at workspace offset 0
 enum Header : int {

@@ -44,7 +44,7 @@ k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t coun
     for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&hist[0][0])[i] = 0;
     __syncthreads();
     const int64_t count = pass_count(count_ptr, count_host);
-    const int64_t p = blockIdx.x;
+    const int64_t p = xcd_part(blockIdx.x, (count + kSortTile - 1) / kSortTile);
     const int64_t base = p * kSortTile;
 #pragma unroll 4
     for (int k = 0; k < kSortItems; ++k) {
@@ -142,8 +142,8 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     __shared__ uint32_t s_kept;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t p = blockIdx.x;
     const int64_t count = pass_count(count_ptr, count_host);
+    const int64_t p = xcd_part(blockIdx.x, (count + kSortTile - 1) / kSortTile);
     const int64_t base = p * kSortTile;
     if (base >= count) return;
     for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&s_wave[0][0])[i] = 0;

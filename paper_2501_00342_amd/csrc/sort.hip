@@ -96,7 +96,10 @@ k_duplicate(Workspace ws, int64_t n) {
     const uint32_t nn = (uint32_t)n;
     const int64_t n_vis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
     const int64_t row = 2 * ws.pair_parts;   // histogram row length
-    for (int64_t chunk = blockIdx.x; chunk * kDupChunk < Pc; chunk += gridDim.x) {
+    const int64_t n_chunks = (Pc + kDupChunk - 1) / kDupChunk;
+    for (int64_t round = 0; round + blockIdx.x < n_chunks; round += gridDim.x) {
+        const int64_t live = n_chunks - round < gridDim.x ? n_chunks - round : gridDim.x;
+        const int64_t chunk = round + xcd_part(blockIdx.x, live);
         const int64_t p0 = chunk * kDupChunk;
         const int64_t p1 = (p0 + kDupChunk < Pc) ? p0 + kDupChunk : Pc;
         const int64_t i0 = ws.chunk_start[chunk];
@@ -225,7 +228,7 @@ k_duplicate(Workspace ws, int64_t n) {
         ws.counts[tid * row + chunk] = s_hist[tid];
     }
     // zero rows for the chunks past the pair count
-    for (int64_t chunk = (Pc + kDupChunk - 1) / kDupChunk + blockIdx.x; chunk < row;
+    for (int64_t chunk = n_chunks + blockIdx.x; chunk < row;
          chunk += gridDim.x)
         ws.counts[tid * row + chunk] = 0;
 }
