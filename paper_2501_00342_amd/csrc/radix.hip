@@ -33,32 +33,62 @@ __device__ __forceinline__ uint32_t rect_pairs(uint64_t r) {
 
 // ---------------------------------------------------------------------------
 
-// Digit histogram of one partition (per-wave LDS rows, atomics).
+// Digit histogram of one partition (per-wave LDS rows, atomics).  A digit of
+// fewer than 8 bits takes few values, each repeated across a wave's lanes;
+// its bins are spread over 2^c copies per wave (c = min(3, 8 - bits)),
+// picked by lane, so equal digits rarely hit the same LDS word.  Only the
+// 2^bits live digit rows are written.
 template <typename KeyT>
 __global__ void __launch_bounds__(kSortThreads)
 k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t count_host,
-          int shift, uint32_t* __restrict__ counts, int64_t parts, bool drop) {
+          int shift, uint32_t* __restrict__ counts, int64_t parts, bool drop, int digit_bits) {
     constexpr int WAVES = kSortThreads / 64;
     __shared__ uint32_t hist[WAVES][kRadix];
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int cl = kRadixBits - digit_bits < 3 ? kRadixBits - digit_bits : 3;
+    const uint32_t dmask = (1u << digit_bits) - 1u, cmask = (1u << cl) - 1u;
     for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&hist[0][0])[i] = 0;
     __syncthreads();
     const int64_t count = pass_count(count_ptr, count_host);
     const int64_t p = xcd_part(blockIdx.x, (count + kSortTile - 1) / kSortTile);
     const int64_t base = p * kSortTile;
+    const uint32_t lane_bin = (uint32_t)lane & cmask;
+    auto add = [&](uint32_t key) {
+        if (!drop || key != 0xFFFFFFFFu) atomicAdd(&hist[wave][(((key >> shift) & dmask) << cl) | lane_bin], 1u);
+    };
+    if (base + kSortTile <= count && ((uintptr_t)keys & 15u) == 0) {
+        // a full partition: 16-byte loads, each wave instruction reading 1 KB
+        // contiguous (a histogram does not depend on the order of the items)
+        constexpr int PER = 16 / (int)sizeof(KeyT);
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(keys + base);
+#pragma unroll
+        for (int j = 0; j < kSortItems / PER; ++j) {
+            const uint4 q = src[j * kSortThreads + tid];
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if constexpr (sizeof(KeyT) == 2) {
+                    add(w[e] & 0xFFFFu);
+                    add(w[e] >> 16);
+                } else {
+                    add(w[e]);
+                }
+            }
+        }
+    } else {
 #pragma unroll 4
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = base + (int64_t)k * kSortThreads + tid;
-        if (i < count) {
-            const uint32_t key = keys[i];
-            if (!drop || key != 0xFFFFFFFFu) atomicAdd(&hist[wave][(key >> shift) & (kRadix - 1)], 1u);
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t i = base + (int64_t)k * kSortThreads + tid;
+            if (i < count) add(keys[i]);
         }
     }
     __syncthreads();
     const int d = tid;
+    if (d > (int)dmask) return;
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) c += hist[w][d];
+    for (int w = 0; w < WAVES; ++w)
+        for (int j = 0; j <= (int)cmask; ++j) c += hist[w][(d << cl) + j];
     counts[(int64_t)d * parts + p] = c;
 }
 
@@ -117,10 +147,31 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
     }
 }
 
+// Exclusive scan of one value per thread of a 256-thread block: lane
+// shuffles within each wave, then the four wave totals through s_w (4 words
+// no other thread touches until the next barrier).  One barrier; *total
+// receives the block's sum.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_w, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    const uint32_t w0 = s_w[0], w1 = s_w[1], w2 = s_w[2], w3 = s_w[3];
+    *total = w0 + w1 + w2 + w3;
+    const uint32_t before = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    return before + x - v;
+}
+
 // NB: significant bits of the digit (the key has no bits above shift + NB),
-// so ranking needs NB ballots instead of kRadixBits
+// so ranking needs NB ballots instead of kRadixBits.  Four waves per SIMD
+// (128 VGPRs): the LDS of four blocks fills a CU.
 template <typename KeyT, int NB>
-__global__ void __launch_bounds__(kSortThreads)
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
             KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
             const uint32_t* count_ptr, int64_t count_host, int shift,
@@ -139,34 +190,24 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     unsigned long long* s_match = reinterpret_cast<unsigned long long*>(s_keys);
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_global[kRadix];
-    __shared__ uint32_t s_kept;
+    __shared__ uint32_t s_scan[2][WAVES];
+    static_assert(kSortThreads == 256, "one thread per digit, four waves");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t count = pass_count(count_ptr, count_host);
     const int64_t p = xcd_part(blockIdx.x, (count + kSortTile - 1) / kSortTile);
     const int64_t base = p * kSortTile;
     if (base >= count) return;
-    for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&s_wave[0][0])[i] = 0;
-    if (kLdsMatch)
-        for (int i = tid; i < WAVES * kRadix; i += kSortThreads) s_match[i] = 0ull;
-    // global start of this partition's run of digit d
-    {
-        const int d = tid;
-        const uint32_t tot = totals[d];
-        s_local[d] = tot;
-        __syncthreads();
-        for (int off = 1; off < kRadix; off <<= 1) {
-            const uint32_t t = d >= off ? s_local[d - off] : 0u;
-            __syncthreads();
-            s_local[d] += t;
-            __syncthreads();
-        }
-        s_global[d] = s_local[d] - tot + counts[((int64_t)d * parts + p) * cstride];
-        __syncthreads();
-    }
+    // digits from 2^NB on do not occur: their rows are not read (nor written
+    // by the upsweep or scanned)
+    constexpr int kLive = 1 << NB;
+    const uint32_t tot = tid < kLive ? totals[tid] : 0u;
+    const uint32_t cnt_dp = tid < kLive ? counts[((int64_t)tid * parts + p) * cstride] : 0u;
 
+    // this partition's items: issued before the digit-start scan, so their
+    // latency overlaps it
     uint32_t key[kSortItems], val[kSortItems];
-    uint16_t rank[kSortItems];
+    uint32_t rank2[kSortItems / 2];   // two 16-bit ranks per register
     // this wave's items in 32-bit offsets from a wave-uniform base pointer
     // (counts stay below 2^30)
     const int64_t wbase = base + (int64_t)wave * WAVE_ITEMS;
@@ -185,6 +226,16 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
             val[k] = 0;
         }
     }
+    for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&s_wave[0][0])[i] = 0;
+    if (kLdsMatch)
+        for (int i = tid; i < WAVES * kRadix; i += kSortThreads) s_match[i] = 0ull;
+    // global start of this partition's run of digit d (the scan's barrier
+    // also orders the clears above before the ranking)
+    {
+        uint32_t all;
+        s_global[tid] = block_excl_scan256(tot, s_scan[0], &all) + cnt_dp;
+    }
+
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
@@ -210,11 +261,13 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
         }
         const uint64_t lower = m & lt_mask;
         const uint32_t prior = valid ? s_wave[wave][d] : 0u;
-        rank[k] = (uint16_t)(prior + __popcll(lower));
+        const uint32_t r = prior + (uint32_t)__popcll(lower);
+        rank2[k >> 1] = (k & 1) ? (rank2[k >> 1] | (r << 16)) : r;
         if (valid && lower == 0) s_wave[wave][d] = prior + (uint32_t)__popcll(m);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+    int n_valid;
     {
         const int d = tid;
         uint32_t total = 0;
@@ -224,16 +277,9 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
             s_wave[w][d] = total;
             total += c;
         }
-        s_local[d] = total;
-        __syncthreads();
-        for (int off = 1; off < kRadix; off <<= 1) {
-            const uint32_t t = d >= off ? s_local[d - off] : 0u;
-            __syncthreads();
-            s_local[d] += t;
-            __syncthreads();
-        }
-        if (d == kRadix - 1) s_kept = s_local[d];
-        s_local[d] -= total;
+        uint32_t kept;
+        s_local[d] = block_excl_scan256(total, s_scan[1], &kept);
+        n_valid = (int)kept;
         __syncthreads();
     }
 #pragma unroll
@@ -241,14 +287,18 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
         const int li = k * 64 + lane;
         if (li < lim && !(drop && key[k] == 0xFFFFFFFFu)) {
             const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
-            const uint32_t pos = s_local[dd] + s_wave[wave][dd] + rank[k];
+            const uint32_t pos = s_local[dd] + s_wave[wave][dd] + ((rank2[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
             s_keys[pos] = key[k];
             s_vals[pos] = val[k];
         }
     }
     __syncthreads();
-    const int n_valid = (int)s_kept;
-    for (int i = tid; i < n_valid; i += kSortThreads) {
+    // unrolled over the thread's fixed slots so that the LDS reads and the
+    // stores of different items overlap
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int i = tid + j * kSortThreads;
+        if (i >= n_valid) break;
         const uint32_t k = s_keys[i];
         const uint32_t dd = (k >> shift) & (kRadix - 1);
         const uint32_t out = s_global[dd] + (uint32_t)(i - (int)s_local[dd]);
@@ -330,19 +380,20 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
     // counted: the digit counts of every half partition are already in
     // counts[d][2 parts] (written by the pass's producer)
     const int cstride = counted ? 2 : 1;
+    const int bits = digit_bits < 1 ? 1 : (digit_bits > kRadixBits ? kRadixBits : digit_bits);
     if (!counted) {
         const dim3 ug((unsigned)parts), ub(kSortThreads);
         hipLaunchKernelGGL(k_upsweep<KeyT>, ug, ub, 0, s, keys_in, count_ptr, count_host, shift,
-                           counts, parts, drop_culled);
+                           counts, parts, drop_culled, bits);
     }
-    hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kScanRowThreads), 0, s, counts,
+    hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kScanRowThreads), 0, s, counts,
                        parts * cstride, totals, drop_culled ? kept_out : nullptr);
     const dim3 g((unsigned)parts);
 #define SGS_DOWNSWEEP(NB)                                                                      \
     downsweep_t<KeyT, NB>(g, s, keys_in, vals_in, keys_out, vals_out, count_ptr, count_host,   \
                           shift, counts, totals, parts, rects, pairs_out, n_rects, drop_culled,  \
                           cstride, ranges, n_tiles)
-    switch (digit_bits) {
+    switch (bits) {
         case 1: SGS_DOWNSWEEP(1); break;
         case 2: SGS_DOWNSWEEP(2); break;
         case 3: SGS_DOWNSWEEP(3); break;
@@ -356,7 +407,7 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
     if (ranges) {
         // the pass's output keys are sorted; its counts hold each partition's
         // exclusive offset within its digit (the key has digit_bits bits here)
-        const int digits = 1 << (digit_bits < kRadixBits ? digit_bits : kRadixBits);
+        const int digits = 1 << bits;
         const dim3 eg((unsigned)((parts + 255) / 256), (unsigned)digits);
         hipLaunchKernelGGL(k_range_edges<KeyT>, eg, dim3(256), 0, s, keys_out, counts, totals, parts,
                            cstride, count_ptr, count_host, ranges, n_tiles);
