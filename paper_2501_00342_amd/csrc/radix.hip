@@ -147,11 +147,12 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
     }
 }
 
-// Exclusive scan of one value per thread of a 256-thread block: lane
-// shuffles within each wave, then the four wave totals through s_w (4 words
-// no other thread touches until the next barrier).  One barrier; *total
+// Exclusive scan of one value per thread of a block of WAVES waves: lane
+// shuffles within each wave, then the wave totals through s_w (WAVES words no
+// other thread touches until the next barrier).  One barrier; *total
 // receives the block's sum.
-__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_w, uint32_t* total) {
+template <int WAVES>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t x = v;
 #pragma unroll
@@ -161,84 +162,132 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_w
     }
     if (lane == 63) s_w[wave] = x;
     __syncthreads();
-    const uint32_t w0 = s_w[0], w1 = s_w[1], w2 = s_w[2], w3 = s_w[3];
-    *total = w0 + w1 + w2 + w3;
-    const uint32_t before = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const uint32_t t = s_w[w];
+        before += w < wave ? t : 0u;
+        all += t;
+    }
+    *total = all;
     return before + x - v;
 }
 
+// The downsweep runs 512 threads of 8 items over a kSortTile partition: a
+// wave's serial ranking chain is 8 items long, and three blocks (24 waves)
+// share a CU.
+constexpr int kDownThreads = 512;
+constexpr int kDownItems = kSortTile / kDownThreads;
+
 // NB: significant bits of the digit (the key has no bits above shift + NB),
-// so ranking needs NB ballots instead of kRadixBits.  Four waves per SIMD
-// (128 VGPRs): the LDS of four blocks fills a CU.
+// so ranking needs NB ballots instead of kRadixBits.
 template <typename KeyT, int NB>
-__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kDownThreads)
 k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
             KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
             const uint32_t* count_ptr, int64_t count_host, int shift,
             const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int64_t parts,
             const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out, int64_t n_rects,
             bool drop, int cstride, uint32_t* __restrict__ ranges, int64_t n_tiles) {
-    constexpr int WAVES = kSortThreads / 64;
-    constexpr int WAVE_ITEMS = 64 * kSortItems;
-    __shared__ __align__(16) uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    constexpr int WAVES = kDownThreads / 64;
+    constexpr int WAVE_ITEMS = 64 * kDownItems;
+    // staged (key, value) words: key in the low half, value in the high half
+    __shared__ __align__(16) uint64_t s_kv[kSortTile];
     __shared__ uint32_t s_wave[WAVES][kRadix];
     // full 8-bit digits: lanes with equal digits are found through a per-wave
     // table of lane masks (one LDS OR and one read per item) instead of eight
-    // ballots; the table lives in s_keys, which the ranking does not use yet
+    // ballots; the table lives in s_kv, which the ranking does not use yet
     constexpr bool kLdsMatch = NB >= kRadixBits;
-    unsigned long long* s_match = reinterpret_cast<unsigned long long*>(s_keys);
+    static_assert(WAVES * kRadix * 8 <= kSortTile * 8, "match tables fit in s_kv");
+    unsigned long long* s_match = reinterpret_cast<unsigned long long*>(s_kv);
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_global[kRadix];
     __shared__ uint32_t s_scan[2][WAVES];
-    static_assert(kSortThreads == 256, "one thread per digit, four waves");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t count = pass_count(count_ptr, count_host);
     const int64_t p = xcd_part(blockIdx.x, (count + kSortTile - 1) / kSortTile);
     const int64_t base = p * kSortTile;
     if (base >= count) return;
-    // digits from 2^NB on do not occur: their rows are not read (nor written
-    // by the upsweep or scanned)
+    // thread d < 2^NB owns digit d; digits from 2^NB on do not occur (their
+    // rows are neither written by the upsweep nor scanned)
     constexpr int kLive = 1 << NB;
     const uint32_t tot = tid < kLive ? totals[tid] : 0u;
     const uint32_t cnt_dp = tid < kLive ? counts[((int64_t)tid * parts + p) * cstride] : 0u;
 
-    // this partition's items: issued before the digit-start scan, so their
-    // latency overlaps it
-    uint32_t key[kSortItems], val[kSortItems];
-    uint32_t rank2[kSortItems / 2];   // two 16-bit ranks per register
+    // this partition's items, issued before the digit-start scan so that
+    // their latency overlaps it.  A full partition comes in by direct
+    // 16-byte global->LDS loads (keys into the first half of s_kv, values
+    // into the second, no
+    // registers held in flight); the ragged last one by per-lane loads.
+    uint32_t key[kDownItems], val[kDownItems];
+    uint32_t rank2[kDownItems / 2];   // two 16-bit ranks per register
     // this wave's items in 32-bit offsets from a wave-uniform base pointer
     // (counts stay below 2^30)
     const int64_t wbase = base + (int64_t)wave * WAVE_ITEMS;
     const int64_t left = count - wbase;
     const int lim = left <= 0 ? 0 : (left >= WAVE_ITEMS ? WAVE_ITEMS : (int)left);
-    const KeyT* __restrict__ kin = keys_in + wbase;
-    const uint32_t* __restrict__ vin = vals_in ? vals_in + wbase : nullptr;
+    const bool full = base + kSortTile <= count && ((uintptr_t)keys_in & 15u) == 0 &&
+                      ((uintptr_t)vals_in & 15u) == 0;
+    if (full) {
+        constexpr int KCH = kSortTile * (int)sizeof(KeyT) / 1024;   // 1 KB chunks of keys
+        const char* gk = reinterpret_cast<const char*>(keys_in + base);
+        for (int c = wave; c < KCH; c += WAVES)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void*)(gk + c * 1024 + lane * 16),
+                (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(s_kv) + c * 1024),
+                16, 0, 0);
+        if (vals_in) {
+            const char* gv = reinterpret_cast<const char*>(vals_in + base);
+            for (int c = wave; c < kSortTile * 4 / 1024; c += WAVES)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void*)(gv + c * 1024 + lane * 16),
+                    (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(s_kv) + kSortTile * 4 + c * 1024),
+                    16, 0, 0);
+        }
+    } else {
+        const KeyT* __restrict__ kin = keys_in + wbase;
+        const uint32_t* __restrict__ vin = vals_in ? vals_in + wbase : nullptr;
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        const int li = k * 64 + lane;
-        if (li < lim) {
-            key[k] = kin[li];
-            val[k] = vin ? vin[li] : (uint32_t)wbase + (uint32_t)li;
-        } else {
-            key[k] = 0xFFFFFFFFu;
-            val[k] = 0;
+        for (int k = 0; k < kDownItems; ++k) {
+            const int li = k * 64 + lane;
+            if (li < lim) {
+                key[k] = kin[li];
+                val[k] = vin ? vin[li] : (uint32_t)wbase + (uint32_t)li;
+            } else {
+                key[k] = 0xFFFFFFFFu;
+                val[k] = 0;
+            }
         }
     }
-    for (int i = tid; i < WAVES * kRadix; i += kSortThreads) (&s_wave[0][0])[i] = 0;
-    if (kLdsMatch)
-        for (int i = tid; i < WAVES * kRadix; i += kSortThreads) s_match[i] = 0ull;
-    // global start of this partition's run of digit d (the scan's barrier
-    // also orders the clears above before the ranking)
+    for (int i = tid; i < WAVES * kRadix; i += kDownThreads) (&s_wave[0][0])[i] = 0;
+    // this wave's direct loads have landed; the scan's barrier publishes them
+    if (full) __builtin_amdgcn_s_waitcnt(0);
+    // global start of this partition's run of digit d
     {
         uint32_t all;
-        s_global[tid] = block_excl_scan256(tot, s_scan[0], &all) + cnt_dp;
+        const uint32_t st = block_excl_scan<WAVES>(tot, s_scan[0], &all);
+        if (tid < kRadix) s_global[tid] = st + cnt_dp;
+    }
+    if (full) {
+        const KeyT* sk = reinterpret_cast<const KeyT*>(s_kv) + wave * WAVE_ITEMS;
+        const uint32_t* sv = reinterpret_cast<const uint32_t*>(s_kv) + kSortTile + wave * WAVE_ITEMS;
+#pragma unroll
+        for (int k = 0; k < kDownItems; ++k) {
+            const int li = k * 64 + lane;
+            key[k] = sk[li];
+            val[k] = vals_in ? sv[li] : (uint32_t)wbase + (uint32_t)li;
+        }
+        __syncthreads();   // the staged input is read before the tables reuse s_kv
+    }
+    if (kLdsMatch) {
+        for (int i = tid; i < WAVES * kRadix; i += kDownThreads) s_match[i] = 0ull;
+        __syncthreads();
     }
 
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
+    for (int k = 0; k < kDownItems; ++k) {
         const int li = k * 64 + lane;
         const bool valid = li < lim && !(drop && key[k] == 0xFFFFFFFFu);
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
@@ -269,49 +318,55 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     __syncthreads();
     int n_valid;
     {
-        const int d = tid;
+        // per digit: exclusive offsets of the waves, then the block's digit starts
         uint32_t total = 0;
+        if (tid < kRadix) {
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            const uint32_t c = s_wave[w][d];
-            s_wave[w][d] = total;
-            total += c;
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = s_wave[w][tid];
+                s_wave[w][tid] = total;
+                total += c;
+            }
         }
         uint32_t kept;
-        s_local[d] = block_excl_scan256(total, s_scan[1], &kept);
+        const uint32_t st = block_excl_scan<WAVES>(total, s_scan[1], &kept);
+        if (tid < kRadix) {
+            s_local[tid] = st;
+            s_global[tid] -= st;   // now: output index of staged slot i is s_global[d] + i
+        }
         n_valid = (int)kept;
         __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
+    for (int k = 0; k < kDownItems; ++k) {
         const int li = k * 64 + lane;
         if (li < lim && !(drop && key[k] == 0xFFFFFFFFu)) {
             const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
             const uint32_t pos = s_local[dd] + s_wave[wave][dd] + ((rank2[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
-            s_keys[pos] = key[k];
-            s_vals[pos] = val[k];
+            s_kv[pos] = (uint64_t)key[k] | ((uint64_t)val[k] << 32);
         }
     }
     __syncthreads();
     // unrolled over the thread's fixed slots so that the LDS reads and the
     // stores of different items overlap
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        const int i = tid + j * kSortThreads;
+    for (int j = 0; j < kDownItems; ++j) {
+        const int i = tid + j * kDownThreads;
         if (i >= n_valid) break;
-        const uint32_t k = s_keys[i];
+        const uint64_t kv = s_kv[i];
+        const uint32_t k = (uint32_t)kv, v = (uint32_t)(kv >> 32);
         const uint32_t dd = (k >> shift) & (kRadix - 1);
-        const uint32_t out = s_global[dd] + (uint32_t)(i - (int)s_local[dd]);
+        const uint32_t out = s_global[dd] + (uint32_t)i;
         __builtin_assume(out < (1u << 30));
-        const uint32_t v = s_vals[i];
         if (keys_out) keys_out[out] = (KeyT)k;
         vals_out[out] = v;
         if (pairs_out) pairs_out[out] = v < (uint64_t)n_rects ? rect_pairs(rects[v]) : 0u;
         // last tile pass: a key change between neighbours of this block's run
-        // is a tile boundary (run starts are checked by k_range_edges)
-        if (ranges && i > (int)s_local[dd]) {
-            const uint32_t pk = s_keys[i - 1];
-            if (pk != k) {
+        // of one digit is a tile boundary (run starts, where the previous
+        // staged key has another digit, are checked by k_range_edges)
+        if (ranges && i > 0) {
+            const uint32_t pk = (uint32_t)s_kv[i - 1];
+            if (pk != k && ((pk >> shift) & (kRadix - 1)) == dd) {
                 if (k < (uint64_t)n_tiles) ranges[2 * (int64_t)k] = out;
                 if (pk < (uint64_t)n_tiles) ranges[2 * (int64_t)pk + 1] = out;
             }
@@ -364,7 +419,7 @@ static void downsweep_t(dim3 grid, hipStream_t s, const KeyT* keys_in, const uin
                         const uint32_t* totals, int64_t parts, const uint64_t* rects,
                         uint32_t* pairs_out, int64_t n_rects, bool drop, int cstride,
                         uint32_t* ranges, int64_t n_tiles) {
-    hipLaunchKernelGGL((k_downsweep<KeyT, NB>), grid, dim3(kSortThreads), 0, s, keys_in, vals_in,
+    hipLaunchKernelGGL((k_downsweep<KeyT, NB>), grid, dim3(kDownThreads), 0, s, keys_in, vals_in,
                        keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts,
                        rects, pairs_out, n_rects, drop, cstride, ranges, n_tiles);
 }
