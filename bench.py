@@ -51,11 +51,17 @@ def parse():
     return ap.parse_args()
 
 
-def stage_bytes(name, n, nvis, P, tiles, fpg, tile_passes, npix):
-    """Algorithmic HBM bytes of each stage for one frame."""
+GEOM_FLOATS = 3 + 3 + 4 + 1   # mean, log-scale, quaternion, opacity logit
+
+
+def stage_bytes(name, n, nvis, nvis_g, P, tiles, fpg, tile_passes, npix):
+    """Algorithmic HBM bytes of each stage for one frame: n Gaussians, nvis
+    visible (camera, Gaussian) items, nvis_g Gaussians visible in some
+    camera (the only ones whose colour is read), P pairs."""
     kb = 2 if tiles <= 65536 else 4   # bytes per tile key
+    fc = fpg - GEOM_FLOATS             # colour floats per Gaussian
     return {
-        "fwd.preprocess": n * (4 * fpg) + n * (4 + 8) + nvis * 64,
+        "fwd.preprocess": n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + n * (4 + 8) + nvis * 64,
         "fwd.depth_sort": 56 * n,
         "fwd.pair_scan": n * (4 + 8 + 4),
         "fwd.duplicate": nvis * (4 + 4 + 8) + 8 * P,
@@ -65,7 +71,9 @@ def stage_bytes(name, n, nvis, P, tiles, fpg, tile_passes, npix):
         "fwd.tile_order": None,  # heavy-first order of the queue schedule
         "fwd.blend": None,
         "bwd.blend": None,
-        "bwd.preprocess": nvis * 36 + 2 * n * (4 * fpg),
+        # geometry read and its gradient written for every Gaussian, colour
+        # read for the visible ones, colour gradient written for all
+        "bwd.preprocess": nvis * 36 + 2 * n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + n * 4 * fc,
     }.get(name)
 
 
@@ -313,7 +321,9 @@ def main():
     names = L.stage_names()
     bits, P = rast.status()
     visited, evaluated = rast.blend_work(m["params"])
-    n_vis = int(np.count_nonzero(rast.depth_keys().cpu().numpy().view(np.uint32) != 0xFFFFFFFF))
+    vis_items = (rast.depth_keys().cpu().numpy().view(np.uint32) != 0xFFFFFFFF).reshape(len(cams), sc.n)
+    n_vis = int(np.count_nonzero(vis_items))
+    n_vis_g = int(np.count_nonzero(vis_items.any(axis=0)))
     tiles = int(rast.layout.n_tiles)
     tile_passes = math.ceil(max(1, math.ceil(math.log2(max(tiles, 2)))) / 8)
     fpg = sc.floats_per_gaussian()
@@ -325,7 +335,7 @@ def main():
         if calls <= 0:
             continue
         ms = src[i] / calls
-        b = stage_bytes(nm, sc.n, n_vis, P, tiles, fpg, tile_passes, W * H)
+        b = stage_bytes(nm, sc.n, n_vis, n_vis_g, P, tiles, fpg, tile_passes, W * H)
         ent = {"ms": round(ms, 5)}
         if b is not None and ms > 0:
             ent["alg_bytes"] = int(b)

@@ -57,7 +57,12 @@ typedef enum sgs_status {
 #define SGS_MAX_CAMERAS 1024
 #define SGS_MAX_IMAGE_SIDE 32767
 
-/* Gaussian parameters (device, float32, SoA).  n may be 0. */
+/* Gaussian parameters (device, float32).  n may be 0.
+ * The geometry, which every Gaussian needs for culling, is component-major
+ * (one contiguous row per component: coalesced over all n).  The colour,
+ * which only Gaussians that survive culling need, is Gaussian-major (each
+ * Gaussian's coefficients contiguous), so a culled Gaussian's colour is
+ * never read. */
 typedef struct sgs_gaussians {
     int64_t n;
     int32_t sh_degree;               /* 0..3 */
@@ -66,10 +71,10 @@ typedef struct sgs_gaussians {
     const float* log_scales;         /* [3][n]   log of the scale vector s (eq. 3) */
     const float* quats;              /* [4][n]   rotation q, (w,x,y,z) (eq. 3)     */
     const float* opacity_logits;     /* [n]      logit of opacity sigma            */
-    const float* sh;                 /* [(deg+1)^2][3][n] SH coefficients (eq. 4)  */
-    const float* sg_axes;            /* [K][3][n] lobe axis mu, any length (eq. 5) */
-    const float* sg_log_sharpness;   /* [K][n]   log of lobe sharpness lambda      */
-    const float* sg_amplitudes;      /* [K][3][n] lobe RGB amplitude alpha          */
+    const float* sh;                 /* [n][(deg+1)^2][3] SH coefficients (eq. 4)  */
+    const float* sg_axes;            /* [n][K][3] lobe axis mu, any length (eq. 5) */
+    const float* sg_log_sharpness;   /* [n][K]   log of lobe sharpness lambda      */
+    const float* sg_amplitudes;      /* [n][K][3] lobe RGB amplitude alpha          */
 } sgs_gaussians;
 
 /* Gradient outputs, same shapes as sgs_gaussians (device, float32).  Every

@@ -51,63 +51,42 @@ __device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int 
     return ok;
 }
 
-// the colour of Gaussian g read from the global (component-major) arrays
-template <int DEG, int KMAX>
-__device__ __forceinline__ bool colour(const Params& p, int64_t g, float d0, float d1, float d2,
-                                       float rgb[3]) {
-    const int64_t n = p.n;
-    return colour_eval<DEG, KMAX>(
-        [&](int l, int c) { return p.sh[((int64_t)l * 3 + c) * n + g]; },
-        [&](int k, int j) { return p.sg_axes[((int64_t)k * 3 + j) * n + g]; },
-        [&](int k) { return p.sg_log_sharpness[(int64_t)k * n + g]; },
-        [&](int k, int c) { return p.sg_amplitudes[((int64_t)k * 3 + c) * n + g]; }, p.n_lobes,
-        d0, d1, d2, rgb);
-}
-
-// pointer to colour parameter row r of the component-major arrays: SH
-// coefficient (l, c) is row 3 l + c, then per lobe k the axis (3 rows), then
-// the log-sharpness rows, then the amplitudes (3 rows per lobe)
-__device__ __forceinline__ const float* colour_row(const Params& p, int nc3, int r) {
+// Colour row r of a Gaussian, in the order the LDS staging uses: SH
+// coefficient (l, c) is row 3 l + c, then per lobe k the axis (3 rows
+// 3 NC + 3 k + j), then the log-sharpness rows (3 NC + 3 K + k), then the
+// amplitudes (3 NC + 4 K + 3 k + c).  The global arrays are Gaussian-major:
+// sh[g][NC][3], sg_axes[g][K][3], sg_log_sharpness[g][K], sg_amplitudes[g][K][3].
+//
+// Direct 4-byte global->LDS loads of every colour row of this lane's
+// Gaussian g into column `col` of s_col[rows][kPreTile] (col = the thread's
+// index in the block; the LDS destination of a direct load is the
+// wave-uniform base plus 4 bytes per lane).  Called by the lanes that need
+// their colour only: the loads follow the execution mask, so culled
+// Gaussians fetch nothing.  The caller waits (s_waitcnt) before reading.
+template <int NC3>
+__device__ __forceinline__ void gather_colour(const Params& p, int64_t g, float* s_col) {
     const int K = p.n_lobes;
-    const int64_t n = p.n;
-    if (r < nc3) return p.sh + (int64_t)r * n;
-    r -= nc3;
-    if (r < 3 * K) return p.sg_axes + (int64_t)r * n;
-    r -= 3 * K;
-    if (r < K) return p.sg_log_sharpness + (int64_t)r * n;
-    return p.sg_amplitudes + (int64_t)(r - K) * n;
-}
-
-// Direct global->LDS loads (no registers) of the colour rows of the
-// kPreTile Gaussians from `base` into s_col[rows][kPreTile] (a block of
-// kPreTile threads; s_col holds an even number of rows).  vec4: the rows
-// start 16-byte aligned (n a multiple of 4), one instruction fills two
-// rows; otherwise 4 bytes per lane.  Lanes past the end read in-bounds
-// data that nothing uses.  The caller waits (s_waitcnt) and synchronises
-// before reading s_col.
-__device__ __forceinline__ void stage_colour_rows(const Params& p, int nc3, int rows, int64_t base,
-                                                  bool vec4, float* s_col) {
-    const int64_t n = p.n;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (vec4) {
-        // lanes 0-31 row r, lanes 32-63 row r + 1; wave w takes rows 2 w, 2 w + 4, ...
-        int64_t src = base + 4 * (lane & 31);
-        src = src + 4 <= n ? src : n - 4;
-        for (int r = 2 * wave; r < rows; r += 4) {
-            const int rr = r + (lane >> 5) < rows ? r + (lane >> 5) : r;
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void*)(colour_row(p, nc3, rr) + src),
-                (__attribute__((address_space(3))) void*)(s_col + r * kPreTile), 16, 0, 0);
-        }
-    } else {
-        // wave w loads floats [64 w, 64 w + 64) of every row
-        int64_t src = base + wave * 64 + lane;
-        src = src < n ? src : n - 1;
-        for (int r = 0; r < rows; ++r)
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void*)(colour_row(p, nc3, r) + src),
-                (__attribute__((address_space(3))) void*)(s_col + r * kPreTile + wave * 64), 4, 0,
-                0);
+    const int wave_col = threadIdx.x & ~63;
+    auto dma = [&](const float* src, int row) {
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(s_col + row * kPreTile + wave_col),
+                                         4, 0, 0);
+    };
+    // rolled loops: one address pair walks the rows (an unrolled gather
+    // would hold every row's 64-bit address in registers at once)
+    const float* sh = p.sh + g * NC3;
+#pragma unroll 1
+    for (int r = 0; r < NC3; ++r) dma(sh + r, r);
+    if (K > 0) {
+        const float* ax = p.sg_axes + g * (3 * K);
+        const float* ls = p.sg_log_sharpness + g * K;
+        const float* am = p.sg_amplitudes + g * (3 * K);
+#pragma unroll 1
+        for (int r = 0; r < 3 * K; ++r) dma(ax + r, NC3 + r);
+#pragma unroll 1
+        for (int r = 0; r < K; ++r) dma(ls + r, NC3 + 3 * K + r);
+#pragma unroll 1
+        for (int r = 0; r < 3 * K; ++r) dma(am + r, NC3 + 4 * K + r);
     }
 }
 

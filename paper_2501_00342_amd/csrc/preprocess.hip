@@ -120,27 +120,23 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
     return r;
 }
 
-// A block takes tiles of kPreTile consecutive Gaussians.  At the start of a
-// tile each wave issues direct global->LDS loads of its half of every colour
-// row (no registers held), then runs the float64 geometry while they are in
-// flight; the colour is evaluated from LDS afterwards.  The geometry's and
-// the colour's registers are then never live together.
+// A block takes tiles of kPreTile consecutive Gaussians, one per thread.
+// The float64 geometry comes first; a lane whose Gaussian is visible in a
+// camera then issues direct global->LDS loads of its colour rows into its
+// own column of s_col (once per tile, at the first camera that sees it), so
+// culled Gaussians never fetch colour and no lane reads another lane's
+// column: the waves need no barrier.  The colour is evaluated from LDS, so
+// the geometry's and the colour's registers are never live together.
 template <int DEG, int KMAX>
 __global__ void __launch_bounds__(kPreTile)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     constexpr int MAXROWS = 3 * NC + 7 * KMAX;
-    // an even number of rows: the 16-byte loads fill rows in pairs
-    __shared__ float s_col[(MAXROWS + 1) & ~1][kPreTile];
+    __shared__ float s_col[MAXROWS > 0 ? MAXROWS : 1][kPreTile];
     const int64_t n = p.n;
-    const int rows = 3 * NC + 7 * p.n_lobes;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // rows start 16-byte aligned when n is a multiple of 4 (the arrays are)
-    const bool vec4 = (n & 3) == 0;
+    const int tid = threadIdx.x;
     for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
          base += (int64_t)gridDim.x * kPreTile) {
-        __syncthreads();   // the previous tile's colour rows are no longer read
-        stage_colour_rows(p, 3 * NC, rows, base, vec4, &s_col[0][0]);
         const int64_t g0 = base + tid;
         const bool active = g0 < n;
         const int64_t g = active ? g0 : n - 1;
@@ -159,17 +155,21 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
         finite = finite && isfinite(logit);
         const float opacity = 1.0f / (1.0f + fast_exp(-logit));
 
+        bool staged = false;   // this lane's colour rows are in s_col
         for (int ci = 0; ci < n_cams; ++ci) {
             const sgs_camera& cam = cams[ci];
             const CamTable ct = ws.cams[ci];
             const int64_t item = (int64_t)ci * n + g;
             const Geo geo = project(X, ls, q, cam, ct, o);
             bool vis = active && finite && geo.visible;
-            if (ci == 0) {
-                // this wave's LDS loads, then every wave's, have landed
-                __builtin_amdgcn_s_waitcnt(0);
-                __syncthreads();
+            const bool fetch = vis && !staged;
+            if (fetch) {
+                gather_colour<3 * NC>(p, g, &s_col[0][0]);
+                staged = true;
             }
+            // this wave's direct loads have landed (each lane reads only its
+            // own column)
+            if (__ballot(fetch)) __builtin_amdgcn_s_waitcnt(0);
             float rgb[3] = {0.0f, 0.0f, 0.0f};
             if (vis) {
                 float d[3], dist;

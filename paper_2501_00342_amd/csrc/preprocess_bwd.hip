@@ -21,26 +21,39 @@ __device__ __forceinline__ bool item_visible(const Workspace& ws, int64_t item) 
     return (int)((tr >> 16) & 0xFFFF) >= (int)(tr & 0xFFFF);
 }
 
-// A block takes tiles of kPreTile consecutive Gaussians and stages their
-// colour rows in LDS with direct loads (as the forward preprocess does); the
-// gradients are written from registers, one coalesced row at a time.
+// A block takes tiles of kPreTile consecutive Gaussians, one per thread; a
+// lane whose Gaussian is visible in some camera fetches its colour rows into
+// its own LDS column by direct loads (as the forward preprocess does).  The
+// gradients then go through LDS as one record per Gaussian, so that the
+// block writes each gradient array's Gaussian-major tile region (contiguous)
+// with consecutive threads on consecutive floats; a Gaussian no camera sees
+// gets zeros.
+// waves per SIMD asked of the compiler: 4 up to 40 colour rows (no spills
+// there); larger forms keep their natural register count
+template <int DEG, int KMAX>
+struct ColourBwdWaves {
+    static constexpr int value = 3 * (DEG + 1) * (DEG + 1) + 7 * KMAX <= 40 ? 4 : (3 * (DEG + 1) * (DEG + 1) + 7 * KMAX <= 48 ? 3 : 1);
+};
+
 template <int DEG, int KMAX>
 __global__ void __launch_bounds__(kPreTile)
+__attribute__((amdgpu_waves_per_eu(ColourBwdWaves<DEG, KMAX>::value)))
 k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspace ws,
              sgs_grads gr, float* __restrict__ gx_colour) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     constexpr int MAXROWS = 3 * NC + 7 * KMAX;
-    __shared__ float s_col[(MAXROWS + 1) & ~1][kPreTile];
+    // gradient records: an odd stride keeps a wave's record writes on
+    // distinct banks
+    constexpr int SG = (MAXROWS % 2 == 0) ? MAXROWS + 1 : MAXROWS;
+    __shared__ float s_buf[kPreTile * SG];
+    float(*s_col)[kPreTile] = reinterpret_cast<float(*)[kPreTile]>(s_buf);   // [rows][kPreTile]
     const int64_t n = p.n;
     const int64_t M = ws.n_items;
     const int K = p.n_lobes;
-    const int rows = 3 * NC + 7 * K;
     const int tid = threadIdx.x;
-    const bool vec4 = (n & 3) == 0;
     for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
          base += (int64_t)gridDim.x * kPreTile) {
-        __syncthreads();   // the previous tile's colour rows are no longer read
-        stage_colour_rows(p, 3 * NC, rows, base, vec4, &s_col[0][0]);
+        __syncthreads();   // the previous tile's records are written out
         const int64_t g = base + tid;
         const bool active = g < n;
         float gsh[NC][3];
@@ -56,11 +69,17 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
         float gX[3] = {0.0f, 0.0f, 0.0f};
         const int64_t gc = active ? g : n - 1;
         const double X[3] = {p.means[gc], p.means[n + gc], p.means[2 * n + gc]};
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        bool staged = false;
         for (int ci = 0; ci < n_cams; ++ci) {
             const int64_t item = (int64_t)ci * n + gc;
-            if (!active || !item_visible(ws, item)) continue;
+            const bool vis = active && item_visible(ws, item);
+            const bool fetch = vis && !staged;
+            if (fetch) {
+                gather_colour<3 * NC>(p, gc, &s_col[0][0]);
+                staged = true;
+            }
+            if (__ballot(fetch)) __builtin_amdgcn_s_waitcnt(0);
+            if (!vis) continue;
             const float grgb[3] = {ws.grad2d[6 * M + item], ws.grad2d[7 * M + item],
                                    ws.grad2d[8 * M + item]};
             float d[3], dist;
@@ -78,22 +97,48 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
 #pragma unroll
             for (int c = 0; c < 3; ++c) gX[c] += (gd[c] - d[c] * dd) * inv;
         }
-        if (!active) continue;
+        if (active)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gx_colour[c * n + g] = gX[c];
+        __syncthreads();   // every lane is done with its colour column
+        // record layout with KMAX lobe slots (compile-time offsets): SH rows,
+        // then axes at 3 NC + 3 k + c, log-sharpness at 3 NC + 3 KMAX + k,
+        // amplitudes at 3 NC + 4 KMAX + 3 k + c; slots k >= K hold zeros
+        float* rec = s_buf + tid * SG;
 #pragma unroll
         for (int l = 0; l < NC; ++l)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) gr.sh[((int64_t)l * 3 + c) * n + g] = gsh[l][c];
+            for (int c = 0; c < 3; ++c) rec[3 * l + c] = gsh[l][c];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            if (k >= K) break;
-            for (int c = 0; c < 3; ++c) {
-                gr.sg_axes[((int64_t)k * 3 + c) * n + g] = gax[k][c];
-                gr.sg_amplitudes[((int64_t)k * 3 + c) * n + g] = gamp[k][c];
-            }
-            gr.sg_log_sharpness[(int64_t)k * n + g] = glsh[k];
-        }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gx_colour[c * n + g] = gX[c];
+            for (int c = 0; c < 3; ++c) {
+                rec[3 * NC + 3 * k + c] = gax[k][c];
+                rec[3 * NC + 4 * KMAX + 3 * k + c] = gamp[k][c];
+            }
+            rec[3 * NC + 3 * KMAX + k] = glsh[k];
+        }
+        __syncthreads();
+        // array with S floats per Gaussian at record offset R: the tile's
+        // region is `count * S` consecutive floats from Gaussian `base`
+        const int count = n - base < kPreTile ? (int)(n - base) : kPreTile;
+        auto write_out = [&](float* dst, int S, int R) {
+            if (S <= 0) return;
+            dst += base * S;
+            const float inv_s = 1.0f / (float)S;
+            for (int e = tid; e < count * S; e += kPreTile) {
+                // e / S through the reciprocal: (e + 0.5) / S is at least
+                // 0.5 / S from an integer, far above the rounding error
+                const int j = (int)(((float)e + 0.5f) * inv_s);
+                dst[e] = s_buf[j * SG + R + (e - j * S)];
+            }
+        };
+        write_out(gr.sh, 3 * NC, 0);
+        if (K > 0) {
+            write_out(gr.sg_axes, 3 * K, 3 * NC);
+            write_out(gr.sg_log_sharpness, K, 3 * NC + 3 * KMAX);
+            write_out(gr.sg_amplitudes, 3 * K, 3 * NC + 4 * KMAX);
+        }
     }
 }
 

@@ -20,9 +20,29 @@ REC_FIELDS = ("u_hi", "v_hi", "u_lo", "v_lo", "w1x", "w1y", "w2x", "w2y", "opaci
               "r", "g", "b", "z", "rect_x", "rect_y", "radius")
 
 
+# The C-ABI keeps the geometry component-major ((C, N) rows, read for every
+# Gaussian) and the colour Gaussian-major ((N, ...), read only for Gaussians
+# that survive culling); a Scene holds every array component-major.
+COLOUR_FIELDS = ("sh", "sg_axes", "sg_log_sharpness", "sg_amplitudes")
+
+
+def to_device_layout(name: str, a: np.ndarray) -> np.ndarray:
+    """One Scene array in the C-ABI layout: colour (..., N) -> (N, ...)."""
+    if name in COLOUR_FIELDS:
+        return np.ascontiguousarray(np.moveaxis(a, -1, 0))
+    return np.ascontiguousarray(a)
+
+
+def to_scene_layout(arrays: dict) -> dict:
+    """Arrays in the C-ABI layout (parameters or gradients, numpy) in the
+    Scene's component-major layout: colour (N, ...) -> (..., N)."""
+    return {k: (np.ascontiguousarray(np.moveaxis(v, 0, -1)) if k in COLOUR_FIELDS else v)
+            for k, v in arrays.items()}
+
+
 def params_to_device(scene: Scene, device="cuda") -> dict:
-    """Scene arrays -> contiguous float32 device tensors (same SoA layout)."""
-    return {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).to(device)
+    """Scene arrays -> contiguous float32 device tensors in the C-ABI layout."""
+    return {k: torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
             for k in FIELDS}
 
 
@@ -104,7 +124,8 @@ class Rasterizer:
         for k in FIELDS:
             t = params[k]
             assert t.device == self.device and t.dtype == torch.float32 and t.is_contiguous(), k
-            assert t.shape[-1] == self.n or t.numel() == 0, k
+            axis = 0 if k in COLOUR_FIELDS else -1
+            assert t.shape[axis] == self.n or t.numel() == 0, k
 
     # -- passes --------------------------------------------------------------
     def forward(self, params: dict, out: Outputs | None = None, check: bool | None = None) -> Outputs:

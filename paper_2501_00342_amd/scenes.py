@@ -1,8 +1,9 @@
 """Seeded synthetic scenes and cameras (input generators only).
 
 This module builds the inputs that both the HIP path and the FP64 CPU oracle
-consume: Gaussian parameters in the component-major (SoA) float32 layout of
-the C-ABI, pinhole cameras and target images.  It holds none of the
+consume: Gaussian parameters as component-major float32 arrays (the
+rasteriser's front end moves the colour arrays Gaussian-major for the
+C-ABI), pinhole cameras and target images.  It holds none of the
 rasteriser's arithmetic: no projection, no colour model, no blending.
 
 The paper trains on photographic datasets (Mip-NeRF360, Tanks&Temples,

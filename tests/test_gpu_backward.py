@@ -57,14 +57,14 @@ def test_backward_matches_oracle(n, w, h, seed):
     g2r = {k: g2_ref[k] for k in OB.GRAD2D}
     g2g = {k: g2_gpu[i] for i, k in enumerate(OB.GRAD2D)}
     _assert_grads(g2g, g2r, ex, "2D")
-    _assert_grads({k: grads[k].cpu().numpy() for k in FIELDS}, grads_ref, ex, "raw")
+    _assert_grads(raster.to_scene_layout({k: grads[k].cpu().numpy() for k in FIELDS}), grads_ref, ex, "raw")
 
 
 def test_backward_sh3_form():
     sc = scenes.sh3_scene(3000, 23, n_clusters=20)
     cam = scenes.config1_camera(96, 64)
     rast, grads, g2_gpu, g2_ref, grads_ref, ex = _backward_case(sc, cam, scenes.Options(), 23)
-    _assert_grads({k: grads[k].cpu().numpy() for k in FIELDS}, grads_ref, ex, "raw")
+    _assert_grads(raster.to_scene_layout({k: grads[k].cpu().numpy() for k in FIELDS}), grads_ref, ex, "raw")
 
 
 @pytest.mark.parametrize("tw,th,batch,ppt_bwd", [(32, 8, 512, 4), (16, 16, 256, 1),
@@ -73,7 +73,7 @@ def test_backward_other_tile_shape_and_batch(tw, th, batch, ppt_bwd):
     sc, cam = scenes.small_clustered(4000, 24, 120, 80)
     opts = scenes.Options(tile_w=tw, tile_h=th, batch=batch, ppt_bwd=ppt_bwd)
     rast, grads, g2_gpu, g2_ref, grads_ref, ex = _backward_case(sc, cam, opts, 24)
-    _assert_grads({k: grads[k].cpu().numpy() for k in FIELDS}, grads_ref, ex, "raw")
+    _assert_grads(raster.to_scene_layout({k: grads[k].cpu().numpy() for k in FIELDS}), grads_ref, ex, "raw")
 
 
 def test_l1_kernel_matches_definition():

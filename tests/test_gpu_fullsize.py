@@ -93,7 +93,7 @@ def test_full_frame_1m_gradients_on_sampled_tiles():
     out = rast.forward(params, check=True)
     grads = rast.backward(params, out, torch.from_numpy(gimg.reshape(-1)).cuda())
     g2_gpu = rast.grad2d().cpu().numpy().astype(np.float64)
-    grads = {k: v.cpu().numpy() for k, v in grads.items()}
+    grads = raster.to_scene_layout({k: v.cpu().numpy() for k, v in grads.items()})
     del rast, out
     torch.cuda.empty_cache()
 
