@@ -27,11 +27,9 @@
 // T_{j+1} / (1 - alpha_j).  Per-Gaussian 2D gradients are summed over a
 // thread's pixels, then across the wave (lane swaps and DPP), and added with
 // one float atomic per value per wave.
-#include <map>
-#include <mutex>
-#include <tuple>
 
 #include "common.hpp"
+#include "occupancy.hpp"
 
 namespace sgs {
 
@@ -457,27 +455,6 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
 }
 
 // ---------------------------------------------------------------------------
-
-// workgroups of `kernel` resident on the whole chip at once (cached per
-// device, kernel and LDS size): the grid of the queue schedule
-template <typename K>
-static int64_t resident_blocks(K kernel, int threads, size_t lds) {
-    static std::mutex mu;
-    static std::map<std::tuple<int, const void*, size_t>, int64_t> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    const auto key = std::make_tuple(dev, reinterpret_cast<const void*>(kernel), lds);
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    const int64_t r = (int64_t)(per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
-    cache[key] = r;
-    return r;
-}
 
 static unsigned grid_of(int64_t resident, int64_t n_tiles) {
     const int64_t g = resident < 1 || resident > n_tiles ? n_tiles : resident;

@@ -51,43 +51,73 @@ __device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int 
     return ok;
 }
 
-// Colour row r of a Gaussian, in the order the LDS staging uses: SH
-// coefficient (l, c) is row 3 l + c, then per lobe k the axis (3 rows
-// 3 NC + 3 k + j), then the log-sharpness rows (3 NC + 3 K + k), then the
-// amplitudes (3 NC + 4 K + 3 k + c).  The global arrays are Gaussian-major:
-// sh[g][NC][3], sg_axes[g][K][3], sg_log_sharpness[g][K], sg_amplitudes[g][K][3].
-//
-// Direct 4-byte global->LDS loads of every colour row of this lane's
-// Gaussian g into column `col` of s_col[rows][kPreTile] (col = the thread's
-// index in the block; the LDS destination of a direct load is the
-// wave-uniform base plus 4 bytes per lane).  Called by the lanes that need
-// their colour only: the loads follow the execution mask, so culled
-// Gaussians fetch nothing.  The caller waits (s_waitcnt) before reading.
+// Colour record of a Gaussian: its colour coefficients in the row order
+// SH coefficient (l, c) at 3 l + c, then per lobe k the axis at
+// 3 NC + 3 k + j, the log-sharpness at 3 NC + 3 K + k and the amplitudes at
+// 3 NC + 4 K + 3 k + c: 3 NC + 7 K floats.  The global arrays are
+// Gaussian-major (sh[g][NC][3], sg_axes[g][K][3], sg_log_sharpness[g][K],
+// sg_amplitudes[g][K][3]), so a record is the concatenation of one
+// contiguous block from each array.
+__device__ __forceinline__ int colour_record_floats(int nc3, int K) { return nc3 + 7 * K; }
+
+// Cooperative gather of colour records into LDS for the lanes of this wave
+// that set `fetch`: the j-th of them (in lane order) gets record slot
+// slot0 + j of `rec` (records of colour_record_floats() floats, back to back)
+// and learns its slot in *slot.  Consecutive lanes of each direct
+// global->LDS load fetch consecutive 16-byte pieces (4-byte pieces when a
+// block is not a whole number of 16-byte pieces) of the same Gaussian's
+// blocks, so one instruction covers several Gaussians' contiguous blocks
+// rather than one float of each of 64 Gaussians.  s_g: 64 entries of the
+// wave's LDS.  Returns how many lanes fetched (wave-uniform); the caller
+// waits (s_waitcnt) before reading the records.
 template <int NC3>
-__device__ __forceinline__ void gather_colour(const Params& p, int64_t g, float* s_col) {
-    const int K = p.n_lobes;
-    const int wave_col = threadIdx.x & ~63;
-    auto dma = [&](const float* src, int row) {
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                         (__attribute__((address_space(3))) void*)(s_col + row * kPreTile + wave_col),
-                                         4, 0, 0);
-    };
-    // rolled loops: one address pair walks the rows (an unrolled gather
-    // would hold every row's 64-bit address in registers at once)
-    const float* sh = p.sh + g * NC3;
-#pragma unroll 1
-    for (int r = 0; r < NC3; ++r) dma(sh + r, r);
-    if (K > 0) {
-        const float* ax = p.sg_axes + g * (3 * K);
-        const float* ls = p.sg_log_sharpness + g * K;
-        const float* am = p.sg_amplitudes + g * (3 * K);
-#pragma unroll 1
-        for (int r = 0; r < 3 * K; ++r) dma(ax + r, NC3 + r);
-#pragma unroll 1
-        for (int r = 0; r < K; ++r) dma(ls + r, NC3 + 3 * K + r);
-#pragma unroll 1
-        for (int r = 0; r < 3 * K; ++r) dma(am + r, NC3 + 4 * K + r);
+__device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fetch, int slot0,
+                                             float* rec, int64_t* s_g, int* slot) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t b = __ballot(fetch);
+    const int m = __popcll(b);
+    if (m == 0) return 0;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int rank = __popcll(b & lt);
+    if (fetch) {
+        s_g[rank] = g;   // read back below by other lanes of this wave (LDS order)
+        *slot = slot0 + rank;
     }
+    const int K = p.n_lobes;
+    const bool v4 = (NC3 % 4 == 0) && (K % 4 == 0) &&
+                    (((uintptr_t)p.sh | (uintptr_t)p.sg_axes | (uintptr_t)p.sg_log_sharpness |
+                      (uintptr_t)p.sg_amplitudes) & 15u) == 0;
+    const int wdt = v4 ? 4 : 1;   // floats per piece
+    const int q_sh = NC3 / wdt, q_ax = 3 * K / wdt, q_ls = K / wdt;
+    const int Q = q_sh + 2 * q_ax + q_ls;   // pieces per record
+    const float invQ = 1.0f / (float)Q;
+    const int total = m * Q;
+    float* base = rec + slot0 * colour_record_floats(NC3, K);
+    for (int P0 = 0; P0 < total; P0 += 64) {
+        const int P = P0 + lane;
+        const bool on = P < total;
+        // P / Q through the reciprocal: (P + 0.5) / Q is at least 0.5 / Q
+        // from an integer, far above its rounding error (P < 64 Q)
+        const int j = on ? (int)(((float)P + 0.5f) * invQ) : 0;
+        const int q = P - j * Q;
+        const int64_t gj = s_g[j];
+        const float* src;
+        if (q < q_sh) src = p.sh + gj * NC3 + q * wdt;
+        else if (q < q_sh + q_ax) src = p.sg_axes + gj * (3 * K) + (q - q_sh) * wdt;
+        else if (q < q_sh + q_ax + q_ls) src = p.sg_log_sharpness + gj * K + (q - q_sh - q_ax) * wdt;
+        else src = p.sg_amplitudes + gj * (3 * K) + (q - q_sh - q_ax - q_ls) * wdt;
+        if (on) {
+            if (v4)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                                 (__attribute__((address_space(3))) void*)(base + P0 * 4),
+                                                 16, 0, 0);
+            else
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                                 (__attribute__((address_space(3))) void*)(base + P0),
+                                                 4, 0, 0);
+        }
+    }
+    return m;
 }
 
 // Unit view direction from the camera centre (-R^T t) to the mean X: the

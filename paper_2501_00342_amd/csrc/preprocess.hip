@@ -121,20 +121,41 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
 }
 
 // A block takes tiles of kPreTile consecutive Gaussians, one per thread.
-// The float64 geometry comes first; a lane whose Gaussian is visible in a
-// camera then issues direct global->LDS loads of its colour rows into its
-// own column of s_col (once per tile, at the first camera that sees it), so
-// culled Gaussians never fetch colour and no lane reads another lane's
-// column: the waves need no barrier.  The colour is evaluated from LDS, so
-// the geometry's and the colour's registers are never live together.
+// The float64 geometry comes first; the lanes of a wave whose Gaussians are
+// visible in a camera then gather their colour records into the wave's LDS
+// buffer together (once per tile, at the first camera that sees each), so
+// culled Gaussians never fetch colour and the waves need no barrier.  The
+// next tile's geometry is loaded into registers while this tile computes,
+// so only the colour gather's latency is exposed per tile.  The colour is
+// evaluated from LDS, so the geometry's and the colour's registers are never
+// live together.
 template <int DEG, int KMAX>
 __global__ void __launch_bounds__(kPreTile)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     constexpr int MAXROWS = 3 * NC + 7 * KMAX;
-    __shared__ float s_col[MAXROWS > 0 ? MAXROWS : 1][kPreTile];
+    constexpr int WAVES = kPreTile / 64;
+    __shared__ __align__(16) float s_rec[WAVES][64 * (MAXROWS > 0 ? MAXROWS : 1)];
+    __shared__ int64_t s_g[WAVES][64];
     const int64_t n = p.n;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int RS = colour_record_floats(3 * NC, p.n_lobes);
+    float* rec = s_rec[wave];
+    // geometry of this thread's Gaussian in the next tile: 3 + 3 + 4 + 1 floats
+    float nxt[11];
+    auto load_geometry = [&](int64_t base) {
+        const int64_t g0 = base + tid;
+        const int64_t g = g0 < n ? g0 : n - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            nxt[c] = p.means[c * n + g];
+            nxt[3 + c] = p.log_scales[c * n + g];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) nxt[6 + c] = p.quats[c * n + g];
+        nxt[10] = p.opacity_logits[g];
+    };
+    if ((int64_t)blockIdx.x * kPreTile < n) load_geometry((int64_t)blockIdx.x * kPreTile);
     for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
          base += (int64_t)gridDim.x * kPreTile) {
         const int64_t g0 = base + tid;
@@ -143,43 +164,44 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
         double X[3], ls[3], q[4];
         bool finite = true;
         for (int c = 0; c < 3; ++c) {
-            X[c] = p.means[c * n + g];
-            ls[c] = p.log_scales[c * n + g];
+            X[c] = nxt[c];
+            ls[c] = nxt[3 + c];
             finite = finite && finite_d(X[c]) && finite_d(ls[c]);
         }
         for (int c = 0; c < 4; ++c) {
-            q[c] = p.quats[c * n + g];
+            q[c] = nxt[6 + c];
             finite = finite && finite_d(q[c]);
         }
-        const float logit = p.opacity_logits[g];
+        const float logit = nxt[10];
         finite = finite && isfinite(logit);
         const float opacity = 1.0f / (1.0f + fast_exp(-logit));
+        const int64_t next = base + (int64_t)gridDim.x * kPreTile;
+        if (next < n) load_geometry(next);
 
-        bool staged = false;   // this lane's colour rows are in s_col
+        int slot = -1;    // this lane's colour record in the wave's buffer
+        int used = 0;     // records gathered by the wave in this tile (uniform)
         for (int ci = 0; ci < n_cams; ++ci) {
             const sgs_camera& cam = cams[ci];
             const CamTable ct = ws.cams[ci];
             const int64_t item = (int64_t)ci * n + g;
             const Geo geo = project(X, ls, q, cam, ct, o);
             bool vis = active && finite && geo.visible;
-            const bool fetch = vis && !staged;
-            if (fetch) {
-                gather_colour<3 * NC>(p, g, &s_col[0][0]);
-                staged = true;
-            }
-            // this wave's direct loads have landed (each lane reads only its
-            // own column)
-            if (__ballot(fetch)) __builtin_amdgcn_s_waitcnt(0);
+            const int got = gather_colour<3 * NC>(p, g, vis && slot < 0, used, rec, s_g[wave], &slot);
+            used += got;
+            // this wave's direct loads have landed (it reads only its own buffer)
+            if (got) __builtin_amdgcn_s_waitcnt(0);
             float rgb[3] = {0.0f, 0.0f, 0.0f};
             if (vis) {
                 float d[3], dist;
                 view_dir(X, cam, d, &dist);
+                const float* r = rec + slot * RS;
+                const int K = p.n_lobes;
                 vis = colour_eval<DEG, KMAX>(
-                    [&](int l, int c) { return s_col[3 * l + c][tid]; },
-                    [&](int k, int j) { return s_col[3 * NC + 3 * k + j][tid]; },
-                    [&](int k) { return s_col[3 * NC + 3 * p.n_lobes + k][tid]; },
-                    [&](int k, int c) { return s_col[3 * NC + 4 * p.n_lobes + 3 * k + c][tid]; },
-                    p.n_lobes, d[0], d[1], d[2], rgb);
+                    [&](int l, int c) { return r[3 * l + c]; },
+                    [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
+                    [&](int k) { return r[3 * NC + 3 * K + k]; },
+                    [&](int k, int c) { return r[3 * NC + 4 * K + 3 * k + c]; }, K, d[0], d[1],
+                    d[2], rgb);
             }
             if (!active) continue;
             uint32_t key = 0xFFFFFFFFu;

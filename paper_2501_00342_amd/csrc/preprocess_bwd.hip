@@ -21,9 +21,10 @@ __device__ __forceinline__ bool item_visible(const Workspace& ws, int64_t item) 
     return (int)((tr >> 16) & 0xFFFF) >= (int)(tr & 0xFFFF);
 }
 
-// A block takes tiles of kPreTile consecutive Gaussians, one per thread; a
-// lane whose Gaussian is visible in some camera fetches its colour rows into
-// its own LDS column by direct loads (as the forward preprocess does).  The
+// A block takes tiles of kPreTile consecutive Gaussians, one per thread; the
+// lanes of a wave whose Gaussians are visible in some camera gather their
+// colour records into the wave's LDS buffer (as the forward preprocess
+// does).  The
 // gradients then go through LDS as one record per Gaussian, so that the
 // block writes each gradient array's Gaussian-major tile region (contiguous)
 // with consecutive threads on consecutive floats; a Gaussian no camera sees
@@ -45,12 +46,17 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
     // gradient records: an odd stride keeps a wave's record writes on
     // distinct banks
     constexpr int SG = (MAXROWS % 2 == 0) ? MAXROWS + 1 : MAXROWS;
-    __shared__ float s_buf[kPreTile * SG];
-    float(*s_col)[kPreTile] = reinterpret_cast<float(*)[kPreTile]>(s_buf);   // [rows][kPreTile]
+    constexpr int WAVES = kPreTile / 64;
+    // first the waves' colour record buffers (64 records each), then the
+    // gradient records of the tile
+    __shared__ __align__(16) float s_buf[kPreTile * SG];
+    __shared__ int64_t s_g[WAVES][64];
     const int64_t n = p.n;
     const int64_t M = ws.n_items;
     const int K = p.n_lobes;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int RS = colour_record_floats(3 * NC, K);
+    float* crec = s_buf + wave * 64 * MAXROWS;
     for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
          base += (int64_t)gridDim.x * kPreTile) {
         __syncthreads();   // the previous tile's records are written out
@@ -69,28 +75,26 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
         float gX[3] = {0.0f, 0.0f, 0.0f};
         const int64_t gc = active ? g : n - 1;
         const double X[3] = {p.means[gc], p.means[n + gc], p.means[2 * n + gc]};
-        bool staged = false;
+        int slot = -1, used = 0;
         for (int ci = 0; ci < n_cams; ++ci) {
             const int64_t item = (int64_t)ci * n + gc;
             const bool vis = active && item_visible(ws, item);
-            const bool fetch = vis && !staged;
-            if (fetch) {
-                gather_colour<3 * NC>(p, gc, &s_col[0][0]);
-                staged = true;
-            }
-            if (__ballot(fetch)) __builtin_amdgcn_s_waitcnt(0);
+            const int got = gather_colour<3 * NC>(p, gc, vis && slot < 0, used, crec, s_g[wave], &slot);
+            used += got;
+            if (got) __builtin_amdgcn_s_waitcnt(0);
             if (!vis) continue;
+            const float* r = crec + slot * RS;
             const float grgb[3] = {ws.grad2d[6 * M + item], ws.grad2d[7 * M + item],
                                    ws.grad2d[8 * M + item]};
             float d[3], dist;
             view_dir(X, cams[ci], d, &dist);
             float gd[3];
             colour_bwd_eval<DEG, KMAX>(
-                [&](int l, int c) { return s_col[3 * l + c][tid]; },
-                [&](int k, int j) { return s_col[3 * NC + 3 * k + j][tid]; },
-                [&](int k) { return s_col[3 * NC + 3 * K + k][tid]; },
-                [&](int k, int c) { return s_col[3 * NC + 4 * K + 3 * k + c][tid]; }, K, d[0],
-                d[1], d[2], grgb, gsh, gamp, gax, glsh, gd);
+                [&](int l, int c) { return r[3 * l + c]; },
+                [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
+                [&](int k) { return r[3 * NC + 3 * K + k]; },
+                [&](int k, int c) { return r[3 * NC + 4 * K + 3 * k + c]; }, K, d[0], d[1], d[2],
+                grgb, gsh, gamp, gax, glsh, gd);
             // through d = (X - c) / |X - c|: (I - d d^T) / |X - c|
             const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
             const float inv = 1.0f / dist;
@@ -100,7 +104,7 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
         if (active)
 #pragma unroll
             for (int c = 0; c < 3; ++c) gx_colour[c * n + g] = gX[c];
-        __syncthreads();   // every lane is done with its colour column
+        __syncthreads();   // every wave is done with its colour records
         // record layout with KMAX lobe slots (compile-time offsets): SH rows,
         // then axes at 3 NC + 3 k + c, log-sharpness at 3 NC + 3 KMAX + k,
         // amplitudes at 3 NC + 4 KMAX + 3 k + c; slots k >= K hold zeros
