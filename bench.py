@@ -223,7 +223,7 @@ def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, ta
         rast_b = raster.Rasterizer(cams, opts_b, scene.n, scene.sh_degree, scene.n_lobes)
         out_b = rast_b.forward(params, check=True)
     grad_img = torch.empty_like(out_b.image)
-    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    grads = raster.new_grads(params)
 
     def fwd():
         rast.forward(params, out=out, check=False)

@@ -60,9 +60,14 @@ typedef enum sgs_status {
 /* Gaussian parameters (device, float32).  n may be 0.
  * The geometry, which every Gaussian needs for culling, is component-major
  * (one contiguous row per component: coalesced over all n).  The colour,
- * which only Gaussians that survive culling need, is Gaussian-major (each
- * Gaussian's coefficients contiguous), so a culled Gaussian's colour is
- * never read. */
+ * which only Gaussians that survive culling need, is Gaussian-major: each
+ * colour array holds one block per Gaussian, so a culled Gaussian's colour
+ * is never read.  Block g of an array starts at g * colour_stride floats
+ * (colour_stride 0: the array's own block size, i.e. packed).  With
+ * colour_stride = 3 (deg+1)^2 + 7 K and the four arrays at offsets 0,
+ * 3 (deg+1)^2, 3 (deg+1)^2 + 3 K and 3 (deg+1)^2 + 4 K of one buffer, a
+ * Gaussian's whole colour is one contiguous record, which the rasteriser
+ * fetches with the fewest cache lines. */
 typedef struct sgs_gaussians {
     int64_t n;
     int32_t sh_degree;               /* 0..3 */
@@ -75,10 +80,15 @@ typedef struct sgs_gaussians {
     const float* sg_axes;            /* [n][K][3] lobe axis mu, any length (eq. 5) */
     const float* sg_log_sharpness;   /* [n][K]   log of lobe sharpness lambda      */
     const float* sg_amplitudes;      /* [n][K][3] lobe RGB amplitude alpha          */
+    int64_t colour_stride;           /* floats between consecutive blocks of each colour
+                                        array; 0 = packed; else >= every block size and a
+                                        multiple of 4 gives 16-byte fetches */
 } sgs_gaussians;
 
-/* Gradient outputs, same shapes as sgs_gaussians (device, float32).  Every
- * array is overwritten (not accumulated).  Arrays of zero size may be NULL. */
+/* Gradient outputs, same shapes as sgs_gaussians (device, float32), every
+ * array packed (the colour arrays Gaussian-major with colour_stride 0).
+ * Every array is overwritten (not accumulated).  Arrays of zero size may be
+ * NULL. */
 typedef struct sgs_grads {
     float* means;
     float* log_scales;

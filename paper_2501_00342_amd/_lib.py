@@ -24,7 +24,8 @@ class Gaussians(Structure):
     _fields_ = [("n", c_int64), ("sh_degree", c_int32), ("n_lobes", c_int32),
                 ("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
                 ("opacity_logits", c_void_p), ("sh", c_void_p), ("sg_axes", c_void_p),
-                ("sg_log_sharpness", c_void_p), ("sg_amplitudes", c_void_p)]
+                ("sg_log_sharpness", c_void_p), ("sg_amplitudes", c_void_p),
+                ("colour_stride", c_int64)]
 
 
 class Grads(Structure):
@@ -166,12 +167,13 @@ def options_struct(opts) -> Options:
     return o
 
 
-def gaussians_struct(n, sh_degree, n_lobes, ptrs: dict) -> Gaussians:
+def gaussians_struct(n, sh_degree, n_lobes, ptrs: dict, colour_stride: int = 0) -> Gaussians:
     g = Gaussians()
     g.n, g.sh_degree, g.n_lobes = int(n), int(sh_degree), int(n_lobes)
     for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "sg_axes",
               "sg_log_sharpness", "sg_amplitudes"):
         setattr(g, k, ptrs.get(k) or None)
+    g.colour_stride = int(colour_stride)
     return g
 
 

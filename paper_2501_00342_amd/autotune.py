@@ -126,7 +126,7 @@ def tune(params: dict, cams, base: Options, n: int, sh_degree: int, n_lobes: int
             del rast
             continue
         gimg = torch.empty_like(out.image)
-        grads = {k: torch.empty_like(v) for k, v in params.items()}
+        grads = raster.new_grads(params)
 
         def step():
             rast.forward(params, out=out, check=False)

@@ -55,9 +55,9 @@ __device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int 
 // SH coefficient (l, c) at 3 l + c, then per lobe k the axis at
 // 3 NC + 3 k + j, the log-sharpness at 3 NC + 3 K + k and the amplitudes at
 // 3 NC + 4 K + 3 k + c: 3 NC + 7 K floats.  The global arrays are
-// Gaussian-major (sh[g][NC][3], sg_axes[g][K][3], sg_log_sharpness[g][K],
-// sg_amplitudes[g][K][3]), so a record is the concatenation of one
-// contiguous block from each array.
+// Gaussian-major (block g of each at g times its stride p.cs_*), so a
+// record is the concatenation of one contiguous block from each array (one
+// run of memory when the four arrays interleave with a common stride).
 __device__ __forceinline__ int colour_record_floats(int nc3, int K) { return nc3 + 7 * K; }
 
 // Cooperative gather of colour records into LDS for the lanes of this wave
@@ -85,6 +85,7 @@ __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fe
     }
     const int K = p.n_lobes;
     const bool v4 = (NC3 % 4 == 0) && (K % 4 == 0) &&
+                    ((p.cs_sh | p.cs_ax | p.cs_ls | p.cs_am) & 3) == 0 &&
                     (((uintptr_t)p.sh | (uintptr_t)p.sg_axes | (uintptr_t)p.sg_log_sharpness |
                       (uintptr_t)p.sg_amplitudes) & 15u) == 0;
     const int wdt = v4 ? 4 : 1;   // floats per piece
@@ -102,10 +103,10 @@ __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fe
         const int q = P - j * Q;
         const int64_t gj = s_g[j];
         const float* src;
-        if (q < q_sh) src = p.sh + gj * NC3 + q * wdt;
-        else if (q < q_sh + q_ax) src = p.sg_axes + gj * (3 * K) + (q - q_sh) * wdt;
-        else if (q < q_sh + q_ax + q_ls) src = p.sg_log_sharpness + gj * K + (q - q_sh - q_ax) * wdt;
-        else src = p.sg_amplitudes + gj * (3 * K) + (q - q_sh - q_ax - q_ls) * wdt;
+        if (q < q_sh) src = p.sh + gj * p.cs_sh + q * wdt;
+        else if (q < q_sh + q_ax) src = p.sg_axes + gj * p.cs_ax + (q - q_sh) * wdt;
+        else if (q < q_sh + q_ax + q_ls) src = p.sg_log_sharpness + gj * p.cs_ls + (q - q_sh - q_ax) * wdt;
+        else src = p.sg_amplitudes + gj * p.cs_am + (q - q_sh - q_ax - q_ls) * wdt;
         if (on) {
             if (v4)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,

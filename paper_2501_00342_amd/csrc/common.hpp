@@ -86,6 +86,8 @@ struct Params {
     const float* sg_axes;
     const float* sg_log_sharpness;
     const float* sg_amplitudes;
+    // floats from one Gaussian's block to the next in each colour array
+    int64_t cs_sh, cs_ax, cs_ls, cs_am;
 };
 
 struct Workspace {

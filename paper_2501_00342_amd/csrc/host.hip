@@ -235,6 +235,12 @@ sgs::Params params_of(const sgs_gaussians* g) {
     p.sg_axes = g->sg_axes;
     p.sg_log_sharpness = g->sg_log_sharpness;
     p.sg_amplitudes = g->sg_amplitudes;
+    const int64_t nc3 = 3 * (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1), K = g->n_lobes;
+    const int64_t cs = g->colour_stride;
+    p.cs_sh = cs > 0 ? cs : nc3;
+    p.cs_ax = cs > 0 ? cs : 3 * K;
+    p.cs_ls = cs > 0 ? cs : K;
+    p.cs_am = cs > 0 ? cs : 3 * K;
     return p;
 }
 
@@ -244,6 +250,10 @@ int check_params(const sgs_gaussians* g) {
         return fail(SGS_E_INVALID, "a Gaussian parameter array is NULL");
     if (g->n_lobes > 0 && (!g->sg_axes || !g->sg_log_sharpness || !g->sg_amplitudes))
         return fail(SGS_E_INVALID, "an SG lobe array is NULL");
+    const int64_t nc3 = 3 * (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+    if (g->colour_stride < 0 ||
+        (g->colour_stride > 0 && (g->colour_stride < nc3 || g->colour_stride < 3 * (int64_t)g->n_lobes)))
+        return fail(SGS_E_INVALID, "colour_stride is below a colour block size");
     return SGS_OK;
 }
 

@@ -40,10 +40,51 @@ def to_scene_layout(arrays: dict) -> dict:
             for k, v in arrays.items()}
 
 
-def params_to_device(scene: Scene, device="cuda") -> dict:
-    """Scene arrays -> contiguous float32 device tensors in the C-ABI layout."""
-    return {k: torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
-            for k in FIELDS}
+def colour_record_floats(sh_degree: int, n_lobes: int) -> int:
+    return 3 * (sh_degree + 1) ** 2 + 7 * n_lobes
+
+
+def params_to_device(scene: Scene, device="cuda", packed: bool = True) -> dict:
+    """Scene arrays -> float32 device tensors in the C-ABI layout.
+
+    packed: the four colour tensors are views into one (N, 3 (L+1)^2 + 7 K)
+    buffer, each Gaussian's colour one contiguous record (the layout the
+    rasteriser fetches fastest); otherwise each colour tensor is contiguous
+    on its own."""
+    out = {k: torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
+           for k in FIELDS if k not in COLOUR_FIELDS or not packed}
+    if packed:
+        n, nc3, K = scene.n, 3 * (scene.sh_degree + 1) ** 2, scene.n_lobes
+        rec = torch.empty((n, nc3 + 7 * K), dtype=torch.float32, device=device)
+        at = 0
+        for k, width in (("sh", nc3), ("sg_axes", 3 * K), ("sg_log_sharpness", K),
+                         ("sg_amplitudes", 3 * K)):
+            a = torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
+            view = rec[:, at:at + width].view(a.shape)
+            view.copy_(a)
+            out[k] = view
+            at += width
+    return out
+
+
+def colour_stride(params: dict) -> int:
+    """The colour_stride of the C-ABI for these tensors: 0 when every colour
+    tensor is contiguous, else their common first-dimension stride."""
+    cols = [params[k] for k in COLOUR_FIELDS if params[k].numel()]
+    if all(t.is_contiguous() for t in cols):
+        return 0
+    st = {t.stride(0) for t in cols}
+    assert len(st) == 1, "colour tensors with different strides"
+    for t in cols:   # each Gaussian's block is dense
+        assert t[0].is_contiguous(), "colour blocks are not contiguous"
+    return st.pop()
+
+
+def new_grads(params: dict) -> dict:
+    """Gradient tensors for `params`: the shapes of the parameters, every
+    array packed (the layout the backward writes)."""
+    return {k: torch.empty(tuple(v.shape), dtype=torch.float32, device=v.device)
+            for k, v in params.items()}
 
 
 def _ptr(t):
@@ -102,7 +143,8 @@ class Rasterizer:
     def _gstruct(self, params: dict | None):
         ptrs = {k: (params[k].data_ptr() if params[k].numel() else None) for k in FIELDS} \
             if params else {}
-        return L.gaussians_struct(self.n, self.sh_degree, self.n_lobes, ptrs)
+        cs = colour_stride(params) if params else 0
+        return L.gaussians_struct(self.n, self.sh_degree, self.n_lobes, ptrs, cs)
 
     def _alloc(self):
         g = self._gstruct(None)
@@ -123,9 +165,12 @@ class Rasterizer:
     def _check_params(self, params):
         for k in FIELDS:
             t = params[k]
-            assert t.device == self.device and t.dtype == torch.float32 and t.is_contiguous(), k
-            axis = 0 if k in COLOUR_FIELDS else -1
-            assert t.shape[axis] == self.n or t.numel() == 0, k
+            assert t.device == self.device and t.dtype == torch.float32, k
+            if k in COLOUR_FIELDS:
+                assert t.shape[0] == self.n or t.numel() == 0, k
+            else:
+                assert t.is_contiguous() and (t.shape[-1] == self.n or t.numel() == 0), k
+        colour_stride(params)   # the colour tensors share one layout
 
     # -- passes --------------------------------------------------------------
     def forward(self, params: dict, out: Outputs | None = None, check: bool | None = None) -> Outputs:
@@ -154,7 +199,7 @@ class Rasterizer:
             return out
 
     def backward(self, params: dict, out: Outputs, grad_image: torch.Tensor) -> dict:
-        grads = {k: torch.empty_like(params[k]) for k in FIELDS}
+        grads = new_grads(params)
         self.backward_into(params, out, grad_image, grads)
         return grads
 
@@ -165,6 +210,8 @@ class Rasterizer:
         self._check_params(params)
         assert grad_image.dtype == torch.float32 and grad_image.is_contiguous()
         assert grad_image.numel() == 3 * self.n_pixels
+        for k in FIELDS:   # the backward writes every gradient array packed
+            assert grads[k].is_contiguous() and grads[k].shape == params[k].shape, k
         g = self._gstruct(params)
         gr = L.grads_struct({k: (grads[k].data_ptr() if grads[k].numel() else None)
                              for k in FIELDS})

@@ -211,7 +211,7 @@ def test_graph_replay_matches_eager(schedule):
 
     out = rast.new_outputs()
     gimg = torch.empty_like(out.image)
-    grads = {k: torch.empty_like(v) for k, v in params.items()}
+    grads = raster.new_grads(params)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):           # warm-up outside capture
@@ -235,3 +235,30 @@ def test_graph_replay_matches_eager(schedule):
             assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(b.abs().max() + 1e-30)), (rep, k)
         run_forward(other_sc, [other_cam], opts)   # unrelated eager work between replays
         torch.cuda.synchronize()
+
+
+def test_packed_and_separate_colour_layouts_agree():
+    """The colour arrays as one record per Gaussian (shared stride) and as
+    four packed arrays give the same image and keys bit for bit, and the same
+    gradients up to the order of the backward's float atomics."""
+    import torch
+
+    from paper_2501_00342_amd import raster
+    sc, cam = scenes.small_clustered(6000, 17, 160, 120)
+    opts = scenes.Options()
+    res = []
+    for packed in (True, False):
+        params = raster.params_to_device(sc, packed=packed)
+        rast = raster.Rasterizer([cam], opts, sc.n, sc.sh_degree, sc.n_lobes)
+        out = rast.forward(params, check=True)
+        tgt = torch.from_numpy(scenes.target_image(160, 120, 2).reshape(-1)).cuda()
+        _, gimg = rast.l1(out.image, tgt)
+        grads = rast.backward(params, out, gimg)
+        res.append((out.image.clone(), rast.depth_keys().clone(),
+                    {k: v.clone() for k, v in grads.items()}))
+    (i1, k1, g1), (i2, k2, g2) = res
+    assert torch.equal(i1, i2) and torch.equal(k1, k2)
+    for k in g1:
+        scale = float(g1[k].abs().max()) + 1e-30
+        assert float((g1[k] - g2[k]).abs().max()) <= 1e-5 * scale, k
+
