@@ -194,10 +194,12 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     // staged (key, value) words: key in the low half, value in the high half
     __shared__ __align__(16) uint64_t s_kv[kSortTile];
     __shared__ uint32_t s_wave[WAVES][kRadix];
-    // full 8-bit digits: lanes with equal digits are found through a per-wave
-    // table of lane masks (one LDS OR and one read per item) instead of eight
-    // ballots; the table lives in s_kv, which the ranking does not use yet
-    constexpr bool kLdsMatch = NB >= kRadixBits;
+    // digits of 5 bits or more: lanes with equal digits are found through a
+    // per-wave table of lane masks (one LDS OR and one read per item) instead
+    // of NB ballots; the table lives in s_kv, which the ranking does not use
+    // yet.  Shorter digits keep the ballots (few, and many lanes would share
+    // a table entry).
+    constexpr bool kLdsMatch = NB >= 5;
     static_assert(WAVES * kRadix * 8 <= kSortTile * 8, "match tables fit in s_kv");
     unsigned long long* s_match = reinterpret_cast<unsigned long long*>(s_kv);
     __shared__ uint32_t s_local[kRadix];
