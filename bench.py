@@ -64,10 +64,14 @@ def stage_bytes(name, n, nvis, nvis_g, P, tiles, fpg, tile_passes, npix):
         "fwd.preprocess": n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + n * (4 + 8) + nvis * 64,
         "fwd.depth_sort": 56 * n,
         "fwd.pair_scan": n * (4 + 8 + 4),
-        "fwd.duplicate": nvis * (4 + 4 + 8) + 8 * P,
-        # per pass: the downsweep reads and writes (key, value); every pass but
-        # the first (counted by the duplicate) reads the keys once more
-        "fwd.tile_sort": (2 * (kb + 4) * tile_passes + kb * (tile_passes - 1)) * P,
+        # the duplicate only counts: it reads each chunk's items (offset,
+        # item, rectangle)
+        "fwd.duplicate": nvis * (4 + 4 + 8),
+        # the first pass generates the pairs from the items again and writes
+        # (key, value); every later pass reads the keys (upsweep), then reads
+        # and writes (key, value)
+        "fwd.tile_sort": nvis * (4 + 4 + 8) + (kb + 4) * P
+        + (tile_passes - 1) * (kb + 2 * (kb + 4)) * P,
         "fwd.tile_order": None,  # heavy-first order of the queue schedule
         "fwd.blend": None,
         "bwd.blend": None,

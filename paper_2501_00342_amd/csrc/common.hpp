@@ -114,11 +114,12 @@ struct Workspace {
     uint32_t* counts;            // radix pass: [256][partitions] digit counts -> offsets
     uint32_t* totals;            // radix pass: [256] digit totals
     uint32_t* pair_counts;       // pairs of each item, in depth order
+    uint64_t* sorted_rects;      // tile rectangle of each item, in depth order
     uint64_t* scan_sums;         // per scan block
     double* loss_partial;
     int64_t n_items, n_tiles, n_pixels, capacity;
     int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
-    int dup_blocks;              // persistent grid of the duplicate kernel
+    int dup_blocks;              // grid of the duplicate kernel (one block per chunk)
     int tile_passes, tile_bits;
     bool key16;                  // pair tile ids stored as u16 (at most 65536 tiles)
 };
@@ -140,16 +141,22 @@ void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, 
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
-                       uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                       hipStream_t s, int digit_bits = kRadixBits, bool counted = false,
-                       uint32_t* ranges = nullptr, int64_t n_tiles = 0);
+                       uint32_t* pairs_out, uint64_t* rects_out, int64_t n_rects, bool drop_culled,
+                       uint32_t* kept_out, hipStream_t s, int digit_bits = kRadixBits,
+                       bool counted = false, uint32_t* ranges = nullptr, int64_t n_tiles = 0);
 void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                          uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s,
                          int digit_bits = kRadixBits, bool counted = false,
                          uint32_t* ranges = nullptr, int64_t n_tiles = 0);
 void launch_scan_pairs(const Workspace& ws, hipStream_t s);
-void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s);
+void launch_duplicate_counts(const Workspace& ws, int64_t n, hipStream_t s);
+// the first tile pass fused with pair generation: scans the duplicate's
+// counts, ranks and scatters into (keys_out, vals_out); ranges when it is
+// also the last pass
+void launch_dup_scatter(const Workspace& ws, int64_t n, uint32_t* keys_out, uint32_t* vals_out,
+                        int64_t parts, int digit_bits, uint32_t* ranges, int64_t pair_capacity,
+                        hipStream_t s);
 // tile_order = tiles sorted by decreasing list length (one stable 8-bit pass
 // over a log-scale length bucket)
 void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s);

@@ -42,7 +42,7 @@ struct Plan {
     int pre_blocks, dup_blocks;
     int64_t max_parts;
     // offsets not exported in sgs_layout
-    size_t sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
+    size_t sorted_rects, sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
         pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial, gx_colour,
         tile_keys, tile_order;
     int64_t tile_parts;   // partitions of the heavy-first tile sort
@@ -128,7 +128,9 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     int64_t pb = cdiv(n, sgs::kPreThreads);
     pl->pre_blocks = (int)(pb < 1 ? 1 : (pb > sgs::kPersistentBlocks ? sgs::kPersistentBlocks : pb));
     int64_t db = pl->dup_chunks;
-    pl->dup_blocks = (int)(db < 1 ? 1 : (db > sgs::kPersistentBlocks ? sgs::kPersistentBlocks : db));
+    // one block per chunk: a chunk's work is a short chain of dependent loads,
+    // so many blocks in flight hide it better than a persistent loop
+    pl->dup_blocks = (int)(db < 1 ? 1 : (db > (1 << 30) ? (1 << 30) : db));
     pl->tile_parts = cdiv(tiles, sgs::kSortTile);
     pl->max_parts = pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts;
     if (pl->tile_parts > pl->max_parts) pl->max_parts = pl->tile_parts;
@@ -169,6 +171,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->counts = take((size_t)pl->max_parts * sgs::kRadix * 4);
     pl->totals = take((size_t)sgs::kRadix * 4);
     pl->pair_counts = take((size_t)items * 4);
+    pl->sorted_rects = take((size_t)items * 8);
     pl->scan_sums = take((size_t)(pl->scan_parts + 1) * 8);
     L.total_bytes = off;
     L.n_items = items;
@@ -205,6 +208,7 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.counts = reinterpret_cast<uint32_t*>(b + pl.counts);
     w.totals = reinterpret_cast<uint32_t*>(b + pl.totals);
     w.pair_counts = reinterpret_cast<uint32_t*>(b + pl.pair_counts);
+    w.sorted_rects = reinterpret_cast<uint64_t*>(b + pl.sorted_rects);
     w.scan_sums = reinterpret_cast<uint64_t*>(b + pl.scan_sums);
     w.loss_partial = reinterpret_cast<double*>(b + pl.loss_partial);
     w.n_items = L.n_items;
@@ -355,7 +359,8 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
                                    first ? nullptr : ws.header + sgs::kHdrVisible, ws.n_items,
                                    ps * sgs::kRadixBits, ws.counts, ws.totals, pl.depth_parts,
                                    last ? ws.tile_rects : nullptr, last ? ws.pair_counts : nullptr,
-                                   ws.n_items, first, ws.header + sgs::kHdrVisible, s);
+                                   last ? ws.sorted_rects : nullptr, ws.n_items, first,
+                                   ws.header + sgs::kHdrVisible, s);
         }
         SGS_LAUNCHED();
         mk.mark(3);
@@ -381,37 +386,39 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
         }
     }
     if (pl.n > 0 && pair_capacity > 0) {
-        // the duplicate writes where the last tile pass leaves the primary buffers
-        sgs::Workspace wd = ws;
-        if (pl.tile_passes % 2 == 1) {
-            wd.pair_tiles = ws.pair_tiles_alt;
-            wd.pair_values = ws.pair_values_alt;
-        }
-        sgs::launch_duplicate(wd, pl.n, s);
+        // the duplicate counts the first tile digit of every chunk; the first
+        // tile pass generates the pairs again and scatters them directly.
+        // Pass ps writes the buffer that leaves the last pass in the primary
+        // buffers.
+        sgs::launch_duplicate_counts(ws, pl.n, s);
         SGS_LAUNCHED();
         mk.mark(5);
-        uint32_t* tk[2] = {wd.pair_tiles, wd.pair_tiles == ws.pair_tiles ? ws.pair_tiles_alt : ws.pair_tiles};
-        uint32_t* tv[2] = {wd.pair_values, wd.pair_values == ws.pair_values ? ws.pair_values_alt : ws.pair_values};
-        for (int ps = 0; ps < pl.tile_passes; ++ps) {
-            const int a = ps % 2, b = 1 - a;
+        const int L = pl.tile_passes;
+        auto out_t = [&](int ps) { return (L - 1 - ps) % 2 == 0 ? ws.pair_tiles : ws.pair_tiles_alt; };
+        auto out_v = [&](int ps) { return (L - 1 - ps) % 2 == 0 ? ws.pair_values : ws.pair_values_alt; };
+        {
+            const int nb = pl.tile_bits < sgs::kRadixBits ? pl.tile_bits : sgs::kRadixBits;
+            sgs::launch_dup_scatter(ws, pl.n, out_t(0), out_v(0), pl.pair_parts, nb,
+                                    L == 1 ? ws.ranges : nullptr, pair_capacity, s);
+        }
+        for (int ps = 1; ps < L; ++ps) {
             // tile ids are below 2^tile_bits: the last pass has fewer digit bits
             const int left = pl.tile_bits - ps * sgs::kRadixBits;
             const int nb = left < sgs::kRadixBits ? left : sgs::kRadixBits;
-            // the duplicate counted the first pass's digits; the last pass
-            // writes the tile ranges
-            const bool counted = ps == 0;
-            uint32_t* rng = ps == pl.tile_passes - 1 ? ws.ranges : nullptr;
+            // the last pass writes the tile ranges
+            uint32_t* rng = ps == L - 1 ? ws.ranges : nullptr;
+            uint32_t *ti = out_t(ps - 1), *vi = out_v(ps - 1), *to = out_t(ps), *vo = out_v(ps);
             if (ws.key16)
-                sgs::launch_radix_pass16(reinterpret_cast<const uint16_t*>(tk[a]), tv[a],
-                                         reinterpret_cast<uint16_t*>(tk[b]), tv[b],
+                sgs::launch_radix_pass16(reinterpret_cast<const uint16_t*>(ti), vi,
+                                         reinterpret_cast<uint16_t*>(to), vo,
                                          ws.header + sgs::kHdrPairs, pair_capacity,
                                          ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts, s,
-                                         nb, counted, rng, ws.n_tiles);
+                                         nb, false, rng, ws.n_tiles);
             else
-                sgs::launch_radix_pass(tk[a], tv[a], tk[b], tv[b], ws.header + sgs::kHdrPairs,
-                                       pair_capacity, ps * sgs::kRadixBits, ws.counts, ws.totals,
-                                       pl.pair_parts, nullptr, nullptr, 0, false, nullptr, s, nb,
-                                       counted, rng, ws.n_tiles);
+                sgs::launch_radix_pass(ti, vi, to, vo, ws.header + sgs::kHdrPairs, pair_capacity,
+                                       ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts,
+                                       nullptr, nullptr, nullptr, 0, false, nullptr, s, nb, false,
+                                       rng, ws.n_tiles);
         }
         SGS_LAUNCHED();
         mk.mark(6);

@@ -15,6 +15,7 @@
 // number of (tile, Gaussian) pairs of each item; the scan below turns
 // those into pair offsets.
 #include "common.hpp"
+#include "pairs.hpp"
 
 namespace sgs {
 
@@ -179,21 +180,24 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, u
 constexpr int kDownThreads = 512;
 constexpr int kDownItems = kSortTile / kDownThreads;
 
-// NB: significant bits of the digit (the key has no bits above shift + NB),
-// so ranking needs NB ballots instead of kRadixBits.
+// The downsweep after its items are in registers (key[k], val[k] of item
+// k * 64 + lane of this wave; lim: the wave's valid items): stable ranking
+// by digit, block digit offsets, staging in LDS in digit order and the
+// scatter to s_global[d] + staged index.  Expects s_global to hold the
+// partition's digit starts, s_wave cleared and s_kv free (a barrier after
+// their last use).
 template <typename KeyT, int NB>
-__global__ void __launch_bounds__(kDownThreads)
-k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-            KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-            const uint32_t* count_ptr, int64_t count_host, int shift,
-            const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int64_t parts,
-            const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out, int64_t n_rects,
-            bool drop, int cstride, uint32_t* __restrict__ ranges, int64_t n_tiles) {
+__device__ __forceinline__ void rank_scatter(uint32_t (&key)[kDownItems], const uint32_t (&val)[kDownItems],
+                                             int lim, bool drop, int shift, uint64_t* s_kv,
+                                             uint32_t (*s_wave)[kRadix], uint32_t* s_local,
+                                             uint32_t* s_global, uint32_t* s_scan1,
+                                             KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                             const uint64_t* __restrict__ rects,
+                                             uint32_t* __restrict__ pairs_out,
+                                             uint64_t* __restrict__ rects_out, int64_t n_rects,
+                                             uint32_t* __restrict__ ranges, int64_t n_tiles,
+                                             int64_t out_limit) {
     constexpr int WAVES = kDownThreads / 64;
-    constexpr int WAVE_ITEMS = 64 * kDownItems;
-    // staged (key, value) words: key in the low half, value in the high half
-    __shared__ __align__(16) uint64_t s_kv[kSortTile];
-    __shared__ uint32_t s_wave[WAVES][kRadix];
     // digits of 5 bits or more: lanes with equal digits are found through a
     // per-wave table of lane masks (one LDS OR and one read per item) instead
     // of NB ballots; the table lives in s_kv, which the ranking does not use
@@ -202,6 +206,126 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     constexpr bool kLdsMatch = NB >= 5;
     static_assert(WAVES * kRadix * 8 <= kSortTile * 8, "match tables fit in s_kv");
     unsigned long long* s_match = reinterpret_cast<unsigned long long*>(s_kv);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t rank2[kDownItems / 2];   // two 16-bit ranks per register
+    if (kLdsMatch) {
+        for (int i = tid; i < WAVES * kRadix; i += kDownThreads) s_match[i] = 0ull;
+        __syncthreads();
+    }
+
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int k = 0; k < kDownItems; ++k) {
+        const int li = k * 64 + lane;
+        const bool valid = li < lim && !(drop && key[k] == 0xFFFFFFFFu);
+        const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+        uint64_t m;
+        if constexpr (kLdsMatch) {
+            // a wave's LDS instructions execute in order: every lane's OR
+            // lands before any lane reads, every read before the clear
+            unsigned long long* slot = s_match + wave * kRadix + d;
+            if (valid) atomicOr(slot, 1ull << lane);
+            m = valid ? *slot : 0ull;
+            if (valid) *slot = 0ull;
+        } else {
+            m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+        }
+        const uint64_t lower = m & lt_mask;
+        const uint32_t prior = valid ? s_wave[wave][d] : 0u;
+        const uint32_t r = prior + (uint32_t)__popcll(lower);
+        rank2[k >> 1] = (k & 1) ? (rank2[k >> 1] | (r << 16)) : r;
+        if (valid && lower == 0) s_wave[wave][d] = prior + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    int n_valid;
+    {
+        // per digit: exclusive offsets of the waves, then the block's digit starts
+        uint32_t total = 0;
+        if (tid < kRadix) {
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = s_wave[w][tid];
+                s_wave[w][tid] = total;
+                total += c;
+            }
+        }
+        uint32_t kept;
+        const uint32_t st = block_excl_scan<WAVES>(total, s_scan1, &kept);
+        if (tid < kRadix) {
+            s_local[tid] = st;
+            s_global[tid] -= st;   // now: output index of staged slot i is s_global[d] + i
+        }
+        n_valid = (int)kept;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kDownItems; ++k) {
+        const int li = k * 64 + lane;
+        if (li < lim && !(drop && key[k] == 0xFFFFFFFFu)) {
+            const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
+            const uint32_t pos = s_local[dd] + s_wave[wave][dd] + ((rank2[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+            s_kv[pos] = (uint64_t)key[k] | ((uint64_t)val[k] << 32);
+        }
+    }
+    __syncthreads();
+    // unrolled over the thread's fixed slots so that the LDS reads and the
+    // stores of different items overlap
+#pragma unroll
+    for (int j = 0; j < kDownItems; ++j) {
+        const int i = tid + j * kDownThreads;
+        if (i >= n_valid) break;
+        const uint64_t kv = s_kv[i];
+        const uint32_t k = (uint32_t)kv, v = (uint32_t)(kv >> 32);
+        const uint32_t dd = (k >> shift) & (kRadix - 1);
+        const uint32_t out = s_global[dd] + (uint32_t)i;
+        // counts that disagree with the items would point past the pass's
+        // output: such an item is not written (the result is then wrong,
+        // never out of bounds)
+        if ((int64_t)out >= out_limit) continue;
+        __builtin_assume(out < (1u << 30));
+        if (keys_out) keys_out[out] = (KeyT)k;
+        vals_out[out] = v;
+        if (pairs_out) {   // last depth pass: pair count and rectangle in depth order
+            const uint64_t r = v < (uint64_t)n_rects ? rects[v] : 1ull;   // 1: no pairs
+            pairs_out[out] = rect_pairs(r);
+            if (rects_out) rects_out[out] = r;
+        }
+        // last tile pass: a key change between neighbours of this block's run
+        // of one digit is a tile boundary (run starts, where the previous
+        // staged key has another digit, are checked by k_range_edges)
+        if (ranges && i > 0) {
+            const uint32_t pk = (uint32_t)s_kv[i - 1];
+            if (pk != k && ((pk >> shift) & (kRadix - 1)) == dd) {
+                if (k < (uint64_t)n_tiles) ranges[2 * (int64_t)k] = out;
+                if (pk < (uint64_t)n_tiles) ranges[2 * (int64_t)pk + 1] = out;
+            }
+        }
+    }
+}
+
+// NB: significant bits of the digit (the key has no bits above shift + NB),
+// so ranking needs NB ballots instead of kRadixBits.
+template <typename KeyT, int NB>
+__global__ void __launch_bounds__(kDownThreads)
+k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+            KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+            const uint32_t* count_ptr, int64_t count_host, int shift,
+            const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int64_t parts,
+            const uint64_t* __restrict__ rects, uint32_t* __restrict__ pairs_out,
+            uint64_t* __restrict__ rects_out, int64_t n_rects,
+            bool drop, int cstride, uint32_t* __restrict__ ranges, int64_t n_tiles) {
+    constexpr int WAVES = kDownThreads / 64;
+    constexpr int WAVE_ITEMS = 64 * kDownItems;
+    // staged (key, value) words: key in the low half, value in the high half
+    __shared__ __align__(16) uint64_t s_kv[kSortTile];
+    __shared__ uint32_t s_wave[WAVES][kRadix];
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_global[kRadix];
     __shared__ uint32_t s_scan[2][WAVES];
@@ -223,7 +347,6 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
     // into the second, no
     // registers held in flight); the ragged last one by per-lane loads.
     uint32_t key[kDownItems], val[kDownItems];
-    uint32_t rank2[kDownItems / 2];   // two 16-bit ranks per register
     // this wave's items in 32-bit offsets from a wave-uniform base pointer
     // (counts stay below 2^30)
     const int64_t wbase = base + (int64_t)wave * WAVE_ITEMS;
@@ -282,98 +405,97 @@ k_downsweep(const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_
         }
         __syncthreads();   // the staged input is read before the tables reuse s_kv
     }
-    if (kLdsMatch) {
-        for (int i = tid; i < WAVES * kRadix; i += kDownThreads) s_match[i] = 0ull;
-        __syncthreads();
-    }
+    rank_scatter<KeyT, NB>(key, val, lim, drop, shift, s_kv, s_wave, s_local, s_global, s_scan[1],
+                           keys_out, vals_out, rects, pairs_out, rects_out, n_rects, ranges, n_tiles,
+                           count);
+}
 
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+// Fused first tile pass: the pairs of each kSortTile partition are
+// generated from the item rectangles (as the duplicate does) into LDS
+// instead of being written out and read back, then ranked by their first
+// tile digit and scattered.  The duplicate has counted that digit per
+// chunk (counts[d][2 parts], two chunks per partition) and the rows are
+// scanned.  Positions that got no pair hold the key 0xFFFFFFFF and are
+// dropped, as the duplicate's counts dropped them.
+template <typename KeyT, int NB>
+__global__ void __launch_bounds__(kDownThreads)
+k_dup_scatter(Workspace ws, int64_t n, KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+              const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
+              int64_t parts, uint32_t* __restrict__ ranges, int64_t n_tiles) {
+    constexpr int WAVES = kDownThreads / 64;
+    constexpr int WAVE_ITEMS = 64 * kDownItems;
+    constexpr int RUN = kDupChunk / kDownThreads;   // pairs per thread per chunk
+    static_assert(2 * kDupChunk == kSortTile, "two chunks per partition");
+    // the staged (key, value) words; before them, one chunk's items
+    constexpr int kItemBytes = 4 * kChunkItems * 4;
+    constexpr int kKvBytes = kSortTile * 8;
+    __shared__ __align__(16) unsigned char s_raw[kItemBytes > kKvBytes ? kItemBytes : kKvBytes];
+    uint64_t* s_kv = reinterpret_cast<uint64_t*>(s_raw);
+    uint32_t* s_it = reinterpret_cast<uint32_t*>(s_raw);
+    const ChunkItems ci = {s_it, s_it + kChunkItems, s_it + 2 * kChunkItems, s_it + 3 * kChunkItems};
+    __shared__ uint32_t s_wave[WAVES][kRadix];
+    __shared__ uint32_t s_local[kRadix];
+    __shared__ uint32_t s_global[kRadix];
+    __shared__ uint32_t s_scan[2][WAVES];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t P = ws.header[kHdrPairs];
+    const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
+    const uint32_t nn = (uint32_t)n;
+    const int64_t n_vis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
+    const int64_t p = xcd_part(blockIdx.x, (Pc + kSortTile - 1) / kSortTile);
+    const int64_t base = p * kSortTile;
+    if (base >= Pc) return;
+    constexpr int kLive = 1 << NB;
+    const uint32_t tot = tid < kLive ? totals[tid] : 0u;
+    const uint32_t cnt_dp = tid < kLive ? counts[((int64_t)tid * parts + p) * 2] : 0u;
+    for (int i = tid; i < WAVES * kRadix; i += kDownThreads) (&s_wave[0][0])[i] = 0;
+
+    // the partition's two chunks, RUN consecutive pairs per thread each
+    uint32_t tl[2][RUN], vl[2][RUN];
+    int got[2] = {0, 0};
 #pragma unroll
-    for (int k = 0; k < kDownItems; ++k) {
-        const int li = k * 64 + lane;
-        const bool valid = li < lim && !(drop && key[k] == 0xFFFFFFFFu);
-        const uint32_t d = (key[k] >> shift) & (kRadix - 1);
-        uint64_t m;
-        if constexpr (kLdsMatch) {
-            // a wave's LDS instructions execute in order: every lane's OR
-            // lands before any lane reads, every read before the clear
-            unsigned long long* slot = s_match + wave * kRadix + d;
-            if (valid) atomicOr(slot, 1ull << lane);
-            m = valid ? *slot : 0ull;
-            if (valid) *slot = 0ull;
-        } else {
-            m = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bb = __ballot(bit);
-                m &= bit ? bb : ~bb;
-            }
-        }
-        const uint64_t lower = m & lt_mask;
-        const uint32_t prior = valid ? s_wave[wave][d] : 0u;
-        const uint32_t r = prior + (uint32_t)__popcll(lower);
-        rank2[k >> 1] = (k & 1) ? (rank2[k >> 1] | (r << 16)) : r;
-        if (valid && lower == 0) s_wave[wave][d] = prior + (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    int n_valid;
-    {
-        // per digit: exclusive offsets of the waves, then the block's digit starts
-        uint32_t total = 0;
-        if (tid < kRadix) {
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const uint32_t c = s_wave[w][tid];
-                s_wave[w][tid] = total;
-                total += c;
-            }
-        }
-        uint32_t kept;
-        const uint32_t st = block_excl_scan<WAVES>(total, s_scan[1], &kept);
-        if (tid < kRadix) {
-            s_local[tid] = st;
-            s_global[tid] -= st;   // now: output index of staged slot i is s_global[d] + i
-        }
-        n_valid = (int)kept;
+    for (int h = 0; h < 2; ++h) {
+        const int64_t chunk = 2 * p + h;
+        const int64_t p0 = chunk * kDupChunk;
+        if (p0 >= Pc) continue;   // uniform
+        const int64_t p1 = p0 + kDupChunk < Pc ? p0 + kDupChunk : Pc;
+        __syncthreads();   // the item arrays are free
+        const int nloc = load_chunk_items(ws, chunk, p1, Pc, n_vis, nn, ci, tid, kDownThreads);
         __syncthreads();
+        const int64_t q0 = p0 + (int64_t)tid * RUN;
+        if (nloc > 0 && q0 < p1) {
+            got[h] = p1 - q0 < RUN ? (int)(p1 - q0) : RUN;
+            gen_pairs<RUN>(ci, nloc, q0, got[h], tl[h], vl[h]);
+        }
     }
+    __syncthreads();   // the item arrays are done: s_kv takes the pairs
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < RUN; ++e)
+            s_kv[h * kDupChunk + tid * RUN + e] =
+                e < got[h] ? ((uint64_t)tl[h][e] | ((uint64_t)vl[h][e] << 32)) : 0xFFFFFFFFull;
+    // global start of this partition's run of digit d (the barrier also
+    // publishes the staged pairs)
+    {
+        uint32_t all;
+        const uint32_t st = block_excl_scan<WAVES>(tot, s_scan[0], &all);
+        if (tid < kRadix) s_global[tid] = st + cnt_dp;
+    }
+    const int64_t left = Pc - (base + (int64_t)wave * WAVE_ITEMS);
+    const int lim = left <= 0 ? 0 : (left >= WAVE_ITEMS ? WAVE_ITEMS : (int)left);
+    uint32_t key[kDownItems], val[kDownItems];
 #pragma unroll
     for (int k = 0; k < kDownItems; ++k) {
         const int li = k * 64 + lane;
-        if (li < lim && !(drop && key[k] == 0xFFFFFFFFu)) {
-            const uint32_t dd = (key[k] >> shift) & (kRadix - 1);
-            const uint32_t pos = s_local[dd] + s_wave[wave][dd] + ((rank2[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
-            s_kv[pos] = (uint64_t)key[k] | ((uint64_t)val[k] << 32);
-        }
+        const uint64_t kv = li < lim ? s_kv[wave * WAVE_ITEMS + li] : 0xFFFFFFFFull;
+        key[k] = (uint32_t)kv;
+        val[k] = (uint32_t)(kv >> 32);
     }
-    __syncthreads();
-    // unrolled over the thread's fixed slots so that the LDS reads and the
-    // stores of different items overlap
-#pragma unroll
-    for (int j = 0; j < kDownItems; ++j) {
-        const int i = tid + j * kDownThreads;
-        if (i >= n_valid) break;
-        const uint64_t kv = s_kv[i];
-        const uint32_t k = (uint32_t)kv, v = (uint32_t)(kv >> 32);
-        const uint32_t dd = (k >> shift) & (kRadix - 1);
-        const uint32_t out = s_global[dd] + (uint32_t)i;
-        __builtin_assume(out < (1u << 30));
-        if (keys_out) keys_out[out] = (KeyT)k;
-        vals_out[out] = v;
-        if (pairs_out) pairs_out[out] = v < (uint64_t)n_rects ? rect_pairs(rects[v]) : 0u;
-        // last tile pass: a key change between neighbours of this block's run
-        // of one digit is a tile boundary (run starts, where the previous
-        // staged key has another digit, are checked by k_range_edges)
-        if (ranges && i > 0) {
-            const uint32_t pk = (uint32_t)s_kv[i - 1];
-            if (pk != k && ((pk >> shift) & (kRadix - 1)) == dd) {
-                if (k < (uint64_t)n_tiles) ranges[2 * (int64_t)k] = out;
-                if (pk < (uint64_t)n_tiles) ranges[2 * (int64_t)pk + 1] = out;
-            }
-        }
-    }
+    __syncthreads();   // the pairs are read before the tables reuse s_kv
+    rank_scatter<KeyT, NB>(key, val, lim, true, 0, s_kv, s_wave, s_local, s_global, s_scan[1],
+                           keys_out, vals_out, nullptr, nullptr, nullptr, 0, ranges, n_tiles, Pc);
 }
 
 // Tile boundaries at the start of each (digit, partition) run of the last
@@ -419,20 +541,20 @@ static void downsweep_t(dim3 grid, hipStream_t s, const KeyT* keys_in, const uin
                         KeyT* keys_out, uint32_t* vals_out, const uint32_t* count_ptr,
                         int64_t count_host, int shift, const uint32_t* counts,
                         const uint32_t* totals, int64_t parts, const uint64_t* rects,
-                        uint32_t* pairs_out, int64_t n_rects, bool drop, int cstride,
-                        uint32_t* ranges, int64_t n_tiles) {
+                        uint32_t* pairs_out, uint64_t* rects_out, int64_t n_rects, bool drop,
+                        int cstride, uint32_t* ranges, int64_t n_tiles) {
     hipLaunchKernelGGL((k_downsweep<KeyT, NB>), grid, dim3(kDownThreads), 0, s, keys_in, vals_in,
                        keys_out, vals_out, count_ptr, count_host, shift, counts, totals, parts,
-                       rects, pairs_out, n_rects, drop, cstride, ranges, n_tiles);
+                       rects, pairs_out, rects_out, n_rects, drop, cstride, ranges, n_tiles);
 }
 
 template <typename KeyT>
 static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* keys_out,
                          uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                          uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
-                         uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                         int digit_bits, bool counted, uint32_t* ranges, int64_t n_tiles,
-                         hipStream_t s) {
+                         uint32_t* pairs_out, uint64_t* rects_out, int64_t n_rects,
+                         bool drop_culled, uint32_t* kept_out, int digit_bits, bool counted,
+                         uint32_t* ranges, int64_t n_tiles, hipStream_t s) {
     if (parts <= 0) return;
     // counted: the digit counts of every half partition are already in
     // counts[d][2 parts] (written by the pass's producer)
@@ -448,8 +570,8 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
     const dim3 g((unsigned)parts);
 #define SGS_DOWNSWEEP(NB)                                                                      \
     downsweep_t<KeyT, NB>(g, s, keys_in, vals_in, keys_out, vals_out, count_ptr, count_host,   \
-                          shift, counts, totals, parts, rects, pairs_out, n_rects, drop_culled,  \
-                          cstride, ranges, n_tiles)
+                          shift, counts, totals, parts, rects, pairs_out, rects_out, n_rects,    \
+                          drop_culled, cstride, ranges, n_tiles)
     switch (bits) {
         case 1: SGS_DOWNSWEEP(1); break;
         case 2: SGS_DOWNSWEEP(2); break;
@@ -474,12 +596,12 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
 void launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                        uint32_t* vals_out, const uint32_t* count_ptr, int64_t count_host, int shift,
                        uint32_t* counts, uint32_t* totals, int64_t parts, const uint64_t* rects,
-                       uint32_t* pairs_out, int64_t n_rects, bool drop_culled, uint32_t* kept_out,
-                       hipStream_t s, int digit_bits, bool counted, uint32_t* ranges,
-                       int64_t n_tiles) {
+                       uint32_t* pairs_out, uint64_t* rects_out, int64_t n_rects, bool drop_culled,
+                       uint32_t* kept_out, hipStream_t s, int digit_bits, bool counted,
+                       uint32_t* ranges, int64_t n_tiles) {
     radix_pass_t<uint32_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
-                           totals, parts, rects, pairs_out, n_rects, drop_culled, kept_out,
-                           digit_bits, counted, ranges, n_tiles, s);
+                           totals, parts, rects, pairs_out, rects_out, n_rects, drop_culled,
+                           kept_out, digit_bits, counted, ranges, n_tiles, s);
 }
 
 void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint16_t* keys_out,
@@ -487,8 +609,48 @@ void launch_radix_pass16(const uint16_t* keys_in, const uint32_t* vals_in, uint1
                          uint32_t* counts, uint32_t* totals, int64_t parts, hipStream_t s,
                          int digit_bits, bool counted, uint32_t* ranges, int64_t n_tiles) {
     radix_pass_t<uint16_t>(keys_in, vals_in, keys_out, vals_out, count_ptr, count_host, shift, counts,
-                           totals, parts, nullptr, nullptr, 0, false, nullptr, digit_bits, counted,
+                           totals, parts, nullptr, nullptr, nullptr, 0, false, nullptr, digit_bits, counted,
                            ranges, n_tiles, s);
+}
+
+template <typename KeyT>
+static void dup_scatter_t(const Workspace& ws, int64_t n, KeyT* keys_out, uint32_t* vals_out,
+                          int64_t parts, int digit_bits, uint32_t* ranges, int64_t pair_capacity,
+                          hipStream_t s) {
+    if (parts <= 0) return;
+    const int bits = digit_bits < 1 ? 1 : (digit_bits > kRadixBits ? kRadixBits : digit_bits);
+    hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kScanRowThreads), 0, s, ws.counts,
+                       parts * 2, ws.totals, nullptr);
+    const dim3 g((unsigned)parts), b(kDownThreads);
+#define SGS_DUPSCAT(NB)                                                                        \
+    hipLaunchKernelGGL((k_dup_scatter<KeyT, NB>), g, b, 0, s, ws, n, keys_out, vals_out,      \
+                       ws.counts, ws.totals, parts, ranges, ws.n_tiles)
+    switch (bits) {
+        case 1: SGS_DUPSCAT(1); break;
+        case 2: SGS_DUPSCAT(2); break;
+        case 3: SGS_DUPSCAT(3); break;
+        case 4: SGS_DUPSCAT(4); break;
+        case 5: SGS_DUPSCAT(5); break;
+        case 6: SGS_DUPSCAT(6); break;
+        case 7: SGS_DUPSCAT(7); break;
+        default: SGS_DUPSCAT(8); break;
+    }
+#undef SGS_DUPSCAT
+    if (ranges) {
+        const dim3 eg((unsigned)((parts + 255) / 256), 1u << bits);
+        hipLaunchKernelGGL(k_range_edges<KeyT>, eg, dim3(256), 0, s, keys_out, ws.counts, ws.totals,
+                           parts, 2, ws.header + kHdrPairs, pair_capacity, ranges, ws.n_tiles);
+    }
+}
+
+void launch_dup_scatter(const Workspace& ws, int64_t n, uint32_t* keys_out, uint32_t* vals_out,
+                        int64_t parts, int digit_bits, uint32_t* ranges, int64_t pair_capacity,
+                        hipStream_t s) {
+    if (ws.key16)
+        dup_scatter_t<uint16_t>(ws, n, reinterpret_cast<uint16_t*>(keys_out), vals_out, parts,
+                                digit_bits, ranges, pair_capacity, s);
+    else
+        dup_scatter_t<uint32_t>(ws, n, keys_out, vals_out, parts, digit_bits, ranges, pair_capacity, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -12,6 +12,7 @@
 // A stable partition of a depth-ordered sequence is ordered by (tile,
 // depth, item).  The radix passes live in radix.hip.
 #include "common.hpp"
+#include "pairs.hpp"
 
 namespace sgs {
 
@@ -70,26 +71,28 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
 }
 
 // --------------------------------------------------------------------------
-// duplicate: one block per 2048-pair chunk, eight consecutive pairs per
-// thread (balanced: pairs, not Gaussians, are split between threads)
+// duplicate (counting): one block per 2048-pair chunk, eight consecutive
+// pairs per thread (balanced: pairs, not Gaussians, are split between
+// threads).  It generates every pair and counts the low 8 bits of its tile
+// id: chunk c's counts go to counts[d * 2 * pair_parts + c] (two chunks per
+// radix partition), the first tile pass's digit histogram; chunks past the
+// pair count get zero rows.  The pairs themselves are generated again by
+// that pass, which scatters them directly (nothing else is written here).
+// (Counting row segments of each item's rectangle instead of single pairs
+// does less work but keeps one thread per item busy, and measured slower.)
 // --------------------------------------------------------------------------
 
-// Also the first tile-sort pass's digit histogram: chunk c's counts of the
-// low 8 bits of its tile ids go to counts[d * 2 * pair_parts + c] (two
-// chunks per radix partition, so that pass needs no upsweep of its own);
-// chunks past the pair count get zero rows.
 static_assert(2 * kDupChunk == kSortTile, "two duplicate chunks per radix partition");
 constexpr int kDupRun = kDupChunk / 256;   // consecutive pairs per thread
-static_assert(kDupRun == 8, "vector stores of eight pairs");
 
 __global__ void __launch_bounds__(256)
 k_duplicate(Workspace ws, int64_t n) {
-    __shared__ uint32_t s_off[kDupChunk + 1];
-    // after the walk these two stage the chunk's output (16-byte reads)
-    __shared__ __align__(16) uint32_t s_origin[kDupChunk + 1];   // global tile id of the rectangle origin
-    __shared__ __align__(16) uint32_t s_wgx[kDupChunk + 1];      // width | GX << 16
-    __shared__ uint32_t s_item[kDupChunk + 1];
+    __shared__ uint32_t s_off[kChunkItems];
+    __shared__ uint32_t s_origin[kChunkItems];
+    __shared__ uint32_t s_wgx[kChunkItems];
+    __shared__ uint32_t s_item[kChunkItems];
     __shared__ uint32_t s_hist[kRadix];
+    const ChunkItems ci = {s_off, s_origin, s_wgx, s_item};
     const int tid = threadIdx.x;
     const uint32_t P = ws.header[kHdrPairs];
     const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
@@ -102,138 +105,33 @@ k_duplicate(Workspace ws, int64_t n) {
         const int64_t chunk = round + xcd_part(blockIdx.x, live);
         const int64_t p0 = chunk * kDupChunk;
         const int64_t p1 = (p0 + kDupChunk < Pc) ? p0 + kDupChunk : Pc;
-        const int64_t i0 = ws.chunk_start[chunk];
         __syncthreads();   // previous chunk done with LDS
         s_hist[tid] = 0;
-        // visible items i0 .. cover [p0, p1); every visible item has >= 1 pair
-        int64_t i_end = n_vis;
-        if (chunk + 1 < ws.dup_chunks && p1 < Pc) i_end = (int64_t)ws.chunk_start[chunk + 1] + 1;
-        int64_t nloc = i0 < n_vis ? i_end - i0 : 0;   // 0: no chunk start was recorded
-        if (nloc > kDupChunk + 1) nloc = kDupChunk + 1;
+        const int nloc = load_chunk_items(ws, chunk, p1, Pc, n_vis, nn, ci, tid, 256);
         if (nloc < 1) {
             ws.counts[tid * row + chunk] = 0;
             continue;   // uniform
         }
-        for (int j = tid; j < nloc; j += 256) {
-            const int64_t i = i0 + j;
-            uint32_t item = ws.sorted_items[i];
-            if (item >= (uint64_t)ws.n_items) item = 0;
-            s_off[j] = ws.pair_offsets[i];
-            s_item[j] = item;
-            const uint64_t r = ws.tile_rects[item];
-            const int tx0 = (int)(r & 0xFFFF), tx1 = (int)((r >> 16) & 0xFFFF);
-            const int ty0 = (int)((r >> 32) & 0xFFFF);
-            const CamTable ct = ws.cams[item / nn];
-            s_origin[j] = (uint32_t)(ct.tile_base + ty0 * ct.GX + tx0);
-            s_wgx[j] = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)ct.GX << 16);
-        }
         __syncthreads();
-        // thread t emits the kDupRun consecutive pairs from p0 + kDupRun t:
-        // one search for the first, then a walk along the rectangles
+        // thread t walks the kDupRun consecutive pairs from p0 + kDupRun t
         const int64_t q0 = p0 + (int64_t)tid * kDupRun;
-        uint32_t tl[kDupRun], vl[kDupRun];
         if (q0 < p1) {
-            int lo = 0, hi = (int)nloc - 1;     // last local item with offset <= q0
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((int64_t)s_off[mid] <= q0) lo = mid; else hi = mid - 1;
-            }
-            uint32_t wgx = s_wgx[lo];
-            int w = (int)(wgx & 0xFFFF), gx = (int)(wgx >> 16);
-            const int j = (int)(q0 - s_off[lo]);
-            // j / w in float: the quotient is at least 0.5/w from an integer
-            int ty = (int)(((float)j + 0.5f) * (1.0f / (float)w));
-            int tx = j - ty * w;
-            if (tx < 0) { --ty; tx += w; } else if (tx >= w) { ++ty; tx -= w; }
-            uint32_t origin = s_origin[lo], item = s_item[lo];
-            int64_t next = lo + 1 < nloc ? (int64_t)s_off[lo + 1] : INT64_MAX;
+            uint32_t tl[kDupRun], vl[kDupRun];
             const int cnt = p1 - q0 < kDupRun ? (int)(p1 - q0) : kDupRun;
+            gen_pairs<kDupRun>(ci, nloc, q0, cnt, tl, vl);
 #pragma unroll
-            for (int e = 0; e < kDupRun; ++e) {
-                if (e < cnt) {
-                    if (q0 + e >= next) {   // the next item (every item has >= 1 pair)
-                        ++lo;
-                        wgx = s_wgx[lo];
-                        w = (int)(wgx & 0xFFFF);
-                        gx = (int)(wgx >> 16);
-                        origin = s_origin[lo];
-                        item = s_item[lo];
-                        next = lo + 1 < nloc ? (int64_t)s_off[lo + 1] : INT64_MAX;
-                        tx = ty = 0;
-                    }
-                    tl[e] = origin + (uint32_t)(ty * gx + tx);
-                    vl[e] = item;
-                    atomicAdd(&s_hist[tl[e] & (kRadix - 1)], 1u);
-                    if (++tx == w) {
-                        tx = 0;
-                        ++ty;
-                    }
-                }
-            }
-        }
-        // stage the chunk's pairs in LDS (the rectangle arrays are done), then
-        // write them with whole-wave contiguous 16-byte stores
-        __syncthreads();
-        uint32_t* st_val = s_origin;                              // 2048 values
-        uint16_t* st_tile = reinterpret_cast<uint16_t*>(s_wgx);   // 2048 tile ids (u16 keys)
-        uint32_t* st_tile32 = s_wgx;                              // or (u32 keys)
-        if (q0 + kDupRun <= p1) {
-            uint4* v4 = reinterpret_cast<uint4*>(st_val) + 2 * tid;
-            v4[0] = make_uint4(vl[0], vl[1], vl[2], vl[3]);
-            v4[1] = make_uint4(vl[4], vl[5], vl[6], vl[7]);
-            if (ws.key16) {
-                reinterpret_cast<uint4*>(st_tile)[tid] =
-                    make_uint4((tl[0] & 0xFFFF) | (tl[1] << 16), (tl[2] & 0xFFFF) | (tl[3] << 16),
-                               (tl[4] & 0xFFFF) | (tl[5] << 16), (tl[6] & 0xFFFF) | (tl[7] << 16));
-            } else {
-                uint4* t4 = reinterpret_cast<uint4*>(st_tile32) + 2 * tid;
-                t4[0] = make_uint4(tl[0], tl[1], tl[2], tl[3]);
-                t4[1] = make_uint4(tl[4], tl[5], tl[6], tl[7]);
-            }
-        } else if (q0 < p1) {
-            const int cnt = (int)(p1 - q0);
-            for (int e = 0; e < cnt; ++e) {
-                const int at = tid * kDupRun + e;
-                st_val[at] = vl[e];
-                if (ws.key16) st_tile[at] = (uint16_t)tl[e];
-                else st_tile32[at] = tl[e];
-            }
-        }
-        __syncthreads();
-        const int n_here = (int)(p1 - p0);
-        if (n_here == kDupChunk) {
-            // p0 is a multiple of 2048: every vector store is aligned
-            uint4* vdst = reinterpret_cast<uint4*>(ws.pair_values + p0);
-            const uint4* vsrc = reinterpret_cast<const uint4*>(st_val);
-            vdst[tid] = vsrc[tid];
-            vdst[256 + tid] = vsrc[256 + tid];
-            if (ws.key16) {
-                reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(ws.pair_tiles) + p0)[tid] =
-                    reinterpret_cast<const uint4*>(st_tile)[tid];
-            } else {
-                uint4* tdst = reinterpret_cast<uint4*>(ws.pair_tiles + p0);
-                tdst[tid] = reinterpret_cast<const uint4*>(st_tile32)[tid];
-                tdst[256 + tid] = reinterpret_cast<const uint4*>(st_tile32)[256 + tid];
-            }
-        } else {
-            for (int e = tid; e < n_here; e += 256) {
-                ws.pair_values[p0 + e] = st_val[e];
-                if (ws.key16)
-                    reinterpret_cast<uint16_t*>(ws.pair_tiles)[p0 + e] = st_tile[e];
-                else
-                    ws.pair_tiles[p0 + e] = st_tile32[e];
-            }
+            for (int e = 0; e < kDupRun; ++e)
+                if (e < cnt) atomicAdd(&s_hist[tl[e] & (kRadix - 1)], 1u);
         }
         __syncthreads();
         ws.counts[tid * row + chunk] = s_hist[tid];
     }
     // zero rows for the chunks past the pair count
-    for (int64_t chunk = n_chunks + blockIdx.x; chunk < row;
-         chunk += gridDim.x)
+    for (int64_t chunk = n_chunks + blockIdx.x; chunk < row; chunk += gridDim.x)
         ws.counts[tid * row + chunk] = 0;
 }
 
-void launch_duplicate(const Workspace& ws, int64_t n, hipStream_t s) {
+void launch_duplicate_counts(const Workspace& ws, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_duplicate, dim3((unsigned)ws.dup_blocks), dim3(256), 0, s, ws, n);
 }
 
@@ -264,7 +162,7 @@ void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s) {
     const int64_t blocks = (ws.n_tiles + 255) / 256;
     hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)blocks), dim3(256), 0, s, ws);
     launch_radix_pass(ws.tile_keys, nullptr, nullptr, ws.tile_order, nullptr, ws.n_tiles, 0,
-                      ws.counts, ws.totals, parts, nullptr, nullptr, 0, false, nullptr, s);
+                      ws.counts, ws.totals, parts, nullptr, nullptr, nullptr, 0, false, nullptr, s);
 }
 
 // --------------------------------------------------------------------------
