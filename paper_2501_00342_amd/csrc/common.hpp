@@ -125,7 +125,6 @@ struct Workspace {
 };
 
 // launchers (defined in the .hip files)
-void launch_clear(const Workspace& ws, hipStream_t s);
 void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, int tile_w, int tile_h,
                   float guard, hipStream_t s);
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,

@@ -339,8 +339,7 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
     Marker mk{timing_slot(g_timing.fwd, g_timing.fwd_used), s};
 
     mk.mark(0);
-    sgs::launch_clear(ws, s);
-    sgs::launch_setup(ws, dev_cams, n_cams, o.tile_w, o.tile_h, o.guard, s);
+    sgs::launch_setup(ws, dev_cams, n_cams, o.tile_w, o.tile_h, o.guard, s);   // clears too
     SGS_LAUNCHED();
     mk.mark(1);
     if (pl.n > 0) {

@@ -34,14 +34,19 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
 }
 
-void launch_clear(const Workspace& ws, hipStream_t s) {
-    launch_fill_u32(ws.header, 0u, kHdrWords, s);
-    launch_fill_u32(ws.ranges, 0u, 2 * ws.n_tiles, s);
-}
-
-__global__ void k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, int tw,
-                        int th, float guard) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The start of a forward in one launch: every block clears tile ranges;
+// block 0 clears the header, then its thread 0 builds the camera table
+// (after the clear, so a camera error bit survives it).
+__global__ void __launch_bounds__(256)
+k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, int tw, int th,
+        float guard) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ws.n_tiles;
+         i += (int64_t)gridDim.x * blockDim.x)
+        ws.ranges[i] = 0u;
+    if (blockIdx.x != 0) return;   // uniform
+    if (threadIdx.x < kHdrWords) ws.header[threadIdx.x] = 0u;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     int64_t tiles = 0, pix = 0;
     bool ok = true;
     for (int c = 0; c < n_cams; ++c) {
@@ -67,7 +72,10 @@ __global__ void k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n
 
 void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, int tile_w, int tile_h,
                   float guard, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, ws, dev_cams, n_cams, tile_w, tile_h, guard);
+    int64_t blocks = (2 * ws.n_tiles + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(256), 0, s, ws, dev_cams, n_cams, tile_w,
+                       tile_h, guard);
 }
 
 // --------------------------------------------------------------------------
