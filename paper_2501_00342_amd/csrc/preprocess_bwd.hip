@@ -152,32 +152,62 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
     const int64_t n = p.n;
     const int64_t M = ws.n_items;
     const double dil = o.dilation;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // inputs of this thread's next Gaussian, loaded while the current one
+    // computes: geometry, the colour part of the mean's gradient, and the
+    // first camera's rectangle and 2D gradients (u, v, Qa, Qb, Qc, sigma)
+    struct In {
+        float X[3], ls[3], q[4], logit, gxc[3];
+        uint64_t rect0;
+        float g0[6];
+    };
+    auto load = [&](int64_t g, In& in) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            in.X[c] = p.means[c * n + g];
+            in.ls[c] = p.log_scales[c * n + g];
+            in.gxc[c] = gx_colour[c * n + g];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) in.q[c] = p.quats[c * n + g];
+        in.logit = p.opacity_logits[g];
+        in.rect0 = ws.tile_rects[g];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) in.g0[c] = ws.grad2d[c * M + g];
+    };
+    In cur;
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) load(g, cur);
+    for (; g < n; g += stride) {
+        In nxt;
+        if (g + stride < n) load(g + stride, nxt);
         double gX[3] = {0.0, 0.0, 0.0}, gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
         double glogit = 0.0;
-        const double X[3] = {p.means[g], p.means[n + g], p.means[2 * n + g]};
-        const double s[3] = {exp((double)p.log_scales[g]), exp((double)p.log_scales[n + g]),
-                             exp((double)p.log_scales[2 * n + g])};
-        const double q[4] = {p.quats[g], p.quats[n + g], p.quats[2 * n + g], p.quats[3 * n + g]};
+        const double X[3] = {cur.X[0], cur.X[1], cur.X[2]};
+        const double s[3] = {exp((double)cur.ls[0]), exp((double)cur.ls[1]), exp((double)cur.ls[2])};
+        const double q[4] = {cur.q[0], cur.q[1], cur.q[2], cur.q[3]};
         const double iq = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
         const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
         const double Rq[3][3] = {
             {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
             {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
             {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-        const double sig = 1.0 / (1.0 + exp(-(double)p.opacity_logits[g]));
+        const double sig = 1.0 / (1.0 + exp(-(double)cur.logit));
         bool any = false;
         for (int ci = 0; ci < n_cams; ++ci) {
             const int64_t item = (int64_t)ci * n + g;
-            if (!item_visible(ws, item)) continue;
+            const uint64_t tr = ci == 0 ? cur.rect0 : ws.tile_rects[item];
+            if ((int)((tr >> 16) & 0xFFFF) < (int)(tr & 0xFFFF)) continue;   // not visible
             any = true;
             const sgs_camera& cam = cams[ci];
             const CamTable ct = ws.cams[ci];
-            const double gu = ws.grad2d[item], gv = ws.grad2d[M + item];
-            const double gQa = ws.grad2d[2 * M + item], gQb = ws.grad2d[3 * M + item];
-            const double gQc = ws.grad2d[4 * M + item];
-            glogit += (double)ws.grad2d[5 * M + item] * sig * (1.0 - sig);
+            float g2d[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) g2d[c] = ci == 0 ? cur.g0[c] : ws.grad2d[c * M + item];
+            const double gu = g2d[0], gv = g2d[1];
+            const double gQa = g2d[2], gQb = g2d[3];
+            const double gQc = g2d[4];
+            glogit += (double)g2d[5] * sig * (1.0 - sig);
             const double fx = cam.fx, fy = cam.fy;
             double xc[3];
             for (int i = 0; i < 3; ++i)
@@ -270,11 +300,12 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
         const double dq = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
         const double qh[4] = {w, x, y, z};
         for (int c = 0; c < 3; ++c) {
-            gr.means[c * n + g] = (float)(gX[c] + (any ? (double)gx_colour[c * n + g] : 0.0));
+            gr.means[c * n + g] = (float)(gX[c] + (any ? (double)cur.gxc[c] : 0.0));
             gr.log_scales[c * n + g] = (float)gls[c];
         }
         for (int c = 0; c < 4; ++c) gr.quats[c * n + g] = (float)((gq[c] - qh[c] * dq) * iq);
         gr.opacity_logits[g] = (float)glogit;
+        cur = nxt;
     }
 }
 
