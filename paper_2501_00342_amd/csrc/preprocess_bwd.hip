@@ -57,11 +57,30 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
     const int tid = threadIdx.x, wave = tid >> 6;
     const int RS = colour_record_floats(3 * NC, K);
     float* crec = s_buf + wave * 64 * MAXROWS;
+    // this thread's Gaussian in the next tile: its mean and the first
+    // camera's rectangle, loaded while this tile computes (only where the
+    // registers allow it without spilling)
+    constexpr bool PF = ColourBwdWaves<DEG, KMAX>::value >= 4;
+    float nX[3];
+    uint64_t nrect;
+    auto load = [&](int64_t b) {
+        const int64_t gg = b + tid < n ? b + tid : n - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            nX[c] = p.means[c * n + gg];
+        }
+        nrect = ws.tile_rects[gg];
+    };
+    if (PF && (int64_t)blockIdx.x * kPreTile < n) load((int64_t)blockIdx.x * kPreTile);
     for (int64_t base = (int64_t)blockIdx.x * kPreTile; base < n;
          base += (int64_t)gridDim.x * kPreTile) {
         __syncthreads();   // the previous tile's records are written out
         const int64_t g = base + tid;
         const bool active = g < n;
+        if (!PF) load(base);
+        const double X[3] = {nX[0], nX[1], nX[2]};
+        const uint64_t rect0 = nrect;
+        if (PF && base + (int64_t)gridDim.x * kPreTile < n) load(base + (int64_t)gridDim.x * kPreTile);
         float gsh[NC][3];
         float gamp[KMAX + 1][3], gax[KMAX + 1][3], glsh[KMAX + 1];
 #pragma unroll
@@ -74,18 +93,26 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
         }
         float gX[3] = {0.0f, 0.0f, 0.0f};
         const int64_t gc = active ? g : n - 1;
-        const double X[3] = {p.means[gc], p.means[n + gc], p.means[2 * n + gc]};
         int slot = -1, used = 0;
         for (int ci = 0; ci < n_cams; ++ci) {
             const int64_t item = (int64_t)ci * n + gc;
-            const bool vis = active && item_visible(ws, item);
+            const uint64_t tr = PF && ci == 0 ? rect0 : ws.tile_rects[item];
+            const bool vis = active && (int)((tr >> 16) & 0xFFFF) >= (int)(tr & 0xFFFF);
+            // with registers to spare, issued before the gather's wait
+            float grgb[3];
+            if constexpr (PF) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[(6 + c) * M + item];
+            }
             const int got = gather_colour<3 * NC>(p, gc, vis && slot < 0, used, crec, s_g[wave], &slot);
             used += got;
             if (got) __builtin_amdgcn_s_waitcnt(0);
             if (!vis) continue;
+            if constexpr (!PF) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[(6 + c) * M + item];
+            }
             const float* r = crec + slot * RS;
-            const float grgb[3] = {ws.grad2d[6 * M + item], ws.grad2d[7 * M + item],
-                                   ws.grad2d[8 * M + item]};
             float d[3], dist;
             view_dir(X, cams[ci], d, &dist);
             float gd[3];
