@@ -54,16 +54,22 @@ def parse():
 GEOM_FLOATS = 3 + 3 + 4 + 1   # mean, log-scale, quaternion, opacity logit
 
 
-def stage_bytes(name, n, nvis, nvis_g, P, tiles, fpg, tile_passes, npix):
-    """Algorithmic HBM bytes of each stage for one frame: n Gaussians, nvis
-    visible (camera, Gaussian) items, nvis_g Gaussians visible in some
-    camera (the only ones whose colour is read), P pairs."""
+def stage_bytes(name, n, items, nvis, nvis_g, P, tiles, fpg, tile_passes, npix):
+    """Algorithmic HBM bytes of each stage for one frame, as this design moves
+    them: n Gaussians, items (camera, Gaussian) items, nvis of them visible,
+    nvis_g Gaussians visible in some camera (the only ones whose colour is
+    read), P pairs."""
     kb = 2 if tiles <= 65536 else 4   # bytes per tile key
     fc = fpg - GEOM_FLOATS             # colour floats per Gaussian
     return {
-        "fwd.preprocess": n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + n * (4 + 8) + nvis * 64,
-        "fwd.depth_sort": 56 * n,
-        "fwd.pair_scan": n * (4 + 8 + 4),
+        "fwd.preprocess": n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + items * (4 + 8) + nvis * 64,
+        # pass 0 reads every depth key twice (count, then rank) and writes the
+        # visible (key, item); the two middle passes read keys (count), read
+        # and write (key, item); the last reads keys, then (key, item) and each
+        # item's rectangle, and writes item, pair count and rectangle
+        "fwd.depth_sort": 8 * items + 8 * nvis + 2 * 20 * nvis + 36 * nvis,
+        # counts read twice (block sums, then the scan), offsets written
+        "fwd.pair_scan": 12 * nvis,
         # the duplicate only counts: it reads each chunk's items (offset,
         # item, rectangle)
         "fwd.duplicate": nvis * (4 + 4 + 8),
@@ -79,6 +85,25 @@ def stage_bytes(name, n, nvis, nvis_g, P, tiles, fpg, tile_passes, npix):
         # read for the visible ones, colour gradient written for all
         "bwd.preprocess": nvis * 36 + 2 * n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + n * 4 * fc,
     }.get(name)
+
+
+def stage_bytes_all_params(name, n, items, nvis, fpg):
+    """The same stages counted with every Gaussian's full parameter record
+    read (and, backward, its gradient written), visible or not: what a
+    layout that cannot skip the colour of culled Gaussians moves."""
+    return {
+        "fwd.preprocess": n * 4 * fpg + 4 * items + 64 * nvis,
+        "bwd.preprocess": 36 * nvis + 2 * n * 4 * fpg,
+    }.get(name)
+
+
+def standard_binning_bytes(items, nvis, P, tiles):
+    """Bytes of the usual binning: an exclusive scan of the per-item pair
+    counts, the duplicate writing 64-bit (tile << 32 | depth) keys with
+    32-bit values, an LSD radix sort of 8-bit digits over the low 32 +
+    ceil(log2 tiles) key bits, and the range search over the sorted keys."""
+    passes = math.ceil((32 + math.ceil(math.log2(max(tiles, 2)))) / 8)
+    return (8 * items + (16 * nvis + 12 * P) + (8 + 24 * passes) * P + (8 * P + 8 * tiles)), passes
 
 
 def timed_loop(fn, steps, torch):
@@ -339,13 +364,29 @@ def main():
         if calls <= 0:
             continue
         ms = src[i] / calls
-        b = stage_bytes(nm, sc.n, n_vis, n_vis_g, P, tiles, fpg, tile_passes, W * H)
+        items = len(cams) * sc.n
+        b = stage_bytes(nm, sc.n, items, n_vis, n_vis_g, P, tiles, fpg, tile_passes, W * H)
         ent = {"ms": round(ms, 5)}
         if b is not None and ms > 0:
             ent["alg_bytes"] = int(b)
             ent["GBps"] = round(b / (ms * 1e-3) / 1e9, 1)
             ent["hbm_frac"] = round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        ba = stage_bytes_all_params(nm, sc.n, items, n_vis, fpg)
+        if ba is not None and ms > 0:
+            ent["alg_bytes_all_params"] = int(ba)
+            ent["hbm_frac_all_params"] = round(ba / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         stages[nm] = ent
+
+    # binning as a whole (depth sort to the last tile pass, which also writes
+    # the ranges) beside the bytes the usual 64-bit key sort would move
+    bin_names = ("fwd.depth_sort", "fwd.pair_scan", "fwd.duplicate", "fwd.tile_sort")
+    bin_ms = sum(stages[nm]["ms"] for nm in bin_names if nm in stages)
+    std_b, std_passes = standard_binning_bytes(len(cams) * sc.n, n_vis, P, tiles)
+    binning = {"ms": round(bin_ms, 5),
+               "alg_bytes": int(sum(stages[nm].get("alg_bytes", 0) for nm in bin_names if nm in stages)),
+               "bytes_64bit_key_sort": int(std_b), "key_sort_passes": std_passes}
+    if bin_ms > 0:
+        binning["ms_64bit_key_sort_at_hbm_peak"] = round(std_b / (HBM_PEAK_GBS * 1e9) * 1e3, 5)
 
     # roofline of the forward's dominant kernel (stages that are one launch)
     dom = max((n for n in SINGLE_KERNEL_STAGES if n in stages), key=lambda n: stages[n]["ms"])
@@ -384,7 +425,7 @@ def main():
                   "fwd_bwd_ms": round(m["fb_ms"], 4)},
         "pairs": int(P), "visible": n_vis, "tiles": tiles,
         "blend_visited": visited, "blend_evaluated": evaluated,
-        "stages": stages, "roofline": roof,
+        "stages": stages, "binning": binning, "roofline": roof,
     }
     if m["reports"]:
         result["autotune"] = m["reports"]

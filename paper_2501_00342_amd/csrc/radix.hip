@@ -93,27 +93,40 @@ k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t coun
     counts[(int64_t)d * parts + p] = c;
 }
 
-// block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row
-// sum.  1024 threads x 8 consecutive entries per round, wave scans with
-// lane shuffles, then a scan of the 16 wave totals.
 constexpr int kScanRowThreads = 1024;
+constexpr int kScanRowItems = 16;
 
+// block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row
+// sum (also added to *kept_out when given).  Each thread owns 16 consecutive
+// entries per round, read and written as four 16-byte words when the row is
+// 16-byte aligned, so a row of up to 16K partitions takes one round; wave
+// scans with lane shuffles, then a scan of the 16 wave totals.
 __global__ void __launch_bounds__(kScanRowThreads)
 k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__ totals,
             uint32_t* kept_out) {
     constexpr int WAVES = kScanRowThreads / 64;
+    constexpr int IT = kScanRowItems;
     __shared__ uint32_t s_w[WAVES];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t* row = counts + (int64_t)blockIdx.x * parts;
+    const bool vec = (reinterpret_cast<uintptr_t>(row) & 15) == 0;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < parts; b0 += kScanRowThreads * 8) {
-        uint32_t v[8], run = 0;
+    for (int64_t b0 = 0; b0 < parts; b0 += kScanRowThreads * IT) {
+        const int64_t i0 = b0 + (int64_t)tid * IT;
+        const bool whole = vec && i0 + IT <= parts;
+        uint32_t v[IT], run = 0;
+        if (whole) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t i = b0 + (int64_t)tid * 8 + k;
-            v[k] = i < parts ? row[i] : 0u;
-            run += v[k];
+            for (int q = 0; q < IT / 4; ++q) {
+                const uint4 t = *reinterpret_cast<const uint4*>(row + i0 + 4 * q);
+                v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < IT; ++k) v[k] = i0 + k < parts ? row[i0 + k] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < IT; ++k) run += v[k];
         uint32_t x = run;   // inclusive scan over the wave
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -134,10 +147,20 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
         __syncthreads();
         uint32_t off = carry + (w > 0 ? s_w[w - 1] : 0u) + x - run;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t i = b0 + (int64_t)tid * 8 + k;
-            if (i < parts) row[i] = off;
+        for (int k = 0; k < IT; ++k) {
+            const uint32_t e = off;
             off += v[k];
+            v[k] = e;
+        }
+        if (whole) {
+#pragma unroll
+            for (int q = 0; q < IT / 4; ++q)
+                *reinterpret_cast<uint4*>(row + i0 + 4 * q) =
+                    make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < IT; ++k)
+                if (i0 + k < parts) row[i0 + k] = v[k];
         }
         carry += s_w[WAVES - 1];
         __syncthreads();
