@@ -418,14 +418,16 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                 const int64_t item =
                     __builtin_amdgcn_readfirstlane(__float_as_uint(e.c.w));
                 float* gi = G + item;
-                // the last lane of each row adds its row's totals (channel
-                // order of grad2d: u, v, Qa, Qb, Qc, sigma, r, g, b)
-                if ((lane & 15) == 15) {
-                    const int r = lane >> 4;
+                // every lane of row r holds the row's totals: lane 15 adds
+                // x[0] to channel ch, lane 14 x[1] to channel 4 + ch and, in
+                // row 0, lane 13 x[2] to channel 8 -- nine lanes of one
+                // atomic instruction (channel order of grad2d: u, v, Qa, Qb,
+                // Qc, sigma, r, g, b)
+                const int r = lane >> 4, sel = 15 - (lane & 15);
+                if (sel < 2 || (sel == 2 && r == 0)) {
                     const int ch = 2 * (r & 1) + (r >> 1);
-                    unsafeAtomicAdd(gi + ch * M, x[0]);
-                    unsafeAtomicAdd(gi + (4 + ch) * M, x[1]);
-                    if (r == 0) unsafeAtomicAdd(gi + 8 * M, x[2]);
+                    const int chan = sel == 0 ? ch : (sel == 1 ? 4 + ch : 8);
+                    unsafeAtomicAdd(gi + chan * M, sel == 0 ? x[0] : (sel == 1 ? x[1] : x[2]));
                 }
             }
         }
