@@ -30,9 +30,9 @@ SOURCES = {
     "preprocess_bwd.hip": ["-ffp-contract=off"],
     "sort.hip": [],
     "radix.hip": [],
-    # the blends' atomics come from one lane with a wave-uniform address
-    # (already reduced with DPP): LLVM's atomic optimizer would only wrap
-    # each of them in a second, redundant wave reduction
+    # the blends' atomics add values already reduced across the wave (the
+    # work counters from one lane at a wave-uniform address): LLVM's atomic
+    # optimizer would only wrap them in a second, redundant wave reduction
     "blend.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
 }
 
