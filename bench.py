@@ -426,6 +426,10 @@ def main():
         "pairs": int(P), "visible": n_vis, "tiles": tiles,
         "blend_visited": visited, "blend_evaluated": evaluated,
         "stages": stages, "binning": binning, "roofline": roof,
+        # the paper's own rendering speed (Table 1: trained Mip-NeRF360
+        # scenes, one RTX 3090, Gaussian counts not given): context only
+        "paper_context": {"hardware": "RTX 3090", "scenes": "Mip-NeRF360, trained",
+                          "fps_3dgs_sh3": 247, "fps_sg_splatting": 334},
     }
     if m["reports"]:
         result["autotune"] = m["reports"]
