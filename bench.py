@@ -349,7 +349,7 @@ def main():
     rast, opts = m["rast"], m["opts_f"]
     names = L.stage_names()
     bits, P = rast.status()
-    visited, evaluated = rast.blend_work(m["params"])
+    visited, evaluated, blended = rast.blend_work(m["params"])
     vis_items = (rast.depth_keys().cpu().numpy().view(np.uint32) != 0xFFFFFFFF).reshape(len(cams), sc.n)
     n_vis = int(np.count_nonzero(vis_items))
     n_vis_g = int(np.count_nonzero(vis_items.any(axis=0)))
@@ -393,7 +393,12 @@ def main():
     shape = shape_of(rast, opts)
     tr = counter_traffic(dom, args.workload, shape)
     if dom == "fwd.blend":
-        ops = evaluated * 24 + visited * 4          # lane-ops per launch
+        # lane-ops per launch: 4 per thread visit (dx, the two x-terms, the
+        # column test), 9 per evaluated pair (dy, the two whitened
+        # coordinates, q, exp2, opacity product, alpha_max clamp, alpha_min
+        # test), 8 more per pair that blends (1 - alpha, T (1 - alpha), the
+        # T_min test, w, three colour and one depth FMA)
+        ops = visited * 4 + evaluated * 9 + blended * 8
         ach = ops / (stages[dom]["ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tlane-op/s",
@@ -424,7 +429,7 @@ def main():
         "eager": {"frames_per_s": round(1000.0 / m["fwd_ms"], 2), "fwd_ms": round(m["fwd_ms"], 4),
                   "fwd_bwd_ms": round(m["fb_ms"], 4)},
         "pairs": int(P), "visible": n_vis, "tiles": tiles,
-        "blend_visited": visited, "blend_evaluated": evaluated,
+        "blend_visited": visited, "blend_evaluated": evaluated, "blend_blended": blended,
         "stages": stages, "binning": binning, "roofline": roof,
         # the paper's own rendering speed (Table 1: trained Mip-NeRF360
         # scenes, one RTX 3090, Gaussian counts not given): context only

@@ -262,10 +262,11 @@ const char* render_stage_name(int32_t stage);
  * workspace, cameras, options and outputs) and counts the list entries
  * visited by each thread while one of its pixels still blends (counts[0];
  * a thread owns pixels_per_thread pixels of one column and tests the
- * column once per entry) and, over all pixels, the entries whose pixel
- * rectangle holds the pixel, i.e. whose alpha is evaluated (counts[1]).
- * counts: device u64[2], overwritten.  For roofline figures; not part of
- * the render.
+ * column once per entry), over all pixels the entries whose pixel
+ * rectangle holds the pixel, i.e. whose alpha is evaluated (counts[1]), and
+ * the entries that blend into the pixel: alpha at least alpha_min and the
+ * pixel not stopped by them (counts[2]).  counts: device u64[3],
+ * overwritten.  For roofline figures; not part of the render.
  */
 int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams,
                       const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,

@@ -121,7 +121,8 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
                                          int n_cams, const Opts& o, const sgs_outputs& out,
                                          int batch, int64_t tile, Entry* s_e, int* s_cam,
                                          unsigned long long& visited,
-                                         unsigned long long& evaluated) {
+                                         unsigned long long& evaluated,
+                                         unsigned long long& blended) {
     constexpr int NT = TW * TH / PPT;
     const int tid = threadIdx.x;
     if (tid == 0) *s_cam = find_camera(ws.cams, n_cams, tile);
@@ -154,34 +155,41 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
         for (int k = tid; k < cnt; k += NT)
             s_e[k] = load_entry(ws, (int64_t)bs + k, x0, y0, TW, TH);
         __syncthreads();
-        if (live) {
+        // the loop exits are wave-uniform: a thread whose pixels are all done
+        // stays in it with every pixel skipped by its live bit, instead of a
+        // divergent exit whose bookkeeping costs VALU on every entry
+        if (__any(live != 0u)) {
             for (int j = 0; j < cnt; ++j) {
                 const Entry e = s_e[j];
-                if (COUNT) ++visited;   // per thread: its pixels share the column work
-                if (!(e.m.x & colbit)) continue;
-                const float dx = lxf + e.a.x;
-                const float t1 = e.a.z * dx, t2 = e.b.x * dx;
+                if (COUNT && live) ++visited;   // per thread: its pixels share the column work
+                // nested tests rather than `continue`: no exit flag to track
+                if (e.m.x & colbit) {
+                    const float dx = lxf + e.a.x;
+                    const float t1 = e.a.z * dx, t2 = e.b.x * dx;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (!((live >> k) & 1u)) continue;
-                    if (!((e.m.y >> (ry + k)) & 1u)) continue;
-                    if (COUNT) ++evaluated;
-                    const Eval v = eval_splat(e, t1, t2, (float)(ry + k) + e.a.y, amax);
-                    if (v.alpha < amin) continue;
-                    const float Tn = T[k] * (1.0f - v.alpha);
-                    if (Tn < tmin) {
-                        live &= ~(1u << k);
-                        continue;
+                    for (int k = 0; k < PPT; ++k) {
+                        if (((live >> k) & 1u) && ((e.m.y >> (ry + k)) & 1u)) {
+                            if (COUNT) ++evaluated;
+                            const Eval v = eval_splat(e, t1, t2, (float)(ry + k) + e.a.y, amax);
+                            if (!(v.alpha < amin)) {
+                                const float Tn = T[k] * (1.0f - v.alpha);
+                                if (Tn < tmin) {
+                                    live &= ~(1u << k);
+                                } else {
+                                    const float w = v.alpha * T[k];
+                                    C0[k] = fmaf(w, e.c.x, C0[k]);
+                                    C1[k] = fmaf(w, e.c.y, C1[k]);
+                                    C2[k] = fmaf(w, e.c.z, C2[k]);
+                                    D[k] = fmaf(w, e.b.w, D[k]);
+                                    T[k] = Tn;
+                                    n[k] = (int)(bs - start) + j + 1;
+                                    if (COUNT) ++blended;
+                                }
+                            }
+                        }
                     }
-                    const float w = v.alpha * T[k];
-                    C0[k] = fmaf(w, e.c.x, C0[k]);
-                    C1[k] = fmaf(w, e.c.y, C1[k]);
-                    C2[k] = fmaf(w, e.c.z, C2[k]);
-                    D[k] = fmaf(w, e.b.w, D[k]);
-                    T[k] = Tn;
-                    n[k] = (int)(bs - start) + j + 1;
                 }
-                if (!live) break;
+                if (!__any(live != 0u)) break;
             }
         }
     }
@@ -225,30 +233,32 @@ k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
     __shared__ int s_cam;
     __shared__ uint32_t s_next;
     if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
-    unsigned long long visited = 0, evaluated = 0;
+    unsigned long long visited = 0, evaluated = 0, blended = 0;
     if (QUEUE) {
         for (;;) {
             const int64_t tile = pop_tile(ws, ws.header + kHdrQueueFwd, &s_next);
             if (tile < 0) break;
             fwd_tile<TW, TH, PPT, COUNT>(ws, cams, n_cams, o, out, batch, tile, s_e, &s_cam,
-                                         visited, evaluated);
+                                         visited, evaluated, blended);
         }
     } else {
         fwd_tile<TW, TH, PPT, COUNT>(ws, cams, n_cams, o, out, batch,
                                      xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, visited,
-                                     evaluated);
+                                     evaluated, blended);
     }
     if (COUNT) {
-        __shared__ unsigned long long s_cnt[2];
+        __shared__ unsigned long long s_cnt[3];
         __syncthreads();
-        if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0ull;
+        if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = 0ull;
         __syncthreads();
         atomicAdd(&s_cnt[0], visited);
         atomicAdd(&s_cnt[1], evaluated);
+        atomicAdd(&s_cnt[2], blended);
         __syncthreads();
         if (threadIdx.x == 0) {
             atomicAdd(&counts[0], s_cnt[0]);
             atomicAdd(&counts[1], s_cnt[1]);
+            atomicAdd(&counts[2], s_cnt[2]);
         }
     }
 }

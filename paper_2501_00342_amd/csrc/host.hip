@@ -567,7 +567,7 @@ int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams, const
     hipStream_t s = static_cast<hipStream_t>(stream);
     const sgs::Workspace ws = bind(pl, const_cast<void*>(workspace));
     (void)hipGetLastError();
-    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 0u, 4, s);
+    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 0u, 6, s);
     sgs::launch_blend_count(ws, dev_cams, n_cams, pl.o, counts, s);
     SGS_LAUNCHED();
     return SGS_OK;

@@ -231,14 +231,14 @@ class Rasterizer:
         return loss, grad
 
     def blend_work(self, params: dict) -> tuple:
-        """(visited, evaluated) pixel-entry pairs of the last forward."""
-        counts = torch.zeros(2, dtype=torch.int64, device=self.device)
+        """(visited, evaluated, blended) pixel-entry pairs of the last forward."""
+        counts = torch.zeros(3, dtype=torch.int64, device=self.device)
         g = self._gstruct(params)
         L.check(L.LIB.render_blend_work(ctypes.byref(g), self.host_cams, _ptr(self.dev_cams),
                                         len(self.cams), ctypes.byref(self.copts), _ptr(self.ws),
                                         self.ws.numel(), self.capacity, _ptr(counts), _stream()))
         c = counts.cpu()
-        return int(c[0]), int(c[1])
+        return int(c[0]), int(c[1]), int(c[2])
 
     def status(self) -> tuple:
         bits, pairs = L.c_uint32(0), L.c_int64(0)
