@@ -166,9 +166,11 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
                 if (e.m.x & colbit) {
                     const float dx = lxf + e.a.x;
                     const float t1 = e.a.z * dx, t2 = e.b.x * dx;
+                    // bit k: pixel k still blends and lies in the splat's rows
+                    const uint32_t take = (e.m.y >> ry) & live;
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
-                        if (((live >> k) & 1u) && ((e.m.y >> (ry + k)) & 1u)) {
+                        if ((take >> k) & 1u) {
                             if (COUNT) ++evaluated;
                             const Eval v = eval_splat(e, t1, t2, (float)(ry + k) + e.a.y, amax);
                             if (!(v.alpha < amin)) {
