@@ -262,3 +262,67 @@ def test_packed_and_separate_colour_layouts_agree():
         scale = float(g1[k].abs().max()) + 1e-30
         assert float((g1[k] - g2[k]).abs().max()) <= 1e-5 * scale, k
 
+
+
+def _oracle_blend_work(pre, cam, opts, ref, ppt):
+    """The blend's work counters from the oracle's walk of every tile list:
+    thread visits (a thread owns `ppt` rows of one column and visits an entry
+    while one of its pixels still blends), evaluated (pixel, entry) pairs (the
+    pixel still blends and lies in the rectangle) and blended pairs (alpha at
+    least alpha_min and the pixel not stopped by the entry).  Also the slack a
+    tie-band decision allows: the list length of every flagged pixel."""
+    W, H = int(cam.width), int(cam.height)
+    tw, th = int(opts.tile_w), int(opts.tile_h)
+    GX, GY = pre.grid
+    amin, amax, tmin = F._f(opts.alpha_min), F._f(opts.alpha_max), F._f(opts.t_min)
+    visited = evaluated = blended = slack = 0
+    for t in range(GX * GY):
+        tx, ty = t % GX, t // GX
+        lo, hi = ref.ranges[t]
+        entries = ref.values[lo:hi].astype(np.int64)
+        px, py = F.tile_pixels(tx, ty, opts, W, H)
+        T = np.ones(px.size)
+        done = np.zeros(px.size, bool)
+        visits = np.full(px.size, len(entries), np.int64)   # entries seen while live
+        for j, g in enumerate(entries):
+            inr = ((px >= pre.rect[0, g]) & (px <= pre.rect[1, g])
+                   & (py >= pre.rect[2, g]) & (py <= pre.rect[3, g]))
+            evald = ~done & inr
+            a = F._alpha(pre, g, px - pre.u[g], py - pre.v[g], amax)
+            take = evald & (a >= amin)
+            Tn = T * (1.0 - a)
+            stop = take & (Tn < tmin)
+            blend = take & ~stop
+            evaluated += int(evald.sum())
+            blended += int(blend.sum())
+            visits[stop] = j + 1
+            done |= stop
+            T = np.where(blend, Tn, T)
+        flagged = ref.flagged[py, px]
+        slack += int(flagged.sum()) * len(entries)
+        # threads: column lx, rows (r // ppt) * ppt .. + ppt - 1 of the tile
+        lx = px - tx * tw
+        grp = (py - ty * th) // ppt
+        thread_visits = {}
+        for x, r, v in zip(lx, grp, visits):
+            thread_visits[(x, r)] = max(thread_visits.get((x, r), 0), int(v))
+        visited += sum(thread_visits.values())
+    return visited, evaluated, blended, slack
+
+
+@pytest.mark.parametrize("tw,th,ppt", [(16, 16, 2), (32, 8, 4)])
+def test_blend_work_counters_match_the_oracle_walk(tw, th, ppt):
+    """The counters behind the forward blend's roofline figure
+    (render_blend_work) against the same events counted along the oracle's
+    walk of the tile lists, on a ragged image."""
+    sc, cam = scenes.small_clustered(6000, 11, 200, 136)
+    opts = scenes.Options(tile_w=tw, tile_h=th, ppt=ppt)
+    rast, params, out = run_forward(sc, [cam], opts)
+    ref = F.render(sc, cam, opts)
+    pre = F.preprocess(sc, cam, opts)
+    got = rast.blend_work(params)
+    want = _oracle_blend_work(pre, cam, opts, ref, ppt)
+    slack = want[3]
+    for name, g, w in zip(("visited", "evaluated", "blended"), got, want[:3]):
+        assert abs(g - w) <= slack, (name, g, w, slack)
+    assert want[2] > 0 and want[1] >= want[2]
