@@ -1,0 +1,71 @@
+"""The benchmark's algorithmic-byte and lane-op accounting (CPU).
+
+The roofline fractions the benchmark reports are only as good as these
+per-stage byte counts; each is checked against the traffic of the passes as
+they are built (one 3M-Gaussian frame: 646,587 visible items, 29.6M pairs,
+6,700 tiles).
+"""
+import math
+
+import bench
+
+N, NVIS, P, TILES = 3_000_000, 646_587, 29_641_109, 6_700
+FPG_SG = 51             # 11 geometry floats + SH1 (12) + 4 lobes x 7
+GEOM = 11
+
+
+def test_geometry_floats():
+    assert bench.GEOM_FLOATS == GEOM
+
+
+def test_preprocess_bytes():
+    fc = FPG_SG - GEOM
+    want = N * 4 * GEOM + NVIS * 4 * fc + N * 12 + NVIS * 64
+    assert bench.stage_bytes("fwd.preprocess", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == want
+    # every parameter counted: the full record of every Gaussian
+    assert bench.stage_bytes_all_params("fwd.preprocess", N, N, NVIS, FPG_SG) == \
+        N * 4 * FPG_SG + 4 * N + 64 * NVIS
+
+
+def test_depth_sort_bytes_follow_the_passes():
+    # pass 0: N keys read twice (count, rank), visible (key, item) written
+    p0 = 4 * N + 4 * N + 8 * NVIS
+    # passes 1-2: keys read (count), (key, item) read and written
+    mid = 2 * (4 * NVIS + 8 * NVIS + 8 * NVIS)
+    # last: keys read, (key, item) and each item's rectangle read, then
+    # item, pair count and rectangle written
+    last = 4 * NVIS + 8 * NVIS + 8 * NVIS + 4 * NVIS + 4 * NVIS + 8 * NVIS
+    assert bench.stage_bytes("fwd.depth_sort", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == \
+        p0 + mid + last
+
+
+def test_scan_duplicate_and_tile_sort_bytes():
+    assert bench.stage_bytes("fwd.pair_scan", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == 12 * NVIS
+    assert bench.stage_bytes("fwd.duplicate", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == 16 * NVIS
+    # u16 tile keys (6,700 tiles): first pass writes (key, value) = 6 B per
+    # pair, the second reads keys (2), then reads and writes 6 B per pair
+    want = 16 * NVIS + 6 * P + (2 + 12) * P
+    assert bench.stage_bytes("fwd.tile_sort", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == want
+    # u32 keys beyond 65,536 tiles, three passes
+    want32 = 16 * NVIS + 8 * P + 2 * (4 + 16) * P
+    assert bench.stage_bytes("fwd.tile_sort", N, N, NVIS, NVIS, P, 100_000, FPG_SG, 3, 0) == want32
+
+
+def test_blends_have_no_byte_bound():
+    for st in ("fwd.blend", "bwd.blend", "fwd.tile_order"):
+        assert bench.stage_bytes(st, N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) is None
+
+
+def test_standard_binning_bytes():
+    # scan 8 N, duplicate 16 N_vis + 12 P, LSD sort of 8-bit digits over the
+    # low 32 + ceil(log2 tiles) key bits at 8 + 24 bytes per pair and pass,
+    # range search 8 P + 8 tiles
+    b, passes = bench.standard_binning_bytes(N, NVIS, P, TILES)
+    assert passes == math.ceil((32 + 13) / 8) == 6
+    assert b == 8 * N + 16 * NVIS + 12 * P + (8 + 24 * 6) * P + 8 * P + 8 * TILES
+
+
+def test_peaks():
+    assert bench.HBM_PEAK_GBS == 8000
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-packed lane-op per lane
+    assert abs(bench.VALU_PEAK_TOPS - 256 * 4 * 16 * 2.4e9 / 1e12) < 1e-9
