@@ -12,9 +12,13 @@
  *   - All array pointers marked "device" are HIP device pointers owned by the
  *     caller.  The library allocates no device memory: every buffer it needs
  *     lives in a caller-provided workspace sized by render_workspace_bytes().
- *   - Arrays are component-major (SoA): component c of Gaussian g is at
- *     [c * n + g].  SH coefficients are [(deg+1)^2][3][n], l-major then
- *     m = -l..l, channel (r,g,b) inside; lobe arrays are [K][3][n] or [K][n].
+ *   - Geometry arrays (means, log_scales, quats, opacity_logits) are
+ *     component-major (SoA): component c of Gaussian g is at [c * n + g].
+ *     Colour arrays are Gaussian-major: Gaussian g's block starts at
+ *     g * colour_stride floats (colour_stride 0 = packed), and inside it SH
+ *     coefficients are [(deg+1)^2][3] (l-major, then m = -l..l, then the
+ *     channel r, g, b), lobe axes and amplitudes [K][3], log-sharpness [K].
+ *     See struct sgs_gaussians.
  *   - Quaternions are (w, x, y, z).  Raw parameters cross the ABI; the
  *     library applies scale = exp(log_scale), opacity = sigmoid(logit),
  *     sharpness = exp(log_sharpness) and normalises q and each lobe axis.
@@ -24,7 +28,9 @@
  *     Real SH with the Condon-Shortley phase.  K = 0 with degree 3 is the
  *     plain degree-3 SH form (eq. 4).
  *   - Cameras: pinhole, OpenCV axes, x_cam = R x_world + t, pixel (i, j)
- *     sampled at integer coordinates (i, j).
+ *     sampled at integer coordinates (i, j).  znear, fx and fy must be
+ *     finite and > 0 (host cameras: SGS_E_INVALID; device cameras: status
+ *     bit SGS_STATUS_CAMERAS, and no image is written).
  *   - Several cameras render in one call ("batched views"): their pixels are
  *     packed camera after camera.  Camera k's image is the (3, H_k, W_k)
  *     block starting at float offset 3 * pix_base_k of `image`, and its
@@ -67,7 +73,11 @@ typedef enum sgs_status {
  * colour_stride = 3 (deg+1)^2 + 7 K and the four arrays at offsets 0,
  * 3 (deg+1)^2, 3 (deg+1)^2 + 3 K and 3 (deg+1)^2 + 4 K of one buffer, a
  * Gaussian's whole colour is one contiguous record, which the rasteriser
- * fetches with the fewest cache lines. */
+ * fetches with the fewest cache lines (there, with colour_stride a multiple
+ * of 4, the record may be read rounded up to whole 16-byte pieces: the
+ * buffer must then span n * colour_stride floats from `sh`).  The axis
+ * block holds A 3-vectors: A = K (free lobes), 1 (frame) or 0 (world);
+ * record offsets then read 3 (deg+1)^2 + 3 A etc. in place of 3 K. */
 typedef struct sgs_gaussians {
     int64_t n;
     int32_t sh_degree;               /* 0..3 */
@@ -77,13 +87,35 @@ typedef struct sgs_gaussians {
     const float* quats;              /* [4][n]   rotation q, (w,x,y,z) (eq. 3)     */
     const float* opacity_logits;     /* [n]      logit of opacity sigma            */
     const float* sh;                 /* [n][(deg+1)^2][3] SH coefficients (eq. 4)  */
-    const float* sg_axes;            /* [n][K][3] lobe axis mu, any length (eq. 5) */
+    const float* sg_axes;            /* [n][A][3] lobe axis mu, any length (eq. 5), or the
+                                        frame parameters (lobe_axes below) */
     const float* sg_log_sharpness;   /* [n][K]   log of lobe sharpness lambda      */
     const float* sg_amplitudes;      /* [n][K][3] lobe RGB amplitude alpha          */
     int64_t colour_stride;           /* floats between consecutive blocks of each colour
                                         array; 0 = packed; else >= every block size and a
                                         multiple of 4 gives 16-byte fetches */
+    int32_t lobe_axes;               /* how the lobe axes are given (SGS_LOBES_*):
+                                        FREE  sg_axes [n][K][3], one axis per lobe (eq. 5);
+                                        WORLD K = 3 lobes on the fixed world axes (1,0,0),
+                                              (0,1,0), (0,0,1); sg_axes unused, may be NULL
+                                              (eqs. 7-8; Experiments, Implementation);
+                                        FRAME K = 3 mutually orthogonal lobes on the columns
+                                              of the rotation of the unit quaternion
+                                              (1, w)/|(1, w)|, sg_axes [n][1][3] holding w
+                                              (eq. 8; Methods, Multi-Axis Orthogonal
+                                              Gaussians: 3 parameters for the frame) */
+    int32_t sh_adaptive[2];          /* adaptive SH degree by projected radius r (pixels,
+                                        the 3-sigma radius): degree 0 where r <= [0], at
+                                        most 1 where r <= [1], else sh_degree (Methods,
+                                        Mixing Spherical Harmonics and Spherical
+                                        Gaussians).  {0, 0} = every Gaussian uses
+                                        sh_degree; else 0 <= [0] <= [1]. */
+    int32_t reserved;                /* must be 0 */
 } sgs_gaussians;
+
+#define SGS_LOBES_FREE 0
+#define SGS_LOBES_WORLD 1
+#define SGS_LOBES_FRAME 2
 
 /* Gradient outputs, same shapes as sgs_gaussians (device, float32), every
  * array packed (the colour arrays Gaussian-major with colour_stride 0).
@@ -165,14 +197,16 @@ typedef struct sgs_layout {
 } sgs_layout;
 
 #define SGS_STATUS_CAPACITY 1u   /* header[0] bit: P exceeded pair_capacity; pairs truncated */
-#define SGS_STATUS_CAMERAS  2u   /* header[0] bit: device cameras disagree with host sizes */
+#define SGS_STATUS_CAMERAS  2u   /* header[0] bit: a device camera is invalid or disagrees
+                                    with the host cameras' sizes; the blends write nothing */
 
 #define SGS_FLAG_CHECK_CAPACITY 1 /* render_forward: read P on the host after binning */
 
 /*
  * render_workspace_bytes / render_layout
  *   Size (and section offsets) of the workspace for n Gaussians, the given
- *   host cameras (only width/height are read) and options, holding up to
+ *   host cameras (sizes fix the layout; znear, fx, fy are validated) and
+ *   options, holding up to
  *   pair_capacity (tile, Gaussian) pairs (< 2^30).  Returns 0 (or
  *   SGS_E_INVALID from render_layout) on invalid arguments.
  */
@@ -210,11 +244,23 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams,
 
 /*
  * render_backward — gradients of a scalar loss L w.r.t. every raw
- * parameter, given dL/dimage (device, packed like `image`).  Walks each
- * tile back to front from the saved final transmittance, recomputing each
- * alpha, then applies the chain rule through the preprocess.  Arguments as
- * render_forward; `workspace` and `fwd` must be those of the matching
- * forward (same g, cameras, options, capacity).  Depth has no gradient.
+ * parameter, given dL/dimage (device, packed like `image`): the exact
+ * derivative of what render_forward computes.  Paper: Preliminaries (the
+ * front-to-back compositing C = sum_i c_i a_i prod_{j<i} (1 - a_j) over the
+ * depth-sorted splats, a_i from the EWA-projected density of eqs. 2-3),
+ * and the colour model of eqs. 4-9 (SH basis, SG lobes a exp(lambda (d.mu
+ * - 1)), their sum).  Walks each tile back to front from the saved final
+ * transmittance and contributor count, recomputing each alpha, reduces the
+ * nine 2D gradients per splat (mean, conic, opacity, rgb), then applies the
+ * chain rule through the preprocess to the raw parameters (means through
+ * the projection, the EWA Jacobian and the view direction; log-scales and
+ * the quaternion through Sigma = R S S^T R^T; the opacity logit; SH
+ * coefficients; lobe axes through their normalisation, log-sharpness and
+ * amplitudes).  Arguments as render_forward; `workspace` and `fwd` must be
+ * those of the matching forward (same g, cameras, options, capacity) and
+ * untouched since.  `grads`: every array is overwritten (packed layout).
+ * Depth has no gradient.  Returns SGS_E_INVALID on a NULL required pointer
+ * or a too-small workspace; otherwise enqueues and returns SGS_OK.
  */
 int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams,
                     const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,

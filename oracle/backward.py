@@ -160,15 +160,18 @@ def preprocess_backward(scene, cam, opts, pre, g2):
     grgb = np.stack([g2["r"], g2["g"], g2["b"]]) * (pre.rgb_raw >= 0.0)
     d = pre.dirs
     nc = (scene.sh_degree + 1) ** 2
-    Y = sh_basis(scene.sh_degree, d)
-    dY = sh_basis_grad(scene.sh_degree, d)
+    # adaptive SH: coefficients above a Gaussian's degree take no part
+    mask = R.sh_mask(scene, R.sh_degrees(scene, pre.radius))
+    Y = sh_basis(scene.sh_degree, d) * mask
+    dY = sh_basis_grad(scene.sh_degree, d) * mask[:, None, :]
     sh = scene.sh.astype(F64)
     out["sh"][:nc] = grgb[None, :, :] * Y[:, None, :]
     g_dir = np.einsum("cn,lcn,lkn->kn", grgb, sh[:nc], dY)
+    mode = getattr(scene, "lobe_mode", R.LOBES_FREE)
+    mu_all = R.lobe_axes(scene)
+    g_mus = []
     for k in range(scene.n_lobes):
-        mu_raw = scene.sg_axes[k].astype(F64)
-        mlen = np.sqrt((mu_raw * mu_raw).sum(axis=0))
-        mu = mu_raw / mlen
+        mu = mu_all[k]
         lam = np.exp(scene.sg_log_sharpness[k].astype(F64))
         cosv = (d * mu).sum(axis=0)
         e = np.where(cosv - 1.0 == 0.0, 1.0, np.exp(lam * (cosv - 1.0)))
@@ -176,9 +179,24 @@ def preprocess_backward(scene, cam, opts, pre, g2):
         out["sg_amplitudes"][k] = grgb * e
         s = (grgb * amp).sum(axis=0) * e
         out["sg_log_sharpness"][k] = s * (cosv - 1.0) * lam
-        g_mu = s * lam * d
-        out["sg_axes"][k] = (g_mu - mu * (mu * g_mu).sum(axis=0)) / mlen
+        g_mu = s * lam * d                       # w.r.t. the unit axis mu_k
+        if mode == R.LOBES_FREE:
+            mu_raw = scene.sg_axes[k].astype(F64)
+            mlen = np.sqrt((mu_raw * mu_raw).sum(axis=0))
+            out["sg_axes"][k] = (g_mu - mu * (mu * g_mu).sum(axis=0)) / mlen
+        g_mus.append(g_mu)
         g_dir = g_dir + s * lam * mu
+    if mode == R.LOBES_FRAME and scene.n_lobes:
+        # mu_k is column k of R(q_hat), q = (1, omega): dL/dR[i][k] = dL/dmu_k[i],
+        # then the rotation's quaternion gradient, the normalisation of q,
+        # and the three free components of q
+        q, qn = R.frame_quaternion(scene.sg_axes[0])
+        qh = q / qn
+        gRf = [[g_mus[k][i] if k < len(g_mus) else 0.0 * qn for k in range(3)]
+               for i in range(3)]
+        gqh = np.array(_quat_rotation_grad(*qh, gRf))
+        gq = (gqh - qh * (qh * gqh).sum(axis=0)) / qn
+        out["sg_axes"][0] = gq[1:4]
     gX = (g_dir - d * (d * g_dir).sum(axis=0)) / pre.dist
 
     # conic -> Sigma' = [[A, B], [B, C]]
@@ -279,7 +297,8 @@ def signature(scene, cam, opts, target):
     img = R.render(scene, cam, opts)
     W, H = int(cam.width), int(cam.height)
     amax = R._f(opts.alpha_max)
-    parts = [pre.visible.tobytes(), pre.rect.tobytes(), pre.xclamp.tobytes(),
+    parts = [pre.visible.tobytes(), pre.rect.tobytes(), pre.radius.tobytes(),
+             pre.xclamp.tobytes(),
              pre.yclamp.tobytes(), (pre.rgb_raw >= 0).tobytes(),
              img.n_contrib.tobytes(), img.values.tobytes(), img.ranges.tobytes(),
              np.sign(img.image - target).tobytes()]

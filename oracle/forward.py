@@ -106,15 +106,73 @@ def camera_centre(cam) -> np.ndarray:
     return np.array([-((R[0, j] * t[0] + R[1, j] * t[1]) + R[2, j] * t[2]) for j in range(3)])
 
 
-def colour(scene, dirs):
-    """rgb_raw = 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1))  (eq. 9, R4)."""
+LOBES_FREE, LOBES_WORLD, LOBES_FRAME = 0, 1, 2
+
+
+def frame_quaternion(omega):
+    """Unit quaternion of the orthonormal lobe frame from its 3 parameters
+    omega (3,N): q = (1, omega) / |(1, omega)|, i.e. the rotation whose
+    Gibbs (Cayley) vector is omega.  Every rotation but the half-turns is
+    reached, and the map is smooth everywhere (|q| >= 1)."""
+    w = np.asarray(omega, F64)
+    q = np.stack([np.ones(w.shape[1]), w[0], w[1], w[2]])
+    return q, np.sqrt((q * q).sum(axis=0))
+
+
+def lobe_axes(scene):
+    """Unit lobe axes mu_k, (K, 3, N), by the scene's lobe mode.
+
+    free : each lobe's own axis, normalised (eq. 5's mu).
+    world: the paper's fixed orthogonal axes (1,0,0), (0,1,0), (0,0,1)
+           (Experiments, Implementation; eqs. 7-8).
+    frame: the columns of a rotation R(q) with q from 3 parameters per
+           Gaussian (Methods, Multi-Axis Orthogonal Gaussians: three
+           orthogonal lobes need 3 extra parameters for their directions;
+           eq. 8 holds by construction)."""
+    n, K = scene.n, scene.n_lobes
+    mode = getattr(scene, "lobe_mode", LOBES_FREE)
+    if mode == LOBES_FREE:
+        mu = scene.sg_axes.astype(F64)
+        return mu / np.sqrt((mu * mu).sum(axis=1, keepdims=True))
+    if mode == LOBES_WORLD:
+        return np.broadcast_to(np.eye(3)[:K, :, None], (K, 3, n)).astype(F64)
+    q, qn = frame_quaternion(scene.sg_axes[0])
+    Rq = quat_to_rotation(*(q / qn))
+    return np.array([[Rq[i][k] for i in range(3)] for k in range(K)])
+
+
+def sh_degrees(scene, radius):
+    """SH degree used by each Gaussian (N,): sh_degree, or with adaptive
+    thresholds (t0, t1) on the projected radius r: 0 where r <= t0, at most
+    1 where r <= t1, sh_degree above (Methods, Mixing Spherical Harmonics
+    and Spherical Gaussians: degree 0-2 chosen by the size of the 2D
+    projection, large Gaussians degree 2)."""
+    L = scene.sh_degree
+    t0, t1 = tuple(getattr(scene, "sh_adaptive", (0, 0)))
+    deg = np.full(scene.n, L, np.int64)
+    if t0 > 0 and radius is not None:
+        r = np.asarray(radius)
+        deg = np.where(r <= t1, np.minimum(1, L), deg)
+        deg = np.where(r <= t0, 0, deg)
+    return deg
+
+
+def sh_mask(scene, deg):
+    """(NC, N) 1 where coefficient l is used (l < (deg + 1)^2), else 0."""
     nc = (scene.sh_degree + 1) ** 2
-    Y = sh_basis(scene.sh_degree, dirs)                         # (nc, N)
+    return (np.arange(nc)[:, None] < (deg[None, :] + 1) ** 2).astype(F64)
+
+
+def colour(scene, dirs, radius=None):
+    """rgb_raw = 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1))  (eq. 9, R4);
+    with adaptive SH, coefficients above a Gaussian's degree are unused."""
+    Y = sh_basis(scene.sh_degree, dirs) * sh_mask(scene, sh_degrees(scene, radius))
+    nc = Y.shape[0]
     sh = scene.sh.astype(F64)
     raw = 0.5 + np.einsum("lcn,ln->cn", sh[:nc], Y)
+    mu_all = lobe_axes(scene)
     for k in range(scene.n_lobes):
-        mu = scene.sg_axes[k].astype(F64)
-        mu = mu / np.sqrt((mu * mu).sum(axis=0))
+        mu = mu_all[k]
         lam = np.exp(scene.sg_log_sharpness[k].astype(F64))
         t = (dirs * mu).sum(axis=0) - 1.0
         # eq. 5; along the axis (t = 0) the lobe is 1 for any sharpness
@@ -124,8 +182,11 @@ def colour(scene, dirs):
 
 
 def zero_axis(scene) -> np.ndarray:
-    """Gaussians with a lobe axis of zero length (no direction to normalise)."""
+    """Gaussians with a free lobe axis of zero length (no direction to
+    normalise; the orthogonal modes have none)."""
     bad = np.zeros(scene.n, bool)
+    if getattr(scene, "lobe_mode", LOBES_FREE) != LOBES_FREE:
+        return bad
     for k in range(scene.n_lobes):
         a = scene.sg_axes[k].astype(F64)
         bad |= (a * a).sum(axis=0) == 0.0
@@ -200,7 +261,7 @@ def preprocess(scene, cam, opts) -> Pre:
         dvec = X - cc[:, None]
         dist = np.sqrt((dvec * dvec).sum(axis=0))
         dirs = dvec / dist
-        rgb_raw = colour(scene, dirs)
+        rgb_raw = colour(scene, dirs, radius)
         opacity = 1.0 / (1.0 + np.exp(-scene.opacity_logits.astype(F64)))
 
     finite = (_finite_params(scene) & ~zero_axis(scene) & np.isfinite(A) & np.isfinite(B)

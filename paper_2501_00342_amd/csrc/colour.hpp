@@ -11,38 +11,95 @@ namespace sgs {
 
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
+// Unit lobe axes of the orthogonal modes.  FRAME: the columns of the
+// rotation of the unit quaternion (1, w) / |(1, w)| built from the three
+// frame parameters w (so the three axes are orthonormal by construction,
+// eq. 8); *iq receives 1 / |(1, w)|.
+__device__ __forceinline__ void frame_rotation(float w0, float w1, float w2, float r[3][3],
+                                               float* iq) {
+    const float n2 = 1.0f + w0 * w0 + w1 * w1 + w2 * w2;
+    const float i = rsqrtf(n2);
+    const float w = i, x = w0 * i, y = w1 * i, z = w2 * i;
+    r[0][0] = 1.0f - 2.0f * (y * y + z * z);
+    r[0][1] = 2.0f * (x * y - w * z);
+    r[0][2] = 2.0f * (x * z + w * y);
+    r[1][0] = 2.0f * (x * y + w * z);
+    r[1][1] = 1.0f - 2.0f * (x * x + z * z);
+    r[1][2] = 2.0f * (y * z - w * x);
+    r[2][0] = 2.0f * (x * z - w * y);
+    r[2][1] = 2.0f * (y * z + w * x);
+    r[2][2] = 1.0f - 2.0f * (x * x + y * y);
+    *iq = i;
+}
+
+// Number of axis 3-vectors per Gaussian in sg_axes for a lobe mode.
+template <int LM, int KMAX>
+struct AxisRows {
+    static constexpr int value = LM == kLobesFree ? KMAX : (LM == kLobesFrame ? 1 : 0);
+};
+
+// SH coefficients used at projected radius r: (deg + 1)^2 with deg = 0 where
+// r <= t0, at most 1 where r <= t1, else the stored degree (both thresholds
+// 0: the stored degree everywhere).
+template <int DEG>
+__device__ __forceinline__ int sh_used(const Params& p, int radius) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    if ((p.sh_ad0 | p.sh_ad1) == 0) return NC;
+    if (radius <= p.sh_ad0) return 1;
+    if (radius <= p.sh_ad1) return DEG >= 1 ? 4 : 1;
+    return NC;
+}
+
 // colour of eq. 9 in float32: 0.5 + SH(d) + sum_k a_k exp(lambda_k (d.mu_k - 1)),
-// reading the parameters through accessors: sh(l, c), axis(k, j),
-// lsh(k) (log-sharpness) and amp(k, c).  Returns false when a colour
-// parameter is non-finite or a lobe axis has zero length (the Gaussian is
-// culled).  KMAX >= n_lobes bounds the unrolled lobe loop.
-template <int DEG, int KMAX, typename SH, typename AX, typename LS, typename AM>
-__device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int n_lobes, float d0,
-                                            float d1, float d2, float rgb[3]) {
+// reading the parameters through accessors: sh(l, c), axis(k, j) (lobe k's
+// free axis, or the frame parameters as axis(0, j)), lsh(k)
+// (log-sharpness) and amp(k, c).  Only the first `ncu` SH coefficients are
+// used (adaptive degree).  Returns false when a colour parameter is
+// non-finite or a free lobe axis has zero length (the Gaussian is culled).
+// KMAX >= n_lobes bounds the unrolled lobe loop; LM is the lobe mode.
+template <int DEG, int KMAX, int LM, typename SH, typename AX, typename LS, typename AM>
+__device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int n_lobes, int ncu,
+                                            float d0, float d1, float d2, float rgb[3]) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     bool ok = true;
     float Y[NC];
     sh_eval<DEG, float>(d0, d1, d2, Y);
     rgb[0] = rgb[1] = rgb[2] = 0.5f;
 #pragma unroll
-    for (int l = 0; l < NC; ++l)
+    for (int l = 0; l < NC; ++l) {
+        const float y = l < ncu ? Y[l] : 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float f = sh(l, c);
             ok = ok && isfinite(f);
-            rgb[c] = fmaf(f, Y[l], rgb[c]);
+            rgb[c] = fmaf(f, y, rgb[c]);
         }
+    }
+    float fr[3][3];
+    if constexpr (LM == kLobesFrame) {
+        const float w0 = axis(0, 0), w1 = axis(0, 1), w2 = axis(0, 2);
+        ok = ok && isfinite(w0) && isfinite(w1) && isfinite(w2);
+        float iq;
+        frame_rotation(w0, w1, w2, fr, &iq);
+    }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         if (k >= n_lobes) break;
-        const float m0 = axis(k, 0), m1 = axis(k, 1), m2 = axis(k, 2);
         const float ls = lsh(k);
         const float a0 = amp(k, 0), a1 = amp(k, 1), a2 = amp(k, 2);
-        ok = ok && isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(ls) &&
-             isfinite(a0) && isfinite(a1) && isfinite(a2);
-        const float mn2 = m0 * m0 + m1 * m1 + m2 * m2;
-        ok = ok && mn2 > 0.0f;
-        const float t = (d0 * m0 + d1 * m1 + d2 * m2) * rsqrtf(mn2) - 1.0f;
+        ok = ok && isfinite(ls) && isfinite(a0) && isfinite(a1) && isfinite(a2);
+        float t;
+        if constexpr (LM == kLobesFree) {
+            const float m0 = axis(k, 0), m1 = axis(k, 1), m2 = axis(k, 2);
+            ok = ok && isfinite(m0) && isfinite(m1) && isfinite(m2);
+            const float mn2 = m0 * m0 + m1 * m1 + m2 * m2;
+            ok = ok && mn2 > 0.0f;
+            t = (d0 * m0 + d1 * m1 + d2 * m2) * rsqrtf(mn2) - 1.0f;
+        } else if constexpr (LM == kLobesWorld) {
+            t = (k == 0 ? d0 : (k == 1 ? d1 : d2)) - 1.0f;
+        } else {
+            t = (d0 * fr[0][k] + d1 * fr[1][k] + d2 * fr[2][k]) - 1.0f;
+        }
         const float e = t == 0.0f ? 1.0f : fast_exp(fast_exp(ls) * t);
         rgb[0] = fmaf(a0, e, rgb[0]);
         rgb[1] = fmaf(a1, e, rgb[1]);
@@ -51,25 +108,27 @@ __device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int 
     return ok;
 }
 
-// Colour record of a Gaussian: its colour coefficients in the row order
-// SH coefficient (l, c) at 3 l + c, then per lobe k the axis at
-// 3 NC + 3 k + j, the log-sharpness at 3 NC + 3 K + k and the amplitudes at
-// 3 NC + 4 K + 3 k + c: 3 NC + 7 K floats.  The global arrays are
+// Colour record of a Gaussian: its colour coefficients in the order SH
+// coefficient (l, c) at 3 l + c, then the axis rows (A 3-vectors: one per
+// free lobe, the three frame parameters, or none on the world axes) at
+// 3 NC + 3 a + j, the log-sharpness at 3 NC + 3 A + k and the amplitudes
+// at 3 NC + 3 A + K + 3 k + c: 3 NC + 3 A + 4 K floats (p.rec_floats, which
+// rounds that up to whole 16-byte pieces when the four arrays interleave in
+// one buffer whose stride leaves room).  The global arrays are
 // Gaussian-major (block g of each at g times its stride p.cs_*), so a
 // record is the concatenation of one contiguous block from each array (one
-// run of memory when the four arrays interleave with a common stride).
-__device__ __forceinline__ int colour_record_floats(int nc3, int K) { return nc3 + 7 * K; }
-
+// run of memory when they interleave).
+//
 // Cooperative gather of colour records into LDS for the lanes of this wave
 // that set `fetch`: the j-th of them (in lane order) gets record slot
-// slot0 + j of `rec` (records of colour_record_floats() floats, back to back)
-// and learns its slot in *slot.  Consecutive lanes of each direct
-// global->LDS load fetch consecutive 16-byte pieces (4-byte pieces when a
-// block is not a whole number of 16-byte pieces) of the same Gaussian's
-// blocks, so one instruction covers several Gaussians' contiguous blocks
-// rather than one float of each of 64 Gaussians.  s_g: 64 entries of the
-// wave's LDS.  Returns how many lanes fetched (wave-uniform); the caller
-// waits (s_waitcnt) before reading the records.
+// slot0 + j of `rec` (records of p.rec_floats floats, back to back) and
+// learns its slot in *slot.  Consecutive lanes of each direct global->LDS
+// load fetch consecutive 16-byte pieces (4-byte pieces when a block is not
+// a whole number of 16-byte pieces) of the same Gaussian's blocks, so one
+// instruction covers several Gaussians' contiguous blocks rather than one
+// float of each of 64 Gaussians.  s_g: 64 entries of the wave's LDS.
+// Returns how many lanes fetched (wave-uniform); the caller waits
+// (s_waitcnt) before reading the records.
 template <int NC3>
 __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fetch, int slot0,
                                              float* rec, int64_t* s_g, int* slot) {
@@ -83,17 +142,31 @@ __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fe
         s_g[rank] = g;   // read back below by other lanes of this wave (LDS order)
         *slot = slot0 + rank;
     }
-    const int K = p.n_lobes;
-    const bool v4 = (NC3 % 4 == 0) && (K % 4 == 0) &&
-                    ((p.cs_sh | p.cs_ax | p.cs_ls | p.cs_am) & 3) == 0 &&
-                    (((uintptr_t)p.sh | (uintptr_t)p.sg_axes | (uintptr_t)p.sg_log_sharpness |
-                      (uintptr_t)p.sg_amplitudes) & 15u) == 0;
+    const int K = p.n_lobes, A = p.n_axes;
+    const int RSF = p.rec_floats;
+    float* base = rec + slot0 * RSF;
+    bool v4;
+    int q_sh, q_ax, q_ls, Q;
+    if (p.contig) {
+        // one run of RSF floats per Gaussian
+        v4 = (RSF % 4 == 0) && (p.cs_sh % 4 == 0) && (((uintptr_t)p.sh) & 15u) == 0;
+        q_sh = RSF / (v4 ? 4 : 1);
+        q_ax = q_ls = 0;
+        Q = q_sh;
+    } else {
+        v4 = (NC3 % 4 == 0) && ((3 * A) % 4 == 0) && (K % 4 == 0) &&
+             ((p.cs_sh | p.cs_ax | p.cs_ls | p.cs_am) & 3) == 0 &&
+             (((uintptr_t)p.sh | (uintptr_t)p.sg_axes | (uintptr_t)p.sg_log_sharpness |
+               (uintptr_t)p.sg_amplitudes) & 15u) == 0;
+        const int w = v4 ? 4 : 1;
+        q_sh = NC3 / w;
+        q_ax = 3 * A / w;
+        q_ls = K / w;
+        Q = q_sh + q_ax + q_ls + 3 * K / w;   // pieces per record
+    }
     const int wdt = v4 ? 4 : 1;   // floats per piece
-    const int q_sh = NC3 / wdt, q_ax = 3 * K / wdt, q_ls = K / wdt;
-    const int Q = q_sh + 2 * q_ax + q_ls;   // pieces per record
     const float invQ = 1.0f / (float)Q;
     const int total = m * Q;
-    float* base = rec + slot0 * colour_record_floats(NC3, K);
     for (int P0 = 0; P0 < total; P0 += 64) {
         const int P = P0 + lane;
         const bool on = P < total;
@@ -141,15 +214,18 @@ __device__ __forceinline__ void view_dir(const double X[3], const sgs_camera& ca
 // Backward of the colour.  grgb: dL/d(clamped rgb).  Adds the parameter
 // gradients into the accumulators and returns dL/dd (the view direction,
 // before the normalisation Jacobian).  Parameters are read through the same
-// accessors as colour_eval.
-template <int DEG, int KMAX, typename SH, typename AX, typename LS, typename AM>
+// accessors as colour_eval.  gax: per free lobe, its axis gradient; in the
+// frame mode gax[0] receives the gradient of the three frame parameters;
+// untouched on the world axes.
+template <int DEG, int KMAX, int LM, typename SH, typename AX, typename LS, typename AM>
 __device__ __forceinline__ void colour_bwd_eval(SH sh, AX axis, LS lsh, AM amp, int n_lobes,
-                                                float d0, float d1, float d2, const float grgb[3],
-                                                float gsh[][3], float gamp[][3], float gax[][3],
-                                                float glsh[], float gd[3]) {
+                                                int ncu, float d0, float d1, float d2,
+                                                const float grgb[3], float gsh[][3],
+                                                float gamp[][3], float gax[][3], float glsh[],
+                                                float gd[3]) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     float raw[3];
-    colour_eval<DEG, KMAX>(sh, axis, lsh, amp, n_lobes, d0, d1, d2, raw);
+    colour_eval<DEG, KMAX, LM>(sh, axis, lsh, amp, n_lobes, ncu, d0, d1, d2, raw);
     // max(0, .): derivative 1 where the raw colour is >= 0
     const float gc[3] = {raw[0] >= 0.0f ? grgb[0] : 0.0f, raw[1] >= 0.0f ? grgb[1] : 0.0f,
                          raw[2] >= 0.0f ? grgb[2] : 0.0f};
@@ -159,6 +235,7 @@ __device__ __forceinline__ void colour_bwd_eval(SH sh, AX axis, LS lsh, AM amp, 
     gd[0] = gd[1] = gd[2] = 0.0f;
 #pragma unroll
     for (int l = 0; l < NC; ++l) {
+        if (l >= ncu) break;   // unused coefficients: zero gradient, no direction term
         float cl = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -169,14 +246,32 @@ __device__ __forceinline__ void colour_bwd_eval(SH sh, AX axis, LS lsh, AM amp, 
         gd[1] = fmaf(cl, gy[l], gd[1]);
         gd[2] = fmaf(cl, gz[l], gd[2]);
     }
+    float fr[3][3], iq = 1.0f;
+    float gfr[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    if constexpr (LM == kLobesFrame) frame_rotation(axis(0, 0), axis(0, 1), axis(0, 2), fr, &iq);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         if (k >= n_lobes) break;
-        const float m0 = axis(k, 0), m1 = axis(k, 1), m2 = axis(k, 2);
-        const float imn = rsqrtf(m0 * m0 + m1 * m1 + m2 * m2);
-        const float mu0 = m0 * imn, mu1 = m1 * imn, mu2 = m2 * imn;
+        float mu0, mu1, mu2, t, imn = 1.0f;
+        if constexpr (LM == kLobesFree) {
+            const float m0 = axis(k, 0), m1 = axis(k, 1), m2 = axis(k, 2);
+            imn = rsqrtf(m0 * m0 + m1 * m1 + m2 * m2);
+            mu0 = m0 * imn;
+            mu1 = m1 * imn;
+            mu2 = m2 * imn;
+            t = (d0 * m0 + d1 * m1 + d2 * m2) * imn - 1.0f;
+        } else if constexpr (LM == kLobesWorld) {
+            mu0 = k == 0 ? 1.0f : 0.0f;
+            mu1 = k == 1 ? 1.0f : 0.0f;
+            mu2 = k == 2 ? 1.0f : 0.0f;
+            t = (k == 0 ? d0 : (k == 1 ? d1 : d2)) - 1.0f;
+        } else {
+            mu0 = fr[0][k];
+            mu1 = fr[1][k];
+            mu2 = fr[2][k];
+            t = (d0 * mu0 + d1 * mu1 + d2 * mu2) - 1.0f;
+        }
         const float lam = fast_exp(lsh(k));
-        const float t = (d0 * m0 + d1 * m1 + d2 * m2) * imn - 1.0f;
         const float e = t == 0.0f ? 1.0f : fast_exp(lam * t);
         float sk = 0.0f;
 #pragma unroll
@@ -186,15 +281,41 @@ __device__ __forceinline__ void colour_bwd_eval(SH sh, AX axis, LS lsh, AM amp, 
         }
         sk *= e;
         glsh[k] = fmaf(sk * t, lam, glsh[k]);
-        // d/dmu_hat = sk lam d, then (I - mu mu^T) / |m|
+        // d/dmu_hat = sk lam d
         const float sl = sk * lam;
-        const float dot = sl * (mu0 * d0 + mu1 * d1 + mu2 * d2);
-        gax[k][0] += (sl * d0 - mu0 * dot) * imn;
-        gax[k][1] += (sl * d1 - mu1 * dot) * imn;
-        gax[k][2] += (sl * d2 - mu2 * dot) * imn;
+        if constexpr (LM == kLobesFree) {
+            // then (I - mu mu^T) / |m|
+            const float dot = sl * (mu0 * d0 + mu1 * d1 + mu2 * d2);
+            gax[k][0] += (sl * d0 - mu0 * dot) * imn;
+            gax[k][1] += (sl * d1 - mu1 * dot) * imn;
+            gax[k][2] += (sl * d2 - mu2 * dot) * imn;
+        } else if constexpr (LM == kLobesFrame) {
+            // mu_k is column k of the frame rotation
+            gfr[0][k] += sl * d0;
+            gfr[1][k] += sl * d1;
+            gfr[2][k] += sl * d2;
+        }
         gd[0] = fmaf(sl, mu0, gd[0]);
         gd[1] = fmaf(sl, mu1, gd[1]);
         gd[2] = fmaf(sl, mu2, gd[2]);
+    }
+    if constexpr (LM == kLobesFrame) {
+        // rotation entries -> unit quaternion (w, x, y, z) -> q = (1, w0, w1, w2)
+        // through the normalisation (I - q_hat q_hat^T) / |q|; keep x, y, z
+        const float w = iq, x = axis(0, 0) * iq, y = axis(0, 1) * iq, z = axis(0, 2) * iq;
+        const float (*g)[3] = gfr;
+        const float gw = 2.0f * (-z * g[0][1] + y * g[0][2] + z * g[1][0] - x * g[1][2] -
+                                 y * g[2][0] + x * g[2][1]);
+        const float gx_ = 2.0f * (y * g[0][1] + z * g[0][2] + y * g[1][0] - 2.0f * x * g[1][1] -
+                                  w * g[1][2] + z * g[2][0] + w * g[2][1] - 2.0f * x * g[2][2]);
+        const float gy_ = 2.0f * (-2.0f * y * g[0][0] + x * g[0][1] + w * g[0][2] + x * g[1][0] +
+                                  z * g[1][2] - w * g[2][0] + z * g[2][1] - 2.0f * y * g[2][2]);
+        const float gz_ = 2.0f * (-2.0f * z * g[0][0] - w * g[0][1] + x * g[0][2] + w * g[1][0] -
+                                  2.0f * z * g[1][1] + y * g[1][2] + x * g[2][0] + y * g[2][1]);
+        const float dq = w * gw + x * gx_ + y * gy_ + z * gz_;
+        gax[0][0] += (gx_ - x * dq) * iq;
+        gax[0][1] += (gy_ - y * dq) * iq;
+        gax[0][2] += (gz_ - z * dq) * iq;
     }
 }
 

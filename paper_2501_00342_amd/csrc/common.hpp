@@ -75,9 +75,21 @@ struct Opts {
     float dilation, guard, alpha_min, alpha_max, t_min;
 };
 
+// lobe axis modes (sgs_gaussians.lobe_axes)
+enum LobeMode : int { kLobesFree = SGS_LOBES_FREE, kLobesWorld = SGS_LOBES_WORLD, kLobesFrame = SGS_LOBES_FRAME };
+
 struct Params {
     int64_t n;
     int sh_degree, n_lobes;
+    int lobe_mode;          // LobeMode
+    int n_axes;             // 3-vectors per Gaussian in sg_axes: K (free), 0 (world), 1 (frame)
+    int sh_ad0, sh_ad1;     // adaptive SH radius thresholds; both 0 = fixed degree
+    // the four colour arrays interleave in one buffer with a common stride
+    // (Gaussian g's colour is one run of rec_floats at sh + g * cs_sh);
+    // rec_floats may round the record up to whole 16-byte pieces when the
+    // stride leaves room
+    bool contig;
+    int rec_floats;
     const float* means;
     const float* log_scales;
     const float* quats;

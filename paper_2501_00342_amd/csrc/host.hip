@@ -1,6 +1,8 @@
 // C-ABI entry points: argument checks, workspace layout, launch sequence.
 #include <string.h>
 
+#include <cmath>
+
 #include <array>
 #include <string>
 #include <vector>
@@ -64,6 +66,14 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
         return fail(SGS_E_INVALID, "sh_degree must be 0..3");
     if (g->n_lobes < 0 || g->n_lobes > SGS_MAX_LOBES)
         return fail(SGS_E_INVALID, "n_lobes must be 0..8");
+    if (g->lobe_axes != SGS_LOBES_FREE && g->lobe_axes != SGS_LOBES_WORLD &&
+        g->lobe_axes != SGS_LOBES_FRAME)
+        return fail(SGS_E_INVALID, "lobe_axes must be SGS_LOBES_FREE, _WORLD or _FRAME");
+    if (g->lobe_axes != SGS_LOBES_FREE && g->n_lobes != 3)
+        return fail(SGS_E_INVALID, "the orthogonal lobe modes take exactly 3 lobes");
+    if (g->sh_adaptive[0] < 0 || g->sh_adaptive[1] < g->sh_adaptive[0])
+        return fail(SGS_E_INVALID, "sh_adaptive must satisfy 0 <= [0] <= [1]");
+    if (g->reserved != 0) return fail(SGS_E_INVALID, "sgs_gaussians.reserved must be 0");
     if (!cams) return fail(SGS_E_INVALID, "host cameras are NULL");
     if (n_cams < 1 || n_cams > SGS_MAX_CAMERAS) return fail(SGS_E_INVALID, "n_cams must be 1..1024");
     if (cap < 0 || cap >= (int64_t(1) << 30)) return fail(SGS_E_INVALID, "pair_capacity must be in [0, 2^30)");
@@ -106,6 +116,13 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
         const int W = cams[c].width, H = cams[c].height;
         if (W < 1 || H < 1 || W > SGS_MAX_IMAGE_SIDE || H > SGS_MAX_IMAGE_SIDE)
             return fail(SGS_E_INVALID, "camera width/height must be 1..32767");
+        // a non-positive near plane would let depths in (znear, 0] through the
+        // 1/z projection (negative depth keys sort behind every positive one)
+        if (!(std::isfinite(cams[c].znear) && cams[c].znear > 0.0f))
+            return fail(SGS_E_INVALID, "camera znear must be finite and > 0");
+        if (!(std::isfinite(cams[c].fx) && cams[c].fx > 0.0f && std::isfinite(cams[c].fy) &&
+              cams[c].fy > 0.0f))
+            return fail(SGS_E_INVALID, "camera fx and fy must be finite and > 0");
         tiles += cdiv(W, o.tile_w) * cdiv(H, o.tile_h);
         pixels += (int64_t)W * H;
     }
@@ -226,11 +243,20 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     return w;
 }
 
+// 3-vectors per Gaussian in sg_axes for the lobe mode
+int axis_rows(const sgs_gaussians* g) {
+    return g->lobe_axes == SGS_LOBES_FREE ? g->n_lobes : (g->lobe_axes == SGS_LOBES_FRAME ? 1 : 0);
+}
+
 sgs::Params params_of(const sgs_gaussians* g) {
     sgs::Params p;
     p.n = g->n;
     p.sh_degree = g->sh_degree;
     p.n_lobes = g->n_lobes;
+    p.lobe_mode = g->lobe_axes;
+    p.n_axes = axis_rows(g);
+    p.sh_ad0 = g->sh_adaptive[0];
+    p.sh_ad1 = g->sh_adaptive[1];
     p.means = g->means;
     p.log_scales = g->log_scales;
     p.quats = g->quats;
@@ -240,11 +266,22 @@ sgs::Params params_of(const sgs_gaussians* g) {
     p.sg_log_sharpness = g->sg_log_sharpness;
     p.sg_amplitudes = g->sg_amplitudes;
     const int64_t nc3 = 3 * (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1), K = g->n_lobes;
+    const int64_t A3 = 3 * (int64_t)p.n_axes;
     const int64_t cs = g->colour_stride;
     p.cs_sh = cs > 0 ? cs : nc3;
-    p.cs_ax = cs > 0 ? cs : 3 * K;
+    p.cs_ax = cs > 0 ? cs : A3;
     p.cs_ls = cs > 0 ? cs : K;
     p.cs_am = cs > 0 ? cs : 3 * K;
+    const int64_t rs = nc3 + A3 + 4 * K;
+    // the four arrays interleave: one run of rs floats per Gaussian
+    p.contig = cs > 0 && (A3 == 0 || g->sg_axes == g->sh + nc3) &&
+               (K == 0 || (g->sg_log_sharpness == g->sh + nc3 + A3 &&
+                           g->sg_amplitudes == g->sh + nc3 + A3 + K));
+    p.rec_floats = (int)rs;
+    // read whole 16-byte pieces when the stride leaves room for the rounding
+    const int64_t rs4 = (rs + 3) & ~int64_t(3);
+    if (p.contig && cs % 4 == 0 && cs >= rs4 && ((uintptr_t)g->sh & 15u) == 0)
+        p.rec_floats = (int)rs4;
     return p;
 }
 
@@ -252,11 +289,13 @@ int check_params(const sgs_gaussians* g) {
     if (g->n == 0) return SGS_OK;
     if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)
         return fail(SGS_E_INVALID, "a Gaussian parameter array is NULL");
-    if (g->n_lobes > 0 && (!g->sg_axes || !g->sg_log_sharpness || !g->sg_amplitudes))
+    if (g->n_lobes > 0 && (!g->sg_log_sharpness || !g->sg_amplitudes))
         return fail(SGS_E_INVALID, "an SG lobe array is NULL");
+    if (axis_rows(g) > 0 && !g->sg_axes) return fail(SGS_E_INVALID, "sg_axes is NULL");
     const int64_t nc3 = 3 * (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
     if (g->colour_stride < 0 ||
-        (g->colour_stride > 0 && (g->colour_stride < nc3 || g->colour_stride < 3 * (int64_t)g->n_lobes)))
+        (g->colour_stride > 0 && (g->colour_stride < nc3 || g->colour_stride < 3 * (int64_t)g->n_lobes ||
+                                  g->colour_stride < 3 * (int64_t)axis_rows(g))))
         return fail(SGS_E_INVALID, "colour_stride is below a colour block size");
     return SGS_OK;
 }
@@ -448,9 +487,10 @@ int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const s
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats ||
                      !grads->opacity_logits || !grads->sh))
         return fail(SGS_E_INVALID, "a gradient output array is NULL");
-    if (g->n > 0 && g->n_lobes > 0 &&
-        (!grads->sg_axes || !grads->sg_log_sharpness || !grads->sg_amplitudes))
+    if (g->n > 0 && g->n_lobes > 0 && (!grads->sg_log_sharpness || !grads->sg_amplitudes))
         return fail(SGS_E_INVALID, "an SG gradient output array is NULL");
+    if (g->n > 0 && axis_rows(g) > 0 && !grads->sg_axes)
+        return fail(SGS_E_INVALID, "the sg_axes gradient output is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const sgs::Workspace ws = bind(pl, workspace);
     const sgs::Params p = params_of(g);

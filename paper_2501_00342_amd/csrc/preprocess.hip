@@ -4,7 +4,9 @@
 //   covariance Sigma = R S S^T R^T from the quaternion and scales (eq. 3),
 //   EWA projection Sigma' = J W Sigma W^T J^T + dilation I, the 3-sigma
 //   radius, the integer pixel and tile rectangles, the depth key, and the
-//   colour of eq. 9: low-degree SH (eq. 4) plus K SG lobes (eq. 5-7).
+//   colour of eq. 9: low-degree SH (eq. 4, optionally of a degree chosen by
+//   the projected radius) plus K SG lobes (eq. 5-7) on free axes, the world
+//   axes or a per-Gaussian orthonormal frame (eq. 8).
 //
 // This file is compiled with -ffp-contract=off: the values that decide
 // integers (cull, radius, rectangles, depth key) follow one fixed sequence
@@ -129,17 +131,18 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
 // so only the colour gather's latency is exposed per tile.  The colour is
 // evaluated from LDS, so the geometry's and the colour's registers are never
 // live together.
-template <int DEG, int KMAX>
+template <int DEG, int KMAX, int LM>
 __global__ void __launch_bounds__(kPreTile)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    constexpr int MAXROWS = 3 * NC + 7 * KMAX;
+    // record bound: SH, axis rows, sharpness and amplitudes, + 16-byte rounding
+    constexpr int MAXROWS = 3 * NC + 3 * AxisRows<LM, KMAX>::value + 4 * KMAX + 3;
     constexpr int WAVES = kPreTile / 64;
     __shared__ __align__(16) float s_rec[WAVES][64 * (MAXROWS > 0 ? MAXROWS : 1)];
     __shared__ int64_t s_g[WAVES][64];
     const int64_t n = p.n;
     const int tid = threadIdx.x, wave = tid >> 6;
-    const int RS = colour_record_floats(3 * NC, p.n_lobes);
+    const int RS = p.rec_floats;
     float* rec = s_rec[wave];
     // geometry of this thread's Gaussian in the next tile: 3 + 3 + 4 + 1 floats
     float nxt[11];
@@ -195,13 +198,13 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
                 float d[3], dist;
                 view_dir(X, cam, d, &dist);
                 const float* r = rec + slot * RS;
-                const int K = p.n_lobes;
-                vis = colour_eval<DEG, KMAX>(
+                const int K = p.n_lobes, A3 = 3 * p.n_axes;
+                vis = colour_eval<DEG, KMAX, LM>(
                     [&](int l, int c) { return r[3 * l + c]; },
                     [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
-                    [&](int k) { return r[3 * NC + 3 * K + k]; },
-                    [&](int k, int c) { return r[3 * NC + 4 * K + 3 * k + c]; }, K, d[0], d[1],
-                    d[2], rgb);
+                    [&](int k) { return r[3 * NC + A3 + k]; },
+                    [&](int k, int c) { return r[3 * NC + A3 + K + 3 * k + c]; }, K,
+                    sh_used<DEG>(p, geo.radius), d[0], d[1], d[2], rgb);
             }
             if (!active) continue;
             uint32_t key = 0xFFFFFFFFu;
@@ -257,15 +260,15 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
     }
 }
 
-template <int KMAX>
+template <int KMAX, int LM>
 static void launch_pre_k(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                          const Workspace& ws, dim3 grid, hipStream_t s) {
     const dim3 block(kPreTile);
     switch (p.sh_degree) {
-        case 0: hipLaunchKernelGGL((k_preprocess<0, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        case 1: hipLaunchKernelGGL((k_preprocess<1, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        case 2: hipLaunchKernelGGL((k_preprocess<2, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        default: hipLaunchKernelGGL((k_preprocess<3, KMAX>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        case 0: hipLaunchKernelGGL((k_preprocess<0, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        case 1: hipLaunchKernelGGL((k_preprocess<1, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        case 2: hipLaunchKernelGGL((k_preprocess<2, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        default: hipLaunchKernelGGL((k_preprocess<3, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
     }
 }
 
@@ -275,9 +278,12 @@ void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, 
     // persistent: up to 16 blocks of two waves per CU
     const int64_t tiles = (p.n + kPreTile - 1) / kPreTile;
     const dim3 grid((unsigned)(tiles < 4096 ? (tiles < 1 ? 1 : tiles) : 4096));
-    if (p.n_lobes == 0) launch_pre_k<0>(p, dev_cams, n_cams, o, ws, grid, s);
-    else if (p.n_lobes <= 4) launch_pre_k<4>(p, dev_cams, n_cams, o, ws, grid, s);
-    else launch_pre_k<SGS_MAX_LOBES>(p, dev_cams, n_cams, o, ws, grid, s);
+    // the orthogonal modes have exactly three lobes (checked on the host)
+    if (p.lobe_mode == kLobesWorld) launch_pre_k<3, kLobesWorld>(p, dev_cams, n_cams, o, ws, grid, s);
+    else if (p.lobe_mode == kLobesFrame) launch_pre_k<3, kLobesFrame>(p, dev_cams, n_cams, o, ws, grid, s);
+    else if (p.n_lobes == 0) launch_pre_k<0, kLobesFree>(p, dev_cams, n_cams, o, ws, grid, s);
+    else if (p.n_lobes <= 4) launch_pre_k<4, kLobesFree>(p, dev_cams, n_cams, o, ws, grid, s);
+    else launch_pre_k<SGS_MAX_LOBES, kLobesFree>(p, dev_cams, n_cams, o, ws, grid, s);
 }
 
 }  // namespace sgs

@@ -2,8 +2,9 @@
 // raw parameter, one thread per Gaussian summing over cameras, in two
 // kernels so that neither holds both live sets (no register spills):
 //
-//   k_colour_bwd<DEG, KMAX> (float32): colour eq. 9 -> SH coefficients (eq. 4),
-//     SG amplitude, log-sharpness and axis (eq. 5), and the part of the
+//   k_colour_bwd<DEG, KMAX, LM> (float32): colour eq. 9 -> SH coefficients
+//     (eq. 4; only those of the degree each camera used), SG amplitude,
+//     log-sharpness and axis (eq. 5) or frame parameters (eq. 8), and the part of the
 //     mean's gradient that flows through the view direction; the latter is
 //     left in a [3][n] scratch row of the workspace.
 //   k_geom_bwd (float64): conic Q = Sigma'^-1 -> Sigma' (dQ = -Q dSigma' Q),
@@ -31,18 +32,21 @@ __device__ __forceinline__ bool item_visible(const Workspace& ws, int64_t item) 
 // gets zeros.
 // waves per SIMD asked of the compiler: 4 up to 40 colour rows (no spills
 // there); larger forms keep their natural register count
-template <int DEG, int KMAX>
+template <int DEG, int KMAX, int LM>
 struct ColourBwdWaves {
-    static constexpr int value = 3 * (DEG + 1) * (DEG + 1) + 7 * KMAX <= 40 ? 4 : (3 * (DEG + 1) * (DEG + 1) + 7 * KMAX <= 48 ? 3 : 1);
+    static constexpr int rows = 3 * (DEG + 1) * (DEG + 1) + 3 * AxisRows<LM, KMAX>::value + 4 * KMAX;
+    static constexpr int value = rows <= 40 ? 4 : (rows <= 48 ? 3 : 1);
 };
 
-template <int DEG, int KMAX>
+template <int DEG, int KMAX, int LM>
 __global__ void __launch_bounds__(kPreTile)
-__attribute__((amdgpu_waves_per_eu(ColourBwdWaves<DEG, KMAX>::value)))
+__attribute__((amdgpu_waves_per_eu(ColourBwdWaves<DEG, KMAX, LM>::value)))
 k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspace ws,
              sgs_grads gr, float* __restrict__ gx_colour) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    constexpr int MAXROWS = 3 * NC + 7 * KMAX;
+    constexpr int AMAX = AxisRows<LM, KMAX>::value;
+    // record bound: SH, axis rows, sharpness and amplitudes, + 16-byte rounding
+    constexpr int MAXROWS = 3 * NC + 3 * AMAX + 4 * KMAX + 3;
     // gradient records: an odd stride keeps a wave's record writes on
     // distinct banks
     constexpr int SG = (MAXROWS % 2 == 0) ? MAXROWS + 1 : MAXROWS;
@@ -55,12 +59,13 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
     const int64_t M = ws.n_items;
     const int K = p.n_lobes;
     const int tid = threadIdx.x, wave = tid >> 6;
-    const int RS = colour_record_floats(3 * NC, K);
+    const int RS = p.rec_floats;
+    const int A3 = 3 * p.n_axes;
     float* crec = s_buf + wave * 64 * MAXROWS;
     // this thread's Gaussian in the next tile: its mean and the first
     // camera's rectangle, loaded while this tile computes (only where the
     // registers allow it without spilling)
-    constexpr bool PF = ColourBwdWaves<DEG, KMAX>::value >= 4;
+    constexpr bool PF = ColourBwdWaves<DEG, KMAX, LM>::value >= 4;
     float nX[3];
     uint64_t nrect;
     auto load = [&](int64_t b) {
@@ -82,15 +87,16 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
         const uint64_t rect0 = nrect;
         if (PF && base + (int64_t)gridDim.x * kPreTile < n) load(base + (int64_t)gridDim.x * kPreTile);
         float gsh[NC][3];
-        float gamp[KMAX + 1][3], gax[KMAX + 1][3], glsh[KMAX + 1];
+        float gamp[KMAX + 1][3], gax[AMAX + 1][3], glsh[KMAX + 1];
 #pragma unroll
         for (int l = 0; l < NC; ++l) gsh[l][0] = gsh[l][1] = gsh[l][2] = 0.0f;
 #pragma unroll
         for (int k = 0; k < KMAX + 1; ++k) {
             glsh[k] = 0.0f;
             gamp[k][0] = gamp[k][1] = gamp[k][2] = 0.0f;
-            gax[k][0] = gax[k][1] = gax[k][2] = 0.0f;
         }
+#pragma unroll
+        for (int a = 0; a < AMAX + 1; ++a) gax[a][0] = gax[a][1] = gax[a][2] = 0.0f;
         float gX[3] = {0.0f, 0.0f, 0.0f};
         const int64_t gc = active ? g : n - 1;
         int slot = -1, used = 0;
@@ -116,12 +122,14 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
             float d[3], dist;
             view_dir(X, cams[ci], d, &dist);
             float gd[3];
-            colour_bwd_eval<DEG, KMAX>(
+            // adaptive SH: the degree this camera used, from the item's radius
+            const int ncu = (p.sh_ad0 | p.sh_ad1) ? sh_used<DEG>(p, ws.records[item].radius) : NC;
+            colour_bwd_eval<DEG, KMAX, LM>(
                 [&](int l, int c) { return r[3 * l + c]; },
                 [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
-                [&](int k) { return r[3 * NC + 3 * K + k]; },
-                [&](int k, int c) { return r[3 * NC + 4 * K + 3 * k + c]; }, K, d[0], d[1], d[2],
-                grgb, gsh, gamp, gax, glsh, gd);
+                [&](int k) { return r[3 * NC + A3 + k]; },
+                [&](int k, int c) { return r[3 * NC + A3 + K + 3 * k + c]; }, K, ncu, d[0], d[1],
+                d[2], grgb, gsh, gamp, gax, glsh, gd);
             // through d = (X - c) / |X - c|: (I - d d^T) / |X - c|
             const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
             const float inv = 1.0f / dist;
@@ -132,22 +140,24 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
 #pragma unroll
             for (int c = 0; c < 3; ++c) gx_colour[c * n + g] = gX[c];
         __syncthreads();   // every wave is done with its colour records
-        // record layout with KMAX lobe slots (compile-time offsets): SH rows,
-        // then axes at 3 NC + 3 k + c, log-sharpness at 3 NC + 3 KMAX + k,
-        // amplitudes at 3 NC + 4 KMAX + 3 k + c; slots k >= K hold zeros
+        // record layout with AMAX axis and KMAX lobe slots (compile-time
+        // offsets): SH rows, then axis rows at 3 NC + 3 a + c, log-sharpness
+        // at 3 NC + 3 AMAX + k, amplitudes at 3 NC + 3 AMAX + KMAX + 3 k + c;
+        // slots past the live counts hold zeros
         float* rec = s_buf + tid * SG;
 #pragma unroll
         for (int l = 0; l < NC; ++l)
 #pragma unroll
             for (int c = 0; c < 3; ++c) rec[3 * l + c] = gsh[l][c];
 #pragma unroll
+        for (int a = 0; a < AMAX; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rec[3 * NC + 3 * a + c] = gax[a][c];
+#pragma unroll
         for (int k = 0; k < KMAX; ++k) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                rec[3 * NC + 3 * k + c] = gax[k][c];
-                rec[3 * NC + 4 * KMAX + 3 * k + c] = gamp[k][c];
-            }
-            rec[3 * NC + 3 * KMAX + k] = glsh[k];
+            for (int c = 0; c < 3; ++c) rec[3 * NC + 3 * AMAX + KMAX + 3 * k + c] = gamp[k][c];
+            rec[3 * NC + 3 * AMAX + k] = glsh[k];
         }
         __syncthreads();
         // array with S floats per Gaussian at record offset R: the tile's
@@ -166,9 +176,9 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
         };
         write_out(gr.sh, 3 * NC, 0);
         if (K > 0) {
-            write_out(gr.sg_axes, 3 * K, 3 * NC);
-            write_out(gr.sg_log_sharpness, K, 3 * NC + 3 * KMAX);
-            write_out(gr.sg_amplitudes, 3 * K, 3 * NC + 4 * KMAX);
+            write_out(gr.sg_axes, A3, 3 * NC);
+            write_out(gr.sg_log_sharpness, K, 3 * NC + 3 * AMAX);
+            write_out(gr.sg_amplitudes, 3 * K, 3 * NC + 3 * AMAX + KMAX);
         }
     }
 }
@@ -345,12 +355,14 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     float* gxc = ws.gx_colour;
     const int64_t tiles = (p.n + kPreTile - 1) / kPreTile;
     const dim3 cgrid((unsigned)(tiles < 4096 ? tiles : 4096)), cblock(kPreTile);
-#define SGS_COLOUR_BWD(D, K)                                                                   \
-    hipLaunchKernelGGL((k_colour_bwd<D, K>), cgrid, cblock, 0, s, p, dev_cams, n_cams, ws, gr, gxc)
+#define SGS_COLOUR_BWD(D, K, LM)                                                               \
+    hipLaunchKernelGGL((k_colour_bwd<D, K, LM>), cgrid, cblock, 0, s, p, dev_cams, n_cams, ws, gr, gxc)
 #define SGS_COLOUR_BWD_K(D)                                                                    \
-    if (p.n_lobes == 0) SGS_COLOUR_BWD(D, 0);                                                  \
-    else if (p.n_lobes <= 4) SGS_COLOUR_BWD(D, 4);                                             \
-    else SGS_COLOUR_BWD(D, 8)
+    if (p.lobe_mode == kLobesWorld) SGS_COLOUR_BWD(D, 3, kLobesWorld);                         \
+    else if (p.lobe_mode == kLobesFrame) SGS_COLOUR_BWD(D, 3, kLobesFrame);                    \
+    else if (p.n_lobes == 0) SGS_COLOUR_BWD(D, 0, kLobesFree);                                 \
+    else if (p.n_lobes <= 4) SGS_COLOUR_BWD(D, 4, kLobesFree);                                 \
+    else SGS_COLOUR_BWD(D, 8, kLobesFree)
     switch (p.sh_degree) {
         case 0: SGS_COLOUR_BWD_K(0); break;
         case 1: SGS_COLOUR_BWD_K(1); break;

@@ -54,6 +54,10 @@ k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, int tw, i
         t.W = cams[c].width;
         t.H = cams[c].height;
         ok = ok && t.W > 0 && t.H > 0 && t.W <= SGS_MAX_IMAGE_SIDE && t.H <= SGS_MAX_IMAGE_SIDE;
+        // the same camera rules the host checks: a positive near plane and
+        // positive focal lengths (comparisons are false for NaN)
+        ok = ok && cams[c].znear > 0.0f && cams[c].znear <= 3.0e38f && cams[c].fx > 0.0f &&
+             cams[c].fx <= 3.0e38f && cams[c].fy > 0.0f && cams[c].fy <= 3.0e38f;
         t.GX = ok ? (t.W + tw - 1) / tw : 0;
         t.GY = ok ? (t.H + th - 1) / th : 0;
         t.tile_base = (int32_t)tiles;
@@ -65,7 +69,7 @@ k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, int tw, i
         tiles += (int64_t)t.GX * t.GY;
         pix += (int64_t)t.W * t.H;
     }
-    // the device cameras must describe the sizes the host planned for
+    // the device cameras must be valid and describe the sizes the host planned for
     if (!ok || pix != ws.n_pixels || tiles != ws.n_tiles)
         atomicOr(&ws.header[kHdrStatus], SGS_STATUS_CAMERAS);
 }

@@ -40,24 +40,29 @@ def to_scene_layout(arrays: dict) -> dict:
             for k, v in arrays.items()}
 
 
-def colour_record_floats(sh_degree: int, n_lobes: int) -> int:
-    return 3 * (sh_degree + 1) ** 2 + 7 * n_lobes
+def colour_record_floats(sh_degree: int, n_lobes: int, lobe_mode: int = L.LOBES_FREE) -> int:
+    """Floats of one Gaussian's colour: SH, axis rows, sharpness, amplitudes."""
+    from .scenes import axis_vectors
+    return 3 * (sh_degree + 1) ** 2 + 3 * axis_vectors(lobe_mode, n_lobes) + 4 * n_lobes
 
 
 def params_to_device(scene: Scene, device="cuda", packed: bool = True) -> dict:
     """Scene arrays -> float32 device tensors in the C-ABI layout.
 
-    packed: the four colour tensors are views into one (N, 3 (L+1)^2 + 7 K)
-    buffer, each Gaussian's colour one contiguous record (the layout the
-    rasteriser fetches fastest); otherwise each colour tensor is contiguous
-    on its own."""
+    packed: the four colour tensors are views into one (N, S) buffer, each
+    Gaussian's colour one contiguous record of 3 (L+1)^2 + 3 A + 4 K floats
+    and S that rounded up to a multiple of 4 (the layout the rasteriser
+    fetches fastest: whole 16-byte pieces); otherwise each colour tensor is
+    contiguous on its own."""
     out = {k: torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
            for k in FIELDS if k not in COLOUR_FIELDS or not packed}
     if packed:
         n, nc3, K = scene.n, 3 * (scene.sh_degree + 1) ** 2, scene.n_lobes
-        rec = torch.empty((n, nc3 + 7 * K), dtype=torch.float32, device=device)
+        A = scene.n_axis_vectors
+        rs = nc3 + 3 * A + 4 * K
+        rec = torch.zeros((n, (rs + 3) // 4 * 4), dtype=torch.float32, device=device)
         at = 0
-        for k, width in (("sh", nc3), ("sg_axes", 3 * K), ("sg_log_sharpness", K),
+        for k, width in (("sh", nc3), ("sg_axes", 3 * A), ("sg_log_sharpness", K),
                          ("sg_amplitudes", 3 * K)):
             a = torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
             view = rec[:, at:at + width].view(a.shape)
@@ -120,10 +125,12 @@ class Rasterizer:
     """
 
     def __init__(self, cams, opts: Options, n: int, sh_degree: int, n_lobes: int,
-                 device="cuda", capacity: int | None = None, auto_grow: bool = True):
+                 device="cuda", capacity: int | None = None, auto_grow: bool = True,
+                 lobe_mode: int = L.LOBES_FREE, sh_adaptive=(0, 0)):
         self.cams = list(cams)
         self.opts = opts
         self.n, self.sh_degree, self.n_lobes = int(n), int(sh_degree), int(n_lobes)
+        self.lobe_mode, self.sh_adaptive = int(lobe_mode), tuple(int(t) for t in sh_adaptive)
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -137,14 +144,25 @@ class Rasterizer:
         self.capacity = min(self.capacity, (1 << 30) - 1)
         self.ws = None
         self.layout = None
+        # bumped by every forward and every reallocation: the workspace then
+        # holds another render's records, pairs and ranges
+        self.generation = 0
         self._alloc()
+
+    @classmethod
+    def for_scene(cls, scene: Scene, cams, opts: Options, **kw) -> "Rasterizer":
+        """A Rasterizer for the colour form of `scene` (degree, lobes, lobe
+        mode, adaptive SH thresholds)."""
+        return cls(cams, opts, scene.n, scene.sh_degree, scene.n_lobes,
+                   lobe_mode=scene.lobe_mode, sh_adaptive=scene.sh_adaptive, **kw)
 
     # -- planning ----------------------------------------------------------
     def _gstruct(self, params: dict | None):
         ptrs = {k: (params[k].data_ptr() if params[k].numel() else None) for k in FIELDS} \
             if params else {}
         cs = colour_stride(params) if params else 0
-        return L.gaussians_struct(self.n, self.sh_degree, self.n_lobes, ptrs, cs)
+        return L.gaussians_struct(self.n, self.sh_degree, self.n_lobes, ptrs, cs,
+                                  self.lobe_mode, self.sh_adaptive)
 
     def _alloc(self):
         g = self._gstruct(None)
@@ -153,6 +171,7 @@ class Rasterizer:
                                     ctypes.byref(self.copts), self.capacity, ctypes.byref(lay)))
         self.layout = lay
         self.ws = torch.empty(int(lay.total_bytes), dtype=torch.uint8, device=self.device)
+        self.generation += 1
 
     def new_outputs(self) -> Outputs:
         P = self.n_pixels
@@ -181,6 +200,7 @@ class Rasterizer:
         o = L.Outputs(_ptr(out.image), _ptr(out.depth), _ptr(out.final_T), _ptr(out.n_contrib))
         need = L.c_int64(0)
         flags = L.SGS_FLAG_CHECK_CAPACITY if check else 0
+        self.generation += 1
         while True:
             rc = L.LIB.render_forward(ctypes.byref(g), self.host_cams, _ptr(self.dev_cams),
                                       len(self.cams), ctypes.byref(self.copts), _ptr(self.ws),
@@ -276,12 +296,18 @@ class Rasterizer:
         return keys
 
 
+class StaleWorkspaceError(RuntimeError):
+    """A backward whose forward's workspace was overwritten by a later
+    forward (or reallocated) on the same Rasterizer."""
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast: Rasterizer, *params):
         p = dict(zip(FIELDS, params))
         out = rast.forward(p)
         ctx.rast = rast
+        ctx.generation = rast.generation
         ctx.out = out
         ctx.save_for_backward(*params)
         ctx.mark_non_differentiable(out.depth, out.final_T, out.n_contrib)
@@ -289,6 +315,13 @@ class _RenderFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_image, *_):
+        # the backward walks the tile lists of the workspace: they must still
+        # be those of this forward
+        if ctx.rast.generation != ctx.generation:
+            raise StaleWorkspaceError(
+                "the Rasterizer ran another forward (or regrew its workspace) after this "
+                "render; its backward would read that render's tile lists.  Call backward "
+                "before the next forward, or use one Rasterizer per pending render.")
         params = dict(zip(FIELDS, ctx.saved_tensors))
         grads = ctx.rast.backward(params, ctx.out, g_image.contiguous())
         return (None, *[grads[k] for k in FIELDS])

@@ -27,6 +27,19 @@ import numpy as np
 FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh",
           "sg_axes", "sg_log_sharpness", "sg_amplitudes")
 
+# How the lobe axes are given (the values of the C-ABI's lobe_axes field):
+#   LOBES_FREE  every lobe has its own axis, sg_axes (K, 3, N)
+#   LOBES_WORLD three lobes on the fixed world axes (1,0,0), (0,1,0), (0,0,1);
+#               sg_axes is empty (0, 3, N)
+#   LOBES_FRAME three mutually orthogonal lobes on the columns of a rotation
+#               given by 3 parameters per Gaussian, sg_axes (1, 3, N)
+LOBES_FREE, LOBES_WORLD, LOBES_FRAME = 0, 1, 2
+
+
+def axis_vectors(lobe_mode: int, n_lobes: int) -> int:
+    """Rows of sg_axes (3-vectors per Gaussian) for a lobe mode."""
+    return {LOBES_FREE: n_lobes, LOBES_WORLD: 0, LOBES_FRAME: 1}[lobe_mode]
+
 
 @dataclass
 class Scene:
@@ -40,16 +53,31 @@ class Scene:
     sg_axes: np.ndarray
     sg_log_sharpness: np.ndarray
     sg_amplitudes: np.ndarray
+    lobe_mode: int = LOBES_FREE
+    # adaptive SH degree by projected radius r (pixels): degree 0 where
+    # r <= sh_adaptive[0], at most 1 where r <= sh_adaptive[1], else
+    # sh_degree; (0, 0) = every Gaussian uses sh_degree
+    sh_adaptive: tuple = (0, 0)
 
     @property
     def n(self) -> int:
         return int(self.means.shape[1])
 
+    @property
+    def n_axis_vectors(self) -> int:
+        return axis_vectors(self.lobe_mode, self.n_lobes)
+
     def arrays(self) -> dict:
         return {k: getattr(self, k) for k in FIELDS}
 
     def floats_per_gaussian(self) -> int:
-        return 3 + 3 + 4 + 1 + 3 * (self.sh_degree + 1) ** 2 + 7 * self.n_lobes
+        return (3 + 3 + 4 + 1 + 3 * (self.sh_degree + 1) ** 2 + 3 * self.n_axis_vectors
+                + 4 * self.n_lobes)
+
+    def form(self) -> dict:
+        """The colour form (everything but the arrays)."""
+        return {"sh_degree": self.sh_degree, "n_lobes": self.n_lobes,
+                "lobe_mode": self.lobe_mode, "sh_adaptive": tuple(self.sh_adaptive)}
 
     def subset(self, idx) -> "Scene":
         idx = np.asarray(idx)
@@ -57,11 +85,13 @@ class Scene:
         for k in FIELDS:
             a = getattr(self, k)
             out[k] = np.ascontiguousarray(a[..., idx])
-        return Scene(self.sh_degree, self.n_lobes, **out)
+        return Scene(self.sh_degree, self.n_lobes, **out, lobe_mode=self.lobe_mode,
+                     sh_adaptive=tuple(self.sh_adaptive))
 
     def copy(self) -> "Scene":
         return Scene(self.sh_degree, self.n_lobes,
-                     **{k: getattr(self, k).copy() for k in FIELDS})
+                     **{k: getattr(self, k).copy() for k in FIELDS}, lobe_mode=self.lobe_mode,
+                     sh_adaptive=tuple(self.sh_adaptive))
 
 
 @dataclass
@@ -243,6 +273,37 @@ def sh3_scene(n: int, seed: int, **kw) -> Scene:
     return Scene(3, 0, means, ls, q, op, sh, z3, np.zeros((0, n), np.float32), z3.copy())
 
 
+def orthogonal_scene(n: int, seed: int, lobe_mode: int, sh_degree: int = 0,
+                     sh_adaptive=(0, 0), n_clusters: int = 500,
+                     log_sigma_mu: float = math.log(0.5)) -> Scene:
+    """Same geometry as `clustered_scene(n, seed)` with three mutually
+    orthogonal lobes: on the world axes (LOBES_WORLD) or on the columns of a
+    per-Gaussian rotation whose 3 parameters are N(0, 1) (LOBES_FRAME).
+    SH: degree-0 coefficients N(0, 0.3), higher degrees N(0, 0.1); lobe
+    log-sharpness N(1, 0.5), amplitudes N(0, 0.2)."""
+    rng = np.random.default_rng(seed)
+    means = clustered_means(rng, n, n_clusters, log_sigma_mu)
+    ls, q, op = _shape_params(rng, n)
+    crng = np.random.default_rng([seed, sh_degree, 3, 100 + lobe_mode])
+    nc = (sh_degree + 1) ** 2
+    sh = np.empty((nc, 3, n), np.float32)
+    sh[0] = crng.normal(0.0, 0.3, (3, n))
+    if nc > 1:
+        sh[1:] = crng.normal(0.0, 0.1, (nc - 1, 3, n))
+    A = axis_vectors(lobe_mode, 3)
+    axes = crng.normal(0.0, 1.0, (A, 3, n)).astype(np.float32)
+    lsh = crng.normal(1.0, 0.5, (3, n)).astype(np.float32)
+    amp = crng.normal(0.0, 0.2, (3, 3, n)).astype(np.float32)
+    return Scene(sh_degree, 3, means, ls, q, op, sh, axes, lsh, amp, lobe_mode=lobe_mode,
+                 sh_adaptive=tuple(sh_adaptive))
+
+
+# adaptive SH thresholds used by the "full" form (projected radius, pixels):
+# the smallest splats (radius 2, the floor the dilation sets) take degree 0,
+# radius up to 8 degree 1, larger ones degree 2
+ADAPTIVE_SH_RADII = (2, 8)
+
+
 def config1_camera(width: int = 1600, height: int = 1060) -> Camera:
     """Camera inside the scene ball at (0,0,-5), looking at the centre."""
     return pinhole(width, height, np.eye(3), (0.0, 0.0, 5.0))
@@ -278,6 +339,9 @@ def workload(name: str):
     sg-1k-128      : 1,000 Gaussians, SH0 + 3 lobes, 128x128 (seed 0)
     sg-3m-1600     : 3M clustered Gaussians, SH1 + 4 lobes, 1600x1060 (seed 1)
     sh3-3m-1600    : same geometry, degree-3 SH colour
+    orthw-3m-1600  : same geometry, SH0 + 3 lobes on the world axes
+    full-3m-1600   : same geometry, adaptive SH (0-2) + 3 lobes on a
+                     per-Gaussian orthonormal frame
     sg-1m-1297     : 1M clustered, SH1 + 4 lobes, 1297x840 (seed 2), L1 target
     sg-2m-64cam    : 2M clustered, 64 ring cameras of mixed size (seed 3)
     sg-6m-1920     : 6M Gaussians in 2,000 tight clusters, 1920x1080 (seed 4)
@@ -288,6 +352,11 @@ def workload(name: str):
         return clustered_scene(3_000_000, 1), [config1_camera()], Options()
     if name == "sh3-3m-1600":
         return sh3_scene(3_000_000, 1), [config1_camera()], Options()
+    if name == "orthw-3m-1600":
+        return orthogonal_scene(3_000_000, 1, LOBES_WORLD), [config1_camera()], Options()
+    if name == "full-3m-1600":
+        return (orthogonal_scene(3_000_000, 1, LOBES_FRAME, sh_degree=2,
+                                 sh_adaptive=ADAPTIVE_SH_RADII), [config1_camera()], Options())
     if name == "sg-1m-1297":
         return clustered_scene(1_000_000, 2), [config1_camera(1297, 840)], Options()
     if name == "sg-2m-64cam":

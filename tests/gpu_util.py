@@ -10,7 +10,7 @@ from paper_2501_00342_amd.scenes import Scene
 
 
 def run_forward(scene: Scene, cams, opts, capacity=None, check=True):
-    rast = raster.Rasterizer(cams, opts, scene.n, scene.sh_degree, scene.n_lobes,
+    rast = raster.Rasterizer.for_scene(scene, cams, opts,
                              device="cuda", capacity=capacity)
     params = raster.params_to_device(scene)
     out = rast.forward(params, check=check)

@@ -54,7 +54,7 @@ def compare_pixel(gpu, ref_pixel) -> bool:
     return bool(flagged and outs and any(_pixel_ok(*gpu, *o) for o in outs))
 
 
-def compare_grads(gpu: dict, ref: dict, exclude=None) -> dict:
+def compare_grads(gpu: dict, ref: dict, exclude=None, floor: float = 1e-2) -> dict:
     """Per-tensor relative L2 and elementwise bounds; `exclude` is a boolean
     mask over Gaussians whose gradients may legitimately differ."""
     report = {}
@@ -66,9 +66,17 @@ def compare_grads(gpu: dict, ref: dict, exclude=None) -> dict:
         nrm = np.linalg.norm(g_or)
         rel = np.linalg.norm(g - g_or) / nrm if nrm > 0 else np.linalg.norm(g)
         rms = np.sqrt(np.mean(g_or ** 2))
-        bound = GRAD_REL * (np.abs(g_or) + 1e-2 * rms)
+        bound = GRAD_REL * (np.abs(g_or) + floor * rms)
         viol = np.abs(g - g_or) > bound
         if exclude is not None:
             viol = viol & ~exclude.reshape((1,) * (g.ndim - 1) + (-1,))
-        report[k] = {"rel_l2": float(rel), "elem_viol": int(viol.sum()), "size": int(g.size)}
+        worst = []
+        if viol.any():
+            ratio = np.where(viol, np.abs(g - g_or) / bound, 0.0)
+            for flat in np.argsort(ratio, axis=None)[::-1][:5]:
+                idx = np.unravel_index(flat, g.shape)
+                worst.append((tuple(int(i) for i in idx), float(g[idx]), float(g_or[idx]),
+                              float(bound[idx]), float(rms)))
+        report[k] = {"rel_l2": float(rel), "elem_viol": int(viol.sum()), "size": int(g.size),
+                     "worst": worst}
     return report

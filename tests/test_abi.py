@@ -56,9 +56,53 @@ def test_ctypes_structs_match_the_c_layout(lib, tmp_path):
     assert got == want
 
 
-def _args(lib, n=1000, sh=1, K=4, W=128, H=96, opts=None, cap=10000):
-    g = lib.gaussians_struct(n, sh, K, {})
-    cams = lib.camera_array([scenes.pinhole(W, H, np.eye(3), (0, 0, 4))])
+def _header_fields(struct_name):
+    """Field names of a typedef'd struct in the header, in order."""
+    txt = open(HEADER).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct_name, struct_name), txt, re.S)
+    assert body, struct_name
+    code = re.sub(r"/\*.*?\*/", "", body.group(1), flags=re.S)
+    names = []
+    for decl in code.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        # "const float* a, *b" / "int32_t width, height" / "float R[9]"
+        parts = decl.split(",")
+        first = re.sub(r"\[.*?\]", "", parts[0]).split()[-1].lstrip("*")
+        names.append(first)
+        names += [re.sub(r"\[.*?\]", "", q).strip().lstrip("*") for q in parts[1:]]
+    return names
+
+
+@pytest.mark.parametrize("cname,pyname", [
+    ("sgs_gaussians", "Gaussians"), ("sgs_grads", "Grads"), ("sgs_camera", "Camera"),
+    ("sgs_options", "Options"), ("sgs_outputs", "Outputs"), ("sgs_layout", "Layout")])
+def test_header_struct_fields_match_the_binding(lib, cname, pyname):
+    """The binding's ctypes fields are the header's, in the header's order
+    (so a C caller and the Python front end agree on every layout)."""
+    assert _header_fields(cname) == [f[0] for f in getattr(lib, pyname)._fields_]
+
+
+def test_header_states_the_colour_layout_of_the_struct():
+    """The conventions paragraph and the struct comments give the colour
+    arrays Gaussian-major ([n][...]) and the geometry component-major."""
+    txt = open(HEADER).read()
+    assert "Colour arrays are Gaussian-major" in txt
+    for field, layout in (("sh", "[n][(deg+1)^2][3]"), ("sg_axes", "[n][A][3]"),
+                          ("sg_log_sharpness", "[n][K]"), ("sg_amplitudes", "[n][K][3]"),
+                          ("means", "[3][n]"), ("quats", "[4][n]")):
+        assert re.search(r"\*\s*%s;\s*/\*\s*%s" % (field, re.escape(layout)), txt), field
+
+
+def _args(lib, n=1000, sh=1, K=4, W=128, H=96, opts=None, cap=10000, lobes=0, adaptive=(0, 0),
+          znear=0.2, fx=None):
+    g = lib.gaussians_struct(n, sh, K, {}, lobe_axes=lobes, sh_adaptive=adaptive)
+    cam = scenes.pinhole(W, H, np.eye(3), (0, 0, 4))
+    cam.znear = znear
+    if fx is not None:
+        cam.fx = fx
+    cams = lib.camera_array([cam])
     o = lib.options_struct(opts or scenes.Options())
     return g, cams, o, cap
 
@@ -82,7 +126,10 @@ def test_workspace_size_and_layout(lib):
     dict(sh=4), dict(K=9), dict(W=0), dict(H=40000), dict(cap=1 << 30), dict(n=-1),
     dict(opts=scenes.Options(tile_w=12, tile_h=12)), dict(opts=scenes.Options(batch=300)),
     dict(opts=scenes.Options(tile_w=8, tile_h=8, ppt=2)), dict(opts=scenes.Options(ppt=3)),
-    dict(opts=scenes.Options(alpha_max=1.5)), dict(opts=scenes.Options(schedule=3))])
+    dict(opts=scenes.Options(alpha_max=1.5)), dict(opts=scenes.Options(schedule=3)),
+    dict(lobes=3), dict(lobes=1, K=4), dict(lobes=2, K=2), dict(adaptive=(3, 2)),
+    dict(adaptive=(-1, 4)), dict(znear=0.0), dict(znear=-0.5), dict(znear=float("nan")),
+    dict(fx=0.0), dict(fx=float("inf"))])
 def test_invalid_arguments_are_rejected_on_the_host(lib, bad):
     g, cams, o, cap = _args(lib, **bad)
     assert lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap) == 0
@@ -100,3 +147,10 @@ def test_forward_rejects_null_arguments_before_any_launch(lib):
     rc = lib.LIB.render_backward(ctypes.byref(g), cams, None, 1, ctypes.byref(o), None, 0, cap,
                                  None, None, None, None)
     assert rc == lib.SGS_E_INVALID
+
+
+@pytest.mark.parametrize("ok", [dict(lobes=1, K=3), dict(lobes=2, K=3, sh=2, adaptive=(2, 8)),
+                                dict(adaptive=(0, 5)), dict(K=8, sh=3)])
+def test_valid_colour_forms_are_accepted(lib, ok):
+    g, cams, o, cap = _args(lib, **ok)
+    assert lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap) > 0

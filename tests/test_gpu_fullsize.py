@@ -35,7 +35,7 @@ def _sample_pixels(W, H, n, rng):
 def test_full_frame_3m_keys_ranges_and_pixels():
     sc, cams, opts = scenes.workload("sg-3m-1600")
     cam = cams[0]
-    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
+    rast = raster.Rasterizer.for_scene(sc, cams, opts)
     params = raster.params_to_device(sc)
     out = rast.forward(params, check=True)
     bits, P = rast.status()
@@ -88,7 +88,7 @@ def test_full_frame_1m_gradients_on_sampled_tiles():
         gimg[:, py, px] = rng.normal(size=(3, px.size)).astype(np.float32)
     gimg[:, flagged] = 0.0
 
-    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
+    rast = raster.Rasterizer.for_scene(sc, cams, opts)
     params = raster.params_to_device(sc)
     out = rast.forward(params, check=True)
     grads = rast.backward(params, out, torch.from_numpy(gimg.reshape(-1)).cuda())
@@ -143,7 +143,7 @@ def test_batched_64_cameras_sampled():
     four cameras (each size) are checked against the oracle, and every tile
     range of the frame must tile [0, P) in order."""
     sc, cams, opts = scenes.workload("sg-2m-64cam")
-    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
+    rast = raster.Rasterizer.for_scene(sc, cams, opts)
     params = raster.params_to_device(sc)
     out = rast.forward(params, check=True)
     bits, P = rast.status()
@@ -166,7 +166,7 @@ def test_stress_6m_sampled():
     """6M Gaussians in tight clusters at 1920x1080: every tile list length,
     the heaviest and sampled tile lists, and sampled pixels."""
     sc, cams, opts = scenes.workload("sg-6m-1920")
-    rast = raster.Rasterizer(cams, opts, sc.n, sc.sh_degree, sc.n_lobes)
+    rast = raster.Rasterizer.for_scene(sc, cams, opts)
     params = raster.params_to_device(sc)
     out = rast.forward(params, check=True)
     bits, P = rast.status()

@@ -177,3 +177,102 @@ def test_batched_keys_are_per_camera_keys_with_tile_bases():
         assert np.array_equal(k, single.keys)
         assert np.array_equal(vals[m] - ci * 300, single.values)
         base += pres[ci].grid[0] * pres[ci].grid[1]
+
+
+# ---- tie-band enumeration pinned by closed forms --------------------------
+# A pixel at a splat's centre has power 0, so alpha = min(alpha_max, sigma):
+# hand-placed splats put alpha or the next transmittance inside a tie band,
+# and every alternative outcome is the compositing sum written out.
+
+def _centre_splats(sigmas, rgbs, zs):
+    """A Pre-like record of splats all centred on pixel (2, 2)."""
+    from types import SimpleNamespace
+    n = len(sigmas)
+    return SimpleNamespace(
+        rect=np.array([[0] * n, [4] * n, [0] * n, [4] * n], np.int64),
+        conic=np.array([[1.0] * n, [0.0] * n, [1.0] * n]),
+        u=np.full(n, 2.0), v=np.full(n, 2.0),
+        opacity=np.asarray(sigmas, np.float64),
+        rgb=np.asarray(rgbs, np.float64).T.copy(), z=np.asarray(zs, np.float64))
+
+
+AMIN = float(np.float32(1.0 / 255.0))
+AMAX = float(np.float32(0.99))
+TMIN = float(np.float32(1e-4))
+BG = np.array([0.25, 0.5, 0.75])
+
+
+def _same(outs, expected):
+    assert outs is not None and len(outs) == len(expected)
+    for (c, d, T, n), (ce, de, Te, ne) in zip(outs, expected):
+        assert n == ne
+        assert np.allclose(c, ce, rtol=1e-13, atol=1e-15)
+        assert abs(d - de) <= 1e-13 * abs(de) + 1e-15 and abs(T - Te) <= 1e-13 * Te
+
+
+@pytest.mark.parametrize("rel", [5e-5, -5e-5])
+def test_tie_outcomes_alpha_band_closed_form(rel):
+    """One splat with alpha inside the alpha_min band: the skip outcome
+    (background, T = 1, n = 0) and the blend outcome (a c + (1 - a) bg,
+    D = a z, T = 1 - a, n = 1), the FP64 decision last."""
+    a = AMIN * (1.0 + rel)
+    rgb, z = np.array([0.9, 0.2, 0.4]), 3.5
+    pre = _centre_splats([a], [rgb], [z])
+    outs = F.pixel_outcomes(pre, [0], 2, 2, OPTS, BG)
+    skip = (BG.copy(), 0.0, 1.0, 0)
+    blend = (a * rgb + (1.0 - a) * BG, a * z, 1.0 - a, 1)
+    _same(outs, [skip, blend] if rel > 0 else [blend, skip])
+
+
+def test_tie_outcomes_transmittance_band_closed_form():
+    """A saturated splat (alpha = alpha_max) then one whose blend leaves T
+    just above t_min: the stop outcome (only the first splat) and the blend
+    outcome (both), the FP64 decision (blend) last."""
+    a1 = AMAX
+    T1 = 1.0 - a1
+    a2 = 1.0 - TMIN * (1.0 + 5e-4) / T1
+    c1, c2 = np.array([0.3, 0.6, 0.9]), np.array([0.8, 0.1, 0.5])
+    z1, z2 = 2.0, 2.5
+    pre = _centre_splats([1.0, a2], [c1, c2], [z1, z2])
+    outs = F.pixel_outcomes(pre, [0, 1], 2, 2, OPTS, BG)
+    T2 = T1 * (1.0 - a2)
+    stop = (a1 * c1 + T1 * BG, a1 * z1, T1, 1)
+    both = (a1 * c1 + a2 * T1 * c2 + T2 * BG, a1 * z1 + a2 * T1 * z2, T2, 2)
+    _same(outs, [stop, both])
+    assert TMIN <= T2 <= TMIN * (1.0 + F.T_BAND)
+
+
+def test_tie_outcomes_nested_bands_closed_form():
+    """alpha_min band on the first splat, then a saturated splat, then a
+    splat whose T' lies in the t_min band only on the path that blended the
+    first: three outcomes, each the compositing sum of its own subset."""
+    a0 = AMIN * (1.0 + 5e-5)
+    a1 = AMAX
+    Tb = (1.0 - a0) * (1.0 - a1)              # T before splat 2, splat 0 blended
+    a2 = 1.0 - TMIN * (1.0 + 5e-4) / Tb
+    cs = [np.array([0.1, 0.2, 0.3]), np.array([0.7, 0.4, 0.2]), np.array([0.5, 0.9, 0.6])]
+    zs = [1.5, 2.0, 2.5]
+    pre = _centre_splats([a0, 1.0, a2], cs, zs)
+    outs = F.pixel_outcomes(pre, [0, 1, 2], 2, 2, OPTS, BG)
+
+    def composite(used):
+        T, C, D = 1.0, np.zeros(3), 0.0
+        alphas = [a0, a1, a2]
+        for j in used:
+            C = C + alphas[j] * T * cs[j]
+            D = D + alphas[j] * T * zs[j]
+            T = T * (1.0 - alphas[j])
+        return (C + T * BG, D, T, used[-1] + 1 if used else 0)
+
+    # on the skip branch T before splat 2 is 1 - a1, so T' sits 0.4% above
+    # the FP64 path's: outside the t_min band, splat 2 blends
+    assert (1.0 - a1) * (1.0 - a2) > TMIN * (1.0 + F.T_BAND)
+    _same(outs, [composite([1, 2]), composite([0, 1]), composite([0, 1, 2])])
+
+
+def test_tie_outcomes_none_outside_bands():
+    """Decisions far from both bands give the single FP64 outcome."""
+    pre = _centre_splats([0.5, 0.3], [np.ones(3), np.zeros(3)], [1.0, 2.0])
+    outs = F.pixel_outcomes(pre, [0, 1], 2, 2, OPTS, BG)
+    # D = 0.5 * 1.0 + (0.3 * 0.5) * 2.0
+    _same(outs, [(0.5 * np.ones(3) + 0.35 * BG, 0.8, 0.35, 2)])
