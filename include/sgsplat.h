@@ -172,6 +172,8 @@ typedef struct sgs_outputs {
     float* final_T;                  /* [H][W] transmittance after the last blended splat */
     int32_t* n_contrib;              /* [H][W] 1 + position in the tile list of the last
                                         blended splat, 0 if none */
+    float* alpha;                    /* [H][W] accumulated alpha sum alpha_i T_i = 1 - T_final
+                                        (may be NULL) */
 } sgs_outputs;
 
 /* Byte offsets of the workspace sections, for inspection by tests. */
@@ -189,7 +191,8 @@ typedef struct sgs_layout {
                                n_tiles <= 65536, else u32 */
     size_t pair_values;     /* u32 per pair: item = camera * n + g, in blend order */
     size_t ranges;          /* u32[2] per global tile: [start, end), (0,0) if empty */
-    size_t grad2d;          /* f32[9][items]: d/d(u, v, Qa, Qb, Qc, opacity, r, g, b) */
+    size_t grad2d;          /* f32[10][items]: d/d(u, v, Qa, Qb, Qc, opacity, r, g, b, z);
+                               row 9 only when depth or alpha had a gradient */
     int64_t n_items;        /* n_cams * n */
     int64_t n_tiles;        /* total tiles over all cameras */
     int64_t n_pixels;       /* total pixels over all cameras */
@@ -258,15 +261,20 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams,
  * coefficients; lobe axes through their normalisation, log-sharpness and
  * amplitudes).  Arguments as render_forward; `workspace` and `fwd` must be
  * those of the matching forward (same g, cameras, options, capacity) and
- * untouched since.  `grads`: every array is overwritten (packed layout).
- * Depth has no gradient.  Returns SGS_E_INVALID on a NULL required pointer
- * or a too-small workspace; otherwise enqueues and returns SGS_OK.
+ * untouched since.  grad_image: dL/dimage (device, packed like `image`).
+ * grad_depth, grad_alpha: dL/ddepth and dL/dalpha (device, packed like
+ * `depth`; either may be NULL = zero): depth D = sum alpha_i T_i z_i and
+ * accumulated alpha A = 1 - T_final then pass gradients to every splat's
+ * alpha, and D to its camera depth z (hence to the mean).  `grads`: every
+ * array is overwritten (packed layout).  Returns SGS_E_INVALID on a NULL
+ * required pointer or a too-small workspace; otherwise enqueues and
+ * returns SGS_OK.
  */
 int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams,
                     const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
                     void* workspace, size_t workspace_bytes, int64_t pair_capacity,
-                    const sgs_outputs* fwd, const float* grad_image,
-                    const sgs_grads* grads, void* stream);
+                    const sgs_outputs* fwd, const float* grad_image, const float* grad_depth,
+                    const float* grad_alpha, const sgs_grads* grads, void* stream);
 
 /*
  * render_l1 — L = sum over cameras of mean_{3 H W} |image - target| and
@@ -318,6 +326,42 @@ int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams,
                       const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
                       const void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                       uint64_t* counts, void* stream);
+
+/*
+ * Fused Adam step over every parameter array (the optimiser of the training
+ * the rasteriser serves; paper: Experiments, Implementation — the 3D-GS
+ * learning rates, and the SG lobes introduced after the first 2,000
+ * iterations with learning rate 0.0025).
+ *   lr[8]      learning rate per array, in sgs_gaussians order: means,
+ *              log_scales, quats, opacity_logits, sh, sg_axes,
+ *              sg_log_sharpness, sg_amplitudes (0 leaves an array untouched).
+ *   step       1-based iteration of this update (Adam's t for the arrays
+ *              that train from the start).
+ *   sg_start   the lobe arrays (sg_axes, sg_log_sharpness, sg_amplitudes)
+ *              stay untouched, moments included, while step < sg_start; from
+ *              there their own t = step - sg_start + 1.  0 or 1: from the start.
+ */
+typedef struct sgs_adam {
+    float lr[8];
+    float beta1, beta2, eps;         /* 0 = 0.9, 0.999, 1e-15 (the 3D-GS optimiser's eps) */
+    int32_t step;
+    int32_t sg_start;
+} sgs_adam;
+
+/*
+ * render_adam_step — one Adam update, in float32, of every parameter array
+ * of `g` in place (its arrays must be writable device memory, in the
+ * layout sgs_gaussians describes, colour_stride included):
+ *   m = b1 m + (1 - b1) grad,  v = b2 v + (1 - b2) grad^2,
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * grads: the gradients render_backward wrote (packed).  exp_avg,
+ * exp_avg_sq: the first and second moments, packed like the gradients,
+ * caller-owned, zero before the first step (device).  One launch; no
+ * allocation, no synchronisation.  SGS_E_INVALID on a NULL array that the
+ * form needs, step < 1 or a learning rate < 0.
+ */
+int render_adam_step(const sgs_gaussians* g, const sgs_adam* cfg, const sgs_grads* grads,
+                     const sgs_grads* exp_avg, const sgs_grads* exp_avg_sq, void* stream);
 
 /* render_last_error — message for the last non-zero return on this thread. */
 const char* render_last_error(void);

@@ -33,18 +33,25 @@ GRAD2D = ("u", "v", "Qa", "Qb", "Qc", "sigma", "r", "g", "b")
 
 
 def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile_base=0,
-                   tiles=None):
-    """Per-Gaussian gradients of sum(grad_image * image) w.r.t. the 2D
-    quantities (u, v, Qa, Qb, Qc, sigma, rgb) -> dict of (N,) arrays.  With
-    `tiles`, only those local tiles' pixels are summed (the exact gradient
-    when grad_image is zero elsewhere)."""
+                   tiles=None, grad_depth=None, grad_alpha=None):
+    """Per-Gaussian gradients of sum(grad_image * image) (+ sum(grad_depth *
+    depth) + sum(grad_alpha * alpha), alpha = 1 - T_final) w.r.t. the 2D
+    quantities (u, v, Qa, Qb, Qc, sigma, rgb) and the splat depth z -> dict
+    of (N,) arrays.  With `tiles`, only those local tiles' pixels are summed
+    (the exact gradient when the upstream gradients are zero elsewhere).
+
+    Depth D = sum_j alpha_j T_j z_j:  dD/dalpha_j = T_j z_j - D_j / (1 -
+    alpha_j) with D_j the depth composited behind j, dD/dz_j = alpha_j T_j.
+    Alpha A = 1 - prod_j (1 - alpha_j):  dA/dalpha_j = T_final / (1 - alpha_j)."""
     W, H = int(cam.width), int(cam.height)
     amax = R._f(opts.alpha_max)
     bg = cam.bg.astype(F64)
     GX, GY = pre.grid
     n = pre.z.shape[0]
-    out = {k: np.zeros(n) for k in GRAD2D}
+    out = {k: np.zeros(n) for k in GRAD2D + ("z",)}
     gimg = grad_image.astype(F64)
+    gdep = np.zeros((H, W)) if grad_depth is None else np.asarray(grad_depth, F64).reshape(H, W)
+    galp = np.zeros((H, W)) if grad_alpha is None else np.asarray(grad_alpha, F64).reshape(H, W)
     for t in (range(GX * GY) if tiles is None else tiles):
         tx, ty = t % GX, t // GX
         lo, hi = ranges[tile_base + t]
@@ -55,7 +62,10 @@ def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile
         C, D, Tf, nn, fl, trace = R._blend_tile(pre, entries, px, py, opts, bg,
                                                 want_trace=True)
         gC = gimg[:, py, px]                                  # (3, P)
+        gD = gdep[py, px]
+        gA = galp[py, px]
         S = Tf[None, :] * bg[:, None]                         # colour behind
+        Sd = np.zeros(px.size)                                # depth behind
         for (j, g, blend, a, T) in reversed(trace):
             if not blend.any():
                 continue
@@ -66,8 +76,12 @@ def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile
             out["r"][g] += gr[0]
             out["g"][g] += gr[1]
             out["b"][g] += gr[2]
-            dLda = np.where(blend, (gC * (T * c - S / (1.0 - a))).sum(axis=0), 0.0)
+            out["z"][g] += (gD * w).sum()
+            dLda = np.where(blend, (gC * (T * c - S / (1.0 - a))).sum(axis=0)
+                            + gD * (T * pre.z[g] - Sd / (1.0 - a))
+                            + gA * Tf / (1.0 - a), 0.0)
             S = S + w * c
+            Sd = Sd + w * pre.z[g]
             dx = px - pre.u[g]
             dy = py - pre.v[g]
             Qa, Qb, Qc = pre.conic[:, g]
@@ -85,25 +99,29 @@ def blend_backward(pre, cam, opts, values, ranges, grad_image, cam_index=0, tile
     return out
 
 
-def _pixel_contributions(pre, opts, px, py, gC, blended, T_final, bg):
+def _pixel_contributions(pre, opts, px, py, gC, blended, T_final, bg, gD=0.0, gA=0.0):
     """Back-to-front walk of one pixel's blended splats [(g, alpha, T before
-    it)] ending at T_final: dict g -> 9-vector ordered as GRAD2D."""
+    it)] ending at T_final: dict g -> 10-vector ordered as GRAD2D + (z,)."""
     amax = R._f(opts.alpha_max)
     gC = np.asarray(gC, F64)
     S = T_final * bg
+    Sd = 0.0
     out = {}
     for (g, a, T) in reversed(blended):
         w = a * T
         c = pre.rgb[:, g]
         grgb = gC * w
-        dLda = float((gC * (T * c - S / (1.0 - a))).sum())
+        dLda = float((gC * (T * c - S / (1.0 - a))).sum()
+                     + gD * (T * pre.z[g] - Sd / (1.0 - a)) + gA * T_final / (1.0 - a))
         S = S + w * c
+        Sd = Sd + w * pre.z[g]
         dx = px - pre.u[g]
         dy = py - pre.v[g]
         Qa, Qb, Qc = pre.conic[:, g]
         power = -0.5 * (Qa * dx * dx + 2.0 * Qb * dx * dy + Qc * dy * dy)
         E = np.exp(min(power, 0.0))
-        v = np.zeros(9)
+        v = np.zeros(10)
+        v[9] = gD * w
         if pre.opacity[g] * E <= amax:
             dLdp = dLda * a if power <= 0.0 else 0.0
             v[5] = dLda * E
@@ -117,16 +135,18 @@ def _pixel_contributions(pre, opts, px, py, gC, blended, T_final, bg):
     return out
 
 
-def pixel_backward(pre, cam, opts, px, py, gC):
+def pixel_backward(pre, cam, opts, px, py, gC, gD=0.0, gA=0.0):
     """2D-gradient contributions of one pixel (brute-force list, as in
-    `forward.render_pixel`) for upstream gradient gC (3,): (dict g ->
-    9-vector ordered as GRAD2D, tie flag) on the FP64 decision path."""
+    `forward.render_pixel`) for upstream gradients gC (3,) of its colour and
+    gD, gA of its depth and alpha: (dict g -> 10-vector ordered as GRAD2D +
+    (z,), tie flag) on the FP64 decision path."""
     bg = cam.bg.astype(F64)
     entries = R.pixel_list(pre, px, py)
     pxa, pya = np.array([px]), np.array([py])
     C, D, Tf, nn, fl, trace = R._blend_tile(pre, entries, pxa, pya, opts, bg, want_trace=True)
     blended = [(g, float(a[0]), float(T[0])) for (j, g, blend, a, T) in trace if blend[0]]
-    return _pixel_contributions(pre, opts, px, py, gC, blended, float(Tf[0]), bg), bool(fl[0])
+    return (_pixel_contributions(pre, opts, px, py, gC, blended, float(Tf[0]), bg, gD, gA),
+            bool(fl[0]))
 
 
 def _quat_rotation_grad(w, x, y, z, gR):
@@ -253,6 +273,8 @@ def preprocess_backward(scene, cam, opts, pre, g2):
     gxc[1] += np.where(fyc, 0.0, gJ[1][2] * (-fy / z2))
     gxc[2] += np.where(fyc, gJ[1][2] * (fy * yn_c / z2), gJ[1][2] * (2.0 * fy * xc[1] / (z2 * z)))
     gu, gv = g2["u"], g2["v"]
+    if "z" in g2:                       # the splat depth is the camera-space z
+        gxc[2] += g2["z"]
     gxc[0] += gu * fx / z
     gxc[1] += gv * fy / z
     gxc[2] += -gu * fx * xc[0] / z2 - gv * fy * xc[1] / z2
@@ -272,16 +294,19 @@ def l1_loss(image, target):
     return np.abs(diff).sum() / m, np.sign(diff) / m
 
 
-def render_and_grad(scene, cam, opts, target=None, grad_image=None):
-    """Forward render, L1 loss against `target` (or the given grad image),
-    and the analytic gradient of the raw parameters."""
+def render_and_grad(scene, cam, opts, target=None, grad_image=None, grad_depth=None,
+                    grad_alpha=None):
+    """Forward render, L1 loss against `target` (or the given grad image,
+    and optional depth / alpha upstream gradients), and the analytic
+    gradient of the raw parameters."""
     img = R.render(scene, cam, opts)
     pre = R.preprocess(scene, cam, opts)
     if grad_image is None:
         loss, grad_image = l1_loss(img.image, target)
     else:
         loss = None
-    g2 = blend_backward(pre, cam, opts, img.values, img.ranges, grad_image)
+    g2 = blend_backward(pre, cam, opts, img.values, img.ranges, grad_image,
+                        grad_depth=grad_depth, grad_alpha=grad_alpha)
     grads = preprocess_backward(scene, cam, opts, pre, g2)
     return img, loss, g2, grads
 
@@ -339,5 +364,40 @@ def fd_grad(scene, cam, opts, target, field, index, rel_step=1e-6):
         setattr(sc, field, a)
         vals.append(loss_fn(sc, cam, opts, target))
         if signature(sc, cam, opts, target) != sig0:
+            valid = False
+    return (vals[0] - vals[1]) / (2.0 * h), valid
+
+
+def linear_loss(scene, cam, opts, grad_image, grad_depth=None, grad_alpha=None):
+    """sum(grad_image * image) + sum(grad_depth * depth) + sum(grad_alpha *
+    (1 - T_final)): the loss whose gradient blend_backward takes for these
+    upstream gradients."""
+    img = R.render(scene, cam, opts)
+    L = float((np.asarray(grad_image, F64) * img.image).sum())
+    if grad_depth is not None:
+        L += float((np.asarray(grad_depth, F64) * img.depth).sum())
+    if grad_alpha is not None:
+        L += float((np.asarray(grad_alpha, F64) * (1.0 - img.final_T)).sum())
+    return L
+
+
+def fd_grad_linear(scene, cam, opts, grad_image, grad_depth, grad_alpha, field, index,
+                   rel_step=1e-6):
+    """Central difference of linear_loss w.r.t. scene.<field>[index];
+    (value, valid) with valid False when a discrete decision changes."""
+    arr = getattr(scene, field)
+    base = float(arr[index])
+    h = rel_step * max(1.0, abs(base))
+    zero = np.zeros((3, int(cam.height), int(cam.width)))
+    sig0 = signature(scene, cam, opts, zero)
+    vals = []
+    valid = True
+    for sgn in (+1.0, -1.0):
+        sc = scene.copy()
+        a = getattr(sc, field).astype(np.float64)
+        a[index] = base + sgn * h
+        setattr(sc, field, a)
+        vals.append(linear_loss(sc, cam, opts, grad_image, grad_depth, grad_alpha))
+        if signature(sc, cam, opts, zero) != sig0:
             valid = False
     return (vals[0] - vals[1]) / (2.0 * h), valid

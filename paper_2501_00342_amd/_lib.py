@@ -49,9 +49,14 @@ class Options(Structure):
                 ("pixels_per_thread_bwd", c_int32), ("schedule", c_int32)]
 
 
+class Adam(Structure):
+    _fields_ = [("lr", c_float * 8), ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
+                ("step", c_int32), ("sg_start", c_int32)]
+
+
 class Outputs(Structure):
     _fields_ = [("image", c_void_p), ("depth", c_void_p), ("final_T", c_void_p),
-                ("n_contrib", c_void_p)]
+                ("n_contrib", c_void_p), ("alpha", c_void_p)]
 
 
 class Layout(Structure):
@@ -65,7 +70,8 @@ class Layout(Structure):
 
 EXPORTS = ("render_workspace_bytes", "render_layout", "render_forward", "render_backward",
            "render_l1", "render_status", "render_read_keys", "render_set_timing",
-           "render_stage_times", "render_stage_name", "render_blend_work", "render_last_error")
+           "render_stage_times", "render_stage_name", "render_blend_work", "render_adam_step",
+           "render_last_error")
 N_STAGES = 11
 
 
@@ -87,7 +93,7 @@ def _load():
     lib.render_backward.restype = c_int32
     lib.render_backward.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
                                     c_void_p, c_size_t, c_int64, P(Outputs), c_void_p,
-                                    P(Grads), c_void_p]
+                                    c_void_p, c_void_p, P(Grads), c_void_p]
     lib.render_l1.restype = c_int32
     lib.render_l1.argtypes = [P(Camera), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]
@@ -104,6 +110,8 @@ def _load():
     lib.render_blend_work.restype = c_int32
     lib.render_blend_work.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
                                       c_void_p, c_size_t, c_int64, c_void_p, c_void_p]
+    lib.render_adam_step.restype = c_int32
+    lib.render_adam_step.argtypes = [P(Gaussians), P(Adam), P(Grads), P(Grads), P(Grads), c_void_p]
     lib.render_last_error.restype = c_char_p
     lib.render_last_error.argtypes = []
     return lib
@@ -191,7 +199,7 @@ def grads_struct(ptrs: dict) -> Grads:
     return g
 
 
-__all__ = ["LIB", "LIB_PATH", "EXPORTS", "Gaussians", "Grads", "Camera", "Options", "Outputs",
+__all__ = ["LIB", "LIB_PATH", "EXPORTS", "Gaussians", "Grads", "Camera", "Options", "Outputs", "Adam",
            "Layout", "check", "last_error", "SgsError", "camera_struct", "camera_array",
            "options_struct", "gaussians_struct", "grads_struct", "c_int64", "c_uint32",
            "c_double", "c_uint64"]

@@ -26,7 +26,8 @@
 // n_contrib, recomputing alpha with the same instructions, T_j =
 // T_{j+1} / (1 - alpha_j).  Per-Gaussian 2D gradients are summed over a
 // thread's pixels, then across the wave (lane swaps and DPP), and added with
-// one float atomic per value per wave.
+// one float atomic per value per wave.  Depth and accumulated alpha may
+// carry upstream gradients too (then the splat depth z gets one).
 
 #include "common.hpp"
 #include "occupancy.hpp"
@@ -208,6 +209,7 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
         img[W * H + pix] = C1[k] + T[k] * c.bg[1];
         img[2 * W * H + pix] = C2[k] + T[k] * c.bg[2];
         if (out.depth) out.depth[ct.pix_base + pix] = D[k];
+        if (out.alpha) out.alpha[ct.pix_base + pix] = 1.0f - T[k];
         out.final_T[ct.pix_base + pix] = T[k];
         out.n_contrib[ct.pix_base + pix] = n[k];
     }
@@ -289,17 +291,19 @@ __device__ __forceinline__ float2 swap32(float a, float b) {
     return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
-// Sums of nine per-lane values over the wave, scattered over the rows (a
-// reduce-scatter: two halving steps with the gfx950 lane-swap instructions,
-// then a row reduction of three values with DPP, 28 VALU instead of 54 for
-// nine full reductions).  Afterwards every lane of row r (lanes 16 r .. 16 r
-// + 15) holds in x[i] the total of value 4 i + 2 q + h, q = r & 1, h = r >> 1
-// (values 9, 10 and 11 are zero).
-__device__ __forceinline__ void wave_sum9(const float v[9], float x[3]) {
+// Sums of NV (9 or 10) per-lane values over the wave, scattered over the
+// rows (a reduce-scatter: two halving steps with the gfx950 lane-swap
+// instructions, then a row reduction of three values with DPP, 28 VALU
+// instead of 54 for nine full reductions).  Afterwards every lane of row r
+// (lanes 16 r .. 16 r + 15) holds in x[i] the total of value 4 i + 2 q + h,
+// q = r & 1, h = r >> 1 (values NV .. 11 are zero).
+template <int NV>
+__device__ __forceinline__ void wave_sum(const float v[NV], float x[3]) {
+    static_assert(NV >= 9 && NV <= 10, "two halving steps and three row sums cover 9-12 values");
     float w[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-        const float2 t = swap32(v[2 * j], 2 * j + 1 < 9 ? v[2 * j + 1] : 0.0f);
+        const float2 t = swap32(v[2 * j], 2 * j + 1 < NV ? v[2 * j + 1] : 0.0f);
         w[j] = t.x + t.y;   // lanes 0-31: value 2j, lanes 32-63: value 2j + 1
     }
 #pragma unroll
@@ -316,10 +320,23 @@ __device__ __forceinline__ void wave_sum9(const float v[9], float x[3]) {
     }
 }
 
-template <int TW, int TH, int PPT>
+// Upstream gradients of the backward: the image, and (DG) the depth and the
+// accumulated alpha (either may be NULL: zero).
+struct Upstream {
+    const float* image;
+    const float* depth;
+    const float* alpha;
+};
+
+// DG: the depth D = sum alpha T z and accumulated alpha A = 1 - T_final
+// have upstream gradients too.  With gD, gA the pixel's gradients of D and
+// A, the scalar carried back to front becomes gC.S + gD D_behind - gA T_f
+// (dA/dalpha_j = T_f / (1 - alpha_j)), each splat's front term adds gD z,
+// and dL/dz = gD alpha T is a tenth 2D gradient.
+template <int TW, int TH, int PPT, bool DG>
 __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
                                          int n_cams, const Opts& o, const sgs_outputs& fwd,
-                                         const float* __restrict__ grad_image, int batch,
+                                         const Upstream& up, int batch,
                                          int64_t tile, Entry* s_e, int* s_cam, int* s_maxn) {
     constexpr int NT = TW * TH / PPT;
     const int tid = threadIdx.x;
@@ -343,18 +360,20 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     const float amin = o.alpha_min, amax = o.alpha_max;
     const sgs_camera& c = cams[cam];
     const int64_t W = ct.W, H = ct.H;
-    const float* gi = grad_image + 3 * ct.pix_base;
+    const float* gi = up.image + 3 * ct.pix_base;
 
     // SG: dL/dC . S, S = colour composited behind the current splat (only its
-    // product with the pixel's upstream gradient is needed)
-    float T[PPT], g0[PPT], g1[PPT], g2[PPT], SG[PPT];
+    // product with the pixel's upstream gradient is needed); with DG also
+    // gD D_behind - gA T_f
+    float T[PPT], g0[PPT], g1[PPT], g2[PPT], SG[PPT], gD[PPT];
     int nc[PPT];
     int my_max = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int px = x0 + lx, py = y0 + ry + k;
         T[k] = 1.0f;
-        g0[k] = g1[k] = g2[k] = 0.0f;
+        g0[k] = g1[k] = g2[k] = gD[k] = 0.0f;
+        float gA = 0.0f;
         nc[k] = 0;
         if (px < ct.W && py < ct.H) {
             const int64_t pix = (int64_t)py * W + px;
@@ -363,9 +382,14 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
             g0[k] = gi[pix];
             g1[k] = gi[W * H + pix];
             g2[k] = gi[2 * W * H + pix];
+            if (DG) {
+                if (up.depth) gD[k] = up.depth[ct.pix_base + pix];
+                if (up.alpha) gA = up.alpha[ct.pix_base + pix];
+            }
         }
         if (nc[k] > len) nc[k] = (int)len;
         SG[k] = T[k] * (c.bg[0] * g0[k] + c.bg[1] * g1[k] + c.bg[2] * g2[k]);
+        if (DG) SG[k] -= gA * T[k];
         my_max = nc[k] > my_max ? nc[k] : my_max;
     }
     if (my_max > 0) atomicMax(s_maxn, my_max);
@@ -386,7 +410,7 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
             const Entry e = s_e[j];
             const int pos = bb + j;
             float v_u = 0.f, v_v = 0.f, v_qa = 0.f, v_qb = 0.f, v_qc = 0.f, v_s = 0.f;
-            float v_r = 0.f, v_g = 0.f, v_b = 0.f;
+            float v_r = 0.f, v_g = 0.f, v_b = 0.f, v_z = 0.f;
             bool contrib = false;
             if (e.m.x & colbit) {
                 const float dx = lxf + e.a.x;
@@ -405,7 +429,11 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                     v_r = fmaf(w, g0[k], v_r);
                     v_g = fmaf(w, g1[k], v_g);
                     v_b = fmaf(w, g2[k], v_b);
-                    const float cg = e.c.x * g0[k] + e.c.y * g1[k] + e.c.z * g2[k];
+                    float cg = e.c.x * g0[k] + e.c.y * g1[k] + e.c.z * g2[k];
+                    if (DG) {
+                        cg = fmaf(e.b.w, gD[k], cg);   // + z gD
+                        v_z = fmaf(w, gD[k], v_z);      // dL/dz = alpha T gD
+                    }
                     const float sg = SG[k];
                     const float dLda = T[k] * cg - sg * iom;
                     SG[k] = fmaf(w, cg, SG[k]);
@@ -423,22 +451,23 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                 }
             }
             if (__any(contrib)) {
-                const float vals[9] = {v_u, v_v, v_qa, v_qb, v_qc, v_s, v_r, v_g, v_b};
+                constexpr int NV = DG ? 10 : 9;
+                const float vals[10] = {v_u, v_v, v_qa, v_qb, v_qc, v_s, v_r, v_g, v_b, v_z};
                 float x[3];
-                wave_sum9(vals, x);
+                wave_sum<NV>(vals, x);
                 // the entry is the same in every lane: its address is scalar
                 const int64_t item =
                     __builtin_amdgcn_readfirstlane(__float_as_uint(e.c.w));
                 float* gi = G + item;
                 // every lane of row r holds the row's totals: lane 15 adds
                 // x[0] to channel ch, lane 14 x[1] to channel 4 + ch and, in
-                // row 0, lane 13 x[2] to channel 8 -- nine lanes of one
-                // atomic instruction (channel order of grad2d: u, v, Qa, Qb,
-                // Qc, sigma, r, g, b)
+                // the rows with ch < NV - 8, lane 13 x[2] to channel 8 + ch
+                // -- NV lanes of one atomic instruction (channel order of
+                // grad2d: u, v, Qa, Qb, Qc, sigma, r, g, b, z)
                 const int r = lane >> 4, sel = 15 - (lane & 15);
-                if (sel < 2 || (sel == 2 && r == 0)) {
-                    const int ch = 2 * (r & 1) + (r >> 1);
-                    const int chan = sel == 0 ? ch : (sel == 1 ? 4 + ch : 8);
+                const int ch = 2 * (r & 1) + (r >> 1);
+                if (sel < 2 || (sel == 2 && ch < NV - 8)) {
+                    const int chan = sel == 0 ? ch : (sel == 1 ? 4 + ch : 8 + ch);
                     unsafeAtomicAdd(gi + chan * M, sel == 0 ? x[0] : (sel == 1 ? x[1] : x[2]));
                 }
             }
@@ -446,10 +475,10 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     }
 }
 
-template <int TW, int TH, int PPT, bool QUEUE>
+template <int TW, int TH, int PPT, bool QUEUE, bool DG>
 __global__ void __launch_bounds__(TW * TH / PPT)
 k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
-            sgs_outputs fwd, const float* __restrict__ grad_image, int batch) {
+            sgs_outputs fwd, Upstream up, int batch) {
     extern __shared__ __align__(16) Entry s_e[];
     __shared__ int s_cam;
     __shared__ int s_maxn;
@@ -459,12 +488,12 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
         for (;;) {
             const int64_t tile = pop_tile(ws, ws.header + kHdrQueueBwd, &s_next);
             if (tile < 0) break;
-            bwd_tile<TW, TH, PPT>(ws, cams, n_cams, o, fwd, grad_image, batch, tile, s_e, &s_cam,
-                                  &s_maxn);
+            bwd_tile<TW, TH, PPT, DG>(ws, cams, n_cams, o, fwd, up, batch, tile, s_e, &s_cam,
+                                      &s_maxn);
         }
     } else {
-        bwd_tile<TW, TH, PPT>(ws, cams, n_cams, o, fwd, grad_image, batch,
-                              xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, &s_maxn);
+        bwd_tile<TW, TH, PPT, DG>(ws, cams, n_cams, o, fwd, up, batch,
+                                  xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, &s_maxn);
     }
 }
 
@@ -500,19 +529,28 @@ static void launch_count_t(const Workspace& ws, const sgs_camera* cams, int n_ca
                        reinterpret_cast<unsigned long long*>(counts));
 }
 
-template <int TW, int TH, int PPT>
-static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
-                         const sgs_outputs& fwd, const float* gi, bool queue, hipStream_t s) {
+template <int TW, int TH, int PPT, bool DG>
+static void launch_bwd_dg(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
+                          const sgs_outputs& fwd, const Upstream& up, bool queue, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     constexpr int NT = TW * TH / PPT;
     if (queue) {
-        auto k = k_blend_bwd<TW, TH, PPT, true>;
+        auto k = k_blend_bwd<TW, TH, PPT, true, DG>;
         hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, NT, lds), ws.n_tiles)), dim3(NT), lds,
-                           s, ws, cams, n_cams, o, fwd, gi, o.batch);
+                           s, ws, cams, n_cams, o, fwd, up, o.batch);
     } else {
-        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false>), dim3((unsigned)ws.n_tiles), dim3(NT),
-                           lds, s, ws, cams, n_cams, o, fwd, gi, o.batch);
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false, DG>), dim3((unsigned)ws.n_tiles),
+                           dim3(NT), lds, s, ws, cams, n_cams, o, fwd, up, o.batch);
     }
+}
+
+template <int TW, int TH, int PPT>
+static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
+                         const sgs_outputs& fwd, const Upstream& up, bool queue, hipStream_t s) {
+    if (up.depth || up.alpha)
+        launch_bwd_dg<TW, TH, PPT, true>(ws, cams, n_cams, o, fwd, up, queue, s);
+    else
+        launch_bwd_dg<TW, TH, PPT, false>(ws, cams, n_cams, o, fwd, up, queue, s);
 }
 
 // supported (tile, pixels per thread): the block is a whole number of waves
@@ -542,9 +580,11 @@ void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_c
 }
 
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                      const sgs_outputs& fwd, const float* grad_image, bool queue, hipStream_t s) {
+                      const sgs_outputs& fwd, const float* grad_image, const float* grad_depth,
+                      const float* grad_alpha, bool queue, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, grad_image, queue, s)
+    const Upstream up = {grad_image, grad_depth, grad_alpha};
+    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, up, queue, s)
 }
 
 // ---------------------------------------------------------------------------

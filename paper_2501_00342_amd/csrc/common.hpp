@@ -136,7 +136,25 @@ struct Workspace {
     bool key16;                  // pair tile ids stored as u16 (at most 65536 tiles)
 };
 
+// the fused Adam step: one entry per parameter array, in sgs_gaussians order
+constexpr int kAdamArrays = 8;
+struct AdamArrays {
+    float* p[kAdamArrays];
+    const float* g[kAdamArrays];
+    float* m[kAdamArrays];
+    float* v[kAdamArrays];
+    int64_t count[kAdamArrays];    // elements (packed)
+    int64_t width[kAdamArrays];    // floats per Gaussian on the packed side (count: one flat run)
+    int64_t pstride[kAdamArrays];  // floats per Gaussian on the parameter side (== width: packed)
+    float lr[kAdamArrays];
+    float c1[kAdamArrays];         // 1 / (1 - b1^t)
+    float c2[kAdamArrays];         // 1 / (1 - b2^t)
+    bool on[kAdamArrays];
+    float b1, b2, eps;
+};
+
 // launchers (defined in the .hip files)
+void launch_adam(const AdamArrays& a, hipStream_t s);
 void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, int tile_w, int tile_h,
                   float guard, hipStream_t s);
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
@@ -177,10 +195,15 @@ void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cam
                       const sgs_outputs& out, bool queue, hipStream_t s);
 void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                         uint64_t* counts, hipStream_t s);
+// grad_depth / grad_alpha may be NULL (no upstream gradient); with either,
+// the blend also adds dL/dz into grad2d row 9
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                      const sgs_outputs& fwd, const float* grad_image, bool queue, hipStream_t s);
+                      const sgs_outputs& fwd, const float* grad_image, const float* grad_depth,
+                      const float* grad_alpha, bool queue, hipStream_t s);
+// depth_grad: grad2d row 9 (dL/dz per item) holds the depth term
 void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                           const Workspace& ws, const sgs_grads& gr, hipStream_t s);
+                           const Workspace& ws, const sgs_grads& gr, bool depth_grad,
+                           hipStream_t s);
 void launch_l1(const Workspace& ws, int n_cams, const float* image, const float* target,
                float* grad, double* loss, hipStream_t s);
 void launch_read_keys(const Workspace& ws, int64_t count, uint64_t* keys, hipStream_t s);

@@ -183,7 +183,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     L.ranges = take((size_t)tiles * 8);
     pl->tile_keys = take((size_t)tiles * 4);
     pl->tile_order = take((size_t)tiles * 4);
-    L.grad2d = take((size_t)items * 9 * 4);
+    L.grad2d = take((size_t)items * 10 * 4);
     pl->gx_colour = take((size_t)n * 3 * 4);
     pl->counts = take((size_t)pl->max_parts * sgs::kRadix * 4);
     pl->totals = take((size_t)sgs::kRadix * 4);
@@ -476,7 +476,8 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
 int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
                     int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
                     int64_t pair_capacity, const sgs_outputs* fwd, const float* grad_image,
-                    const sgs_grads* grads, void* stream) {
+                    const float* grad_depth, const float* grad_alpha, const sgs_grads* grads,
+                    void* stream) {
     Plan pl;
     int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
     if (rc != SGS_OK) return rc;
@@ -497,14 +498,17 @@ int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const s
     (void)hipGetLastError();
     if (pl.n == 0) return SGS_OK;
     Marker mk{timing_slot(g_timing.bwd, g_timing.bwd_used), s};
+    const bool dg = grad_depth || grad_alpha;
     mk.mark(0);
-    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, 9 * ws.n_items, s);
+    // row 9 (dL/dz) only when depth or alpha carry a gradient
+    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, (dg ? 10 : 9) * ws.n_items, s);
     if (pl.queue) sgs::launch_fill_u32(ws.header + sgs::kHdrQueueBwd, 0u, 1, s);
     mk.mark(1);
-    sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, pl.queue, s);
+    sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, grad_depth, grad_alpha,
+                          pl.queue, s);
     SGS_LAUNCHED();
     mk.mark(2);
-    sgs::launch_preprocess_bwd(p, dev_cams, n_cams, pl.o, ws, *grads, s);
+    sgs::launch_preprocess_bwd(p, dev_cams, n_cams, pl.o, ws, *grads, dg, s);
     SGS_LAUNCHED();
     mk.mark(3);
     return SGS_OK;
@@ -609,6 +613,72 @@ int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams, const
     (void)hipGetLastError();
     sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 0u, 6, s);
     sgs::launch_blend_count(ws, dev_cams, n_cams, pl.o, counts, s);
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
+int render_adam_step(const sgs_gaussians* g, const sgs_adam* cfg, const sgs_grads* grads,
+                     const sgs_grads* exp_avg, const sgs_grads* exp_avg_sq, void* stream) {
+    if (!g || !cfg || !grads || !exp_avg || !exp_avg_sq)
+        return fail(SGS_E_INVALID, "a required Adam argument is NULL");
+    if (g->n < 0 || g->sh_degree < 0 || g->sh_degree > SGS_MAX_SH_DEGREE || g->n_lobes < 0 ||
+        g->n_lobes > SGS_MAX_LOBES)
+        return fail(SGS_E_INVALID, "invalid Gaussian form");
+    if (g->lobe_axes != SGS_LOBES_FREE && g->lobe_axes != SGS_LOBES_WORLD &&
+        g->lobe_axes != SGS_LOBES_FRAME)
+        return fail(SGS_E_INVALID, "lobe_axes must be SGS_LOBES_FREE, _WORLD or _FRAME");
+    if (cfg->step < 1) return fail(SGS_E_INVALID, "step must be >= 1");
+    int rc = check_params(g);
+    if (rc != SGS_OK) return rc;
+    const int64_t n = g->n;
+    const int64_t nc3 = 3 * (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1), K = g->n_lobes;
+    const int64_t width[sgs::kAdamArrays] = {3 * n, 3 * n, 4 * n, n, nc3, 3 * (int64_t)axis_rows(g), K, 3 * K};
+    const bool colour[sgs::kAdamArrays] = {false, false, false, false, true, true, true, true};
+    const bool lobe[sgs::kAdamArrays] = {false, false, false, false, false, true, true, true};
+    const float* params[sgs::kAdamArrays] = {g->means, g->log_scales, g->quats, g->opacity_logits,
+                                             g->sh, g->sg_axes, g->sg_log_sharpness, g->sg_amplitudes};
+    auto arrays = [](const sgs_grads* x, float* out[sgs::kAdamArrays]) {
+        float* const f[sgs::kAdamArrays] = {x->means, x->log_scales, x->quats, x->opacity_logits,
+                                            x->sh, x->sg_axes, x->sg_log_sharpness, x->sg_amplitudes};
+        for (int k = 0; k < sgs::kAdamArrays; ++k) out[k] = f[k];
+    };
+    float *gr[sgs::kAdamArrays], *m[sgs::kAdamArrays], *v[sgs::kAdamArrays];
+    arrays(grads, gr);
+    arrays(exp_avg, m);
+    arrays(exp_avg_sq, v);
+    sgs::AdamArrays a;
+    memset(&a, 0, sizeof(a));
+    const double b1 = cfg->beta1 != 0.0f ? cfg->beta1 : 0.9f;
+    const double b2 = cfg->beta2 != 0.0f ? cfg->beta2 : 0.999f;
+    if (!(b1 > 0.0 && b1 < 1.0 && b2 > 0.0 && b2 < 1.0))
+        return fail(SGS_E_INVALID, "beta1 and beta2 must be in (0, 1)");
+    a.b1 = (float)b1;
+    a.b2 = (float)b2;
+    a.eps = cfg->eps != 0.0f ? cfg->eps : 1e-15f;
+    const int sg0 = cfg->sg_start > 1 ? cfg->sg_start : 1;
+    for (int k = 0; k < sgs::kAdamArrays; ++k) {
+        if (!(cfg->lr[k] >= 0.0f)) return fail(SGS_E_INVALID, "learning rates must be >= 0");
+        const int64_t count = colour[k] ? n * width[k] : width[k];
+        const int t = lobe[k] ? cfg->step - sg0 + 1 : cfg->step;
+        a.on[k] = count > 0 && cfg->lr[k] > 0.0f && t >= 1;
+        if (!a.on[k]) continue;
+        if (!params[k] || !gr[k] || !m[k] || !v[k])
+            return fail(SGS_E_INVALID, "a parameter, gradient or moment array is NULL");
+        a.p[k] = const_cast<float*>(params[k]);
+        a.g[k] = gr[k];
+        a.m[k] = m[k];
+        a.v[k] = v[k];
+        a.count[k] = count;
+        // geometry rows and packed colour arrays are flat runs
+        const int64_t cs = g->colour_stride;
+        a.width[k] = colour[k] ? width[k] : count;
+        a.pstride[k] = colour[k] && cs > 0 ? cs : a.width[k];
+        a.lr[k] = cfg->lr[k];
+        a.c1[k] = (float)(1.0 / (1.0 - std::pow(b1, (double)t)));
+        a.c2[k] = (float)(1.0 / (1.0 - std::pow(b2, (double)t)));
+    }
+    (void)hipGetLastError();
+    sgs::launch_adam(a, static_cast<hipStream_t>(stream));
     SGS_LAUNCHED();
     return SGS_OK;
 }

@@ -185,7 +185,7 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
 
 __global__ void __launch_bounds__(kPreThreads)
 k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws,
-           sgs_grads gr, const float* __restrict__ gx_colour) {
+           sgs_grads gr, const float* __restrict__ gx_colour, bool depth_grad) {
     const int64_t n = p.n;
     const int64_t M = ws.n_items;
     const double dil = o.dilation;
@@ -242,6 +242,9 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
 #pragma unroll
             for (int c = 0; c < 6; ++c) g2d[c] = ci == 0 ? cur.g0[c] : ws.grad2d[c * M + item];
             const double gu = g2d[0], gv = g2d[1];
+            // depth z = x_cam[2] carries dL/dz from the blend when depth or
+            // alpha had an upstream gradient
+            const double gzd = depth_grad ? (double)ws.grad2d[9 * M + item] : 0.0;
             const double gQa = g2d[2], gQb = g2d[3];
             const double gQc = g2d[4];
             glogit += (double)g2d[5] * sig * (1.0 - sig);
@@ -318,7 +321,7 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
             // J and (u, v) -> camera-space mean
             const double iz2 = iz * iz;
             double g0 = gu * fx * iz, g1 = gv * fy * iz;
-            double g2 = -(gJ00 * fx + gJ11 * fy) * iz2 - (gu * fx * xc[0] + gv * fy * xc[1]) * iz2;
+            double g2 = -(gJ00 * fx + gJ11 * fy) * iz2 - (gu * fx * xc[0] + gv * fy * xc[1]) * iz2 + gzd;
             if (clx) {
                 g2 += gJ02 * fx * xnc * iz2;
             } else {
@@ -347,7 +350,8 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
 }
 
 void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
-                           const Workspace& ws, const sgs_grads& gr, hipStream_t s) {
+                           const Workspace& ws, const sgs_grads& gr, bool depth_grad,
+                           hipStream_t s) {
     if (p.n <= 0) return;
     int64_t blocks = (p.n + kPreThreads - 1) / kPreThreads;
     if (blocks > 4096) blocks = 4096;
@@ -371,7 +375,7 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     }
 #undef SGS_COLOUR_BWD_K
 #undef SGS_COLOUR_BWD
-    hipLaunchKernelGGL(k_geom_bwd, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr, gxc);
+    hipLaunchKernelGGL(k_geom_bwd, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr, gxc, depth_grad);
 }
 
 }  // namespace sgs

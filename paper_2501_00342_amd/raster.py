@@ -106,6 +106,11 @@ class Outputs:
     depth: torch.Tensor      # packed (sum W H,)
     final_T: torch.Tensor
     n_contrib: torch.Tensor  # int32
+    alpha: torch.Tensor | None = None   # packed (sum W H,): 1 - final_T, when asked for
+
+    def struct(self) -> "L.Outputs":
+        return L.Outputs(_ptr(self.image), _ptr(self.depth), _ptr(self.final_T),
+                         _ptr(self.n_contrib), _ptr(self.alpha))
 
     def camera(self, k: int, cams) -> tuple:
         """(image (3,H,W), depth, final_T, n_contrib) views of camera k."""
@@ -173,13 +178,14 @@ class Rasterizer:
         self.ws = torch.empty(int(lay.total_bytes), dtype=torch.uint8, device=self.device)
         self.generation += 1
 
-    def new_outputs(self) -> Outputs:
+    def new_outputs(self, alpha: bool = False) -> Outputs:
         P = self.n_pixels
         d = self.device
         return Outputs(torch.empty(3 * P, dtype=torch.float32, device=d),
                        torch.empty(P, dtype=torch.float32, device=d),
                        torch.empty(P, dtype=torch.float32, device=d),
-                       torch.empty(P, dtype=torch.int32, device=d))
+                       torch.empty(P, dtype=torch.int32, device=d),
+                       torch.empty(P, dtype=torch.float32, device=d) if alpha else None)
 
     def _check_params(self, params):
         for k in FIELDS:
@@ -197,7 +203,7 @@ class Rasterizer:
         out = out or self.new_outputs()
         check = self.auto_grow if check is None else check
         g = self._gstruct(params)
-        o = L.Outputs(_ptr(out.image), _ptr(out.depth), _ptr(out.final_T), _ptr(out.n_contrib))
+        o = out.struct()
         need = L.c_int64(0)
         flags = L.SGS_FLAG_CHECK_CAPACITY if check else 0
         self.generation += 1
@@ -218,28 +224,36 @@ class Rasterizer:
             L.check(rc)
             return out
 
-    def backward(self, params: dict, out: Outputs, grad_image: torch.Tensor) -> dict:
+    def backward(self, params: dict, out: Outputs, grad_image: torch.Tensor,
+                 grad_depth: torch.Tensor | None = None,
+                 grad_alpha: torch.Tensor | None = None) -> dict:
         grads = new_grads(params)
-        self.backward_into(params, out, grad_image, grads)
+        self.backward_into(params, out, grad_image, grads, grad_depth, grad_alpha)
         return grads
 
     def backward_into(self, params: dict, out: Outputs, grad_image: torch.Tensor,
-                      grads: dict) -> dict:
+                      grads: dict, grad_depth: torch.Tensor | None = None,
+                      grad_alpha: torch.Tensor | None = None) -> dict:
         """Backward writing into preallocated gradient tensors (no allocation:
-        usable under stream capture)."""
+        usable under stream capture).  grad_depth / grad_alpha: optional
+        upstream gradients of the depth and accumulated-alpha images."""
         self._check_params(params)
         assert grad_image.dtype == torch.float32 and grad_image.is_contiguous()
         assert grad_image.numel() == 3 * self.n_pixels
+        for t in (grad_depth, grad_alpha):
+            assert t is None or (t.dtype == torch.float32 and t.is_contiguous()
+                                 and t.numel() == self.n_pixels)
         for k in FIELDS:   # the backward writes every gradient array packed
             assert grads[k].is_contiguous() and grads[k].shape == params[k].shape, k
         g = self._gstruct(params)
         gr = L.grads_struct({k: (grads[k].data_ptr() if grads[k].numel() else None)
                              for k in FIELDS})
-        o = L.Outputs(_ptr(out.image), _ptr(out.depth), _ptr(out.final_T), _ptr(out.n_contrib))
+        o = out.struct()
         L.check(L.LIB.render_backward(ctypes.byref(g), self.host_cams, _ptr(self.dev_cams),
                                       len(self.cams), ctypes.byref(self.copts), _ptr(self.ws),
                                       self.ws.numel(), self.capacity, ctypes.byref(o),
-                                      _ptr(grad_image), ctypes.byref(gr), _stream()))
+                                      _ptr(grad_image), _ptr(grad_depth), _ptr(grad_alpha),
+                                      ctypes.byref(gr), _stream()))
         return grads
 
     def l1(self, image: torch.Tensor, target: torch.Tensor, grad_out: torch.Tensor | None = None):
@@ -287,7 +301,9 @@ class Rasterizer:
         return self._view(self.layout.pair_values, count, torch.int32)
 
     def grad2d(self):
-        return self._view(self.layout.grad2d, 9 * self.layout.n_items, torch.float32).view(9, -1)
+        """(10, items): d/d(u, v, Qa, Qb, Qc, opacity, r, g, b, z) of the last
+        backward (row 9 only after one with a depth or alpha gradient)."""
+        return self._view(self.layout.grad2d, 10 * self.layout.n_items, torch.float32).view(10, -1)
 
     def sorted_keys(self, count) -> torch.Tensor:
         keys = torch.empty(count, dtype=torch.int64, device=self.device)
@@ -305,16 +321,18 @@ class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rast: Rasterizer, *params):
         p = dict(zip(FIELDS, params))
-        out = rast.forward(p)
+        out = rast.forward(p, out=rast.new_outputs(alpha=True))
         ctx.rast = rast
         ctx.generation = rast.generation
         ctx.out = out
         ctx.save_for_backward(*params)
-        ctx.mark_non_differentiable(out.depth, out.final_T, out.n_contrib)
-        return out.image, out.depth, out.final_T, out.n_contrib
+        ctx.mark_non_differentiable(out.final_T, out.n_contrib)
+        # unused outputs give None, not zeros: no depth or alpha pass then
+        ctx.set_materialize_grads(False)
+        return out.image, out.depth, out.alpha, out.final_T, out.n_contrib
 
     @staticmethod
-    def backward(ctx, g_image, *_):
+    def backward(ctx, g_image, g_depth, g_alpha, *_):
         # the backward walks the tile lists of the workspace: they must still
         # be those of this forward
         if ctx.rast.generation != ctx.generation:
@@ -323,11 +341,23 @@ class _RenderFn(torch.autograd.Function):
                 "render; its backward would read that render's tile lists.  Call backward "
                 "before the next forward, or use one Rasterizer per pending render.")
         params = dict(zip(FIELDS, ctx.saved_tensors))
-        grads = ctx.rast.backward(params, ctx.out, g_image.contiguous())
+        if g_image is None:
+            g_image = torch.zeros_like(ctx.out.image)
+        grads = ctx.rast.backward(params, ctx.out, g_image.contiguous(),
+                                  None if g_depth is None else g_depth.contiguous(),
+                                  None if g_alpha is None else g_alpha.contiguous())
         return (None, *[grads[k] for k in FIELDS])
 
 
 def render(rast: Rasterizer, params: dict):
     """Differentiable render: returns packed (image, depth, final_T,
-    n_contrib); only `image` carries gradients (to every parameter)."""
+    n_contrib); image and depth carry gradients to every parameter."""
+    image, depth, alpha, final_T, n_contrib = _RenderFn.apply(rast, *[params[k] for k in FIELDS])
+    return image, depth, final_T, n_contrib
+
+
+def render_with_alpha(rast: Rasterizer, params: dict):
+    """Differentiable render with the accumulated alpha (1 - final_T):
+    returns packed (image, depth, alpha, final_T, n_contrib); image, depth
+    and alpha carry gradients."""
     return _RenderFn.apply(rast, *[params[k] for k in FIELDS])

@@ -145,7 +145,7 @@ def test_forward_rejects_null_arguments_before_any_launch(lib):
                                 ctypes.byref(outs), 0, None, None)
     assert rc == lib.SGS_E_INVALID
     rc = lib.LIB.render_backward(ctypes.byref(g), cams, None, 1, ctypes.byref(o), None, 0, cap,
-                                 None, None, None, None)
+                                 None, None, None, None, None, None)
     assert rc == lib.SGS_E_INVALID
 
 

@@ -16,13 +16,17 @@ class _StandIn:
         self.generation = 1
         self.backwards = 0
 
-    def forward(self, p):
+    def forward(self, p, out=None):
         self.generation += 1
         n = 4
         return raster.Outputs(p["opacity_logits"].detach().repeat(3) * 1.0,
-                              torch.zeros(n), torch.ones(n), torch.zeros(n, dtype=torch.int32))
+                              torch.zeros(n), torch.ones(n), torch.zeros(n, dtype=torch.int32),
+                              torch.zeros(n))
 
-    def backward(self, params, out, g):
+    def new_outputs(self, alpha=False):
+        return None
+
+    def backward(self, params, out, g, g_depth=None, g_alpha=None):
         self.backwards += 1
         return {k: torch.zeros_like(v) for k, v in params.items()}
 

@@ -99,7 +99,7 @@ def test_l1_kernel_matches_definition():
 def test_autograd_function_equals_explicit_backward():
     sc, cam = scenes.small_clustered(2000, 26, 64, 48)
     opts = scenes.Options()
-    rast = raster.Rasterizer([cam], opts, sc.n, sc.sh_degree, sc.n_lobes)
+    rast = raster.Rasterizer.for_scene(sc, [cam], opts)
     params = raster.params_to_device(sc)
     leaves = {k: v.clone().requires_grad_(True) for k, v in params.items()}
     image, depth, T, n = raster.render(rast, leaves)
@@ -137,3 +137,65 @@ def test_batched_backward_sums_camera_gradients():
         a, b = gb[k].double(), total[k].double()
         scale = float(b.abs().max()) + 1e-30
         assert float((a - b).abs().max()) <= 1e-4 * scale, k
+
+
+def test_depth_and_alpha_gradients_match_oracle():
+    """Upstream gradients on the image, the depth and the accumulated alpha
+    (1 - T_final): the ten 2D gradients (with the splat depth) and every raw
+    parameter gradient against the oracle."""
+    sc, cam = scenes.small_clustered(3000, 28, 96, 64)
+    opts = scenes.Options()
+    rast = raster.Rasterizer.for_scene(sc, [cam], opts)
+    params = raster.params_to_device(sc)
+    out = rast.forward(params, out=rast.new_outputs(alpha=True))
+    torch.cuda.synchronize()
+    T = out.final_T.cpu().numpy()
+    assert np.array_equal(out.alpha.cpu().numpy(), (np.float32(1.0) - T).astype(np.float32))
+    ref = F.render(sc, cam, opts)
+    pre = F.preprocess(sc, cam, opts)
+    rng = np.random.default_rng(28)
+    gimg = rng.normal(size=(3, 64, 96))
+    gdep = rng.normal(size=(64, 96)) * 0.1
+    galp = rng.normal(size=(64, 96))
+    dev = lambda a: torch.from_numpy(a.astype(np.float32).reshape(-1)).cuda()
+    grads = rast.backward(params, out, dev(gimg), dev(gdep), dev(galp))
+    g2_gpu = rast.grad2d().cpu().numpy().astype(np.float64)
+    g2_ref = OB.blend_backward(pre, cam, opts, ref.values, ref.ranges, gimg,
+                               grad_depth=gdep, grad_alpha=galp)
+    ex = _tie_exclusion(pre, ref)
+    names = OB.GRAD2D + ("z",)
+    _assert_grads({k: g2_gpu[i] for i, k in enumerate(names)}, {k: g2_ref[k] for k in names},
+                  ex, "2D+z")
+    grads_ref = OB.preprocess_backward(sc, cam, opts, pre, g2_ref)
+    _assert_grads(raster.to_scene_layout({k: grads[k].cpu().numpy() for k in FIELDS}), grads_ref,
+                  ex, "raw")
+
+
+def test_autograd_depth_and_alpha_equal_explicit_backward():
+    sc, cam = scenes.small_clustered(2000, 29, 64, 48)
+    rast = raster.Rasterizer.for_scene(sc, [cam], scenes.Options())
+    params = raster.params_to_device(sc)
+    leaves = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    image, depth, alpha, T, n = raster.render_with_alpha(rast, leaves)
+    wi = torch.linspace(-1, 1, image.numel(), device=image.device)
+    wd = torch.linspace(1, -1, depth.numel(), device=image.device) * 0.1
+    wa = torch.cos(torch.arange(alpha.numel(), device=image.device, dtype=torch.float32))
+    ((image * wi).sum() + (depth * wd).sum() + (alpha * wa).sum()).backward()
+    out = rast.forward(params, out=rast.new_outputs(alpha=True))
+    grads = rast.backward(params, out, wi.contiguous(), wd.contiguous(), wa.contiguous())
+    for k in FIELDS:
+        a, b = leaves[k].grad, grads[k]
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-9 * float(b.abs().max() + 1e-30)), k
+
+
+def test_two_renders_then_backward_raises():
+    """The autograd Function refuses the first render's backward once a
+    second forward has overwritten the shared workspace."""
+    sc, cam = scenes.small_clustered(500, 30, 48, 32)
+    rast = raster.Rasterizer.for_scene(sc, [cam], scenes.Options())
+    leaves = {k: v.clone().requires_grad_(True) for k, v in raster.params_to_device(sc).items()}
+    img1, *_ = raster.render(rast, leaves)
+    img2, *_ = raster.render(rast, leaves)
+    with pytest.raises(raster.StaleWorkspaceError):
+        img1.sum().backward()
+    img2.sum().backward()

@@ -101,5 +101,82 @@ def test_pixel_backward_matches_tiled_backward():
             for g, v in contrib.items():
                 acc[g] = acc.get(g, 0.0) + v
     for g, v in acc.items():
-        ref = np.array([tiled[k][g] for k in G.GRAD2D])
+        ref = np.array([tiled[k][g] for k in G.GRAD2D + ("z",)])
         assert np.allclose(v, ref, rtol=1e-9, atol=1e-15), g
+
+
+def _depth_alpha_upstream(H, W, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=(3, H, W)), rng.normal(size=(H, W)), rng.normal(size=(H, W)))
+
+
+def test_pixel_backward_with_depth_and_alpha_matches_tiled_backward():
+    sc, cam, _ = fd_subcase()
+    img = F.render(sc, cam, OPTS)
+    pre = F.preprocess(sc, cam, OPTS)
+    gimg, gdep, galp = _depth_alpha_upstream(32, 32, 5)
+    tiled = G.blend_backward(pre, cam, OPTS, img.values, img.ranges, gimg,
+                             grad_depth=gdep, grad_alpha=galp)
+    acc = {}
+    for py in range(32):
+        for px in range(32):
+            contrib, _ = G.pixel_backward(pre, cam, OPTS, px, py, gimg[:, py, px],
+                                          gdep[py, px], galp[py, px])
+            for g, v in contrib.items():
+                acc[g] = acc.get(g, 0.0) + v
+    assert any(abs(v[9]) > 0 for v in acc.values())
+    for g, v in acc.items():
+        ref = np.array([tiled[k][g] for k in G.GRAD2D + ("z",)])
+        assert np.allclose(v, ref, rtol=1e-9, atol=1e-15), g
+
+
+@pytest.mark.parametrize("field", ["means", "opacity_logits", "log_scales", "quats",
+                                   "sg_amplitudes"])
+def test_depth_and_alpha_gradients_match_finite_differences(field):
+    """Loss = sum gC.image + sum gD depth + sum gA (1 - T_final)."""
+    sc, cam, _ = fd_subcase()
+    gimg, gdep, galp = _depth_alpha_upstream(32, 32, 6)
+    _, _, _, grads = G.render_and_grad(sc, cam, OPTS, grad_image=gimg, grad_depth=gdep,
+                                       grad_alpha=galp)
+    pre = F.preprocess(sc, cam, OPTS)
+    vis = np.nonzero(pre.visible)[0]
+    rng = np.random.default_rng(abs(hash(("da", field))) % 2 ** 32)
+    arr = getattr(sc, field)
+    checked = 0
+    for _ in range(10):
+        g = int(rng.choice(vis))
+        idx = tuple(int(rng.integers(0, s)) for s in arr.shape[:-1]) + (g,)
+        fd, ok = G.fd_grad_linear(sc, cam, OPTS, gimg, gdep, galp, field, idx)
+        if not ok:
+            continue
+        an = grads[field][idx]
+        assert abs(an - fd) <= 1e-4 * max(abs(an), abs(fd)) + 2e-9, (field, idx, an, fd)
+        checked += 1
+    assert checked >= 6
+
+
+def test_single_gaussian_depth_and_alpha_closed_forms():
+    """One splat: D = a z and A = a with a = sigma E, so dD/dsigma = E z,
+    dD/dz = a and dA/dsigma = E."""
+    cam = scenes.pinhole(17, 17, np.eye(3), (0.0, 0.0, 0.0))
+    sh = np.zeros((1, 3, 1), np.float32)
+    sc = scenes.Scene(0, 0, np.array([[0.0], [0.0], [3.0]], np.float32),
+                      np.full((3, 1), -1.5, np.float32),
+                      np.array([[1], [0], [0], [0]], np.float32), np.array([0.2], np.float32),
+                      sh, np.zeros((0, 3, 1), np.float32), np.zeros((0, 1), np.float32),
+                      np.zeros((0, 3, 1), np.float32))
+    pre = F.preprocess(sc, cam, OPTS)
+    img = F.render(sc, cam, OPTS)
+    px, py = 9, 7
+    one = np.zeros((17, 17))
+    one[py, px] = 1.0
+    zero3 = np.zeros((3, 17, 17))
+    d2 = (px - pre.u[0]) ** 2 + (py - pre.v[0]) ** 2
+    E = math.exp(-0.5 * d2 / pre.A[0])
+    a = pre.opacity[0] * E
+    gd = G.blend_backward(pre, cam, OPTS, img.values, img.ranges, zero3, grad_depth=one)
+    assert gd["sigma"][0] == pytest.approx(E * pre.z[0], rel=1e-12)
+    assert gd["z"][0] == pytest.approx(a, rel=1e-14)
+    ga = G.blend_backward(pre, cam, OPTS, img.values, img.ranges, zero3, grad_alpha=one)
+    assert ga["sigma"][0] == pytest.approx(E, rel=1e-12)
+    assert ga["z"][0] == 0.0
