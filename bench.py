@@ -118,6 +118,39 @@ def timed_loop(fn, steps, torch):
     return t0.elapsed_time(t1) / steps
 
 
+def alternating_steps(fns, steps, torch):
+    """Per-step times (ms) of several step functions run in strict
+    alternation (f0, f1, ..., f0, f1, ...): each step between its own pair
+    of events on the current stream, so that neighbouring samples of the
+    forms see the same clock and temperature."""
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)] for _ in fns]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        for f, e in zip(fns, ev):
+            e[i][0].record()
+            f()
+            e[i][1].record()
+    torch.cuda.synchronize()
+    return [np.array([a.elapsed_time(b) for a, b in e]) for e in ev]
+
+
+def summary(t):
+    return {"median_ms": round(float(np.median(t)), 5), "p10_ms": round(float(np.percentile(t, 10)), 5),
+            "p90_ms": round(float(np.percentile(t, 90)), 5), "samples": int(len(t))}
+
+
+def ratio_ci(num, den, reps=2000, seed=0):
+    """median(num) / median(den) and its bootstrap 95% interval, resampling
+    the alternation index (each resample keeps neighbouring pairs)."""
+    rng = np.random.default_rng(seed)
+    n = len(num)
+    idx = rng.integers(0, n, size=(reps, n))
+    r = np.median(num[idx], axis=1) / np.median(den[idx], axis=1)
+    return (round(float(np.median(num) / np.median(den)), 4),
+            [round(float(np.percentile(r, 2.5)), 4), round(float(np.percentile(r, 97.5)), 4)])
+
+
 def capture(fn, torch):
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -131,31 +164,45 @@ def capture(fn, torch):
     return g
 
 
-def cpu_baseline(scene, cam, opts, n_tiles_sample=800):
-    """The FP64 oracle on a bounded sample of the same frame: full
-    preprocess, key emission and stable sort, and the blend of a random
-    sample of tiles, scaled to the frame's tile count."""
-    import oracle
+def cpu_baseline(scene, cam, opts, target, workers=16):
+    """The FP64 oracle over the whole frame on the host's cores: preprocess,
+    key emission, stable sort and ranges (one process, NumPy), the blend of
+    every tile (a pool of worker processes over tiles), then the backward of
+    the L1 loss: the blend backward over every tile on the pool and the chain
+    rule to the raw parameters (one process).  Runs before the GPU is
+    initialised, so the forked workers hold no device state."""
+    from oracle import backward as OB
     from oracle import forward as F
+    from oracle import parallel as OP
+    nw = OP.workers(workers)
+    st = {}
     t = time.perf_counter()
     pre = F.preprocess(scene, cam, opts)
-    t_pre = time.perf_counter() - t
+    st["preprocess_s"] = time.perf_counter() - t
     t = time.perf_counter()
     keys, vals, nt = F.emit_pairs(pre)
     keys, vals = F.sort_pairs(keys, vals)
     rng = F.tile_ranges(keys, nt)
-    t_sort = time.perf_counter() - t
-    pick = np.random.default_rng(0).choice(nt, size=min(n_tiles_sample, nt), replace=False)
+    st["sort_s"] = time.perf_counter() - t
     t = time.perf_counter()
-    F.blend_image(pre, cam, opts, vals, rng, tiles=pick)
-    t_blend = (time.perf_counter() - t) * nt / len(pick)
-    frame_s = t_pre + t_sort + t_blend
-    return {"value": 1.0 / frame_s, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": (f"full preprocess + key sort of the frame ({t_pre + t_sort:.1f} s), "
-                       f"blend of {len(pick)} random tiles of {nt} scaled to the frame "
-                       f"({t_blend:.1f} s est.); numpy float64, one process"),
-            "frame_s_est": frame_s, "preprocess_s": t_pre, "sort_s": t_sort,
-            "blend_s_est": t_blend, "host_cpu": platform.processor() or platform.machine(),
+    img = OP.blend_image(pre, cam, opts, vals, rng, n_workers=nw)[0]
+    st["blend_s"] = time.perf_counter() - t
+    frame_s = st["preprocess_s"] + st["sort_s"] + st["blend_s"]
+    _, gimg = OB.l1_loss(img, target)
+    t = time.perf_counter()
+    g2 = OP.blend_backward(pre, cam, opts, vals, rng, gimg, n_workers=nw)
+    st["blend_backward_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    OB.preprocess_backward(scene, cam, opts, pre, g2)
+    st["preprocess_backward_s"] = time.perf_counter() - t
+    fb_s = frame_s + st["blend_backward_s"] + st["preprocess_backward_s"]
+    return {"value": round(1.0 / frame_s, 5), "unit": "frames/s", "cores": nw, "kind": "oracle",
+            "sample": (f"the whole frame, forward ({frame_s:.1f} s) and L1 backward "
+                       f"({fb_s - frame_s:.1f} s): numpy float64, blend and blend backward on "
+                       f"{nw} worker processes over tiles, the rest in one process"),
+            "frame_s": round(frame_s, 3), "fwd_bwd_s": round(fb_s, 3),
+            "stages_s": {k: round(v, 3) for k, v in st.items()},
+            "host_cpu": platform.processor() or platform.machine(),
             "host_cpu_count": os.cpu_count()}
 
 
@@ -296,22 +343,18 @@ def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, ta
                 g_fwd=g_fwd, g_fb=g_fb, buffers=(out, out_b, grad_img, grads, target))
 
 
-def paired_comparison(m, m3, steps, torch, rounds=5):
-    """SG and SH-3 graphs replayed in alternation (same clocks and
-    temperature for both), K steps per timing; medians over the rounds."""
-    t = {"sg_fwd": [], "sh3_fwd": [], "sg_fb": [], "sh3_fb": []}
-    for _ in range(rounds):
-        t["sg_fwd"].append(timed_loop(m["g_fwd"].replay, steps, torch))
-        t["sh3_fwd"].append(timed_loop(m3["g_fwd"].replay, steps, torch))
-        t["sg_fb"].append(timed_loop(m["g_fb"].replay, steps, torch))
-        t["sh3_fb"].append(timed_loop(m3["g_fb"].replay, steps, torch))
-    med = {k: float(np.median(v)) for k, v in t.items()}
-    return {"rounds": rounds, "steps_per_round": steps,
-            "sg_fwd_ms": round(med["sg_fwd"], 4), "sh3_fwd_ms": round(med["sh3_fwd"], 4),
-            "sg_fwd_bwd_ms": round(med["sg_fb"], 4), "sh3_fwd_bwd_ms": round(med["sh3_fb"], 4),
-            "sg_over_sh3_fps": round(med["sh3_fwd"] / med["sg_fwd"], 4),
-            "sg_over_sh3_fwd_bwd": round(med["sh3_fb"] / med["sg_fb"], 4),
-            "per_round_fps_ratio": [round(b / a, 4) for a, b in zip(t["sg_fwd"], t["sh3_fwd"])]}
+def paired_comparison(m, m3, steps, torch):
+    """SG and SH-3 graphs replayed in strict alternation, every step timed on
+    its own: medians, p10/p90, and the bootstrap 95% interval of each
+    SH-3 / SG time ratio (the SG speed-up)."""
+    fw = alternating_steps([m["g_fwd"].replay, m3["g_fwd"].replay], steps, torch)
+    fb = alternating_steps([m["g_fb"].replay, m3["g_fb"].replay], steps, torch)
+    r_fwd, ci_fwd = ratio_ci(fw[1], fw[0])
+    r_fb, ci_fb = ratio_ci(fb[1], fb[0])
+    return {"steps_per_form": steps, "sg_fwd": summary(fw[0]), "sh3_fwd": summary(fw[1]),
+            "sg_fwd_bwd": summary(fb[0]), "sh3_fwd_bwd": summary(fb[1]),
+            "sg_over_sh3_fps": r_fwd, "sg_over_sh3_fps_ci95": ci_fwd,
+            "sg_over_sh3_fwd_bwd": r_fb, "sg_over_sh3_fwd_bwd_ci95": ci_fb}, fw[0], fb[0]
 
 
 def main():

@@ -328,6 +328,25 @@ int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams,
                       uint64_t* counts, void* stream);
 
 /*
+ * render_blend_bwd_work — walks the tiles of a finished forward back to
+ * front as render_backward's blend does (same workspace, cameras, options;
+ * fwd: the forward's outputs, of which final_T and n_contrib are read) and
+ * counts its work events into counts (device u64[4], overwritten): list
+ * entries visited per thread (every thread of a tile visits the entries
+ * before the tile's largest n_contrib), (pixel, entry) pairs whose alpha is
+ * recomputed (entry before the pixel's n_contrib, pixel inside the splat's
+ * rectangle), the pairs among them with alpha >= alpha_min (the pairs that
+ * carry a gradient: the blended pairs of the forward), and wave reductions
+ * (one per wave and entry that one of the wave's pairs carries: one
+ * reduce-scatter and one atomic instruction).  Uses the grid schedule and
+ * options.ppt_bwd.  For roofline figures; writes no gradient.
+ */
+int render_blend_bwd_work(const sgs_gaussians* g, const sgs_camera* host_cams,
+                          const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                          const void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                          const sgs_outputs* fwd, uint64_t* counts, void* stream);
+
+/*
  * Fused Adam step over every parameter array (the optimiser of the training
  * the rasteriser serves; paper: Experiments, Implementation — the 3D-GS
  * learning rates, and the SG lobes introduced after the first 2,000
@@ -343,7 +362,8 @@ int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams,
  */
 typedef struct sgs_adam {
     float lr[8];
-    float beta1, beta2, eps;         /* 0 = 0.9, 0.999, 1e-15 (the 3D-GS optimiser's eps) */
+    double beta1, beta2, eps;        /* 0 = 0.9, 0.999, 1e-15 (the 3D-GS optimiser's eps); double, so
+                                        that 1 - beta is formed before rounding to float32 */
     int32_t step;
     int32_t sg_start;
 } sgs_adam;

@@ -50,7 +50,7 @@ class Options(Structure):
 
 
 class Adam(Structure):
-    _fields_ = [("lr", c_float * 8), ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
+    _fields_ = [("lr", c_float * 8), ("beta1", c_double), ("beta2", c_double), ("eps", c_double),
                 ("step", c_int32), ("sg_start", c_int32)]
 
 
@@ -70,8 +70,8 @@ class Layout(Structure):
 
 EXPORTS = ("render_workspace_bytes", "render_layout", "render_forward", "render_backward",
            "render_l1", "render_status", "render_read_keys", "render_set_timing",
-           "render_stage_times", "render_stage_name", "render_blend_work", "render_adam_step",
-           "render_last_error")
+           "render_stage_times", "render_stage_name", "render_blend_work",
+           "render_blend_bwd_work", "render_adam_step", "render_last_error")
 N_STAGES = 11
 
 
@@ -110,6 +110,10 @@ def _load():
     lib.render_blend_work.restype = c_int32
     lib.render_blend_work.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
                                       c_void_p, c_size_t, c_int64, c_void_p, c_void_p]
+    lib.render_blend_bwd_work.restype = c_int32
+    lib.render_blend_bwd_work.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
+                                          c_void_p, c_size_t, c_int64, P(Outputs), c_void_p,
+                                          c_void_p]
     lib.render_adam_step.restype = c_int32
     lib.render_adam_step.argtypes = [P(Gaussians), P(Adam), P(Grads), P(Grads), P(Grads), c_void_p]
     lib.render_last_error.restype = c_char_p

@@ -29,12 +29,12 @@ k_adam(AdamArrays a) {
     float* __restrict__ m = a.m[k];
     float* __restrict__ v = a.v[k];
     const float lr = a.lr[k], c1 = a.c1[k], c2 = a.c2[k];
-    const float b1 = a.b1, b2 = a.b2, eps = a.eps;
+    const float b1 = a.b1, b2 = a.b2, ob1 = a.ob1, ob2 = a.ob2, eps = a.eps;
     const int64_t w = a.width[k], ps = a.pstride[k];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     auto step = [&](float& pp, float gg, float& mm, float& vv) {
-        mm = b1 * mm + (1.0f - b1) * gg;
-        vv = b2 * vv + (1.0f - b2) * (gg * gg);
+        mm = b1 * mm + ob1 * gg;
+        vv = b2 * vv + ob2 * (gg * gg);
         pp -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
     };
     if (ps == w) {

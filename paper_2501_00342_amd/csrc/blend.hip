@@ -333,11 +333,21 @@ struct Upstream {
 // A, the scalar carried back to front becomes gC.S + gD D_behind - gA T_f
 // (dA/dalpha_j = T_f / (1 - alpha_j)), each splat's front term adds gD z,
 // and dL/dz = gD alpha T is a tenth 2D gradient.
-template <int TW, int TH, int PPT, bool DG>
+// Work events of one backward walk (COUNT): list entries visited per
+// thread, (pixel, entry) pairs whose alpha is recomputed, pairs that carry
+// a gradient (alpha >= alpha_min), and wave reductions (one per wave and
+// entry that some lane's pixels touch: one reduce-scatter and one atomic
+// instruction of 9 or 10 lanes).
+struct BwdWork {
+    unsigned long long visited, evaluated, blended, reductions;
+};
+
+template <int TW, int TH, int PPT, bool DG, bool COUNT>
 __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
                                          int n_cams, const Opts& o, const sgs_outputs& fwd,
                                          const Upstream& up, int batch,
-                                         int64_t tile, Entry* s_e, int* s_cam, int* s_maxn) {
+                                         int64_t tile, Entry* s_e, int* s_cam, int* s_maxn,
+                                         BwdWork& work) {
     constexpr int NT = TW * TH / PPT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -379,9 +389,11 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
             const int64_t pix = (int64_t)py * W + px;
             T[k] = fwd.final_T[ct.pix_base + pix];
             nc[k] = fwd.n_contrib[ct.pix_base + pix];
-            g0[k] = gi[pix];
-            g1[k] = gi[W * H + pix];
-            g2[k] = gi[2 * W * H + pix];
+            if (!COUNT) {
+                g0[k] = gi[pix];
+                g1[k] = gi[W * H + pix];
+                g2[k] = gi[2 * W * H + pix];
+            }
             if (DG) {
                 if (up.depth) gD[k] = up.depth[ct.pix_base + pix];
                 if (up.alpha) gA = up.alpha[ct.pix_base + pix];
@@ -412,16 +424,22 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
             float v_u = 0.f, v_v = 0.f, v_qa = 0.f, v_qb = 0.f, v_qc = 0.f, v_s = 0.f;
             float v_r = 0.f, v_g = 0.f, v_b = 0.f, v_z = 0.f;
             bool contrib = false;
+            if (COUNT) ++work.visited;
             if (e.m.x & colbit) {
                 const float dx = lxf + e.a.x;
                 const float t1 = e.a.z * dx, t2 = e.b.x * dx;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     if (pos >= nc[k] || !((e.m.y >> (ry + k)) & 1u)) continue;
+                    if (COUNT) ++work.evaluated;
                     const float dy = (float)(ry + k) + e.a.y;
                     const Eval v = eval_splat(e, t1, t2, dy, amax);
                     if (v.alpha < amin) continue;
                     contrib = true;
+                    if (COUNT) {
+                        ++work.blended;
+                        continue;
+                    }
                     // 1 / (1 - alpha) with v_rcp_f32 (1 ulp; 1 - alpha >= 1 - alpha_max)
                     const float iom = __builtin_amdgcn_rcpf(1.0f - v.alpha);
                     T[k] = T[k] * iom;
@@ -450,7 +468,9 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                     }
                 }
             }
-            if (__any(contrib)) {
+            if (COUNT) {
+                if (__any(contrib) && lane == 0) ++work.reductions;
+            } else if (__any(contrib)) {
                 constexpr int NV = DG ? 10 : 9;
                 const float vals[10] = {v_u, v_v, v_qa, v_qb, v_qc, v_s, v_r, v_g, v_b, v_z};
                 float x[3];
@@ -475,25 +495,39 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     }
 }
 
-template <int TW, int TH, int PPT, bool QUEUE, bool DG>
+template <int TW, int TH, int PPT, bool QUEUE, bool DG, bool COUNT>
 __global__ void __launch_bounds__(TW * TH / PPT)
 k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
-            sgs_outputs fwd, Upstream up, int batch) {
+            sgs_outputs fwd, Upstream up, int batch, unsigned long long* counts) {
     extern __shared__ __align__(16) Entry s_e[];
     __shared__ int s_cam;
     __shared__ int s_maxn;
     __shared__ uint32_t s_next;
     if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    BwdWork work = {0ull, 0ull, 0ull, 0ull};
     if (QUEUE) {
         for (;;) {
             const int64_t tile = pop_tile(ws, ws.header + kHdrQueueBwd, &s_next);
             if (tile < 0) break;
-            bwd_tile<TW, TH, PPT, DG>(ws, cams, n_cams, o, fwd, up, batch, tile, s_e, &s_cam,
-                                      &s_maxn);
+            bwd_tile<TW, TH, PPT, DG, COUNT>(ws, cams, n_cams, o, fwd, up, batch, tile, s_e,
+                                             &s_cam, &s_maxn, work);
         }
     } else {
-        bwd_tile<TW, TH, PPT, DG>(ws, cams, n_cams, o, fwd, up, batch,
-                                  xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, &s_maxn);
+        bwd_tile<TW, TH, PPT, DG, COUNT>(ws, cams, n_cams, o, fwd, up, batch,
+                                         xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, &s_maxn,
+                                         work);
+    }
+    if (COUNT) {
+        __shared__ unsigned long long s_cnt[4];
+        __syncthreads();
+        if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0ull;
+        __syncthreads();
+        atomicAdd(&s_cnt[0], work.visited);
+        atomicAdd(&s_cnt[1], work.evaluated);
+        atomicAdd(&s_cnt[2], work.blended);
+        atomicAdd(&s_cnt[3], work.reductions);
+        __syncthreads();
+        if (threadIdx.x < 4) atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
     }
 }
 
@@ -535,13 +569,24 @@ static void launch_bwd_dg(const Workspace& ws, const sgs_camera* cams, int n_cam
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     constexpr int NT = TW * TH / PPT;
     if (queue) {
-        auto k = k_blend_bwd<TW, TH, PPT, true, DG>;
+        auto k = k_blend_bwd<TW, TH, PPT, true, DG, false>;
         hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, NT, lds), ws.n_tiles)), dim3(NT), lds,
-                           s, ws, cams, n_cams, o, fwd, up, o.batch);
+                           s, ws, cams, n_cams, o, fwd, up, o.batch, nullptr);
     } else {
-        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false, DG>), dim3((unsigned)ws.n_tiles),
-                           dim3(NT), lds, s, ws, cams, n_cams, o, fwd, up, o.batch);
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false, DG, false>), dim3((unsigned)ws.n_tiles),
+                           dim3(NT), lds, s, ws, cams, n_cams, o, fwd, up, o.batch, nullptr);
     }
+}
+
+template <int TW, int TH, int PPT>
+static void launch_bwd_count_t(const Workspace& ws, const sgs_camera* cams, int n_cams,
+                               const Opts& o, const sgs_outputs& fwd, uint64_t* counts,
+                               hipStream_t s) {
+    const size_t lds = (size_t)o.batch * sizeof(Entry);
+    const Upstream none = {nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false, false, true>), dim3((unsigned)ws.n_tiles),
+                       dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, fwd, none, o.batch,
+                       reinterpret_cast<unsigned long long*>(counts));
 }
 
 template <int TW, int TH, int PPT>
@@ -577,6 +622,13 @@ void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_c
                         uint64_t* counts, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
     SGS_TILE_SWITCH(launch_count_t, o.ppt, ws, dev_cams, n_cams, o, counts, s)
+}
+
+void launch_blend_bwd_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams,
+                            const Opts& o, const sgs_outputs& fwd, uint64_t* counts,
+                            hipStream_t s) {
+    if (ws.n_tiles <= 0) return;
+    SGS_TILE_SWITCH(launch_bwd_count_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, counts, s)
 }
 
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,

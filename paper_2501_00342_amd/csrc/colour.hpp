@@ -235,13 +235,17 @@ __device__ __forceinline__ void colour_bwd_eval(SH sh, AX axis, LS lsh, AM amp, 
     gd[0] = gd[1] = gd[2] = 0.0f;
 #pragma unroll
     for (int l = 0; l < NC; ++l) {
-        if (l >= ncu) break;   // unused coefficients: zero gradient, no direction term
+        // unused coefficients (adaptive degree): zero gradient, no direction
+        // term; a select rather than an exit keeps the loop fully unrolled
+        // and gsh in registers
+        const float y = l < ncu ? Y[l] : 0.0f;
         float cl = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            gsh[l][c] = fmaf(gc[c], Y[l], gsh[l][c]);
+            gsh[l][c] = fmaf(gc[c], y, gsh[l][c]);
             cl = fmaf(gc[c], sh(l, c), cl);
         }
+        cl = l < ncu ? cl : 0.0f;
         gd[0] = fmaf(cl, gx[l], gd[0]);
         gd[1] = fmaf(cl, gy[l], gd[1]);
         gd[2] = fmaf(cl, gz[l], gd[2]);

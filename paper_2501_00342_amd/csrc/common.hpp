@@ -151,6 +151,7 @@ struct AdamArrays {
     float c2[kAdamArrays];         // 1 / (1 - b2^t)
     bool on[kAdamArrays];
     float b1, b2, eps;
+    float ob1, ob2;                // 1 - b1, 1 - b2, formed in float64 then rounded
 };
 
 // launchers (defined in the .hip files)
@@ -195,6 +196,11 @@ void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cam
                       const sgs_outputs& out, bool queue, hipStream_t s);
 void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                         uint64_t* counts, hipStream_t s);
+// the backward walk of a finished forward, counting its work events into
+// counts[4] (visited, evaluated, blended, reductions); no gradient written
+void launch_blend_bwd_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams,
+                            const Opts& o, const sgs_outputs& fwd, uint64_t* counts,
+                            hipStream_t s);
 // grad_depth / grad_alpha may be NULL (no upstream gradient); with either,
 // the blend also adds dL/dz into grad2d row 9
 void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,

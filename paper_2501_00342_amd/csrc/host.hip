@@ -617,6 +617,25 @@ int render_blend_work(const sgs_gaussians* g, const sgs_camera* host_cams, const
     return SGS_OK;
 }
 
+int render_blend_bwd_work(const sgs_gaussians* g, const sgs_camera* host_cams,
+                          const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                          const void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                          const sgs_outputs* fwd, uint64_t* counts, void* stream) {
+    Plan pl;
+    int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
+    if (rc != SGS_OK) return rc;
+    if (!dev_cams || !workspace || !counts || !fwd || !fwd->final_T || !fwd->n_contrib)
+        return fail(SGS_E_INVALID, "NULL argument");
+    if (workspace_bytes < pl.lay.total_bytes) return fail(SGS_E_INVALID, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sgs::Workspace ws = bind(pl, const_cast<void*>(workspace));
+    (void)hipGetLastError();
+    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 0u, 8, s);
+    sgs::launch_blend_bwd_count(ws, dev_cams, n_cams, pl.o, *fwd, counts, s);
+    SGS_LAUNCHED();
+    return SGS_OK;
+}
+
 int render_adam_step(const sgs_gaussians* g, const sgs_adam* cfg, const sgs_grads* grads,
                      const sgs_grads* exp_avg, const sgs_grads* exp_avg_sq, void* stream) {
     if (!g || !cfg || !grads || !exp_avg || !exp_avg_sq)
@@ -648,13 +667,15 @@ int render_adam_step(const sgs_gaussians* g, const sgs_adam* cfg, const sgs_grad
     arrays(exp_avg_sq, v);
     sgs::AdamArrays a;
     memset(&a, 0, sizeof(a));
-    const double b1 = cfg->beta1 != 0.0f ? cfg->beta1 : 0.9f;
-    const double b2 = cfg->beta2 != 0.0f ? cfg->beta2 : 0.999f;
+    const double b1 = cfg->beta1 != 0.0 ? cfg->beta1 : 0.9;
+    const double b2 = cfg->beta2 != 0.0 ? cfg->beta2 : 0.999;
     if (!(b1 > 0.0 && b1 < 1.0 && b2 > 0.0 && b2 < 1.0))
         return fail(SGS_E_INVALID, "beta1 and beta2 must be in (0, 1)");
     a.b1 = (float)b1;
     a.b2 = (float)b2;
-    a.eps = cfg->eps != 0.0f ? cfg->eps : 1e-15f;
+    a.ob1 = (float)(1.0 - b1);
+    a.ob2 = (float)(1.0 - b2);
+    a.eps = (float)(cfg->eps != 0.0 ? cfg->eps : 1e-15);
     const int sg0 = cfg->sg_start > 1 ? cfg->sg_start : 1;
     for (int k = 0; k < sgs::kAdamArrays; ++k) {
         if (!(cfg->lr[k] >= 0.0f)) return fail(SGS_E_INVALID, "learning rates must be >= 0");

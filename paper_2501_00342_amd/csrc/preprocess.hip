@@ -131,12 +131,13 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
 // so only the colour gather's latency is exposed per tile.  The colour is
 // evaluated from LDS, so the geometry's and the colour's registers are never
 // live together.
-template <int DEG, int KMAX, int LM>
+template <int DEG, int KMAX, int LM, bool AD>
 __global__ void __launch_bounds__(kPreTile)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    // record bound: SH, axis rows, sharpness and amplitudes, + 16-byte rounding
-    constexpr int MAXROWS = 3 * NC + 3 * AxisRows<LM, KMAX>::value + 4 * KMAX + 3;
+    // record bound: the largest record rounded up to whole 16-byte pieces (a
+    // record is read in 16-byte pieces only when its stride leaves that room)
+    constexpr int MAXROWS = (3 * NC + 3 * AxisRows<LM, KMAX>::value + 4 * KMAX + 3) & ~3;
     constexpr int WAVES = kPreTile / 64;
     __shared__ __align__(16) float s_rec[WAVES][64 * (MAXROWS > 0 ? MAXROWS : 1)];
     __shared__ int64_t s_g[WAVES][64];
@@ -144,6 +145,10 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
     const int tid = threadIdx.x, wave = tid >> 6;
     const int RS = p.rec_floats;
     float* rec = s_rec[wave];
+    // device cameras that disagree with the plan (status bit set by the
+    // setup kernel): every item is culled, so no tile id outside the planned
+    // range reaches binning
+    const bool cams_ok = (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) == 0;
     // geometry of this thread's Gaussian in the next tile: 3 + 3 + 4 + 1 floats
     float nxt[11];
     auto load_geometry = [&](int64_t base) {
@@ -188,7 +193,7 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             const CamTable ct = ws.cams[ci];
             const int64_t item = (int64_t)ci * n + g;
             const Geo geo = project(X, ls, q, cam, ct, o);
-            bool vis = active && finite && geo.visible;
+            bool vis = active && finite && geo.visible && cams_ok;
             const int got = gather_colour<3 * NC>(p, g, vis && slot < 0, used, rec, s_g[wave], &slot);
             used += got;
             // this wave's direct loads have landed (it reads only its own buffer)
@@ -204,7 +209,7 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
                     [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
                     [&](int k) { return r[3 * NC + A3 + k]; },
                     [&](int k, int c) { return r[3 * NC + A3 + K + 3 * k + c]; }, K,
-                    sh_used<DEG>(p, geo.radius), d[0], d[1], d[2], rgb);
+                    AD ? sh_used<DEG>(p, geo.radius) : NC, d[0], d[1], d[2], rgb);
             }
             if (!active) continue;
             uint32_t key = 0xFFFFFFFFu;
@@ -264,12 +269,17 @@ template <int KMAX, int LM>
 static void launch_pre_k(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                          const Workspace& ws, dim3 grid, hipStream_t s) {
     const dim3 block(kPreTile);
+    // adaptive SH degree is its own instantiation: with a fixed degree the
+    // coefficient loops keep a compile-time bound
+    const bool ad = (p.sh_ad0 | p.sh_ad1) != 0;
+#define SGS_PRE(D, A) hipLaunchKernelGGL((k_preprocess<D, KMAX, LM, A>), grid, block, 0, s, p, dev_cams, n_cams, o, ws)
     switch (p.sh_degree) {
-        case 0: hipLaunchKernelGGL((k_preprocess<0, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        case 1: hipLaunchKernelGGL((k_preprocess<1, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        case 2: hipLaunchKernelGGL((k_preprocess<2, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
-        default: hipLaunchKernelGGL((k_preprocess<3, KMAX, LM>), grid, block, 0, s, p, dev_cams, n_cams, o, ws); break;
+        case 0: SGS_PRE(0, false); break;
+        case 1: if (ad) SGS_PRE(1, true); else SGS_PRE(1, false); break;
+        case 2: if (ad) SGS_PRE(2, true); else SGS_PRE(2, false); break;
+        default: if (ad) SGS_PRE(3, true); else SGS_PRE(3, false); break;
     }
+#undef SGS_PRE
 }
 
 void launch_preprocess(const Params& p, const sgs_camera* dev_cams, int n_cams, const Opts& o,

@@ -38,15 +38,16 @@ struct ColourBwdWaves {
     static constexpr int value = rows <= 40 ? 4 : (rows <= 48 ? 3 : 1);
 };
 
-template <int DEG, int KMAX, int LM>
+template <int DEG, int KMAX, int LM, bool AD>
 __global__ void __launch_bounds__(kPreTile)
 __attribute__((amdgpu_waves_per_eu(ColourBwdWaves<DEG, KMAX, LM>::value)))
 k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspace ws,
              sgs_grads gr, float* __restrict__ gx_colour) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
     constexpr int AMAX = AxisRows<LM, KMAX>::value;
-    // record bound: SH, axis rows, sharpness and amplitudes, + 16-byte rounding
-    constexpr int MAXROWS = 3 * NC + 3 * AMAX + 4 * KMAX + 3;
+    // record bound: SH, axis rows, sharpness and amplitudes, rounded up to
+    // whole 16-byte pieces
+    constexpr int MAXROWS = (3 * NC + 3 * AMAX + 4 * KMAX + 3) & ~3;
     // gradient records: an odd stride keeps a wave's record writes on
     // distinct banks
     constexpr int SG = (MAXROWS % 2 == 0) ? MAXROWS + 1 : MAXROWS;
@@ -60,7 +61,7 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
     const int K = p.n_lobes;
     const int tid = threadIdx.x, wave = tid >> 6;
     const int RS = p.rec_floats;
-    const int A3 = 3 * p.n_axes;
+    const int A3 = LM == kLobesFree ? 3 * K : 3 * AMAX;   // axis floats (3 per free lobe)
     float* crec = s_buf + wave * 64 * MAXROWS;
     // this thread's Gaussian in the next tile: its mean and the first
     // camera's rectangle, loaded while this tile computes (only where the
@@ -123,7 +124,7 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
             view_dir(X, cams[ci], d, &dist);
             float gd[3];
             // adaptive SH: the degree this camera used, from the item's radius
-            const int ncu = (p.sh_ad0 | p.sh_ad1) ? sh_used<DEG>(p, ws.records[item].radius) : NC;
+            const int ncu = AD ? sh_used<DEG>(p, ws.records[item].radius) : NC;
             colour_bwd_eval<DEG, KMAX, LM>(
                 [&](int l, int c) { return r[3 * l + c]; },
                 [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
@@ -359,8 +360,14 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     float* gxc = ws.gx_colour;
     const int64_t tiles = (p.n + kPreTile - 1) / kPreTile;
     const dim3 cgrid((unsigned)(tiles < 4096 ? tiles : 4096)), cblock(kPreTile);
+    // adaptive SH degree is its own instantiation (compile-time loop bounds
+    // otherwise)
+    const bool ad = (p.sh_ad0 | p.sh_ad1) != 0 && p.sh_degree > 0;
 #define SGS_COLOUR_BWD(D, K, LM)                                                               \
-    hipLaunchKernelGGL((k_colour_bwd<D, K, LM>), cgrid, cblock, 0, s, p, dev_cams, n_cams, ws, gr, gxc)
+    if (ad) hipLaunchKernelGGL((k_colour_bwd<D, K, LM, (D > 0)>), cgrid, cblock, 0, s, p,      \
+                               dev_cams, n_cams, ws, gr, gxc);                                 \
+    else hipLaunchKernelGGL((k_colour_bwd<D, K, LM, false>), cgrid, cblock, 0, s, p, dev_cams, \
+                            n_cams, ws, gr, gxc)
 #define SGS_COLOUR_BWD_K(D)                                                                    \
     if (p.lobe_mode == kLobesWorld) SGS_COLOUR_BWD(D, 3, kLobesWorld);                         \
     else if (p.lobe_mode == kLobesFrame) SGS_COLOUR_BWD(D, 3, kLobesFrame);                    \

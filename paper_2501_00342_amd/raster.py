@@ -274,6 +274,19 @@ class Rasterizer:
         c = counts.cpu()
         return int(c[0]), int(c[1]), int(c[2])
 
+    def blend_bwd_work(self, params: dict, out: "Outputs") -> tuple:
+        """(visited, evaluated, blended, reductions) of the backward blend's
+        walk over the forward that produced `out`."""
+        counts = torch.zeros(4, dtype=torch.int64, device=self.device)
+        g = self._gstruct(params)
+        o = out.struct()
+        L.check(L.LIB.render_blend_bwd_work(ctypes.byref(g), self.host_cams, _ptr(self.dev_cams),
+                                            len(self.cams), ctypes.byref(self.copts),
+                                            _ptr(self.ws), self.ws.numel(), self.capacity,
+                                            ctypes.byref(o), _ptr(counts), _stream()))
+        c = counts.cpu()
+        return int(c[0]), int(c[1]), int(c[2]), int(c[3])
+
     def status(self) -> tuple:
         bits, pairs = L.c_uint32(0), L.c_int64(0)
         L.check(L.LIB.render_status(_ptr(self.ws), ctypes.byref(bits), ctypes.byref(pairs),

@@ -7,10 +7,11 @@ in a tie band (alpha near alpha_min, or T' near T_min) and one of the
 alternative decision paths matches within the same tolerance.
 
 Gradients: per tensor ||g - g_or|| <= 1e-3 ||g_or|| and elementwise
-|g - g_or| <= 1e-3 (|g_or| + 1e-2 rms(g_or)) outside Gaussians touched by
-a tie-band pixel.  The absolute floor covers components whose value is a
-near-cancelling sum of larger terms: the FP32 2D gradients carry ~1e-7 of
-each term, which a cancellation by 1e4 lifts to ~1e-3 of the result.
+|g - g_or| <= 1e-3 (|g_or| + 1e-3 rms(g_or)) outside Gaussians touched by
+a tie-band pixel.  A component that misses the elementwise bound passes
+only if its Gaussian's vector in that tensor is within 1e-3 in norm (the
+normwise rule of `compare_grads`); at most 1e-3 of a tensor's components
+may pass that way, and at most 5% of the Gaussians may be excluded.
 """
 from __future__ import annotations
 
@@ -41,6 +42,9 @@ def compare_image(img, depth, T, n, ref) -> dict:
         failures.append((int(py), int(px), float(err[py, px]), int(n[py, px]),
                          int(ref.n_contrib[py, px]), bool(ref.flagged[py, px])))
     good = ~bad
+    # a tie-band branch taken differently from the FP64 path is rare: a pixel
+    # needs alpha or T' within the band's width of its threshold
+    assert tie_ok <= 1e-4 * err.size, ("tie-accepted pixels", tie_ok, err.size)
     return {"max_err": float(err[good].max()) if good.any() else 0.0,
             "bad": int(bad.sum()), "tie_accepted": tie_ok, "failures": failures,
             "flagged": int(ref.flagged.sum()), "pixels": int(err.size)}
@@ -54,9 +58,18 @@ def compare_pixel(gpu, ref_pixel) -> bool:
     return bool(flagged and outs and any(_pixel_ok(*gpu, *o) for o in outs))
 
 
-def compare_grads(gpu: dict, ref: dict, exclude=None, floor: float = 1e-2) -> dict:
+def compare_grads(gpu: dict, ref: dict, exclude=None, floor: float = 1e-3) -> dict:
     """Per-tensor relative L2 and elementwise bounds; `exclude` is a boolean
-    mask over Gaussians whose gradients may legitimately differ."""
+    mask over Gaussians whose gradients may legitimately differ (their
+    rectangle holds a tie-band pixel).
+
+    A component that misses the elementwise bound is still accepted when it
+    is small beside the rest of its Gaussian's vector in that tensor (the
+    last axis indexes Gaussians) and that vector as a whole is within
+    GRAD_REL in norm: the kernel computes each Gaussian's vector with
+    float32 operations whose rounding scales with the vector's norm, so a
+    component far below the norm carries that absolute error.  Such
+    components are counted (`normwise`) and capped by the tests."""
     report = {}
     for k, g_or in ref.items():
         g = np.asarray(gpu[k], np.float64)
@@ -70,6 +83,14 @@ def compare_grads(gpu: dict, ref: dict, exclude=None, floor: float = 1e-2) -> di
         viol = np.abs(g - g_or) > bound
         if exclude is not None:
             viol = viol & ~exclude.reshape((1,) * (g.ndim - 1) + (-1,))
+        normwise = np.zeros_like(viol)
+        if g.ndim > 1 and viol.any():
+            axes = tuple(range(g.ndim - 1))
+            dn = np.sqrt(((g - g_or) ** 2).sum(axis=axes))
+            on = np.sqrt((g_or ** 2).sum(axis=axes))
+            vec_ok = dn <= GRAD_REL * on
+            normwise = viol & vec_ok.reshape((1,) * (g.ndim - 1) + (-1,))
+            viol = viol & ~normwise
         worst = []
         if viol.any():
             ratio = np.where(viol, np.abs(g - g_or) / bound, 0.0)
@@ -77,6 +98,27 @@ def compare_grads(gpu: dict, ref: dict, exclude=None, floor: float = 1e-2) -> di
                 idx = np.unravel_index(flat, g.shape)
                 worst.append((tuple(int(i) for i in idx), float(g[idx]), float(g_or[idx]),
                               float(bound[idx]), float(rms)))
+        nw = []
+        for flat in np.flatnonzero(normwise)[:5]:
+            idx = np.unravel_index(flat, g.shape)
+            col = (slice(None),) * (g.ndim - 1) + (idx[-1],)
+            nw.append((tuple(int(i) for i in idx), float(g[idx]), float(g_or[idx]),
+                       float(np.linalg.norm(g_or[col]))))
         report[k] = {"rel_l2": float(rel), "elem_viol": int(viol.sum()), "size": int(g.size),
-                     "worst": worst}
+                     "normwise": int(normwise.sum()), "normwise_cases": nw,
+                     "excluded": 0 if exclude is None else int(exclude.sum()),
+                     "gaussians": int(g.shape[-1]), "worst": worst}
     return report
+
+
+# at most this fraction of a tensor's components may pass by the normwise rule
+NORMWISE_MAX = 1e-3
+# at most this fraction of the Gaussians may be excluded for tie-band pixels
+EXCLUDED_MAX = 0.05
+
+
+def assert_grads(rep: dict, what=""):
+    for k, r in rep.items():
+        assert r["rel_l2"] <= GRAD_REL and r["elem_viol"] == 0, (what, k, r)
+        assert r["normwise"] <= NORMWISE_MAX * r["size"], (what, k, r)
+        assert r["excluded"] <= EXCLUDED_MAX * r["gaussians"], (what, k, r)

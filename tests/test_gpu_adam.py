@@ -52,7 +52,10 @@ def test_adam_matches_oracle_across_sg_start(form, packed):
                 continue
             scale = np.abs(P[k]).max() + 1e-30
             assert np.abs(got_p[k] - P[k]).max() <= 2e-6 * scale, (form, step, k)
-            assert np.allclose(got_m[k], M[k], rtol=1e-5, atol=1e-12), (form, step, k)
+            # m = b1 m + (1 - b1) g in float32 can cancel: the floor is a few
+            # float32 roundings of the array's largest moment (over 5 steps)
+            m_floor = 1e-6 * np.abs(M[k]).max()
+            assert np.all(np.abs(got_m[k] - M[k]) <= 1e-5 * np.abs(M[k]) + m_floor), (form, step, k)
             assert np.allclose(got_v[k], V[k], rtol=1e-5, atol=1e-15), (form, step, k)
             if k in O.LOBE_FIELDS and step < 3:
                 assert not got_m[k].any(), (form, step, k)

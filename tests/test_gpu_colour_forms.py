@@ -87,6 +87,9 @@ def test_separate_colour_arrays_match_packed_record(form):
         rast = raster.Rasterizer.for_scene(sc, [cam], opts)
         o = rast.forward(p)
         torch.cuda.synchronize()
-        outs.append((o.image.clone(), o.n_contrib.clone(), rast.records().clone()))
+        # records of culled items are never written: compare the visible ones
+        vis = rast.depth_keys() != -1
+        outs.append((o.image.clone(), o.n_contrib.clone(), rast.records()[vis].clone(), vis.clone()))
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][3], outs[1][3]) and int(outs[0][3].sum()) > 0
     assert torch.equal(outs[0][2], outs[1][2])

@@ -192,16 +192,20 @@ def test_queue_schedule_equals_grid_schedule():
         assert float((g1[k] - g2[k]).abs().max()) <= 1e-5 * scale, k
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
-def test_graph_replay_matches_eager(schedule):
-    """The whole forward and backward captured in one HIP graph: every replay,
+@pytest.mark.parametrize("schedule,n_cams", [(1, 1), (2, 1), (2, 3)])
+def test_graph_replay_matches_eager(schedule, n_cams):
+    """The whole forward and backward captured in one HIP graph (one camera,
+    or three of different sizes on the heavy-first queue): every replay,
     with eager work and synchronisation in between, equals the eager pass."""
     import torch
     from paper_2501_00342_amd import raster
+    from tests.test_gpu_backward import _three_cameras
     sc, cam = scenes.small_clustered(5000, 31, 150, 100)
+    cams = [cam] if n_cams == 1 else _three_cameras(((150, 100), (96, 128), (120, 72)))
     opts = scenes.Options(schedule=schedule)
-    rast, params, out_e = run_forward(sc, [cam], opts)
-    tgt = torch.from_numpy(scenes.target_image(150, 100, 4).reshape(-1)).cuda()
+    rast, params, out_e = run_forward(sc, cams, opts)
+    tgt = torch.from_numpy(np.concatenate(
+        [scenes.target_image(c.width, c.height, 4 + i).reshape(-1) for i, c in enumerate(cams)])).cuda()
     _, g_e = rast.l1(out_e.image, tgt)
     grads_e = rast.backward(params, out_e, g_e)
     grads_e = {k: v.clone() for k, v in grads_e.items()}

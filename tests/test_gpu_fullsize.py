@@ -1,12 +1,13 @@
 """Parity at the full sizes the benchmark times (GPU).
 
 3M Gaussians, 1600x1060: every sorted key, value and tile range is compared
-bit for bit with the oracle's stable sort, and sampled pixels (random, plus
-tile corners) with the oracle's brute-force per-pixel blend.
-1M Gaussians, 1297x840: the gradients of the whole frame for an upstream
-gradient confined to 300 random tiles (and zero at tie-band pixels), against
-the oracle's tiled backward over those tiles, and the raw-parameter
-gradients through the oracle's chain rule.
+bit for bit with the oracle's stable sort, and every pixel with the
+oracle's tiled blend (run on the host's cores).
+1M and 3M Gaussians: the gradients of the whole frame (upstream gradient on
+every pixel, zero at tie-band pixels) against the oracle's tiled backward
+and its chain rule to the raw parameters.
+2M Gaussians, 64 cameras and 6M Gaussians in tight clusters: sampled tiles
+and pixels.
 """
 import numpy as np
 import pytest
@@ -15,6 +16,7 @@ import torch
 import oracle
 from oracle import backward as OB
 from oracle import forward as F
+from oracle import parallel as OP
 from paper_2501_00342_amd import raster, scenes
 from tests import parity
 from tests.gpu_util import camera_numpy
@@ -55,37 +57,35 @@ def test_full_frame_3m_keys_ranges_and_pixels():
     assert np.array_equal(vals.astype(np.uint64), ovals), "sorted values differ"
     assert np.array_equal(rng_gpu, F.tile_ranges(okeys, ntiles)), "tile ranges differ"
 
-    rng = np.random.default_rng(0)
-    bad = []
-    for (py, px) in _sample_pixels(cam.width, cam.height, 200, rng):
-        ref = F.render_pixel(pre, cam, opts, px, py)
-        gpu = (img[:, py, px], dep[py, px], T[py, px], int(n[py, px]))
-        if not parity.compare_pixel(gpu, ref):
-            bad.append((py, px, np.abs(gpu[0] - ref[0]).max(), gpu[3], ref[3], ref[4]))
-    assert not bad, bad
+    # every pixel of the frame against the oracle's tiled blend (run on the
+    # host's cores)
+    ref = F.Image(*OP.blend_image(pre, cam, opts, ovals, F.tile_ranges(okeys, ntiles)),
+                  None, None, None)
+    rep = parity.compare_image(img, dep, T, n, ref)
+    assert not rep["failures"], rep
+    assert rep["pixels"] == cam.width * cam.height
+    print("3M frame:", {k: rep[k] for k in ("max_err", "bad", "tie_accepted", "flagged")}, flush=True)
 
 
-def test_full_frame_1m_gradients_on_sampled_tiles():
-    """1M Gaussians, 1297x840: the upstream gradient is seeded N(0, 1) on 300
-    random tiles and zero elsewhere, so the 2D gradient of every Gaussian is
-    the sum over those tiles, which the oracle computes exactly.  It is also
-    zero at the pixels where the oracle finds a decision inside a tie band:
-    a pixel with zero upstream gradient adds exactly zero on both sides,
-    whichever side of the tie each takes."""
-    sc, cams, opts = scenes.workload("sg-1m-1297")
+@pytest.mark.parametrize("workload", ["sg-1m-1297", "sg-3m-1600"])
+def test_full_frame_gradients(workload):
+    """The gradients of the whole frame for an upstream gradient seeded
+    N(0, 1) on every pixel, except the pixels where the oracle finds a
+    decision inside a tie band, where it is zero: a pixel with zero upstream
+    gradient adds exactly zero on both sides, whichever side of the tie
+    each takes.  2D gradients against the oracle's tiled backward over every
+    tile (on the host's cores), raw-parameter gradients through the
+    oracle's chain rule."""
+    sc, cams, opts = scenes.workload(workload)
     cam = cams[0]
     W, H = cam.width, cam.height
     pre = F.preprocess(sc, cam, opts)
     keys, vals, nt = F.emit_pairs(pre)
     keys, vals = F.sort_pairs(keys, vals)
     ranges = F.tile_ranges(keys, nt)
+    _, _, _, _, flagged, _ = OP.blend_image(pre, cam, opts, vals, ranges)
     rng = np.random.default_rng(7)
-    tiles = sorted(rng.choice(nt, size=300, replace=False).tolist())
-    _, _, _, _, flagged, _ = F.blend_image(pre, cam, opts, vals, ranges, tiles=tiles)
-    gimg = np.zeros((3, H, W), np.float32)
-    for t in tiles:
-        px, py = F.tile_pixels(t % pre.grid[0], t // pre.grid[0], opts, W, H)
-        gimg[:, py, px] = rng.normal(size=(3, px.size)).astype(np.float32)
+    gimg = rng.normal(size=(3, H, W)).astype(np.float32)
     gimg[:, flagged] = 0.0
 
     rast = raster.Rasterizer.for_scene(sc, cams, opts)
@@ -94,18 +94,21 @@ def test_full_frame_1m_gradients_on_sampled_tiles():
     grads = rast.backward(params, out, torch.from_numpy(gimg.reshape(-1)).cuda())
     g2_gpu = rast.grad2d().cpu().numpy().astype(np.float64)
     grads = raster.to_scene_layout({k: v.cpu().numpy() for k, v in grads.items()})
-    del rast, out
+    del rast, out, params
     torch.cuda.empty_cache()
 
-    g2_ref = OB.blend_backward(pre, cam, opts, vals, ranges, gimg.astype(np.float64), tiles=tiles)
-    assert int((np.abs(np.stack(list(g2_ref.values()))).sum(axis=0) > 0).sum()) >= 300
-    rep = parity.compare_grads({k: g2_gpu[i] for i, k in enumerate(OB.GRAD2D)}, g2_ref)
-    for k, r in rep.items():
-        assert r["rel_l2"] <= parity.GRAD_REL and r["elem_viol"] == 0, ("2D", k, r)
+    g2_ref = OP.blend_backward(pre, cam, opts, vals, ranges, gimg.astype(np.float64))
+    # the camera sits inside the clustered cloud: a few hundred near splats
+    # cover most of the frame and saturate T, the rest are occluded
+    touched = int((np.abs(np.stack(list(g2_ref.values()))).sum(axis=0) > 0).sum())
+    assert touched >= 400, touched
+    rep = parity.compare_grads({k: g2_gpu[i] for i, k in enumerate(OB.GRAD2D)},
+                               {k: g2_ref[k] for k in OB.GRAD2D})
+    parity.assert_grads(rep, "2D")
     ref_raw = OB.preprocess_backward(sc, cam, opts, pre, g2_ref)
     rep = parity.compare_grads(grads, ref_raw)
-    for k, r in rep.items():
-        assert r["rel_l2"] <= parity.GRAD_REL and r["elem_viol"] == 0, ("raw", k, r)
+    parity.assert_grads(rep, "raw")
+    print(workload, touched, {k: (r["rel_l2"], r["normwise"]) for k, r in rep.items()}, flush=True)
 
 
 def _check_sampled_camera(rast, sc, cam, opts, k, tile_base, img_dev, rng, n_tiles=12, n_pix=24):
