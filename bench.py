@@ -367,12 +367,16 @@ def main():
     from paper_2501_00342_amd import _lib as L
     from paper_2501_00342_amd import autotune, raster, scenes
 
-    assert torch.cuda.is_available()
     sc, cams, base = scenes.workload(args.workload)
     cam = cams[0]
     W, H = cam.width, cam.height
-    target = torch.from_numpy(np.concatenate(
-        [scenes.target_image(c.width, c.height, 1 + i).reshape(-1) for i, c in enumerate(cams)])).cuda()
+    targets = [scenes.target_image(c.width, c.height, 1 + i) for i, c in enumerate(cams)]
+    # the oracle's leg first: its worker processes fork before the GPU is used
+    cpu = None
+    if not args.no_cpu_baseline and not args.profile_steps and len(cams) == 1:
+        cpu = cpu_baseline(sc, cam, base, targets[0])
+    assert torch.cuda.is_available()
+    target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in targets])).cuda()
     mods = (torch, L, raster, scenes, autotune)
 
     if args.profile_steps:
@@ -393,6 +397,7 @@ def main():
     names = L.stage_names()
     bits, P = rast.status()
     visited, evaluated, blended = rast.blend_work(m["params"])
+    bwd_work = m["rast_b"].blend_bwd_work(m["params"], m["buffers"][1])
     vis_items = (rast.depth_keys().cpu().numpy().view(np.uint32) != 0xFFFFFFFF).reshape(len(cams), sc.n)
     n_vis = int(np.count_nonzero(vis_items))
     n_vis_g = int(np.count_nonzero(vis_items.any(axis=0)))
@@ -458,6 +463,31 @@ def main():
         roof["traffic_source"] = tr["file"]
     roof["shape"] = shape
 
+    # the backward blend (the largest kernel of forward + backward): 4
+    # lane-ops per thread visit (column test, dx, the two x-terms), 9 per
+    # evaluated pair (as the forward), 32 per pair that carries a gradient
+    # (1 / (1 - alpha), T, w, three colour gradients, the colour dot product,
+    # dL/dalpha, the running sum behind, the clamp test, dL/dopacity and the
+    # five mean and conic gradients), and per wave reduction the 9 x 63
+    # additions that sum nine values over 64 lanes
+    roof_bwd = None
+    if "bwd.blend" in stages:
+        bv, be, bb, br = bwd_work
+        ops_b = 4 * bv + 9 * be + 32 * bb + 9 * 63 * br
+        ms_b = stages["bwd.blend"]["ms"]
+        ach_b = ops_b / (ms_b * 1e-3) / 1e12
+        shape_b = shape_of(m["rast_b"], m["opts_b"])
+        tr_b = counter_traffic("bwd.blend", args.workload, shape_b)
+        roof_bwd = {"kernel": "bwd.blend", "bound": "alu", "achieved": round(ach_b, 3),
+                    "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tlane-op/s",
+                    "frac": round(ach_b / VALU_PEAK_TOPS, 4), "ms_per_launch": ms_b,
+                    "lane_ops_per_launch": int(ops_b),
+                    "work": {"visited": bv, "evaluated": be, "blended": bb, "reductions": br},
+                    "atomic_instructions": br, "traffic": tr_b["bytes"] if tr_b else None,
+                    "shape": shape_b}
+        if tr_b:
+            roof_bwd["traffic_source"] = tr_b["file"]
+
     result = {
         "metric": ("frames/s & fwd+bwd ms at 3M Gaussians 1600x1060, SG vs SH-3 form, same GPU"
                    if args.workload == "sg-3m-1600" else f"frames/s & fwd+bwd ms, {args.workload}"),
@@ -473,7 +503,7 @@ def main():
                   "fwd_bwd_ms": round(m["fb_ms"], 4)},
         "pairs": int(P), "visible": n_vis, "tiles": tiles,
         "blend_visited": visited, "blend_evaluated": evaluated, "blend_blended": blended,
-        "stages": stages, "binning": binning, "roofline": roof,
+        "stages": stages, "binning": binning, "roofline": roof, "roofline_bwd": roof_bwd,
         # the paper's own rendering speed (Table 1: trained Mip-NeRF360
         # scenes, one RTX 3090, Gaussian counts not given): context only
         "paper_context": {"hardware": "RTX 3090", "scenes": "Mip-NeRF360, trained",
@@ -481,8 +511,6 @@ def main():
     }
     if m["reports"]:
         result["autotune"] = m["reports"]
-    if len(cams) > 1:
-        result["views_per_s"] = round(len(cams) * 1000.0 / m["fwd_graph_ms"], 2)
     # per-tile load (list lengths), e.g. for the stress workload
     rng = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
     cnt = rng[:, 1] - rng[:, 0]
@@ -492,6 +520,7 @@ def main():
                            "empty": int((cnt == 0).sum()),
                            "log2_bins": {f"<=2^{i}": int(b) for i, b in enumerate(bins) if b}}
 
+    stat_steps = max(100, args.steps)
     if not args.no_sh3 and args.workload == "sg-3m-1600":
         sh3 = scenes.sh3_scene(sc.n, 1)
         m3 = measure_form(args, *mods, sh3, cams, base, target)
@@ -512,16 +541,35 @@ def main():
         # headline ratios come from the paired replays in alternation
         result["sg_over_sh3_fps_unpaired"] = round(m3["fwd_graph_ms"] / (1000.0 / result["value"]), 4)
         result["sg_over_sh3_fwd_bwd_unpaired"] = round(m3["fb_graph_ms"] / result["fwd_bwd_ms"], 4)
-        paired = paired_comparison(m, m3, args.steps, torch)
+        paired, sg_fwd, sg_fb = paired_comparison(m, m3, stat_steps, torch)
         result["sg_vs_sh3_paired"] = paired
         result["sg_over_sh3_fps"] = paired["sg_over_sh3_fps"]
+        result["sg_over_sh3_fps_ci95"] = paired["sg_over_sh3_fps_ci95"]
         result["sg_over_sh3_fwd_bwd"] = paired["sg_over_sh3_fwd_bwd"]
+        result["sg_over_sh3_fwd_bwd_ci95"] = paired["sg_over_sh3_fwd_bwd_ci95"]
         del m3
+    else:
+        sg_fwd, sg_fb = alternating_steps([m["g_fwd"].replay, m["g_fb"].replay], stat_steps, torch)
+    # the headline: medians of the per-step samples (the paired run's SG
+    # samples when the SH-3 form is measured too)
+    med_f, med_fb = float(np.median(sg_fwd)), float(np.median(sg_fb))
+    result["value"] = round(1000.0 / med_f, 2)
+    result["ms_per_step"] = round(med_f, 4)
+    result["fwd_bwd_ms"] = round(med_fb, 4)
+    result["timing"] = {"fwd": summary(sg_fwd), "fwd_bwd": summary(sg_fb),
+                        "block_fwd_ms": round(m["fwd_graph_ms"], 4),
+                        "block_fwd_bwd_ms": round(m["fb_graph_ms"], 4),
+                        "note": ("value and ms_per_step: median of per-step HIP-event times of "
+                                 "the forward's graph replay; block_*: mean of one K-step block")}
+    if len(cams) > 1:
+        result["views_per_s"] = round(len(cams) * 1000.0 / med_f, 2)
     del m, rast
     torch.cuda.empty_cache()
 
-    if not args.no_cpu_baseline and len(cams) == 1:
-        result["cpu_baseline"] = cpu_baseline(sc, cam, base)
+    if cpu is not None:
+        cpu["gpu_speedup_fwd"] = round(cpu["frame_s"] * 1e3 / result["ms_per_step"], 1)
+        cpu["gpu_speedup_fwd_bwd"] = round(cpu["fwd_bwd_s"] * 1e3 / result["fwd_bwd_ms"], 1)
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

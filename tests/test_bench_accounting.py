@@ -7,6 +7,8 @@ they are built (one 3M-Gaussian frame: 646,587 visible items, 29.6M pairs,
 """
 import math
 
+import numpy as np
+
 import bench
 
 N, NVIS, P, TILES = 3_000_000, 646_587, 29_641_109, 6_700
@@ -69,3 +71,18 @@ def test_peaks():
     assert bench.HBM_PEAK_GBS == 8000
     # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-packed lane-op per lane
     assert abs(bench.VALU_PEAK_TOPS - 256 * 4 * 16 * 2.4e9 / 1e12) < 1e-9
+
+
+def test_ratio_interval_and_summary():
+    """The bench's statistics: the ratio of medians with a bootstrap interval
+    that contains it and shrinks with more samples; p10 <= median <= p90."""
+    import bench
+    rng = np.random.default_rng(4)
+    den = 1.0 + 0.01 * rng.normal(size=400)
+    num = 1.05 * (1.0 + 0.01 * rng.normal(size=400))
+    r, (lo, hi) = bench.ratio_ci(num, den)
+    assert lo <= r <= hi and 1.03 < r < 1.07
+    r2, (lo2, hi2) = bench.ratio_ci(num[:50], den[:50])
+    assert hi2 - lo2 > hi - lo
+    s = bench.summary(den)
+    assert s["p10_ms"] <= s["median_ms"] <= s["p90_ms"] and s["samples"] == 400
