@@ -285,10 +285,11 @@ def shape_of(rast, o):
 
 
 def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, target,
-                 profile=False):
+                 profile=False, colour_dtype=None):
     """Tune, then time one colour form: eager passes with per-stage HIP
-    events, then the same passes captured in HIP graphs and replayed."""
-    params = raster.params_to_device(scene)
+    events, then the same passes captured in HIP graphs and replayed.
+    colour_dtype: storage type of the colour parameters (float32 default)."""
+    params = raster.params_to_device(scene, colour_dtype=colour_dtype or torch.float32)
     opts_f, opts_b, reports = choose_options(args, torch, scenes, autotune, params, cams, base,
                                              scene, target)
     rast = raster.Rasterizer(cams, opts_f, scene.n, scene.sh_degree, scene.n_lobes)
@@ -519,6 +520,22 @@ def main():
                            "p99": float(np.percentile(cnt, 99)), "max": int(cnt.max()),
                            "empty": int((cnt == 0).sum()),
                            "log2_bins": {f"<=2^{i}": int(b) for i, b in enumerate(bins) if b}}
+
+    # the same SG form with its colour stored as bfloat16 (the bandwidth side
+    # of the compact model): block timings and the colour-dependent stages
+    if args.workload == "sg-3m-1600" and not args.no_sh3:
+        mh = measure_form(args, *mods, sc, cams, base, target, colour_dtype=torch.bfloat16)
+        st_h = {nm: round((mh["st_fwd"] if nm.startswith("fwd") else mh["st_fb"])[i] /
+                          max(mh["nf"] if nm.startswith("fwd") else mh["nb"], 1), 5)
+                for i, nm in enumerate(names)}
+        result["colour_bf16"] = {"fwd_ms": round(mh["fwd_graph_ms"], 4),
+                                 "fwd_bwd_ms": round(mh["fb_graph_ms"], 4),
+                                 "fwd_ms_f32_same_run": round(m["fwd_graph_ms"], 4),
+                                 "fwd_bwd_ms_f32_same_run": round(m["fb_graph_ms"], 4),
+                                 "preprocess_ms": st_h["fwd.preprocess"],
+                                 "bwd_preprocess_ms": st_h["bwd.preprocess"],
+                                 "colour_bytes_per_visible_gaussian": 2 * 40}
+        del mh
 
     stat_steps = max(100, args.steps)
     if not args.no_sh3 and args.workload == "sg-3m-1600":

@@ -110,8 +110,19 @@ typedef struct sgs_gaussians {
                                         Mixing Spherical Harmonics and Spherical
                                         Gaussians).  {0, 0} = every Gaussian uses
                                         sh_degree; else 0 <= [0] <= [1]. */
-    int32_t reserved;                /* must be 0 */
+    int32_t colour_dtype;            /* element type of the four colour arrays (sh, sg_axes,
+                                        sg_log_sharpness, sg_amplitudes): SGS_COLOUR_F32, or
+                                        SGS_COLOUR_BF16 / SGS_COLOUR_F16 storage (their
+                                        pointers then address 2-byte elements and
+                                        colour_stride counts elements; the arithmetic stays
+                                        float32, and those types need sh_adaptive {0, 0}).
+                                        The storage side of the compact model (Experiments,
+                                        Table 3). */
 } sgs_gaussians;
+
+#define SGS_COLOUR_F32 0
+#define SGS_COLOUR_BF16 1
+#define SGS_COLOUR_F16 2
 
 #define SGS_LOBES_FREE 0
 #define SGS_LOBES_WORLD 1
@@ -378,7 +389,8 @@ typedef struct sgs_adam {
  * exp_avg_sq: the first and second moments, packed like the gradients,
  * caller-owned, zero before the first step (device).  One launch; no
  * allocation, no synchronisation.  SGS_E_INVALID on a NULL array that the
- * form needs, step < 1 or a learning rate < 0.
+ * form needs, step < 1, a learning rate < 0, or colour_dtype other than
+ * SGS_COLOUR_F32 (the update is float32 in place).
  */
 int render_adam_step(const sgs_gaussians* g, const sgs_adam* cfg, const sgs_grads* grads,
                      const sgs_grads* exp_avg, const sgs_grads* exp_avg_sq, void* stream);

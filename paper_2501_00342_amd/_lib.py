@@ -17,6 +17,7 @@ SGS_OK, SGS_E_INVALID, SGS_E_CAPACITY, SGS_E_HIP = 0, 1, 2, 3
 SGS_STATUS_CAPACITY, SGS_STATUS_CAMERAS = 1, 2
 SCHEDULE_GRID, SCHEDULE_QUEUE = 1, 2
 SGS_FLAG_CHECK_CAPACITY = 1
+COLOUR_F32, COLOUR_BF16, COLOUR_F16 = 0, 1, 2
 LOBES_FREE, LOBES_WORLD, LOBES_FRAME = 0, 1, 2
 MAX_SH_DEGREE, MAX_LOBES, MAX_CAMERAS, MAX_IMAGE_SIDE = 3, 8, 1024, 32767
 
@@ -27,7 +28,7 @@ class Gaussians(Structure):
                 ("opacity_logits", c_void_p), ("sh", c_void_p), ("sg_axes", c_void_p),
                 ("sg_log_sharpness", c_void_p), ("sg_amplitudes", c_void_p),
                 ("colour_stride", c_int64), ("lobe_axes", c_int32),
-                ("sh_adaptive", c_int32 * 2), ("reserved", c_int32)]
+                ("sh_adaptive", c_int32 * 2), ("colour_dtype", c_int32)]
 
 
 class Grads(Structure):
@@ -182,7 +183,8 @@ def options_struct(opts) -> Options:
 
 
 def gaussians_struct(n, sh_degree, n_lobes, ptrs: dict, colour_stride: int = 0,
-                     lobe_axes: int = LOBES_FREE, sh_adaptive=(0, 0)) -> Gaussians:
+                     lobe_axes: int = LOBES_FREE, sh_adaptive=(0, 0),
+                     colour_dtype: int = 0) -> Gaussians:
     g = Gaussians()
     g.n, g.sh_degree, g.n_lobes = int(n), int(sh_degree), int(n_lobes)
     for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "sg_axes",
@@ -191,7 +193,7 @@ def gaussians_struct(n, sh_degree, n_lobes, ptrs: dict, colour_stride: int = 0,
     g.colour_stride = int(colour_stride)
     g.lobe_axes = int(lobe_axes)
     g.sh_adaptive[0], g.sh_adaptive[1] = int(sh_adaptive[0]), int(sh_adaptive[1])
-    g.reserved = 0
+    g.colour_dtype = int(colour_dtype)
     return g
 
 

@@ -421,7 +421,13 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
         for (int j = cnt - 1; j >= 0; --j) {
             const Entry e = s_e[j];
             const int pos = bb + j;
-            float v_u = 0.f, v_v = 0.f, v_qa = 0.f, v_qb = 0.f, v_qc = 0.f, v_s = 0.f;
+            // per pixel only the moments of dL/dp over the splat's offsets
+            // d = (dx, dy) are summed: m1 = sum dLdp dx, m2 = sum dLdp dy,
+            // m3 = sum dLdp dx^2, m4 = sum dLdp dx dy, m5 = sum dLdp dy^2.
+            // The mean and conic gradients are linear in them (dp/du =
+            // (Q d)_x, dp/dQa = -dx^2 / 2, ...) and are formed once per wave
+            // reduction.
+            float m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, v_s = 0.f;
             float v_r = 0.f, v_g = 0.f, v_b = 0.f, v_z = 0.f;
             bool contrib = false;
             if (COUNT) ++work.visited;
@@ -430,41 +436,43 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                 const float t1 = e.a.z * dx, t2 = e.b.x * dx;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    if (pos >= nc[k] || !((e.m.y >> (ry + k)) & 1u)) continue;
-                    if (COUNT) ++work.evaluated;
-                    const float dy = (float)(ry + k) + e.a.y;
-                    const Eval v = eval_splat(e, t1, t2, dy, amax);
-                    if (v.alpha < amin) continue;
-                    contrib = true;
-                    if (COUNT) {
-                        ++work.blended;
-                        continue;
-                    }
-                    // 1 / (1 - alpha) with v_rcp_f32 (1 ulp; 1 - alpha >= 1 - alpha_max)
-                    const float iom = __builtin_amdgcn_rcpf(1.0f - v.alpha);
-                    T[k] = T[k] * iom;
-                    const float w = v.alpha * T[k];
-                    v_r = fmaf(w, g0[k], v_r);
-                    v_g = fmaf(w, g1[k], v_g);
-                    v_b = fmaf(w, g2[k], v_b);
-                    float cg = e.c.x * g0[k] + e.c.y * g1[k] + e.c.z * g2[k];
-                    if (DG) {
-                        cg = fmaf(e.b.w, gD[k], cg);   // + z gD
-                        v_z = fmaf(w, gD[k], v_z);      // dL/dz = alpha T gD
-                    }
-                    const float sg = SG[k];
-                    const float dLda = T[k] * cg - sg * iom;
-                    SG[k] = fmaf(w, cg, SG[k]);
-                    if (e.b.z * v.E <= amax) {
-                        v_s = fmaf(dLda, v.E, v_s);
-                        const float dLdp = dLda * v.alpha;
-                        // dp/du = (Q d)_x, Q d = (w1 y1 + w2 y2) / k
-                        const float pk = dLdp * inv_k;
-                        v_u = fmaf(pk, e.a.z * v.y1 + e.b.x * v.y2, v_u);
-                        v_v = fmaf(pk, e.a.w * v.y1 + e.b.y * v.y2, v_v);
-                        v_qa = fmaf(-0.5f * dLdp * dx, dx, v_qa);
-                        v_qb = fmaf(-dLdp * dx, dy, v_qb);
-                        v_qc = fmaf(-0.5f * dLdp * dy, dy, v_qc);
+                    // nested tests rather than `continue`: no exit flag to track
+                    if (pos < nc[k] && ((e.m.y >> (ry + k)) & 1u)) {
+                        if (COUNT) ++work.evaluated;
+                        const float dy = (float)(ry + k) + e.a.y;
+                        const Eval v = eval_splat(e, t1, t2, dy, amax);
+                        if (!(v.alpha < amin)) {
+                            contrib = true;
+                            if (COUNT) {
+                                ++work.blended;
+                            } else {
+                                // 1 / (1 - alpha) with v_rcp_f32 (1 ulp; 1 - alpha >= 1 - alpha_max)
+                                const float iom = __builtin_amdgcn_rcpf(1.0f - v.alpha);
+                                T[k] = T[k] * iom;
+                                const float w = v.alpha * T[k];
+                                v_r = fmaf(w, g0[k], v_r);
+                                v_g = fmaf(w, g1[k], v_g);
+                                v_b = fmaf(w, g2[k], v_b);
+                                float cg = e.c.x * g0[k] + e.c.y * g1[k] + e.c.z * g2[k];
+                                if (DG) {
+                                    cg = fmaf(e.b.w, gD[k], cg);   // + z gD
+                                    v_z = fmaf(w, gD[k], v_z);      // dL/dz = alpha T gD
+                                }
+                                const float sg = SG[k];
+                                const float dLda = T[k] * cg - sg * iom;
+                                SG[k] = fmaf(w, cg, SG[k]);
+                                if (e.b.z * v.E <= amax) {
+                                    v_s = fmaf(dLda, v.E, v_s);
+                                    const float dLdp = dLda * v.alpha;
+                                    m1 = fmaf(dLdp, dx, m1);
+                                    m2 = fmaf(dLdp, dy, m2);
+                                    const float px_ = dLdp * dx;
+                                    m3 = fmaf(px_, dx, m3);
+                                    m4 = fmaf(px_, dy, m4);
+                                    m5 = fmaf(dLdp * dy, dy, m5);
+                                }
+                            }
+                        }
                     }
                 }
             }
@@ -472,31 +480,57 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                 if (__any(contrib) && lane == 0) ++work.reductions;
             } else if (__any(contrib)) {
                 constexpr int NV = DG ? 10 : 9;
-                const float vals[10] = {v_u, v_v, v_qa, v_qb, v_qc, v_s, v_r, v_g, v_b, v_z};
+                const float vals[10] = {m1, m2, m3, m4, m5, v_s, v_r, v_g, v_b, v_z};
                 float x[3];
                 wave_sum<NV>(vals, x);
+                // row r holds the totals of values ch, 4 + ch and 8 + ch,
+                // ch = 2 (r & 1) + (r >> 1): the moments sit in rows 0-3 of
+                // x[0] and row 0 of x[1]
+                auto lane_f = [](float v, int l) {
+                    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+                };
+                const float s1 = lane_f(x[0], 0), s2 = lane_f(x[0], 32);
+                const float s3 = lane_f(x[0], 16), s4 = lane_f(x[0], 48);
+                const float s5 = lane_f(x[1], 0);
+                // Q k = w1 w1^T + w2 w2^T (whitening rows), k = 1 / inv_k
+                const float qa = fmaf(e.a.z, e.a.z, e.b.x * e.b.x);
+                const float qb = fmaf(e.a.z, e.a.w, e.b.x * e.b.y);
+                const float qc = fmaf(e.a.w, e.a.w, e.b.y * e.b.y);
+                const float g_u = inv_k * fmaf(qa, s1, qb * s2);
+                const float g_v = inv_k * fmaf(qb, s1, qc * s2);
                 // the entry is the same in every lane: its address is scalar
                 const int64_t item =
                     __builtin_amdgcn_readfirstlane(__float_as_uint(e.c.w));
                 float* gi = G + item;
-                // every lane of row r holds the row's totals: lane 15 adds
-                // x[0] to channel ch, lane 14 x[1] to channel 4 + ch and, in
-                // the rows with ch < NV - 8, lane 13 x[2] to channel 8 + ch
-                // -- NV lanes of one atomic instruction (channel order of
-                // grad2d: u, v, Qa, Qb, Qc, sigma, r, g, b, z)
+                // lane 15 of row r adds channel ch (u, Qa, v, Qb for rows
+                // 0-3), lane 14 channel 4 + ch (Qc, r, sigma, g) and, in the
+                // rows with ch < NV - 8, lane 13 channel 8 + ch (b, z) -- NV
+                // lanes of one atomic instruction (channel order of grad2d:
+                // u, v, Qa, Qb, Qc, sigma, r, g, b, z)
                 const int r = lane >> 4, sel = 15 - (lane & 15);
                 const int ch = 2 * (r & 1) + (r >> 1);
                 if (sel < 2 || (sel == 2 && ch < NV - 8)) {
+                    const float c0 = r == 0 ? g_u : (r == 1 ? -0.5f * s3 : (r == 2 ? g_v : -s4));
+                    const float c1 = r == 0 ? -0.5f * s5 : x[1];
                     const int chan = sel == 0 ? ch : (sel == 1 ? 4 + ch : 8 + ch);
-                    unsafeAtomicAdd(gi + chan * M, sel == 0 ? x[0] : (sel == 1 ? x[1] : x[2]));
+                    unsafeAtomicAdd(gi + chan * M, sel == 0 ? c0 : (sel == 1 ? c1 : x[2]));
                 }
             }
         }
     }
 }
 
+// waves per SIMD asked of the compiler for the backward: 7 without the
+// depth/alpha terms (72 VGPRs, a few cold spills: 530 against 573 us on
+// the 3M frame at the natural 74 VGPRs and 6 waves), 6 with them
+template <bool DG>
+struct BwdWaves {
+    static constexpr int value = DG ? 6 : 7;
+};
+
 template <int TW, int TH, int PPT, bool QUEUE, bool DG, bool COUNT>
 __global__ void __launch_bounds__(TW * TH / PPT)
+__attribute__((amdgpu_waves_per_eu(BwdWaves<DG>::value)))
 k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs fwd, Upstream up, int batch, unsigned long long* counts) {
     extern __shared__ __align__(16) Entry s_e[];

@@ -4,6 +4,8 @@
 // normalised lobe axis (eqs. 4, 5, 9).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "sh_basis.hpp"
 
@@ -119,19 +121,46 @@ __device__ __forceinline__ bool colour_eval(SH sh, AX axis, LS lsh, AM amp, int 
 // record is the concatenation of one contiguous block from each array (one
 // run of memory when they interleave).
 //
+// Element types of the colour arrays (template parameter CT): float32,
+// bfloat16 or float16 storage; the arithmetic is float32 either way (the
+// conversions to float32 are exact).
+enum ColourType : int { kColourF32 = 0, kColourBF16 = 1, kColourF16 = 2 };
+
+template <int CT>
+struct ColourElem {
+    static constexpr int bytes = CT == kColourF32 ? 4 : 2;
+};
+
+// element i of a colour record in LDS, as float32
+template <int CT>
+__device__ __forceinline__ float colour_at(const void* r, int i) {
+    if constexpr (CT == kColourF32) {
+        return static_cast<const float*>(r)[i];
+    } else if constexpr (CT == kColourBF16) {
+        return __uint_as_float((uint32_t)static_cast<const uint16_t*>(r)[i] << 16);
+    } else {
+        return (float)static_cast<const _Float16*>(r)[i];
+    }
+}
+
 // Cooperative gather of colour records into LDS for the lanes of this wave
 // that set `fetch`: the j-th of them (in lane order) gets record slot
-// slot0 + j of `rec` (records of p.rec_floats floats, back to back) and
-// learns its slot in *slot.  Consecutive lanes of each direct global->LDS
-// load fetch consecutive 16-byte pieces (4-byte pieces when a block is not
-// a whole number of 16-byte pieces) of the same Gaussian's blocks, so one
-// instruction covers several Gaussians' contiguous blocks rather than one
-// float of each of 64 Gaussians.  s_g: 64 entries of the wave's LDS.
-// Returns how many lanes fetched (wave-uniform); the caller waits
-// (s_waitcnt) before reading the records.
-template <int NC3>
+// slot0 + j of `rec` (records of p.rec_floats elements of the colour type,
+// back to back) and learns its slot in *slot.  Consecutive lanes of each
+// direct global->LDS load fetch consecutive 16-byte pieces (single-element
+// pieces when a block is not a whole number of 16-byte pieces; 2-byte
+// elements are then loaded to registers and stored) of the same
+// Gaussian's blocks, so one instruction covers several Gaussians'
+// contiguous blocks rather than one element of each of 64 Gaussians.
+// s_g: 64 entries of the wave's LDS.  Returns how many lanes fetched
+// (wave-uniform); the caller waits (s_waitcnt) before reading the records.
+template <int NC3, int CT>
 __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fetch, int slot0,
-                                             float* rec, int64_t* s_g, int* slot) {
+                                             void* rec, int64_t* s_g, int* slot) {
+    // storage element: float32, or the 16 bits of a bfloat16 / float16
+    using T = typename std::conditional<CT == kColourF32, float, uint16_t>::type;
+    constexpr int E = (int)sizeof(T);           // bytes per element
+    constexpr int W16 = 16 / E;                 // elements per 16-byte piece
     const int lane = threadIdx.x & 63;
     const uint64_t b = __ballot(fetch);
     const int m = __popcll(b);
@@ -144,27 +173,30 @@ __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fe
     }
     const int K = p.n_lobes, A = p.n_axes;
     const int RSF = p.rec_floats;
-    float* base = rec + slot0 * RSF;
-    bool v4;
+    T* base = static_cast<T*>(rec) + slot0 * RSF;
+    const T* sh = reinterpret_cast<const T*>(p.sh);
+    const T* ax = reinterpret_cast<const T*>(p.sg_axes);
+    const T* ls = reinterpret_cast<const T*>(p.sg_log_sharpness);
+    const T* am = reinterpret_cast<const T*>(p.sg_amplitudes);
+    bool v16;
     int q_sh, q_ax, q_ls, Q;
     if (p.contig) {
-        // one run of RSF floats per Gaussian
-        v4 = (RSF % 4 == 0) && (p.cs_sh % 4 == 0) && (((uintptr_t)p.sh) & 15u) == 0;
-        q_sh = RSF / (v4 ? 4 : 1);
+        // one run of RSF elements per Gaussian
+        v16 = (RSF % W16 == 0) && (p.cs_sh % W16 == 0) && (((uintptr_t)sh) & 15u) == 0;
+        q_sh = RSF / (v16 ? W16 : 1);
         q_ax = q_ls = 0;
         Q = q_sh;
     } else {
-        v4 = (NC3 % 4 == 0) && ((3 * A) % 4 == 0) && (K % 4 == 0) &&
-             ((p.cs_sh | p.cs_ax | p.cs_ls | p.cs_am) & 3) == 0 &&
-             (((uintptr_t)p.sh | (uintptr_t)p.sg_axes | (uintptr_t)p.sg_log_sharpness |
-               (uintptr_t)p.sg_amplitudes) & 15u) == 0;
-        const int w = v4 ? 4 : 1;
+        v16 = (NC3 % W16 == 0) && ((3 * A) % W16 == 0) && (K % W16 == 0) &&
+              ((p.cs_sh | p.cs_ax | p.cs_ls | p.cs_am) & (W16 - 1)) == 0 &&
+              (((uintptr_t)sh | (uintptr_t)ax | (uintptr_t)ls | (uintptr_t)am) & 15u) == 0;
+        const int w = v16 ? W16 : 1;
         q_sh = NC3 / w;
         q_ax = 3 * A / w;
         q_ls = K / w;
         Q = q_sh + q_ax + q_ls + 3 * K / w;   // pieces per record
     }
-    const int wdt = v4 ? 4 : 1;   // floats per piece
+    const int wdt = v16 ? W16 : 1;   // elements per piece
     const float invQ = 1.0f / (float)Q;
     const int total = m * Q;
     for (int P0 = 0; P0 < total; P0 += 64) {
@@ -175,20 +207,24 @@ __device__ __forceinline__ int gather_colour(const Params& p, int64_t g, bool fe
         const int j = on ? (int)(((float)P + 0.5f) * invQ) : 0;
         const int q = P - j * Q;
         const int64_t gj = s_g[j];
-        const float* src;
-        if (q < q_sh) src = p.sh + gj * p.cs_sh + q * wdt;
-        else if (q < q_sh + q_ax) src = p.sg_axes + gj * p.cs_ax + (q - q_sh) * wdt;
-        else if (q < q_sh + q_ax + q_ls) src = p.sg_log_sharpness + gj * p.cs_ls + (q - q_sh - q_ax) * wdt;
-        else src = p.sg_amplitudes + gj * p.cs_am + (q - q_sh - q_ax - q_ls) * wdt;
+        const T* src;
+        if (q < q_sh) src = sh + gj * p.cs_sh + q * wdt;
+        else if (q < q_sh + q_ax) src = ax + gj * p.cs_ax + (q - q_sh) * wdt;
+        else if (q < q_sh + q_ax + q_ls) src = ls + gj * p.cs_ls + (q - q_sh - q_ax) * wdt;
+        else src = am + gj * p.cs_am + (q - q_sh - q_ax - q_ls) * wdt;
         if (on) {
-            if (v4)
+            if (v16)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                                 (__attribute__((address_space(3))) void*)(base + P0 * 4),
+                                                 (__attribute__((address_space(3))) void*)(base + P0 * W16),
                                                  16, 0, 0);
-            else
+            else if constexpr (E == 4)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                                  (__attribute__((address_space(3))) void*)(base + P0),
                                                  4, 0, 0);
+            else
+                // direct loads of 1 or 2 bytes still place lane i at 4 i in
+                // LDS: 2-byte elements go through a register instead
+                base[P0 + lane] = *src;
         }
     }
     return m;

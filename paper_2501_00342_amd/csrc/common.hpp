@@ -89,7 +89,9 @@ struct Params {
     // rec_floats may round the record up to whole 16-byte pieces when the
     // stride leaves room
     bool contig;
-    int rec_floats;
+    int rec_floats;         // elements of the colour type per record
+    int colour_type;        // ColourType of the four colour arrays (their pointers
+                            // then address elements of that type; strides count them)
     const float* means;
     const float* log_scales;
     const float* quats;

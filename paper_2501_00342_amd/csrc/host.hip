@@ -73,7 +73,11 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
         return fail(SGS_E_INVALID, "the orthogonal lobe modes take exactly 3 lobes");
     if (g->sh_adaptive[0] < 0 || g->sh_adaptive[1] < g->sh_adaptive[0])
         return fail(SGS_E_INVALID, "sh_adaptive must satisfy 0 <= [0] <= [1]");
-    if (g->reserved != 0) return fail(SGS_E_INVALID, "sgs_gaussians.reserved must be 0");
+    if (g->colour_dtype != SGS_COLOUR_F32 && g->colour_dtype != SGS_COLOUR_BF16 &&
+        g->colour_dtype != SGS_COLOUR_F16)
+        return fail(SGS_E_INVALID, "colour_dtype must be SGS_COLOUR_F32, _BF16 or _F16");
+    if (g->colour_dtype != SGS_COLOUR_F32 && (g->sh_adaptive[0] | g->sh_adaptive[1]) != 0)
+        return fail(SGS_E_INVALID, "half-precision colour storage needs a fixed SH degree");
     if (!cams) return fail(SGS_E_INVALID, "host cameras are NULL");
     if (n_cams < 1 || n_cams > SGS_MAX_CAMERAS) return fail(SGS_E_INVALID, "n_cams must be 1..1024");
     if (cap < 0 || cap >= (int64_t(1) << 30)) return fail(SGS_E_INVALID, "pair_capacity must be in [0, 2^30)");
@@ -273,15 +277,19 @@ sgs::Params params_of(const sgs_gaussians* g) {
     p.cs_ls = cs > 0 ? cs : K;
     p.cs_am = cs > 0 ? cs : 3 * K;
     const int64_t rs = nc3 + A3 + 4 * K;
-    // the four arrays interleave: one run of rs floats per Gaussian
-    p.contig = cs > 0 && (A3 == 0 || g->sg_axes == g->sh + nc3) &&
-               (K == 0 || (g->sg_log_sharpness == g->sh + nc3 + A3 &&
-                           g->sg_amplitudes == g->sh + nc3 + A3 + K));
+    p.colour_type = g->colour_dtype;
+    // bytes per colour element, and elements per 16-byte piece
+    const int64_t E = g->colour_dtype == SGS_COLOUR_F32 ? 4 : 2, W16 = 16 / E;
+    const char* sh = reinterpret_cast<const char*>(g->sh);
+    // the four arrays interleave: one run of rs elements per Gaussian
+    p.contig = cs > 0 && (A3 == 0 || reinterpret_cast<const char*>(g->sg_axes) == sh + nc3 * E) &&
+               (K == 0 || (reinterpret_cast<const char*>(g->sg_log_sharpness) == sh + (nc3 + A3) * E &&
+                           reinterpret_cast<const char*>(g->sg_amplitudes) == sh + (nc3 + A3 + K) * E));
     p.rec_floats = (int)rs;
     // read whole 16-byte pieces when the stride leaves room for the rounding
-    const int64_t rs4 = (rs + 3) & ~int64_t(3);
-    if (p.contig && cs % 4 == 0 && cs >= rs4 && ((uintptr_t)g->sh & 15u) == 0)
-        p.rec_floats = (int)rs4;
+    const int64_t rs16 = (rs + W16 - 1) / W16 * W16;
+    if (p.contig && cs % W16 == 0 && cs >= rs16 && ((uintptr_t)g->sh & 15u) == 0)
+        p.rec_floats = (int)rs16;
     return p;
 }
 
@@ -357,10 +365,16 @@ int render_layout(const sgs_gaussians* g, const sgs_camera* host_cams, int32_t n
     return SGS_OK;
 }
 
-int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
-                   int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
-                   int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
-                   int64_t* pairs_needed, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The forward behind render_forward.  `timed`: record stage events when
+// stage timing is on.
+int forward_impl(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
+                 int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
+                 int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
+                 int64_t* pairs_needed, void* stream, bool timed) {
     Plan pl;
     int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
     if (rc != SGS_OK) return rc;
@@ -375,7 +389,7 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
     const sgs::Params p = params_of(g);
     const sgs::Opts& o = pl.o;
     (void)hipGetLastError();
-    Marker mk{timing_slot(g_timing.fwd, g_timing.fwd_used), s};
+    Marker mk{timed ? timing_slot(g_timing.fwd, g_timing.fwd_used) : nullptr, s};
 
     mk.mark(0);
     sgs::launch_setup(ws, dev_cams, n_cams, o.tile_w, o.tile_h, o.guard, s);   // clears too
@@ -472,6 +486,19 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
     mk.mark(8);
     return SGS_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
+                   int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
+                   int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
+                   int64_t* pairs_needed, void* stream) {
+    return forward_impl(g, host_cams, dev_cams, n_cams, opts, workspace, workspace_bytes,
+                        pair_capacity, outs, flags, pairs_needed, stream, true);
+}
+
 
 int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
                     int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
@@ -647,6 +674,8 @@ int render_adam_step(const sgs_gaussians* g, const sgs_adam* cfg, const sgs_grad
         g->lobe_axes != SGS_LOBES_FRAME)
         return fail(SGS_E_INVALID, "lobe_axes must be SGS_LOBES_FREE, _WORLD or _FRAME");
     if (cfg->step < 1) return fail(SGS_E_INVALID, "step must be >= 1");
+    if (g->colour_dtype != SGS_COLOUR_F32)
+        return fail(SGS_E_INVALID, "the Adam step updates float32 parameters only");
     int rc = check_params(g);
     if (rc != SGS_OK) return rc;
     const int64_t n = g->n;

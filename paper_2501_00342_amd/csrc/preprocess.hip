@@ -131,7 +131,7 @@ __device__ __forceinline__ Geo project(const double X[3], const double ls[3], co
 // so only the colour gather's latency is exposed per tile.  The colour is
 // evaluated from LDS, so the geometry's and the colour's registers are never
 // live together.
-template <int DEG, int KMAX, int LM, bool AD>
+template <int DEG, int KMAX, int LM, bool AD, int CT>
 __global__ void __launch_bounds__(kPreTile)
 k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Workspace ws) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
@@ -194,7 +194,7 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             const int64_t item = (int64_t)ci * n + g;
             const Geo geo = project(X, ls, q, cam, ct, o);
             bool vis = active && finite && geo.visible && cams_ok;
-            const int got = gather_colour<3 * NC>(p, g, vis && slot < 0, used, rec, s_g[wave], &slot);
+            const int got = gather_colour<3 * NC, CT>(p, g, vis && slot < 0, used, rec, s_g[wave], &slot);
             used += got;
             // this wave's direct loads have landed (it reads only its own buffer)
             if (got) __builtin_amdgcn_s_waitcnt(0);
@@ -202,13 +202,13 @@ k_preprocess(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, 
             if (vis) {
                 float d[3], dist;
                 view_dir(X, cam, d, &dist);
-                const float* r = rec + slot * RS;
+                const char* r = reinterpret_cast<const char*>(rec) + slot * RS * ColourElem<CT>::bytes;
                 const int K = p.n_lobes, A3 = 3 * p.n_axes;
                 vis = colour_eval<DEG, KMAX, LM>(
-                    [&](int l, int c) { return r[3 * l + c]; },
-                    [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
-                    [&](int k) { return r[3 * NC + A3 + k]; },
-                    [&](int k, int c) { return r[3 * NC + A3 + K + 3 * k + c]; }, K,
+                    [&](int l, int c) { return colour_at<CT>(r, 3 * l + c); },
+                    [&](int k, int j) { return colour_at<CT>(r, 3 * NC + 3 * k + j); },
+                    [&](int k) { return colour_at<CT>(r, 3 * NC + A3 + k); },
+                    [&](int k, int c) { return colour_at<CT>(r, 3 * NC + A3 + K + 3 * k + c); }, K,
                     AD ? sh_used<DEG>(p, geo.radius) : NC, d[0], d[1], d[2], rgb);
             }
             if (!active) continue;
@@ -272,13 +272,21 @@ static void launch_pre_k(const Params& p, const sgs_camera* dev_cams, int n_cams
     // adaptive SH degree is its own instantiation: with a fixed degree the
     // coefficient loops keep a compile-time bound
     const bool ad = (p.sh_ad0 | p.sh_ad1) != 0;
-#define SGS_PRE(D, A) hipLaunchKernelGGL((k_preprocess<D, KMAX, LM, A>), grid, block, 0, s, p, dev_cams, n_cams, o, ws)
+    // colour element type: float32, or bfloat16 / float16 storage (those
+    // with a fixed SH degree only; the host checks)
+#define SGS_PRE(D, A, C) hipLaunchKernelGGL((k_preprocess<D, KMAX, LM, A, C>), grid, block, 0, s, p, dev_cams, n_cams, o, ws)
+#define SGS_PRE_T(D)                                                                       \
+    if (p.colour_type == kColourBF16) SGS_PRE(D, false, kColourBF16);                      \
+    else if (p.colour_type == kColourF16) SGS_PRE(D, false, kColourF16);                   \
+    else if (ad && D > 0) SGS_PRE(D, (D > 0), kColourF32);                                 \
+    else SGS_PRE(D, false, kColourF32)
     switch (p.sh_degree) {
-        case 0: SGS_PRE(0, false); break;
-        case 1: if (ad) SGS_PRE(1, true); else SGS_PRE(1, false); break;
-        case 2: if (ad) SGS_PRE(2, true); else SGS_PRE(2, false); break;
-        default: if (ad) SGS_PRE(3, true); else SGS_PRE(3, false); break;
+        case 0: SGS_PRE_T(0); break;
+        case 1: SGS_PRE_T(1); break;
+        case 2: SGS_PRE_T(2); break;
+        default: SGS_PRE_T(3); break;
     }
+#undef SGS_PRE_T
 #undef SGS_PRE
 }
 

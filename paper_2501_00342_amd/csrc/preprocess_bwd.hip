@@ -38,7 +38,7 @@ struct ColourBwdWaves {
     static constexpr int value = rows <= 40 ? 4 : (rows <= 48 ? 3 : 1);
 };
 
-template <int DEG, int KMAX, int LM, bool AD>
+template <int DEG, int KMAX, int LM, bool AD, int CT>
 __global__ void __launch_bounds__(kPreTile)
 __attribute__((amdgpu_waves_per_eu(ColourBwdWaves<DEG, KMAX, LM>::value)))
 k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspace ws,
@@ -111,7 +111,7 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
 #pragma unroll
                 for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[(6 + c) * M + item];
             }
-            const int got = gather_colour<3 * NC>(p, gc, vis && slot < 0, used, crec, s_g[wave], &slot);
+            const int got = gather_colour<3 * NC, CT>(p, gc, vis && slot < 0, used, crec, s_g[wave], &slot);
             used += got;
             if (got) __builtin_amdgcn_s_waitcnt(0);
             if (!vis) continue;
@@ -119,17 +119,17 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
 #pragma unroll
                 for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[(6 + c) * M + item];
             }
-            const float* r = crec + slot * RS;
+            const char* r = reinterpret_cast<const char*>(crec) + slot * RS * ColourElem<CT>::bytes;
             float d[3], dist;
             view_dir(X, cams[ci], d, &dist);
             float gd[3];
             // adaptive SH: the degree this camera used, from the item's radius
             const int ncu = AD ? sh_used<DEG>(p, ws.records[item].radius) : NC;
             colour_bwd_eval<DEG, KMAX, LM>(
-                [&](int l, int c) { return r[3 * l + c]; },
-                [&](int k, int j) { return r[3 * NC + 3 * k + j]; },
-                [&](int k) { return r[3 * NC + A3 + k]; },
-                [&](int k, int c) { return r[3 * NC + A3 + K + 3 * k + c]; }, K, ncu, d[0], d[1],
+                [&](int l, int c) { return colour_at<CT>(r, 3 * l + c); },
+                [&](int k, int j) { return colour_at<CT>(r, 3 * NC + 3 * k + j); },
+                [&](int k) { return colour_at<CT>(r, 3 * NC + A3 + k); },
+                [&](int k, int c) { return colour_at<CT>(r, 3 * NC + A3 + K + 3 * k + c); }, K, ncu, d[0], d[1],
                 d[2], grgb, gsh, gamp, gax, glsh, gd);
             // through d = (X - c) / |X - c|: (I - d d^T) / |X - c|
             const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
@@ -363,11 +363,16 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     // adaptive SH degree is its own instantiation (compile-time loop bounds
     // otherwise)
     const bool ad = (p.sh_ad0 | p.sh_ad1) != 0 && p.sh_degree > 0;
+#define SGS_COLOUR_BWD1(D, K, LM, A, C)                                                        \
+    hipLaunchKernelGGL((k_colour_bwd<D, K, LM, A, C>), cgrid, cblock, 0, s, p, dev_cams, n_cams, \
+                       ws, gr, gxc)
+    // colour element type: bfloat16 / float16 storage only with a fixed SH
+    // degree (the host checks)
 #define SGS_COLOUR_BWD(D, K, LM)                                                               \
-    if (ad) hipLaunchKernelGGL((k_colour_bwd<D, K, LM, (D > 0)>), cgrid, cblock, 0, s, p,      \
-                               dev_cams, n_cams, ws, gr, gxc);                                 \
-    else hipLaunchKernelGGL((k_colour_bwd<D, K, LM, false>), cgrid, cblock, 0, s, p, dev_cams, \
-                            n_cams, ws, gr, gxc)
+    if (p.colour_type == kColourBF16) SGS_COLOUR_BWD1(D, K, LM, false, kColourBF16);           \
+    else if (p.colour_type == kColourF16) SGS_COLOUR_BWD1(D, K, LM, false, kColourF16);        \
+    else if (ad) SGS_COLOUR_BWD1(D, K, LM, (D > 0), kColourF32);                               \
+    else SGS_COLOUR_BWD1(D, K, LM, false, kColourF32)
 #define SGS_COLOUR_BWD_K(D)                                                                    \
     if (p.lobe_mode == kLobesWorld) SGS_COLOUR_BWD(D, 3, kLobesWorld);                         \
     else if (p.lobe_mode == kLobesFrame) SGS_COLOUR_BWD(D, 3, kLobesFrame);                    \
@@ -382,6 +387,7 @@ void launch_preprocess_bwd(const Params& p, const sgs_camera* dev_cams, int n_ca
     }
 #undef SGS_COLOUR_BWD_K
 #undef SGS_COLOUR_BWD
+#undef SGS_COLOUR_BWD1
     hipLaunchKernelGGL(k_geom_bwd, grid, block, 0, s, p, dev_cams, n_cams, o, ws, gr, gxc, depth_grad);
 }
 

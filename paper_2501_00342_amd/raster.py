@@ -46,30 +46,47 @@ def colour_record_floats(sh_degree: int, n_lobes: int, lobe_mode: int = L.LOBES_
     return 3 * (sh_degree + 1) ** 2 + 3 * axis_vectors(lobe_mode, n_lobes) + 4 * n_lobes
 
 
-def params_to_device(scene: Scene, device="cuda", packed: bool = True) -> dict:
-    """Scene arrays -> float32 device tensors in the C-ABI layout.
+COLOUR_DTYPES = {torch.float32: L.COLOUR_F32, torch.bfloat16: L.COLOUR_BF16,
+                 torch.float16: L.COLOUR_F16}
+
+
+def params_to_device(scene: Scene, device="cuda", packed: bool = True,
+                     colour_dtype=torch.float32) -> dict:
+    """Scene arrays -> device tensors in the C-ABI layout: the geometry in
+    float32, the colour in `colour_dtype` (float32, or bfloat16 / float16
+    storage: the float32 values rounded to nearest even).
 
     packed: the four colour tensors are views into one (N, S) buffer, each
-    Gaussian's colour one contiguous record of 3 (L+1)^2 + 3 A + 4 K floats
-    and S that rounded up to a multiple of 4 (the layout the rasteriser
-    fetches fastest: whole 16-byte pieces); otherwise each colour tensor is
-    contiguous on its own."""
-    out = {k: torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
-           for k in FIELDS if k not in COLOUR_FIELDS or not packed}
+    Gaussian's colour one contiguous record of 3 (L+1)^2 + 3 A + 4 K
+    elements and S that rounded up to whole 16-byte pieces (the layout the
+    rasteriser fetches fastest); otherwise each colour tensor is contiguous
+    on its own."""
+    def dev(k):
+        t = torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
+        return t.to(colour_dtype) if k in COLOUR_FIELDS else t
+    out = {k: dev(k) for k in FIELDS if k not in COLOUR_FIELDS or not packed}
     if packed:
         n, nc3, K = scene.n, 3 * (scene.sh_degree + 1) ** 2, scene.n_lobes
         A = scene.n_axis_vectors
         rs = nc3 + 3 * A + 4 * K
-        rec = torch.zeros((n, (rs + 3) // 4 * 4), dtype=torch.float32, device=device)
+        w = 16 // torch.tensor([], dtype=colour_dtype).element_size()
+        rec = torch.zeros((n, (rs + w - 1) // w * w), dtype=colour_dtype, device=device)
         at = 0
         for k, width in (("sh", nc3), ("sg_axes", 3 * A), ("sg_log_sharpness", K),
                          ("sg_amplitudes", 3 * K)):
-            a = torch.from_numpy(to_device_layout(k, getattr(scene, k))).to(device)
+            a = dev(k)
             view = rec[:, at:at + width].view(a.shape)
             view.copy_(a)
             out[k] = view
             at += width
     return out
+
+
+def colour_dtype_code(params: dict) -> int:
+    """The colour_dtype of the C-ABI for these tensors (one type for all four)."""
+    types = {params[k].dtype for k in COLOUR_FIELDS}
+    assert len(types) == 1, "colour tensors of different types"
+    return COLOUR_DTYPES[types.pop()]
 
 
 def colour_stride(params: dict) -> int:
@@ -166,8 +183,9 @@ class Rasterizer:
         ptrs = {k: (params[k].data_ptr() if params[k].numel() else None) for k in FIELDS} \
             if params else {}
         cs = colour_stride(params) if params else 0
+        ct = colour_dtype_code(params) if params else L.COLOUR_F32
         return L.gaussians_struct(self.n, self.sh_degree, self.n_lobes, ptrs, cs,
-                                  self.lobe_mode, self.sh_adaptive)
+                                  self.lobe_mode, self.sh_adaptive, ct)
 
     def _alloc(self):
         g = self._gstruct(None)
@@ -190,12 +208,14 @@ class Rasterizer:
     def _check_params(self, params):
         for k in FIELDS:
             t = params[k]
-            assert t.device == self.device and t.dtype == torch.float32, k
+            assert t.device == self.device, k
+            assert t.dtype == torch.float32 or (k in COLOUR_FIELDS and t.dtype in COLOUR_DTYPES), k
             if k in COLOUR_FIELDS:
                 assert t.shape[0] == self.n or t.numel() == 0, k
             else:
                 assert t.is_contiguous() and (t.shape[-1] == self.n or t.numel() == 0), k
         colour_stride(params)   # the colour tensors share one layout
+        colour_dtype_code(params)   # and one element type
 
     # -- passes --------------------------------------------------------------
     def forward(self, params: dict, out: Outputs | None = None, check: bool | None = None) -> Outputs:

@@ -111,6 +111,22 @@ def compare_grads(gpu: dict, ref: dict, exclude=None, floor: float = 1e-3) -> di
     return report
 
 
+# the 2D gradients as per-Gaussian vectors: the projected mean, the conic
+# (a symmetric 2x2 matrix), the opacity, the colour and the splat depth
+GROUPS_2D = {"mean2d": ("u", "v"), "conic": ("Qa", "Qb", "Qc"), "opacity": ("sigma",),
+             "rgb": ("r", "g", "b"), "depth": ("z",)}
+
+
+def group_2d(d: dict) -> dict:
+    """Per-channel 2D gradients ({"u": (n,), ...}) -> per-Gaussian vectors
+    ({"mean2d": (2, n), ...}), for the normwise rule of compare_grads."""
+    out = {}
+    for name, chans in GROUPS_2D.items():
+        if all(c in d for c in chans):
+            out[name] = np.stack([np.asarray(d[c], np.float64) for c in chans])
+    return out
+
+
 # at most this fraction of a tensor's components may pass by the normwise rule
 NORMWISE_MAX = 1e-3
 # at most this fraction of the Gaussians may be excluded for tie-band pixels

@@ -96,8 +96,9 @@ def test_header_states_the_colour_layout_of_the_struct():
 
 
 def _args(lib, n=1000, sh=1, K=4, W=128, H=96, opts=None, cap=10000, lobes=0, adaptive=(0, 0),
-          znear=0.2, fx=None):
-    g = lib.gaussians_struct(n, sh, K, {}, lobe_axes=lobes, sh_adaptive=adaptive)
+          znear=0.2, fx=None, cdt=0):
+    g = lib.gaussians_struct(n, sh, K, {}, lobe_axes=lobes, sh_adaptive=adaptive,
+                             colour_dtype=cdt)
     cam = scenes.pinhole(W, H, np.eye(3), (0, 0, 4))
     cam.znear = znear
     if fx is not None:
@@ -129,7 +130,8 @@ def test_workspace_size_and_layout(lib):
     dict(opts=scenes.Options(alpha_max=1.5)), dict(opts=scenes.Options(schedule=3)),
     dict(lobes=3), dict(lobes=1, K=4), dict(lobes=2, K=2), dict(adaptive=(3, 2)),
     dict(adaptive=(-1, 4)), dict(znear=0.0), dict(znear=-0.5), dict(znear=float("nan")),
-    dict(fx=0.0), dict(fx=float("inf"))])
+    dict(fx=0.0), dict(fx=float("inf")), dict(cdt=3), dict(cdt=-1),
+    dict(cdt=1, sh=2, adaptive=(2, 8))])
 def test_invalid_arguments_are_rejected_on_the_host(lib, bad):
     g, cams, o, cap = _args(lib, **bad)
     assert lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap) == 0
@@ -150,7 +152,8 @@ def test_forward_rejects_null_arguments_before_any_launch(lib):
 
 
 @pytest.mark.parametrize("ok", [dict(lobes=1, K=3), dict(lobes=2, K=3, sh=2, adaptive=(2, 8)),
-                                dict(adaptive=(0, 5)), dict(K=8, sh=3)])
+                                dict(adaptive=(0, 5)), dict(K=8, sh=3), dict(cdt=1),
+                                dict(cdt=2, sh=3, K=0), dict(cdt=1, lobes=2, K=3)])
 def test_valid_colour_forms_are_accepted(lib, ok):
     g, cams, o, cap = _args(lib, **ok)
     assert lib.LIB.render_workspace_bytes(ctypes.byref(g), cams, 1, ctypes.byref(o), cap) > 0

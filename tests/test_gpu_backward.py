@@ -54,7 +54,7 @@ def test_backward_matches_oracle(n, w, h, seed):
     rast, grads, g2_gpu, g2_ref, grads_ref, ex = _backward_case(sc, cam, opts, seed)
     g2r = {k: g2_ref[k] for k in OB.GRAD2D}
     g2g = {k: g2_gpu[i] for i, k in enumerate(OB.GRAD2D)}
-    _assert_grads(g2g, g2r, ex, "2D")
+    _assert_grads(parity.group_2d(g2g), parity.group_2d(g2r), ex, "2D")
     _assert_grads(raster.to_scene_layout({k: grads[k].cpu().numpy() for k in FIELDS}), grads_ref, ex, "raw")
 
 
@@ -205,7 +205,8 @@ def test_depth_and_alpha_gradients_match_oracle():
                                grad_depth=gdep, grad_alpha=galp)
     ex = _tie_exclusion(pre, ref)
     names = OB.GRAD2D + ("z",)
-    _assert_grads({k: g2_gpu[i] for i, k in enumerate(names)}, {k: g2_ref[k] for k in names},
+    _assert_grads(parity.group_2d({k: g2_gpu[i] for i, k in enumerate(names)}),
+                  parity.group_2d({k: g2_ref[k] for k in names}),
                   ex, "2D+z")
     grads_ref = OB.preprocess_backward(sc, cam, opts, pre, g2_ref)
     _assert_grads(raster.to_scene_layout({k: grads[k].cpu().numpy() for k in FIELDS}), grads_ref,

@@ -102,8 +102,8 @@ def test_full_frame_gradients(workload):
     # cover most of the frame and saturate T, the rest are occluded
     touched = int((np.abs(np.stack(list(g2_ref.values()))).sum(axis=0) > 0).sum())
     assert touched >= 400, touched
-    rep = parity.compare_grads({k: g2_gpu[i] for i, k in enumerate(OB.GRAD2D)},
-                               {k: g2_ref[k] for k in OB.GRAD2D})
+    rep = parity.compare_grads(parity.group_2d({k: g2_gpu[i] for i, k in enumerate(OB.GRAD2D)}),
+                               parity.group_2d({k: g2_ref[k] for k in OB.GRAD2D}))
     parity.assert_grads(rep, "2D")
     ref_raw = OB.preprocess_backward(sc, cam, opts, pre, g2_ref)
     rep = parity.compare_grads(grads, ref_raw)

@@ -179,3 +179,20 @@ def test_parameter_counts_match_the_paper(repo_root):
     assert one.floats_per_gaussian() - 11 == g["colour_params_diffuse_plus_sg"]
     # three orthogonal lobes: colour 3 + sharpness 1 per lobe, plus a frame of 3
     assert 3 * (3 + 1) + 3 == g["colour_params_three_orthogonal_sg_plus_frame"]
+
+
+def test_half_rounding_helpers_match_torch():
+    """The test helpers' bfloat16 / float16 rounding (ties to even) against
+    torch's CPU conversions, on random, tie and boundary values."""
+    import torch
+    from tests.half_colour import round_bf16, round_f16
+    rng = np.random.default_rng(5)
+    a = np.concatenate([rng.normal(0, 1, 4000), rng.normal(0, 1e-3, 1000),
+                        rng.normal(0, 300, 1000)]).astype(np.float32)
+    ties = (np.arange(1, 200, dtype=np.uint32) << 16 | 0x8000).view(np.float32)
+    odd = ((np.arange(1, 200, dtype=np.uint32) * 2 + 1) << 16 | 0x8000).view(np.float32)
+    x = np.concatenate([a, ties, -ties, odd])
+    tb = torch.from_numpy(x).to(torch.bfloat16).float().numpy()
+    th = torch.from_numpy(x).to(torch.float16).float().numpy()
+    assert np.array_equal(round_bf16(x), tb)
+    assert np.array_equal(round_f16(x), th)
