@@ -257,6 +257,33 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams,
                    void* stream);
 
 /*
+ * render_forward_noalloc — render_forward for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments and results as
+ * render_forward, except that the workspace is the library's own
+ * no-allocation scratch: a static device array of
+ * SGS_NOALLOC_WORKSPACE_BYTES per GPU, reserved when the library's code is
+ * loaded on that GPU and held until the process ends.  The call allocates
+ * nothing (no hipMalloc, no events: stage timing does not record it).
+ *   - The current device must be the one the stream and the buffers live
+ *     on; the first call on a device looks up that device's copy of the
+ *     array.
+ *   - SGS_E_INVALID when render_workspace_bytes() for these arguments
+ *     exceeds SGS_NOALLOC_WORKSPACE_BYTES (fewer Gaussians, cameras or
+ *     pairs fit).
+ *   - Every call on one GPU shares the array, which keeps the last call's
+ *     contents (every section the forward reads is written or cleared by
+ *     its own kernels first).  Calls that overlap on one GPU (other
+ *     streams or threads) race: serialise them.  No render_backward can
+ *     follow: its workspace is not exposed.
+ */
+#define SGS_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+int render_forward_noalloc(const sgs_gaussians* g, const sgs_camera* host_cams,
+                           const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                           int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
+                           int64_t* pairs_needed, void* stream);
+
+/*
  * render_backward — gradients of a scalar loss L w.r.t. every raw
  * parameter, given dL/dimage (device, packed like `image`): the exact
  * derivative of what render_forward computes.  Paper: Preliminaries (the

@@ -18,6 +18,7 @@ SGS_STATUS_CAPACITY, SGS_STATUS_CAMERAS = 1, 2
 SCHEDULE_GRID, SCHEDULE_QUEUE = 1, 2
 SGS_FLAG_CHECK_CAPACITY = 1
 COLOUR_F32, COLOUR_BF16, COLOUR_F16 = 0, 1, 2
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 LOBES_FREE, LOBES_WORLD, LOBES_FRAME = 0, 1, 2
 MAX_SH_DEGREE, MAX_LOBES, MAX_CAMERAS, MAX_IMAGE_SIDE = 3, 8, 1024, 32767
 
@@ -69,7 +70,8 @@ class Layout(Structure):
                 ("pair_capacity", c_int64)]
 
 
-EXPORTS = ("render_workspace_bytes", "render_layout", "render_forward", "render_backward",
+EXPORTS = ("render_workspace_bytes", "render_layout", "render_forward", "render_forward_noalloc",
+           "render_backward",
            "render_l1", "render_status", "render_read_keys", "render_set_timing",
            "render_stage_times", "render_stage_name", "render_blend_work",
            "render_blend_bwd_work", "render_adam_step", "render_last_error")
@@ -91,6 +93,9 @@ def _load():
     lib.render_forward.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
                                    c_void_p, c_size_t, c_int64, P(Outputs), c_int32,
                                    P(c_int64), c_void_p]
+    lib.render_forward_noalloc.restype = c_int32
+    lib.render_forward_noalloc.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
+                                           c_int64, P(Outputs), c_int32, P(c_int64), c_void_p]
     lib.render_backward.restype = c_int32
     lib.render_backward.argtypes = [P(Gaussians), P(Camera), c_void_p, c_int32, P(Options),
                                     c_void_p, c_size_t, c_int64, P(Outputs), c_void_p,

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include <array>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -369,8 +370,9 @@ int render_layout(const sgs_gaussians* g, const sgs_camera* host_cams, int32_t n
 
 namespace {
 
-// The forward behind render_forward.  `timed`: record stage events when
-// stage timing is on.
+// The forward behind render_forward and render_forward_noalloc.  `timed`:
+// record stage events when stage timing is on (creating events allocates,
+// which the no-allocation entry point must not do).
 int forward_impl(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
                  int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
                  int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
@@ -487,6 +489,15 @@ int forward_impl(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_
     return SGS_OK;
 }
 
+// Workspace of render_forward_noalloc: one array per device, reserved when
+// the code object is loaded and held until the process ends.  Host code
+// never passes `scratch` itself (on the host it names a stand-in, not
+// device memory): it uses the device address from hipGetSymbolAddress,
+// taken once per device.
+__device__ __align__(256) unsigned char scratch[SGS_NOALLOC_WORKSPACE_BYTES];
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch[kMaxDevices];
+
 }  // namespace
 
 extern "C" {
@@ -499,6 +510,31 @@ int render_forward(const sgs_gaussians* g, const sgs_camera* host_cams, const sg
                         pair_capacity, outs, flags, pairs_needed, stream, true);
 }
 
+int render_forward_noalloc(const sgs_gaussians* g, const sgs_camera* host_cams,
+                           const sgs_camera* dev_cams, int32_t n_cams, const sgs_options* opts,
+                           int64_t pair_capacity, const sgs_outputs* outs, int32_t flags,
+                           int64_t* pairs_needed, void* stream) {
+    int dev = -1;
+    SGS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SGS_E_INVALID, "device index out of range");
+    void* base = g_scratch[dev].load();
+    if (!base) {
+        // first call on this device (current): its copy of the array
+        SGS_HIP(hipGetSymbolAddress(&base, HIP_SYMBOL(scratch)));
+        if (!base) return fail(SGS_E_HIP, "hipGetSymbolAddress returned no address");
+        g_scratch[dev].store(base);
+    }
+    Plan pl;
+    const int rc = plan(g, host_cams, n_cams, opts, pair_capacity, &pl);
+    if (rc != SGS_OK) return rc;
+    if (pl.lay.total_bytes > (size_t)SGS_NOALLOC_WORKSPACE_BYTES)
+        return fail(SGS_E_INVALID, "the workspace needs " + std::to_string(pl.lay.total_bytes) +
+                                       " bytes, more than the " +
+                                       std::to_string((size_t)SGS_NOALLOC_WORKSPACE_BYTES) +
+                                       " bytes of the no-allocation scratch");
+    return forward_impl(g, host_cams, dev_cams, n_cams, opts, base, SGS_NOALLOC_WORKSPACE_BYTES,
+                        pair_capacity, outs, flags, pairs_needed, stream, false);
+}
 
 int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_camera* dev_cams,
                     int32_t n_cams, const sgs_options* opts, void* workspace, size_t workspace_bytes,
