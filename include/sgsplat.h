@@ -169,12 +169,17 @@ typedef struct sgs_options {
     int32_t schedule;                /* tile schedule of both blends: SGS_SCHEDULE_GRID (one
                                         workgroup per tile), SGS_SCHEDULE_QUEUE (persistent
                                         workgroups popping tiles heavy-first from an atomic
-                                        counter); 0 = queue for several cameras, grid for one.
+                                        counter), SGS_SCHEDULE_SLICES (persistent one-wave
+                                        workgroups popping (tile, slice) items heavy-first: a
+                                        slice is the pixels one wave of a whole-tile workgroup
+                                        owns, and each slice streams the tile's list on its
+                                        own); 0 = queue for several cameras, grid for one.
                                         The image does not depend on it. */
 } sgs_options;
 
 #define SGS_SCHEDULE_GRID 1
 #define SGS_SCHEDULE_QUEUE 2
+#define SGS_SCHEDULE_SLICES 3
 
 /* Forward outputs (device, packed over cameras as described above). */
 typedef struct sgs_outputs {

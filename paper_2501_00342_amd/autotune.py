@@ -27,7 +27,7 @@ TILE_PPT = {
     (8, 8): (1,),
 }
 BATCHES = (128, 256, 512)
-SCHEDULES = (1, 2)      # grid, heavy-first queue
+SCHEDULES = (1, 2, 3)   # grid, heavy-first queue, heavy-first one-wave slices
 
 
 def default_cache_path() -> str:

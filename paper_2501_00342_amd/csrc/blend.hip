@@ -117,15 +117,19 @@ __device__ __forceinline__ Entry load_entry(const Workspace& ws, int64_t pos, in
 // Thread t of a TW x TH tile with PPT pixels per thread owns column t % TW
 // and the PPT consecutive rows from (t / TW) * PPT, so that a wave covers a
 // compact TW x (64 / TW) * PPT block and small splats touch few waves.
-template <int TW, int TH, int PPT, bool COUNT>
+// SLICED: the workgroup is one wave and owns slice `slice` of the tile (the
+// pixels wave `slice` of a whole-tile workgroup would own); it streams the
+// tile's list on its own, so no wave waits on another's pixels.
+template <int TW, int TH, int PPT, bool COUNT, bool SLICED>
 __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
                                          int n_cams, const Opts& o, const sgs_outputs& out,
-                                         int batch, int64_t tile, Entry* s_e, int* s_cam,
+                                         int batch, int64_t tile, int slice, Entry* s_e, int* s_cam,
                                          unsigned long long& visited,
                                          unsigned long long& evaluated,
                                          unsigned long long& blended) {
-    constexpr int NT = TW * TH / PPT;
+    constexpr int NT = SLICED ? 64 : TW * TH / PPT;   // threads of the workgroup
     const int tid = threadIdx.x;
+    const int vtid = (SLICED ? slice * 64 : 0) + tid;  // thread of the whole-tile layout
     if (tid == 0) *s_cam = find_camera(ws.cams, n_cams, tile);
     __syncthreads();
     const int cam = *s_cam;
@@ -133,7 +137,7 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int lx = tid % TW, ry = (tid / TW) * PPT;   // rows ry .. ry + PPT - 1
+    const int lx = vtid % TW, ry = (vtid / TW) * PPT;   // rows ry .. ry + PPT - 1
     const uint32_t start = ws.ranges[2 * tile];
     const uint32_t end = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity ? ws.ranges[2 * tile + 1] : start;
     const uint32_t colbit = 1u << lx;
@@ -218,37 +222,47 @@ __device__ __forceinline__ void fwd_tile(const Workspace& ws, const sgs_camera* 
 // next tile of the queue schedule, or -1 once the queue is drained; every
 // thread of the workgroup gets the same answer.  The leading barrier keeps
 // the previous tile's LDS reads ahead of the next tile's writes.
+// With S slices per tile the queue holds S items per tile, consecutive in
+// the heavy-first order; *slice receives the item's slice.
+template <int S>
 __device__ __forceinline__ int64_t pop_tile(const Workspace& ws, uint32_t* counter,
-                                            uint32_t* s_next) {
+                                            uint32_t* s_next, int* slice) {
     __syncthreads();
     if (threadIdx.x == 0) *s_next = atomicAdd(counter, 1u);
     __syncthreads();
-    const uint32_t pos = *s_next;
-    if ((int64_t)pos >= ws.n_tiles) return -1;
-    const uint32_t t = ws.tile_order[pos];
+    const uint32_t item = *s_next;
+    if ((int64_t)item >= ws.n_tiles * S) return -1;
+    *slice = (int)(item % S);
+    const uint32_t t = ws.tile_order[item / S];
     return (int64_t)t < ws.n_tiles ? (int64_t)t : -1;
 }
 
-template <int TW, int TH, int PPT, bool COUNT, bool QUEUE>
-__global__ void __launch_bounds__(TW * TH / PPT)
+// schedule: SGS_SCHEDULE_GRID (one workgroup per tile), _QUEUE (persistent
+// whole-tile workgroups) or _SLICES (persistent one-wave workgroups, one
+// slice of a tile per item)
+template <int TW, int TH, int PPT, bool COUNT, int SCHED>
+__global__ void __launch_bounds__(SCHED == SGS_SCHEDULE_SLICES ? 64 : TW * TH / PPT)
 k_blend_fwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs out, int batch, unsigned long long* counts) {
     extern __shared__ __align__(16) Entry s_e[];
     __shared__ int s_cam;
     __shared__ uint32_t s_next;
     if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    constexpr bool SL = SCHED == SGS_SCHEDULE_SLICES;
+    constexpr int S = SL ? TW * TH / PPT / 64 : 1;   // slices per tile
     unsigned long long visited = 0, evaluated = 0, blended = 0;
-    if (QUEUE) {
+    if (SCHED != SGS_SCHEDULE_GRID) {
         for (;;) {
-            const int64_t tile = pop_tile(ws, ws.header + kHdrQueueFwd, &s_next);
+            int slice = 0;
+            const int64_t tile = pop_tile<S>(ws, ws.header + kHdrQueueFwd, &s_next, &slice);
             if (tile < 0) break;
-            fwd_tile<TW, TH, PPT, COUNT>(ws, cams, n_cams, o, out, batch, tile, s_e, &s_cam,
-                                         visited, evaluated, blended);
+            fwd_tile<TW, TH, PPT, COUNT, SL>(ws, cams, n_cams, o, out, batch, tile, slice, s_e,
+                                             &s_cam, visited, evaluated, blended);
         }
     } else {
-        fwd_tile<TW, TH, PPT, COUNT>(ws, cams, n_cams, o, out, batch,
-                                     xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, visited,
-                                     evaluated, blended);
+        fwd_tile<TW, TH, PPT, COUNT, false>(ws, cams, n_cams, o, out, batch,
+                                            xcd_tile(blockIdx.x, ws.n_tiles), 0, s_e, &s_cam,
+                                            visited, evaluated, blended);
     }
     if (COUNT) {
         __shared__ unsigned long long s_cnt[3];
@@ -342,15 +356,18 @@ struct BwdWork {
     unsigned long long visited, evaluated, blended, reductions;
 };
 
-template <int TW, int TH, int PPT, bool DG, bool COUNT>
+// SLICED: as in the forward, a one-wave workgroup owns one slice of the
+// tile and walks back from the slice's own largest n_contrib.
+template <int TW, int TH, int PPT, bool DG, bool COUNT, bool SLICED>
 __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* __restrict__ cams,
                                          int n_cams, const Opts& o, const sgs_outputs& fwd,
                                          const Upstream& up, int batch,
-                                         int64_t tile, Entry* s_e, int* s_cam, int* s_maxn,
-                                         BwdWork& work) {
-    constexpr int NT = TW * TH / PPT;
+                                         int64_t tile, int slice, Entry* s_e, int* s_cam,
+                                         int* s_maxn, BwdWork& work) {
+    constexpr int NT = SLICED ? 64 : TW * TH / PPT;   // threads of the workgroup
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int vtid = (SLICED ? slice * 64 : 0) + tid;  // thread of the whole-tile layout
     if (tid == 0) {
         *s_cam = find_camera(ws.cams, n_cams, tile);
         *s_maxn = 0;
@@ -361,7 +378,7 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
     const int lt = (int)(tile - ct.tile_base);
     const int tx = lt % ct.GX, ty = lt / ct.GX;
     const int x0 = tx * TW, y0 = ty * TH;
-    const int lx = tid % TW, ry = (tid / TW) * PPT;   // rows ry .. ry + PPT - 1
+    const int lx = vtid % TW, ry = (vtid / TW) * PPT;   // rows ry .. ry + PPT - 1
     const uint32_t start = ws.ranges[2 * tile];
     const int64_t len = (int64_t)ws.ranges[2 * tile + 1] <= ws.capacity
                             ? (int64_t)ws.ranges[2 * tile + 1] - start : 0;
@@ -528,8 +545,8 @@ struct BwdWaves {
     static constexpr int value = DG ? 6 : 7;
 };
 
-template <int TW, int TH, int PPT, bool QUEUE, bool DG, bool COUNT>
-__global__ void __launch_bounds__(TW * TH / PPT)
+template <int TW, int TH, int PPT, int SCHED, bool DG, bool COUNT>
+__global__ void __launch_bounds__(SCHED == SGS_SCHEDULE_SLICES ? 64 : TW * TH / PPT)
 __attribute__((amdgpu_waves_per_eu(BwdWaves<DG>::value)))
 k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts o,
             sgs_outputs fwd, Upstream up, int batch, unsigned long long* counts) {
@@ -538,18 +555,21 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
     __shared__ int s_maxn;
     __shared__ uint32_t s_next;
     if (ws.header[kHdrStatus] & SGS_STATUS_CAMERAS) return;
+    constexpr bool SL = SCHED == SGS_SCHEDULE_SLICES;
+    constexpr int S = SL ? TW * TH / PPT / 64 : 1;   // slices per tile
     BwdWork work = {0ull, 0ull, 0ull, 0ull};
-    if (QUEUE) {
+    if (SCHED != SGS_SCHEDULE_GRID) {
         for (;;) {
-            const int64_t tile = pop_tile(ws, ws.header + kHdrQueueBwd, &s_next);
+            int slice = 0;
+            const int64_t tile = pop_tile<S>(ws, ws.header + kHdrQueueBwd, &s_next, &slice);
             if (tile < 0) break;
-            bwd_tile<TW, TH, PPT, DG, COUNT>(ws, cams, n_cams, o, fwd, up, batch, tile, s_e,
-                                             &s_cam, &s_maxn, work);
+            bwd_tile<TW, TH, PPT, DG, COUNT, SL>(ws, cams, n_cams, o, fwd, up, batch, tile, slice,
+                                                 s_e, &s_cam, &s_maxn, work);
         }
     } else {
-        bwd_tile<TW, TH, PPT, DG, COUNT>(ws, cams, n_cams, o, fwd, up, batch,
-                                         xcd_tile(blockIdx.x, ws.n_tiles), s_e, &s_cam, &s_maxn,
-                                         work);
+        bwd_tile<TW, TH, PPT, DG, COUNT, false>(ws, cams, n_cams, o, fwd, up, batch,
+                                                xcd_tile(blockIdx.x, ws.n_tiles), 0, s_e, &s_cam,
+                                                &s_maxn, work);
     }
     if (COUNT) {
         __shared__ unsigned long long s_cnt[4];
@@ -567,23 +587,30 @@ k_blend_bwd(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, Opts 
 
 // ---------------------------------------------------------------------------
 
-static unsigned grid_of(int64_t resident, int64_t n_tiles) {
-    const int64_t g = resident < 1 || resident > n_tiles ? n_tiles : resident;
+static unsigned grid_of(int64_t resident, int64_t items) {
+    const int64_t g = resident < 1 || resident > items ? items : resident;
     return (unsigned)g;
 }
 
+// sched: the schedule the plan resolved (SGS_SCHEDULE_GRID, _QUEUE or _SLICES)
 template <int TW, int TH, int PPT>
 static void launch_fwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
-                         const sgs_outputs& out, bool queue, hipStream_t s) {
+                         const sgs_outputs& out, int sched, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     constexpr int NT = TW * TH / PPT;
-    if (queue) {
-        auto k = k_blend_fwd<TW, TH, PPT, false, true>;
+    if (sched == SGS_SCHEDULE_SLICES) {
+        auto k = k_blend_fwd<TW, TH, PPT, false, SGS_SCHEDULE_SLICES>;
+        const int64_t items = ws.n_tiles * (NT / 64);
+        hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, 64, lds), items)), dim3(64), lds, s,
+                           ws, cams, n_cams, o, out, o.batch, nullptr);
+    } else if (sched == SGS_SCHEDULE_QUEUE) {
+        auto k = k_blend_fwd<TW, TH, PPT, false, SGS_SCHEDULE_QUEUE>;
         hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, NT, lds), ws.n_tiles)), dim3(NT), lds,
                            s, ws, cams, n_cams, o, out, o.batch, nullptr);
     } else {
-        hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, false, false>), dim3((unsigned)ws.n_tiles),
-                           dim3(NT), lds, s, ws, cams, n_cams, o, out, o.batch, nullptr);
+        hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, false, SGS_SCHEDULE_GRID>),
+                           dim3((unsigned)ws.n_tiles), dim3(NT), lds, s, ws, cams, n_cams, o, out,
+                           o.batch, nullptr);
     }
 }
 
@@ -592,23 +619,29 @@ static void launch_count_t(const Workspace& ws, const sgs_camera* cams, int n_ca
                            uint64_t* counts, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     sgs_outputs none = {};
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, true, false>), dim3((unsigned)ws.n_tiles),
+    hipLaunchKernelGGL((k_blend_fwd<TW, TH, PPT, true, SGS_SCHEDULE_GRID>), dim3((unsigned)ws.n_tiles),
                        dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, none, o.batch,
                        reinterpret_cast<unsigned long long*>(counts));
 }
 
 template <int TW, int TH, int PPT, bool DG>
 static void launch_bwd_dg(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
-                          const sgs_outputs& fwd, const Upstream& up, bool queue, hipStream_t s) {
+                          const sgs_outputs& fwd, const Upstream& up, int sched, hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     constexpr int NT = TW * TH / PPT;
-    if (queue) {
-        auto k = k_blend_bwd<TW, TH, PPT, true, DG, false>;
+    if (sched == SGS_SCHEDULE_SLICES) {
+        auto k = k_blend_bwd<TW, TH, PPT, SGS_SCHEDULE_SLICES, DG, false>;
+        const int64_t items = ws.n_tiles * (NT / 64);
+        hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, 64, lds), items)), dim3(64), lds, s,
+                           ws, cams, n_cams, o, fwd, up, o.batch, nullptr);
+    } else if (sched == SGS_SCHEDULE_QUEUE) {
+        auto k = k_blend_bwd<TW, TH, PPT, SGS_SCHEDULE_QUEUE, DG, false>;
         hipLaunchKernelGGL(k, dim3(grid_of(resident_blocks(k, NT, lds), ws.n_tiles)), dim3(NT), lds,
                            s, ws, cams, n_cams, o, fwd, up, o.batch, nullptr);
     } else {
-        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false, DG, false>), dim3((unsigned)ws.n_tiles),
-                           dim3(NT), lds, s, ws, cams, n_cams, o, fwd, up, o.batch, nullptr);
+        hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, SGS_SCHEDULE_GRID, DG, false>),
+                           dim3((unsigned)ws.n_tiles), dim3(NT), lds, s, ws, cams, n_cams, o, fwd,
+                           up, o.batch, nullptr);
     }
 }
 
@@ -618,18 +651,18 @@ static void launch_bwd_count_t(const Workspace& ws, const sgs_camera* cams, int 
                                hipStream_t s) {
     const size_t lds = (size_t)o.batch * sizeof(Entry);
     const Upstream none = {nullptr, nullptr, nullptr};
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, false, false, true>), dim3((unsigned)ws.n_tiles),
-                       dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o, fwd, none, o.batch,
-                       reinterpret_cast<unsigned long long*>(counts));
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT, SGS_SCHEDULE_GRID, false, true>),
+                       dim3((unsigned)ws.n_tiles), dim3(TW * TH / PPT), lds, s, ws, cams, n_cams, o,
+                       fwd, none, o.batch, reinterpret_cast<unsigned long long*>(counts));
 }
 
 template <int TW, int TH, int PPT>
 static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams, const Opts& o,
-                         const sgs_outputs& fwd, const Upstream& up, bool queue, hipStream_t s) {
+                         const sgs_outputs& fwd, const Upstream& up, int sched, hipStream_t s) {
     if (up.depth || up.alpha)
-        launch_bwd_dg<TW, TH, PPT, true>(ws, cams, n_cams, o, fwd, up, queue, s);
+        launch_bwd_dg<TW, TH, PPT, true>(ws, cams, n_cams, o, fwd, up, sched, s);
     else
-        launch_bwd_dg<TW, TH, PPT, false>(ws, cams, n_cams, o, fwd, up, queue, s);
+        launch_bwd_dg<TW, TH, PPT, false>(ws, cams, n_cams, o, fwd, up, sched, s);
 }
 
 // supported (tile, pixels per thread): the block is a whole number of waves
@@ -649,7 +682,8 @@ static void launch_bwd_t(const Workspace& ws, const sgs_camera* cams, int n_cams
 void launch_blend_fwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
                       const sgs_outputs& out, bool queue, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
-    SGS_TILE_SWITCH(launch_fwd_t, o.ppt, ws, dev_cams, n_cams, o, out, queue, s)
+    const int sched = queue ? o.schedule : SGS_SCHEDULE_GRID;
+    SGS_TILE_SWITCH(launch_fwd_t, o.ppt, ws, dev_cams, n_cams, o, out, sched, s)
 }
 
 void launch_blend_count(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, const Opts& o,
@@ -670,7 +704,8 @@ void launch_blend_bwd(const Workspace& ws, const sgs_camera* dev_cams, int n_cam
                       const float* grad_alpha, bool queue, hipStream_t s) {
     if (ws.n_tiles <= 0) return;
     const Upstream up = {grad_image, grad_depth, grad_alpha};
-    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, up, queue, s)
+    const int sched = queue ? o.schedule : SGS_SCHEDULE_GRID;
+    SGS_TILE_SWITCH(launch_bwd_t, o.ppt_bwd, ws, dev_cams, n_cams, o, fwd, up, sched, s)
 }
 
 // ---------------------------------------------------------------------------

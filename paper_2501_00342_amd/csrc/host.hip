@@ -107,8 +107,9 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
         return fail(SGS_E_INVALID, "batch must be a multiple of 64 in [64, 1024]");
     o.schedule = oin && oin->schedule ? oin->schedule
                                       : (n_cams > 1 ? SGS_SCHEDULE_QUEUE : SGS_SCHEDULE_GRID);
-    if (o.schedule != SGS_SCHEDULE_GRID && o.schedule != SGS_SCHEDULE_QUEUE)
-        return fail(SGS_E_INVALID, "schedule must be 0, SGS_SCHEDULE_GRID or SGS_SCHEDULE_QUEUE");
+    if (o.schedule != SGS_SCHEDULE_GRID && o.schedule != SGS_SCHEDULE_QUEUE &&
+        o.schedule != SGS_SCHEDULE_SLICES)
+        return fail(SGS_E_INVALID, "schedule must be 0, SGS_SCHEDULE_GRID, _QUEUE or _SLICES");
     o.dilation = oin && oin->dilation != 0.0f ? oin->dilation : 0.3f;
     o.guard = oin && oin->guard != 0.0f ? oin->guard : 1.3f;
     o.alpha_min = oin && oin->alpha_min != 0.0f ? oin->alpha_min : 1.0f / 255.0f;
@@ -157,7 +158,9 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->max_parts = pl->depth_parts > pl->pair_parts ? pl->depth_parts : pl->pair_parts;
     if (pl->tile_parts > pl->max_parts) pl->max_parts = pl->tile_parts;
     if (2 * pl->pair_parts > pl->max_parts) pl->max_parts = 2 * pl->pair_parts;   // duplicate's counts
-    pl->queue = o.schedule == SGS_SCHEDULE_QUEUE && n > 0 && cap > 0;
+    // the queue and slice schedules pop items over the heavy-first tile order
+    pl->queue = (o.schedule == SGS_SCHEDULE_QUEUE || o.schedule == SGS_SCHEDULE_SLICES) && n > 0 &&
+                cap > 0;
 
     sgs_layout& L = pl->lay;
     memset(&L, 0, sizeof(L));

@@ -131,7 +131,8 @@ class Options:
     batch: int = 0              # LDS batch depth, 0 = library default
     ppt: int = 0                # pixels per thread, forward blend (0 = library default)
     ppt_bwd: int = 0            # pixels per thread, backward blend
-    schedule: int = 0           # blend tile schedule: 1 grid, 2 heavy-first queue, 0 = library
+    schedule: int = 0           # blend tile schedule: 1 grid, 2 heavy-first queue, 3 heavy-first
+                                # one-wave slices of tiles, 0 = library
                                 # default (queue for several cameras)
     dilation: float = 0.3
     guard: float = 1.3

@@ -127,7 +127,7 @@ def test_workspace_size_and_layout(lib):
     dict(sh=4), dict(K=9), dict(W=0), dict(H=40000), dict(cap=1 << 30), dict(n=-1),
     dict(opts=scenes.Options(tile_w=12, tile_h=12)), dict(opts=scenes.Options(batch=300)),
     dict(opts=scenes.Options(tile_w=8, tile_h=8, ppt=2)), dict(opts=scenes.Options(ppt=3)),
-    dict(opts=scenes.Options(alpha_max=1.5)), dict(opts=scenes.Options(schedule=3)),
+    dict(opts=scenes.Options(alpha_max=1.5)), dict(opts=scenes.Options(schedule=4)),
     dict(lobes=3), dict(lobes=1, K=4), dict(lobes=2, K=2), dict(adaptive=(3, 2)),
     dict(adaptive=(-1, 4)), dict(znear=0.0), dict(znear=-0.5), dict(znear=float("nan")),
     dict(fx=0.0), dict(fx=float("inf")), dict(cdt=3), dict(cdt=-1),

@@ -148,7 +148,7 @@ def _three_cameras(sizes=((72, 48), (48, 64), (88, 40)), radius=6.0):
     return cams
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_batched_backward_matches_oracle(schedule):
     """Three cameras of different sizes in one call: the batched backward of
     the summed per-camera L1 against the oracle's per-camera backward (one

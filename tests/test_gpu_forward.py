@@ -169,30 +169,32 @@ def test_batched_cameras_equal_single_renders():
         assert not rep["failures"], (k, rep)
 
 
-def test_queue_schedule_equals_grid_schedule():
-    """The heavy-first tile queue renders the same pixels as one workgroup per
-    tile (bit for bit) and the same gradients up to atomic summation order."""
+@pytest.mark.parametrize("sched,ppt,ppt_bwd", [(2, 2, 4), (3, 2, 4), (3, 1, 2), (3, 4, 1)])
+def test_queue_schedule_equals_grid_schedule(sched, ppt, ppt_bwd):
+    """The heavy-first tile queue and its one-wave slice variant render the
+    same pixels as one workgroup per tile (bit for bit) and the same
+    gradients up to atomic summation order."""
     import torch
     sc, _ = scenes.small_clustered(20000, 41, 200, 140)
     cams = scenes.ring_cameras(3, radius=6.0, seed=8, sizes=((200, 140), (96, 64)))
     res = {}
-    for sched in (1, 2):
-        opts = scenes.Options(schedule=sched)
+    for sc_id in (1, sched):
+        opts = scenes.Options(schedule=sc_id, ppt=ppt, ppt_bwd=ppt_bwd)
         rast, params, out = run_forward(sc, cams, opts)
         tgt = torch.from_numpy(np.concatenate(
             [scenes.target_image(c.width, c.height, 5 + i).reshape(-1) for i, c in enumerate(cams)])).cuda()
         _, gimg = rast.l1(out.image, tgt)
         grads = rast.backward(params, out, gimg)
-        res[sched] = (out.image.clone(), out.final_T.clone(), out.n_contrib.clone(),
+        res[sc_id] = (out.image.clone(), out.final_T.clone(), out.n_contrib.clone(),
                       {k: v.clone() for k, v in grads.items()})
-    (i1, t1, n1, g1), (i2, t2, n2, g2) = res[1], res[2]
+    (i1, t1, n1, g1), (i2, t2, n2, g2) = res[1], res[sched]
     assert torch.equal(i1, i2) and torch.equal(t1, t2) and torch.equal(n1, n2)
     for k in g1:
         scale = float(g1[k].abs().max()) + 1e-30
         assert float((g1[k] - g2[k]).abs().max()) <= 1e-5 * scale, k
 
 
-@pytest.mark.parametrize("schedule,n_cams", [(1, 1), (2, 1), (2, 3)])
+@pytest.mark.parametrize("schedule,n_cams", [(1, 1), (2, 1), (2, 3), (3, 3)])
 def test_graph_replay_matches_eager(schedule, n_cams):
     """The whole forward and backward captured in one HIP graph (one camera,
     or three of different sizes on the heavy-first queue): every replay,
