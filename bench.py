@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-sh3", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many forward+backward steps (for rocprofv3)")
+    ap.add_argument("--profile-pass", choices=("both", "fwd", "fwdbwd"), default="both",
+                    help="with --profile-steps: run only the forward's launch shape (fwd), "
+                         "only forward + L1 + backward at its own shape (fwdbwd), or both")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuner")
     ap.add_argument("--retune", action="store_true",
                     help="time every launch shape again instead of using the cached choice")
@@ -218,17 +221,25 @@ def source_digest(paths):
     return h.hexdigest()[:16]
 
 
+_CSRC = "paper_2501_00342_amd/csrc/"
+# the source files of each single-kernel stage whose counters may be quoted:
+# a counter summary holds their digest, and goes stale when any of them changes
+TRAFFIC_SOURCES = {
+    "fwd.blend": [_CSRC + "blend.hip", _CSRC + "common.hpp"],
+    "bwd.blend": [_CSRC + "blend.hip", _CSRC + "common.hpp"],
+    "fwd.preprocess": [_CSRC + "preprocess.hip", _CSRC + "colour.hpp", _CSRC + "sh_basis.hpp",
+                       _CSRC + "common.hpp"],
+    "fwd.duplicate": [_CSRC + "sort.hip", _CSRC + "common.hpp"],
+}
+
+
 def counter_traffic(stage, workload, shape):
     """HBM bytes per launch of `stage` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by the calibration kernel), or
     None when there is none for this workload and launch shape, or the
     kernel's source has changed since the counters were taken."""
     import glob
-    c = "paper_2501_00342_amd/csrc/"
-    src = {"fwd.blend": [c + "blend.hip", c + "common.hpp"],
-           "fwd.preprocess": [c + "preprocess.hip", c + "colour.hpp", c + "sh_basis.hpp",
-                              c + "common.hpp"],
-           "fwd.duplicate": [c + "sort.hip", c + "common.hpp"]}.get(stage)
+    src = TRAFFIC_SOURCES.get(stage)
     if src is None:
         return None
     digest = source_digest(src)
@@ -259,7 +270,7 @@ def choose_options(args, torch, scenes, autotune, params, cams, base, scene, tar
         return base, base, None
     # launch shapes picked by the autotuner (cached per GPU and workload): one
     # for the forward alone, one for forward + L1 + backward
-    kw = dict(reps=3, tiles=[(16, 16), (32, 8), (16, 8)], batches=(64, 128, 256), target=target,
+    kw = dict(reps=6 if args.retune else 3, tiles=[(16, 16), (32, 8), (16, 8)], batches=(64, 128, 256), target=target,
               use_cache=not args.retune)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     picked, reports = [], {}
@@ -292,6 +303,31 @@ def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, ta
     params = raster.params_to_device(scene, colour_dtype=colour_dtype or torch.float32)
     opts_f, opts_b, reports = choose_options(args, torch, scenes, autotune, params, cams, base,
                                              scene, target)
+    if profile:
+        # counter runs: one launch shape per pass, so every dispatch of a
+        # kernel name belongs to one shape.  The checked forward that sizes
+        # the pair capacity comes first; a 64-element negation marks where
+        # the profiled steps begin (the counter summaries read only the
+        # dispatches after it)
+        passes = ("fwd", "fwdbwd") if args.profile_pass == "both" else (args.profile_pass,)
+        for ps in passes:
+            o = opts_f if ps == "fwd" else opts_b
+            r = raster.Rasterizer(cams, o, scene.n, scene.sh_degree, scene.n_lobes)
+            ob = r.forward(params, check=True)
+            gi = torch.empty_like(ob.image)
+            gr = raster.new_grads(params)
+            mark = torch.ones(64, device="cuda")
+            torch.cuda.synchronize()
+            torch.neg(mark, out=mark)
+            for _ in range(args.profile_steps):
+                r.forward(params, out=ob, check=False)
+                if ps == "fwdbwd":
+                    r.l1(ob.image, target, grad_out=gi)
+                    r.backward_into(params, ob, gi, gr)
+            torch.cuda.synchronize()
+            print(json.dumps({"profile_pass": ps, "shape": shape_of(r, o)}), flush=True)
+            del r, ob, gi, gr
+        return None
     rast = raster.Rasterizer(cams, opts_f, scene.n, scene.sh_degree, scene.n_lobes)
     out = rast.forward(params, check=True)          # sizes the pair capacity
     if opts_b == opts_f:
@@ -309,13 +345,6 @@ def measure_form(args, torch, L, raster, scenes, autotune, scene, cams, base, ta
         rast_b.forward(params, out=out_b, check=False)
         rast_b.l1(out_b.image, target, grad_out=grad_img)
         rast_b.backward_into(params, out_b, grad_img, grads)
-
-    if profile:
-        for _ in range(args.profile_steps):
-            fwd()
-            fwd_bwd()
-        torch.cuda.synchronize()
-        return None
 
     for _ in range(args.warmup):
         fwd()
