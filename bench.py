@@ -57,30 +57,34 @@ def parse():
 GEOM_FLOATS = 3 + 3 + 4 + 1   # mean, log-scale, quaternion, opacity logit
 
 
-def stage_bytes(name, n, items, nvis, nvis_g, P, tiles, fpg, tile_passes, npix):
+def stage_bytes(name, n, items, nvis, nvis_g, P, tiles, fpg, strips, E, npix):
     """Algorithmic HBM bytes of each stage for one frame, as this design moves
     them: n Gaussians, items (camera, Gaussian) items, nvis of them visible,
     nvis_g Gaussians visible in some camera (the only ones whose colour is
-    read), P pairs."""
-    kb = 2 if tiles <= 65536 else 4   # bytes per tile key
+    read), P pairs, E first-level (strip, item) entries over `strips` strips."""
+    kb = 2 if strips <= 65536 else 4  # bytes per strip key
+    strip_passes = max(1, math.ceil(math.ceil(math.log2(max(strips, 2))) / 8))
     fc = fpg - GEOM_FLOATS             # colour floats per Gaussian
     return {
         "fwd.preprocess": n * 4 * GEOM_FLOATS + nvis_g * 4 * fc + items * (4 + 8) + nvis * 64,
         # pass 0 reads every depth key twice (count, then rank) and writes the
         # visible (key, item); the two middle passes read keys (count), read
         # and write (key, item); the last reads keys, then (key, item) and each
-        # item's rectangle, and writes item, pair count and rectangle
+        # item's rectangle, and writes item, entry count and rectangle
         "fwd.depth_sort": 8 * items + 8 * nvis + 2 * 20 * nvis + 36 * nvis,
-        # counts read twice (block sums, then the scan), offsets written
-        "fwd.pair_scan": 12 * nvis,
+        # entry counts read twice (block sums with the rectangles, then the
+        # scan), offsets written
+        "fwd.pair_scan": 20 * nvis,
         # the duplicate only counts: it reads each chunk's items (offset,
         # item, rectangle)
         "fwd.duplicate": nvis * (4 + 4 + 8),
-        # the first pass generates the pairs from the items again and writes
-        # (key, value); every later pass reads the keys (upsweep), then reads
-        # and writes (key, value)
-        "fwd.tile_sort": nvis * (4 + 4 + 8) + (kb + 4) * P
-        + (tile_passes - 1) * (kb + 2 * (kb + 4)) * P,
+        # first level: the first strip pass generates the entries from the
+        # items again and writes (strip, position); a later pass reads the
+        # strip ids (upsweep), then reads and writes (strip, position).
+        # Second level: the count reads each entry and its rectangle; the
+        # scatter reads entry, rectangle and item and writes every pair once
+        "fwd.tile_sort": nvis * (4 + 4 + 8) + (kb + 4) * E
+        + (strip_passes - 1) * (kb + 2 * (kb + 4)) * E + (4 + 8) * E + (4 + 8 + 4) * E + 4 * P,
         "fwd.tile_order": None,  # heavy-first order of the queue schedule
         "fwd.blend": None,
         "bwd.blend": None,
@@ -432,7 +436,8 @@ def main():
     n_vis = int(np.count_nonzero(vis_items))
     n_vis_g = int(np.count_nonzero(vis_items.any(axis=0)))
     tiles = int(rast.layout.n_tiles)
-    tile_passes = math.ceil(max(1, math.ceil(math.log2(max(tiles, 2)))) / 8)
+    strips = rast.n_strips()
+    E = int(rast.header()[5].item())
     fpg = sc.floats_per_gaussian()
 
     stages = {}
@@ -443,7 +448,7 @@ def main():
             continue
         ms = src[i] / calls
         items = len(cams) * sc.n
-        b = stage_bytes(nm, sc.n, items, n_vis, n_vis_g, P, tiles, fpg, tile_passes, W * H)
+        b = stage_bytes(nm, sc.n, items, n_vis, n_vis_g, P, tiles, fpg, strips, E, W * H)
         ent = {"ms": round(ms, 5)}
         if b is not None and ms > 0:
             ent["alg_bytes"] = int(b)
@@ -531,7 +536,7 @@ def main():
         "fwd_bwd_ms": round(m["fb_graph_ms"], 4),
         "eager": {"frames_per_s": round(1000.0 / m["fwd_ms"], 2), "fwd_ms": round(m["fwd_ms"], 4),
                   "fwd_bwd_ms": round(m["fb_ms"], 4)},
-        "pairs": int(P), "visible": n_vis, "tiles": tiles,
+        "pairs": int(P), "visible": n_vis, "tiles": tiles, "strips": strips, "strip_entries": E,
         "blend_visited": visited, "blend_evaluated": evaluated, "blend_blended": blended,
         "stages": stages, "binning": binning, "roofline": roof, "roofline_bwd": roof_bwd,
         # the paper's own rendering speed (Table 1: trained Mip-NeRF360

@@ -196,16 +196,24 @@ typedef struct sgs_outputs {
 typedef struct sgs_layout {
     size_t total_bytes;
     size_t header;          /* u32[16]: [0] status bits, [1] pair count P, [2] visible
-                               items, [3] forward and [4] backward tile-queue counters */
-    size_t cam_table;       /* per camera: int32 W,H,GX,GY,tile_base,pad; int64 pix_base */
+                               items, [3] forward and [4] backward tile-queue counters,
+                               [5] first-level (strip, item) entries, [6] second-level
+                               entry chunks */
+    size_t cam_table;       /* per camera: int32 W,H,GX,GY,tile_base,strip_base;
+                               int64 pix_base; f64 guard limits */
     size_t records;         /* per (camera, Gaussian) item: 64-byte splat record */
     size_t depth_keys;      /* u32 per item: bits of float32 depth, 0xFFFFFFFF if culled */
     size_t tile_rects;      /* u64 per item: tx0 | tx1<<16 | ty0<<32 | ty1<<48; 0 pairs if culled */
     size_t sorted_items;    /* u32 per item: items in ascending (depth key, item) order */
-    size_t pair_offsets;    /* u32 per item: exclusive scan of pairs in sorted order */
-    size_t pair_tiles;      /* per pair: global tile id, sorted ascending; u16 when
-                               n_tiles <= 65536, else u32 */
-    size_t pair_values;     /* u32 per pair: item = camera * n + g, in blend order */
+    size_t pair_offsets;    /* u32 per item: exclusive scan, in sorted order, of each
+                               item's (strip, item) entries: tile rows times strip
+                               columns (a strip: SGS_STRIP_TILES consecutive tiles of a
+                               row) of its tile rectangle */
+    size_t pair_tiles;      /* binning scratch, capacity entries: strip ids of the
+                               first level (u16 when n_strips <= 65536, else u32); the
+                               tile of a sorted pair is the one whose range holds it */
+    size_t pair_values;     /* u32 per pair: item = camera * n + g, in blend order
+                               (tile ascending, then depth key, then item) */
     size_t ranges;          /* u32[2] per global tile: [start, end), (0,0) if empty */
     size_t grad2d;          /* f32[10][items]: d/d(u, v, Qa, Qb, Qc, opacity, r, g, b, z);
                                row 9 only when depth or alpha had a gradient */
@@ -213,7 +221,11 @@ typedef struct sgs_layout {
     int64_t n_tiles;        /* total tiles over all cameras */
     int64_t n_pixels;       /* total pixels over all cameras */
     int64_t pair_capacity;
+    int64_t n_strips;       /* row strips over all cameras: per camera, tile rows
+                               times ceil(tiles per row / SGS_STRIP_TILES) */
 } sgs_layout;
+
+#define SGS_STRIP_TILES 64   /* tiles per row strip of the first binning level */
 
 #define SGS_STATUS_CAPACITY 1u   /* header[0] bit: P exceeded pair_capacity; pairs truncated */
 #define SGS_STATUS_CAMERAS  2u   /* header[0] bit: a device camera is invalid or disagrees

@@ -67,7 +67,7 @@ class Layout(Structure):
                 ("sorted_items", c_size_t), ("pair_offsets", c_size_t), ("pair_tiles", c_size_t),
                 ("pair_values", c_size_t), ("ranges", c_size_t), ("grad2d", c_size_t),
                 ("n_items", c_int64), ("n_tiles", c_int64), ("n_pixels", c_int64),
-                ("pair_capacity", c_int64)]
+                ("pair_capacity", c_int64), ("n_strips", c_int64)]
 
 
 EXPORTS = ("render_workspace_bytes", "render_layout", "render_forward", "render_forward_noalloc",

@@ -30,6 +30,7 @@ SOURCES = {
     "preprocess_bwd.hip": ["-ffp-contract=off"],
     "sort.hip": [],
     "radix.hip": [],
+    "bin.hip": [],
     "adam.hip": [],
     # the blends' atomics add values already reduced across the wave (the
     # work counters from one lane at a wave-uniform address): LLVM's atomic

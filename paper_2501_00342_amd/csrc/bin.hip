@@ -1,0 +1,451 @@
+// Second binning level: strip entries -> (tile, item) pairs in key order.
+//
+// After the first level the (strip, item) entries are grouped by strip, in
+// ascending strip id, and within a strip in depth order; each entry's value
+// is its item's position in the depth order (sorted_items, sorted_rects).
+// A strip is the run of tiles x0 .. x0 + SW - 1 (SW <= kStripTiles) of one
+// tile row; the entry of an item with tile columns tx0 .. tx1 covers the
+// strip's tiles max(tx0, x0) .. min(tx1, x0 + SW - 1).  A tile's pairs are
+// the entries covering it, in entry order, so writing them in that order
+// gives the order of a stable sort on (tile << 32 | depth) keys.
+//
+// Each strip's entries are cut in chunks of kBinChunk:
+//   k_bin_chunks   one block: the chunk table (per strip its first chunk and
+//                  chunk count, per chunk its entry range and the strip's
+//                  first tile, width and first column)
+//   k_bin_count    one wave per chunk: how many of the chunk's entries cover
+//                  each tile of the strip (difference array over the tiles)
+//   k_bin_strips   per strip: for each tile, the counts of the strip's
+//                  earlier chunks (exclusive sums over chunks), and each
+//                  tile's total
+//   k_bin_tiles    one block: exclusive scan of the tile totals over all
+//                  tiles -> first position of each tile, and the ranges
+//   k_bin_scatter  one wave per chunk, lane t holding tile t of the strip:
+//                  for 64 entries at a time, lane t forms the mask of the
+//                  entries covering its tile and appends them, in order, to
+//                  its tile's run, staged in LDS per tile; the staged pairs
+//                  are then stored with consecutive lanes on consecutive
+//                  positions.  A chunk with more pairs than the LDS stage
+//                  stores each pair directly.
+// Positions at or past the capacity are never written; the ranges are
+// clamped to the capacity (the scan has then set SGS_STATUS_CAPACITY).
+#include "common.hpp"
+
+namespace sgs {
+
+static_assert(kStripTiles == 64, "one wave lane per tile of a strip");
+static_assert(kBinChunk % 64 == 0 && kBinChunk / 64 <= 8, "whole entry batches per lane");
+constexpr int kBinBatches = kBinChunk / 64;   // entries per lane of a chunk
+
+// Inclusive scans over the 64 lanes of a wave with DPP moves: shifts by 1,
+// 2, 4 and 8 lanes within each row of 16, then lane 15 of rows 0 and 2 into
+// rows 1 and 3, then lane 31 into rows 2 and 3.  A lane whose source lies
+// outside its row (or in a row the mask leaves out) receives 0, the identity
+// of both operations.
+#define SGS_DPP(x, ctrl, rows) \
+    ((uint32_t)__builtin_amdgcn_update_dpp(0, (int)(x), (ctrl), (rows), 0xF, false))
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += SGS_DPP(v, 0x111, 0xF);
+    v += SGS_DPP(v, 0x112, 0xF);
+    v += SGS_DPP(v, 0x114, 0xF);
+    v += SGS_DPP(v, 0x118, 0xF);
+    v += SGS_DPP(v, 0x142, 0xA);
+    v += SGS_DPP(v, 0x143, 0xC);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_prefix_or32(uint32_t v) {
+    v |= SGS_DPP(v, 0x111, 0xF);
+    v |= SGS_DPP(v, 0x112, 0xF);
+    v |= SGS_DPP(v, 0x114, 0xF);
+    v |= SGS_DPP(v, 0x118, 0xF);
+    v |= SGS_DPP(v, 0x142, 0xA);
+    v |= SGS_DPP(v, 0x143, 0xC);
+    return v;
+}
+
+// inclusive OR of v over lanes 0 .. lane
+__device__ __forceinline__ uint64_t wave_prefix_or(uint64_t v) {
+    return (uint64_t)wave_prefix_or32((uint32_t)v) | ((uint64_t)wave_prefix_or32((uint32_t)(v >> 32)) << 32);
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// chunk table (one block of 1024 threads; thread t owns a run of strips)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(1024) k_bin_chunks(Workspace ws) {
+    const int n_cams = ws.n_cams;
+    constexpr int WAVES = 1024 / 64;
+    __shared__ uint32_t s_w[WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t S = ws.n_strips;
+    const int64_t per = (S + 1023) / 1024;
+    const int64_t s0 = (int64_t)tid * per < S ? (int64_t)tid * per : S;
+    const int64_t s1 = s0 + per < S ? s0 + per : S;
+    uint32_t local = 0;
+    for (int64_t s = s0; s < s1; ++s) {
+        const uint32_t a = ws.strip_ranges[2 * s], b = ws.strip_ranges[2 * s + 1];
+        const uint32_t e = b > a ? b - a : 0u;
+        local += (e + kBinChunk - 1) / kBinChunk;
+    }
+    // exclusive scan of the chunk counts over threads
+    const uint32_t incl = wave_incl_scan(local);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        before += w < wave ? s_w[w] : 0u;
+        total += s_w[w];
+    }
+    int64_t cb = before + incl - local;
+    if (s0 < s1 && n_cams > 0) {
+        // the camera of s0: the last one whose first strip is <= s0
+        int lo = 0, hi = n_cams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int64_t)ws.cams[mid].strip_base <= s0) lo = mid; else hi = mid - 1;
+        }
+        int cam = lo;
+        for (int64_t s = s0; s < s1; ++s) {
+            while (cam + 1 < n_cams && (int64_t)ws.cams[cam + 1].strip_base <= s) ++cam;
+            const CamTable ct = ws.cams[cam];
+            const int SX = (ct.GX + kStripTiles - 1) >> kStripShift;
+            const int64_t ls = s - ct.strip_base;
+            uint32_t tb = 0, shape = 0;
+            if (SX > 0 && ls >= 0 && ls < (int64_t)SX * ct.GY) {
+                const int ty = (int)(ls / SX), sx = (int)(ls - (int64_t)ty * SX);
+                const int x0 = sx << kStripShift;
+                const int sw = ct.GX - x0 < kStripTiles ? ct.GX - x0 : kStripTiles;
+                tb = (uint32_t)(ct.tile_base + ty * ct.GX + x0);
+                shape = (uint32_t)sw | ((uint32_t)x0 << 16);
+            }
+            const uint32_t a = ws.strip_ranges[2 * s], b = ws.strip_ranges[2 * s + 1];
+            const uint32_t e = b > a ? b - a : 0u;
+            int64_t nch = (e + kBinChunk - 1) / kBinChunk;
+            if (cb + nch > ws.chunk_cap) nch = ws.chunk_cap > cb ? ws.chunk_cap - cb : 0;
+            ws.strip_info[s] = make_uint4((uint32_t)cb, (uint32_t)nch, tb, shape);
+            for (int64_t k = 0; k < nch; ++k) {
+                const uint32_t c0 = a + (uint32_t)k * kBinChunk;
+                uint32_t c1 = c0 + kBinChunk < b ? c0 + kBinChunk : b;
+                if (shape == 0) c1 = c0;   // a strip the device cameras do not have: no work
+                ws.chunk_info[cb + k] = make_uint4(c0, c1, tb, shape);
+            }
+            cb += nch;
+        }
+    }
+    if (tid == 0)
+        ws.header[kHdrChunks] = (uint32_t)((int64_t)total < ws.chunk_cap ? (int64_t)total : ws.chunk_cap);
+}
+
+// The chunk a wave takes in round r of a persistent grid of `blocks` blocks
+// of `wpb` waves: consecutive chunks stay on one XCD (its L2 merges the
+// partial lines that neighbouring chunks of a strip write to each tile).
+__device__ __forceinline__ int64_t bin_chunk_of(int64_t round, int64_t n_chunks, int wpb, int wave) {
+    const int64_t per_round = (int64_t)gridDim.x * wpb;
+    const int64_t left = n_chunks - round * per_round;
+    const int64_t live = left <= 0 ? 0 : (left + wpb - 1) / wpb;
+    const int64_t blk = xcd_part(blockIdx.x, live < gridDim.x ? live : gridDim.x);
+    return round * per_round + blk * wpb + wave;
+}
+
+// The local tile interval of an entry: first tile | tile count << 16 (count
+// 0: it covers none of the strip's tiles)
+__device__ __forceinline__ uint32_t entry_interval(uint64_t r, int x0, int sw) {
+    const int tx0 = (int)(r & 0xFFFF) - x0, tx1 = (int)((r >> 16) & 0xFFFF) - x0;
+    const int a = tx0 > 0 ? tx0 : 0, b = tx1 < sw - 1 ? tx1 : sw - 1;
+    return b >= a ? (uint32_t)a | ((uint32_t)(b - a + 1) << 16) : 0xFFFFu;
+}
+
+// ---------------------------------------------------------------------------
+// per chunk and tile: entries of the chunk covering the tile
+// ---------------------------------------------------------------------------
+
+constexpr int kBinWaves = 4;   // waves per block of the counting kernel
+
+__global__ void __launch_bounds__(64 * kBinWaves)
+k_bin_count(Workspace ws, const uint32_t* __restrict__ entries) {
+    __shared__ int s_diff[kBinWaves][kStripTiles + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nc = ws.header[kHdrChunks];
+    const int64_t nvis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
+    for (int64_t round = 0;; ++round) {
+        if (round * gridDim.x * kBinWaves >= nc) break;   // uniform over the block
+        const int64_t c = bin_chunk_of(round, nc, kBinWaves, wave);
+        if (c >= nc) continue;   // uniform over the wave
+        const uint4 ci = ws.chunk_info[c];
+        const int sw = (int)(ci.w & 0xFFFF), x0 = (int)(ci.w >> 16);
+        s_diff[wave][lane] = 0;
+        if (lane == 0) s_diff[wave][kStripTiles] = 0;
+        uint32_t iv[kBinBatches];
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            const uint32_t e = ci.x + (uint32_t)(k * 64 + lane);
+            uint32_t slot = e < ci.y ? entries[e] : 0xFFFFFFFFu;
+            iv[k] = slot;
+        }
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            const uint32_t slot = iv[k];
+            iv[k] = slot < (uint64_t)nvis ? entry_interval(ws.sorted_rects[slot], x0, sw) : 0xFFFFu;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // a wave's LDS operations complete in order: the clears land before
+        // the additions, the additions before the reads
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            const int a = (int)(iv[k] & 0xFFFF), w = (int)(iv[k] >> 16);
+            if (w > 0) {
+                atomicAdd(&s_diff[wave][a], 1);
+                atomicAdd(&s_diff[wave][a + w], -1);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t cnt = wave_incl_scan((uint32_t)s_diff[wave][lane]);
+        ws.chunk_counts[c * kStripTiles + lane] = (uint16_t)cnt;   // 0 past the strip's width
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per strip: exclusive sums of each tile's chunk counts over the strip's
+// chunks (16 waves, each over a contiguous run of chunks), and tile totals
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(1024) k_bin_strips(Workspace ws) {
+    constexpr int WAVES = 1024 / 64;
+    __shared__ uint32_t s_seg[WAVES][kStripTiles];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t s = blockIdx.x; s < ws.n_strips; s += gridDim.x) {
+        const uint4 si = ws.strip_info[s];
+        const int64_t cb = si.x, nch = si.y;
+        const int sw = (int)(si.w & 0xFFFF);
+        const int64_t seg = (nch + WAVES - 1) / WAVES;
+        const int64_t k0 = (int64_t)wave * seg < nch ? (int64_t)wave * seg : nch;
+        const int64_t k1 = k0 + seg < nch ? k0 + seg : nch;
+        uint32_t sum = 0;
+        for (int64_t k = k0; k < k1; ++k) sum += ws.chunk_counts[(cb + k) * kStripTiles + lane];
+        __syncthreads();   // the previous strip is done with s_seg
+        s_seg[wave][lane] = sum;
+        __syncthreads();
+        uint32_t run = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t v = s_seg[w][lane];
+            run += w < wave ? v : 0u;
+            total += v;
+        }
+        for (int64_t k = k0; k < k1; ++k) {
+            const int64_t i = (cb + k) * kStripTiles + lane;
+            const uint32_t v = ws.chunk_counts[i];
+            ws.chunk_offsets[i] = run;
+            run += v;
+        }
+        if (wave == 0 && lane < sw && (int64_t)si.z + lane < ws.n_tiles) ws.tile_count[si.z + lane] = total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one block: tile starts and ranges from the tile totals
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(1024) k_bin_tiles(Workspace ws) {
+    constexpr int WAVES = 1024 / 64;
+    constexpr int IT = 16;
+    __shared__ uint64_t s_w[WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t T = ws.n_tiles;
+    const uint64_t cap = (uint64_t)ws.capacity;
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < T; b0 += 1024 * IT) {
+        const int64_t i0 = b0 + (int64_t)tid * IT;
+        uint32_t v[IT];
+        uint64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            v[k] = i0 + k < T ? ws.tile_count[i0 + k] : 0u;
+            run += v[k];
+        }
+        const uint64_t incl = wave_incl_scan64(run);
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint64_t before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            before += w < wave ? s_w[w] : 0ull;
+            all += s_w[w];
+        }
+        uint64_t st = carry + before + incl - run;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int64_t i = i0 + k;
+            if (i < T) {
+                ws.tile_start[i] = (uint32_t)(st < 0xFFFFFFFFull ? st : 0xFFFFFFFFull);
+                const uint64_t a = st < cap ? st : cap, e = st + v[k] < cap ? st + v[k] : cap;
+                ws.ranges[2 * i] = a < e ? (uint32_t)a : 0u;
+                ws.ranges[2 * i + 1] = a < e ? (uint32_t)e : 0u;
+            }
+            st += v[k];
+        }
+        carry += all;
+        __syncthreads();   // s_w is read before the next round writes it
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per chunk: the pairs, staged by tile, then stored
+// ---------------------------------------------------------------------------
+
+static_assert(kBinChunk <= 256 && kStripTiles <= 256, "staged tile and entry index are one byte each");
+static_assert((kBinStage & (kBinStage - 1)) == 0, "the stage index is masked");
+
+// One wave per chunk.  For each batch of 64 entries (lane k holds entry k),
+// an entry covering tiles a .. a + w - 1 sets its bit k in the start mark of
+// tile a and the end mark of tile a + w; lane t (tile t) then ORs the marks
+// of tiles 0 .. t: the entries covering t are those started and not ended,
+// in entry order = bit order.  Lane t walks its set bits and stages their
+// entry indices at its tile's running position.
+__global__ void __launch_bounds__(64)
+k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* __restrict__ chunk_info) {
+    __shared__ uint32_t s_item[kBinChunk];          // items of the chunk's entries
+    __shared__ uint16_t s_stage[kBinStage];         // tile << 8 | entry index, by tile
+    __shared__ uint64_t s_start[kStripTiles];       // entries starting at each tile
+    __shared__ uint64_t s_end[kStripTiles + 1];     // entries ending before each tile
+    __shared__ int64_t s_gb[kStripTiles];           // position of staged index 0 of each tile's run
+    const int lane = threadIdx.x;
+    const int64_t nc = ws.header[kHdrChunks];
+    const int64_t nvis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
+    const int64_t cap = ws.capacity;
+    s_start[lane] = 0ull;
+    s_end[lane] = 0ull;
+    // the chunk's table entry and entries (lane l holds entries l, l + 64,
+    // ...), loaded one chunk ahead: the next chunk's arrive while this one
+    // computes
+    auto load_entries = [&](int64_t cc, uint4& cio, uint32_t (&sl)[kBinBatches]) {
+        cio = chunk_info[cc];
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            const uint32_t e = cio.x + (uint32_t)(k * 64 + lane);
+            sl[k] = e < cio.y ? entries[e] : 0xFFFFFFFFu;
+        }
+    };
+    int64_t round = 0;
+    int64_t c = bin_chunk_of(0, nc, 1, 0);
+    uint4 ci = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t slot[kBinBatches];
+    if (c < nc) load_entries(c, ci, slot);
+    while (c < nc) {   // uniform
+        const int sw = (int)(ci.w & 0xFFFF), x0 = (int)(ci.w >> 16);
+        // this lane's tile count, its earlier chunks' count, the tile's
+        // start, and the entries' items and intervals
+        const uint32_t raw = ws.chunk_counts[c * kStripTiles + lane];
+        const uint32_t off = ws.chunk_offsets[c * kStripTiles + lane];
+        const bool live = lane < sw && (int64_t)ci.z + lane < ws.n_tiles;
+        const uint32_t ts = live ? ws.tile_start[ci.z + lane] : 0u;
+        uint32_t item[kBinBatches], iv[kBinBatches];
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            const bool ok = slot[k] < (uint64_t)nvis;
+            item[k] = ok ? ws.sorted_items[slot[k]] : 0u;
+            iv[k] = ok ? entry_interval(ws.sorted_rects[slot[k]], x0, sw) : 0xFFFFu;
+        }
+        const int64_t cn = bin_chunk_of(round + 1, nc, 1, 0);
+        uint4 ci_n = ci;
+        uint32_t slot_n[kBinBatches];
+        if (cn < nc) load_entries(cn, ci_n, slot_n);
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) s_item[k * 64 + lane] = item[k];
+        const uint32_t cnt = live ? raw : 0u;
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t lb = incl - cnt;
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        const int64_t gb = (int64_t)ts + off - lb;   // position = gb + staged index
+        const bool staged = total <= (uint32_t)kBinStage;
+        s_gb[lane] = gb;
+        uint32_t pos = lb;
+        const int ne = (int)(ci.y - ci.x);
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            if (k * 64 >= ne) break;   // uniform
+            const uint32_t a = iv[k] & 0xFFFFu, w = iv[k] >> 16;
+            if (w > 0) {
+                atomicOr(&s_start[a], 1ull << lane);
+                atomicOr(&s_end[a + w], 1ull << lane);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // a wave's LDS operations complete in order: the marks are set
+            // before they are read, and read before they are cleared
+            const uint64_t st = s_start[lane], en = s_end[lane];
+            s_start[lane] = 0ull;
+            s_end[lane] = 0ull;
+            uint64_t m = wave_prefix_or(st) & ~wave_prefix_or(en);
+            if (!live) m = 0ull;
+            if (staged) {
+                // pos stays below the chunk's total; the mask keeps any
+                // count that disagreed with the walk inside the stage
+                const uint32_t tag = ((uint32_t)lane << 8) | (uint32_t)(k * 64);
+                while (m) {
+                    const int j = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    s_stage[pos & (kBinStage - 1)] = (uint16_t)(tag | (uint32_t)j);
+                    ++pos;
+                }
+            } else {
+                while (m) {
+                    const int j = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    const int64_t g = gb + pos;
+                    if (g >= 0 && g < cap) ws.pair_values[g] = s_item[k * 64 + j];
+                    ++pos;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (staged) {
+            // one wave: its LDS writes above complete before these reads
+            for (uint32_t i = lane; i < total; i += 64) {
+                const uint32_t v = s_stage[i];   // total <= kBinStage here
+                const int64_t g = s_gb[v >> 8] + i;
+                if (g >= 0 && g < cap) ws.pair_values[g] = s_item[v & 0xFFu];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        c = cn;
+        ci = ci_n;
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) slot[k] = slot_n[k];
+        ++round;
+    }
+}
+
+void launch_bin_tiles(const Workspace& ws, const uint32_t* entry_slots, hipStream_t s) {
+    if (ws.n_strips <= 0 || ws.n_tiles <= 0) return;
+    hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(1024), 0, s, ws);
+    // persistent grids no larger than what stays resident (a block that
+    // waits for a free slot would run its whole loop after the others)
+    const int64_t cus = ws.cus > 0 ? ws.cus : 256;
+    const int64_t cblocks = (ws.chunk_cap + kBinWaves - 1) / kBinWaves;
+    const int64_t cmax = cus * 4;   // 16 waves per CU
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)(cblocks < cmax ? cblocks : cmax)),
+                       dim3(64 * kBinWaves), 0, s, ws, entry_slots);
+    const int64_t sblocks = ws.n_strips < 1024 ? ws.n_strips : 1024;
+    hipLaunchKernelGGL(k_bin_strips, dim3((unsigned)sblocks), dim3(1024), 0, s, ws);
+    hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, s, ws);
+    const int64_t wmax = cus * 12;   // LDS holds 15 of these one-wave blocks per CU
+    const int64_t wblocks = ws.chunk_cap < wmax ? ws.chunk_cap : wmax;
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)wblocks), dim3(64), 0, s, ws, entry_slots,
+                       ws.chunk_info);
+}
+
+}  // namespace sgs

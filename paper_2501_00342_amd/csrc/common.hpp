@@ -21,6 +21,14 @@ constexpr int kPreThreads = 256;
 constexpr int kPreTile = 128;                        // Gaussians per forward-preprocess block
 constexpr int kPersistentBlocks = 1024;              // grid of the persistent kernels
 constexpr int kDepthPasses = 4;                      // 32-bit depth keys
+// binning of pairs in two levels: items go to row strips of at most
+// kStripTiles tiles (one wave lane per tile), then each strip's entries to
+// its tiles in chunks of kBinChunk entries, one wave per chunk
+constexpr int kStripShift = 6;
+constexpr int kStripTiles = 1 << kStripShift;
+static_assert(kStripTiles == SGS_STRIP_TILES, "strip width of the ABI");
+constexpr int kBinChunk = 256;                       // entries per chunk (< 65536)
+constexpr int kBinStage = 4096;                      // pairs a chunk stages in LDS (a power of two)
 constexpr int kXcds = 8;                             // dies; blocks go to them round-robin
 
 // Renumbers block b of a grid whose first `active` blocks carry work so that
@@ -43,12 +51,15 @@ enum Header : int {
     kHdrVisible = 2,      // items left after culling (length of the depth order)
     kHdrQueueFwd = 3,     // next heavy-first tile position of the forward blend queue
     kHdrQueueBwd = 4,     // same for the backward blend
+    kHdrEntries = 5,      // (item, strip row) entries of the first binning level
+    kHdrChunks = 6,       // entry chunks of the second level
     kHdrWords = 16
 };
 
 // per camera, computed on the device from the device cameras
 struct CamTable {
-    int32_t W, H, GX, GY, tile_base, pad;
+    int32_t W, H, GX, GY, tile_base;
+    int32_t strip_base;   // first global strip id: GY rows of ceil(GX / kStripTiles) strips
     int64_t pix_base;
     double limx, limy;   // guard band: guard * ((0.5 W) / fx), guard * ((0.5 H) / fy)
 };
@@ -121,6 +132,13 @@ struct Workspace {
     uint32_t* pair_tiles_alt;
     uint32_t* pair_values_alt;
     uint32_t* ranges;
+    uint32_t* strip_ranges;      // [start, end) of every strip's entries (first level)
+    uint4* strip_info;           // per strip: first chunk, chunks, first tile, width | x0 << 16
+    uint4* chunk_info;           // per chunk: first entry, end entry, first tile, width | x0 << 16
+    uint16_t* chunk_counts;      // per chunk: pairs of each of its strip's tiles
+    uint32_t* chunk_offsets;     // per chunk: pairs of the strip's earlier chunks, per tile
+    uint32_t* tile_count;        // pairs per tile
+    uint32_t* tile_start;        // first pair position of each tile
     uint32_t* tile_keys;         // heavy-first sort key of every tile
     uint32_t* tile_order;        // tiles by decreasing list length (stable)
     float* grad2d;
@@ -132,10 +150,13 @@ struct Workspace {
     uint64_t* scan_sums;         // per scan block
     double* loss_partial;
     int64_t n_items, n_tiles, n_pixels, capacity;
+    int64_t n_strips, chunk_cap;     // strips; chunk table capacity
+    int n_cams;
+    int cus;                         // compute units of the device (persistent grids)
     int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
     int dup_blocks;              // grid of the duplicate kernel (one block per chunk)
-    int tile_passes, tile_bits;
-    bool key16;                  // pair tile ids stored as u16 (at most 65536 tiles)
+    int strip_passes, strip_bits;
+    bool key16;                  // entry strip ids stored as u16 (at most 65536 strips)
 };
 
 // the fused Adam step: one entry per parameter array, in sgs_gaussians order
@@ -189,6 +210,10 @@ void launch_duplicate_counts(const Workspace& ws, int64_t n, hipStream_t s);
 void launch_dup_scatter(const Workspace& ws, int64_t n, uint32_t* keys_out, uint32_t* vals_out,
                         int64_t parts, int digit_bits, uint32_t* ranges, int64_t pair_capacity,
                         hipStream_t s);
+// second binning level: the strip-sorted entries (values: positions in the
+// depth order) -> pair_values in (tile, depth) order, tile_count, tile_start
+// and the tile ranges; pairs past the capacity are dropped
+void launch_bin_tiles(const Workspace& ws, const uint32_t* entry_slots, hipStream_t s);
 // tile_order = tiles sorted by decreasing list length (one stable 8-bit pass
 // over a log-scale length bucket)
 void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s);

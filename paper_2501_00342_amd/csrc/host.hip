@@ -40,14 +40,16 @@ struct Plan {
     sgs::Opts o;
     int64_t n;
     int n_cams;
-    int tile_passes, tile_bits;
+    int strip_passes, strip_bits;
+    int64_t n_strips, chunk_cap;
     int64_t depth_parts, pair_parts, scan_parts, dup_chunks;
     int pre_blocks, dup_blocks;
     int64_t max_parts;
     // offsets not exported in sgs_layout
     size_t sorted_rects, sort_keys_alt, sort_keys_alt2, sorted_items_alt, chunk_start, pair_tiles_alt,
         pair_values_alt, counts, totals, pair_counts, scan_sums, loss_partial, gx_colour,
-        tile_keys, tile_order;
+        tile_keys, tile_order, strip_ranges, strip_info, chunk_info, chunk_counts, chunk_offsets,
+        tile_count, tile_start;
     int64_t tile_parts;   // partitions of the heavy-first tile sort
     // the blends run the queue schedule: requested, and the forward builds
     // the tile order (it does when there are Gaussians and pair capacity)
@@ -117,7 +119,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     o.t_min = oin && oin->t_min != 0.0f ? oin->t_min : 1e-4f;
     if (!(o.alpha_max > 0.0f && o.alpha_max < 1.0f))
         return fail(SGS_E_INVALID, "alpha_max must be in (0, 1)");
-    int64_t tiles = 0, pixels = 0;
+    int64_t tiles = 0, pixels = 0, strips = 0;
     for (int c = 0; c < n_cams; ++c) {
         const int W = cams[c].width, H = cams[c].height;
         if (W < 1 || H < 1 || W > SGS_MAX_IMAGE_SIDE || H > SGS_MAX_IMAGE_SIDE)
@@ -130,6 +132,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
               cams[c].fy > 0.0f))
             return fail(SGS_E_INVALID, "camera fx and fy must be finite and > 0");
         tiles += cdiv(W, o.tile_w) * cdiv(H, o.tile_h);
+        strips += cdiv(H, o.tile_h) * cdiv(cdiv(W, o.tile_w), sgs::kStripTiles);
         pixels += (int64_t)W * H;
     }
     const int64_t n = g->n;
@@ -140,10 +143,15 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->o = o;
     pl->n = n;
     pl->n_cams = n_cams;
+    // the first binning level sorts (strip, item) entries by strip id
     int bits = 1;
-    while ((int64_t(1) << bits) < tiles) ++bits;
-    pl->tile_bits = bits;
-    pl->tile_passes = (bits + sgs::kRadixBits - 1) / sgs::kRadixBits;
+    while ((int64_t(1) << bits) < strips) ++bits;
+    pl->strip_bits = bits;
+    pl->strip_passes = (bits + sgs::kRadixBits - 1) / sgs::kRadixBits;
+    pl->n_strips = strips;
+    // every chunk but a strip's last holds kBinChunk entries, and there are
+    // at most as many entries as pairs
+    pl->chunk_cap = cdiv(cap, sgs::kBinChunk) + strips;
     pl->depth_parts = cdiv(items, sgs::kSortTile);
     pl->pair_parts = cdiv(cap, sgs::kSortTile);
     pl->scan_parts = cdiv(items, sgs::kScanTile);
@@ -197,13 +205,36 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->totals = take((size_t)sgs::kRadix * 4);
     pl->pair_counts = take((size_t)items * 4);
     pl->sorted_rects = take((size_t)items * 8);
-    pl->scan_sums = take((size_t)(pl->scan_parts + 1) * 8);
+    pl->scan_sums = take((size_t)(pl->scan_parts + 1) * 16);   // entry sums, then pair sums
+    // second binning level (after the sections above, whose offsets then do
+    // not move with the pair capacity's chunk tables)
+    pl->strip_ranges = take((size_t)strips * 8);
+    pl->strip_info = take((size_t)strips * 16);
+    pl->tile_count = take((size_t)tiles * 4);
+    pl->tile_start = take((size_t)tiles * 4);
+    pl->chunk_info = take((size_t)pl->chunk_cap * 16);
+    pl->chunk_counts = take((size_t)pl->chunk_cap * sgs::kStripTiles * 2);
+    pl->chunk_offsets = take((size_t)pl->chunk_cap * sgs::kStripTiles * 4);
     L.total_bytes = off;
     L.n_items = items;
     L.n_tiles = tiles;
     L.n_pixels = pixels;
     L.pair_capacity = cap;
+    L.n_strips = strips;
     return SGS_OK;
+}
+
+// compute units of the current device, queried once per device
+int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cache[dev].load();
+    if (v > 0) return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+        v = 256;
+    cache[dev].store(v);
+    return v;
 }
 
 sgs::Workspace bind(const Plan& pl, void* base) {
@@ -226,6 +257,13 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.pair_tiles_alt = reinterpret_cast<uint32_t*>(b + pl.pair_tiles_alt);
     w.pair_values_alt = reinterpret_cast<uint32_t*>(b + pl.pair_values_alt);
     w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
+    w.strip_ranges = reinterpret_cast<uint32_t*>(b + pl.strip_ranges);
+    w.strip_info = reinterpret_cast<uint4*>(b + pl.strip_info);
+    w.chunk_info = reinterpret_cast<uint4*>(b + pl.chunk_info);
+    w.chunk_counts = reinterpret_cast<uint16_t*>(b + pl.chunk_counts);
+    w.chunk_offsets = reinterpret_cast<uint32_t*>(b + pl.chunk_offsets);
+    w.tile_count = reinterpret_cast<uint32_t*>(b + pl.tile_count);
+    w.tile_start = reinterpret_cast<uint32_t*>(b + pl.tile_start);
     w.tile_keys = reinterpret_cast<uint32_t*>(b + pl.tile_keys);
     w.tile_order = reinterpret_cast<uint32_t*>(b + pl.tile_order);
     w.grad2d = reinterpret_cast<float*>(b + L.grad2d);
@@ -245,9 +283,13 @@ sgs::Workspace bind(const Plan& pl, void* base) {
     w.scan_parts = pl.scan_parts;
     w.dup_chunks = pl.dup_chunks;
     w.dup_blocks = pl.dup_blocks;
-    w.tile_passes = pl.tile_passes;
-    w.tile_bits = pl.tile_bits;
-    w.key16 = L.n_tiles <= 65536;
+    w.strip_passes = pl.strip_passes;
+    w.strip_bits = pl.strip_bits;
+    w.n_strips = pl.n_strips;
+    w.chunk_cap = pl.chunk_cap;
+    w.n_cams = pl.n_cams;
+    w.cus = device_cus();
+    w.key16 = pl.n_strips <= 65536;
     return w;
 }
 
@@ -443,40 +485,41 @@ int forward_impl(const sgs_gaussians* g, const sgs_camera* host_cams, const sgs_
         }
     }
     if (pl.n > 0 && pair_capacity > 0) {
-        // the duplicate counts the first tile digit of every chunk; the first
-        // tile pass generates the pairs again and scatters them directly.
-        // Pass ps writes the buffer that leaves the last pass in the primary
-        // buffers.
+        // first level: the duplicate counts the first strip digit of every
+        // chunk; the first strip pass generates the entries again and
+        // scatters them directly.  The last strip pass leaves the entries in
+        // the alternate pair buffers and writes the strip ranges.
         sgs::launch_duplicate_counts(ws, pl.n, s);
         SGS_LAUNCHED();
         mk.mark(5);
-        const int L = pl.tile_passes;
-        auto out_t = [&](int ps) { return (L - 1 - ps) % 2 == 0 ? ws.pair_tiles : ws.pair_tiles_alt; };
-        auto out_v = [&](int ps) { return (L - 1 - ps) % 2 == 0 ? ws.pair_values : ws.pair_values_alt; };
+        const int L = pl.strip_passes;
+        auto out_t = [&](int ps) { return (L - 1 - ps) % 2 == 0 ? ws.pair_tiles_alt : ws.pair_tiles; };
+        auto out_v = [&](int ps) { return (L - 1 - ps) % 2 == 0 ? ws.pair_values_alt : ws.pair_values; };
         {
-            const int nb = pl.tile_bits < sgs::kRadixBits ? pl.tile_bits : sgs::kRadixBits;
+            const int nb = pl.strip_bits < sgs::kRadixBits ? pl.strip_bits : sgs::kRadixBits;
             sgs::launch_dup_scatter(ws, pl.n, out_t(0), out_v(0), pl.pair_parts, nb,
-                                    L == 1 ? ws.ranges : nullptr, pair_capacity, s);
+                                    L == 1 ? ws.strip_ranges : nullptr, pair_capacity, s);
         }
         for (int ps = 1; ps < L; ++ps) {
-            // tile ids are below 2^tile_bits: the last pass has fewer digit bits
-            const int left = pl.tile_bits - ps * sgs::kRadixBits;
+            // strip ids are below 2^strip_bits: the last pass has fewer digit bits
+            const int left = pl.strip_bits - ps * sgs::kRadixBits;
             const int nb = left < sgs::kRadixBits ? left : sgs::kRadixBits;
-            // the last pass writes the tile ranges
-            uint32_t* rng = ps == L - 1 ? ws.ranges : nullptr;
+            uint32_t* rng = ps == L - 1 ? ws.strip_ranges : nullptr;
             uint32_t *ti = out_t(ps - 1), *vi = out_v(ps - 1), *to = out_t(ps), *vo = out_v(ps);
             if (ws.key16)
                 sgs::launch_radix_pass16(reinterpret_cast<const uint16_t*>(ti), vi,
                                          reinterpret_cast<uint16_t*>(to), vo,
-                                         ws.header + sgs::kHdrPairs, pair_capacity,
+                                         ws.header + sgs::kHdrEntries, pair_capacity,
                                          ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts, s,
-                                         nb, false, rng, ws.n_tiles);
+                                         nb, false, rng, ws.n_strips);
             else
-                sgs::launch_radix_pass(ti, vi, to, vo, ws.header + sgs::kHdrPairs, pair_capacity,
+                sgs::launch_radix_pass(ti, vi, to, vo, ws.header + sgs::kHdrEntries, pair_capacity,
                                        ps * sgs::kRadixBits, ws.counts, ws.totals, pl.pair_parts,
                                        nullptr, nullptr, nullptr, 0, false, nullptr, s, nb, false,
-                                       rng, ws.n_tiles);
+                                       rng, ws.n_strips);
         }
+        // second level: each strip's entries -> its tiles' pairs, in place
+        sgs::launch_bin_tiles(ws, ws.pair_values_alt, s);
         SGS_LAUNCHED();
         mk.mark(6);
         if (pl.queue) sgs::launch_tile_order(ws, pl.tile_parts, s);
@@ -618,11 +661,11 @@ int render_read_keys(const void* workspace, const sgs_layout* layout, int64_t co
     const char* b = static_cast<const char*>(workspace);
     sgs::Workspace ws;
     memset(&ws, 0, sizeof(ws));
-    ws.pair_tiles = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->pair_tiles);
     ws.pair_values = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->pair_values);
+    ws.ranges = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->ranges);
     ws.depth_keys = reinterpret_cast<uint32_t*>(const_cast<char*>(b) + layout->depth_keys);
     ws.n_items = layout->n_items;
-    ws.key16 = layout->n_tiles <= 65536;
+    ws.n_tiles = layout->n_tiles;
     (void)hipGetLastError();
     sgs::launch_read_keys(ws, count, keys_out, static_cast<hipStream_t>(stream));
     SGS_LAUNCHED();

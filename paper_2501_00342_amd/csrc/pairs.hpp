@@ -1,21 +1,26 @@
-// Generation of the (tile, item) pairs of a chunk of the depth-ordered pair
-// sequence, shared by the duplicate (which counts or writes them) and the
-// fused first tile pass (which ranks and scatters them directly).
+// Generation of the first binning level's (strip, item) entries for a chunk
+// of the depth-ordered entry sequence, shared by the duplicate (which
+// counts them) and the fused first strip pass (which ranks and scatters
+// them directly).
 //
-// Pair q belongs to the item whose pair offset is the last one <= q; its
-// tile is the item's rectangle walked row-major from the origin.
+// A strip is a run of at most kStripTiles tiles of one tile row.  Entry q
+// belongs to the item whose entry offset is the last one <= q; its strips
+// are the item's strip rectangle (tile rows ty0..ty1, strip columns
+// tx0 >> kStripShift .. tx1 >> kStripShift) walked row-major.  The entry's
+// value is the item's position in the depth order.
 #pragma once
 
 #include "common.hpp"
 
 namespace sgs {
 
-// a chunk of kDupChunk pairs overlaps at most kDupChunk + 1 items (every
-// visible item has at least one pair)
+// a chunk of kDupChunk entries overlaps at most kDupChunk + 1 items (every
+// visible item has at least one entry)
 constexpr int kChunkItems = kDupChunk + 1;
 
-// LDS arrays of one chunk's items: pair offset, global tile id of the
-// rectangle origin, rectangle width | GX << 16, item id
+// LDS arrays of one chunk's items: entry offset, global strip id of the
+// strip rectangle's origin, its width | strips per row << 16, and the
+// item's position in the depth order
 struct ChunkItems {
     uint32_t* off;
     uint32_t* origin;
@@ -23,7 +28,7 @@ struct ChunkItems {
     uint32_t* item;
 };
 
-// Loads the items whose pairs overlap chunk `chunk` (pairs [p0, p1) of Pc)
+// Loads the items whose entries overlap chunk `chunk` (entries [p0, p1) of Pc)
 // into LDS, `nthreads` threads cooperating.  Returns how many; 0 when the
 // chunk has no recorded start.  The caller synchronises before (the arrays
 // are free) and after (the arrays are read).
@@ -41,20 +46,21 @@ __device__ __forceinline__ int load_chunk_items(const Workspace& ws, int64_t chu
         uint32_t item = ws.sorted_items[i];
         if (item >= (uint64_t)ws.n_items) item = 0;
         c.off[j] = ws.pair_offsets[i];
-        c.item[j] = item;
+        c.item[j] = (uint32_t)i;
         const uint64_t r = ws.sorted_rects[i];   // written in depth order by the depth sort
-        const int tx0 = (int)(r & 0xFFFF), tx1 = (int)((r >> 16) & 0xFFFF);
+        const int sx0 = (int)(r & 0xFFFF) >> kStripShift, sx1 = (int)((r >> 16) & 0xFFFF) >> kStripShift;
         const int ty0 = (int)((r >> 32) & 0xFFFF);
         const CamTable ct = ws.cams[item / nn];
-        c.origin[j] = (uint32_t)(ct.tile_base + ty0 * ct.GX + tx0);
-        c.wgx[j] = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)ct.GX << 16);
+        const int SX = (ct.GX + kStripTiles - 1) >> kStripShift;
+        c.origin[j] = (uint32_t)(ct.strip_base + ty0 * SX + sx0);
+        c.wgx[j] = (uint32_t)(sx1 - sx0 + 1) | ((uint32_t)SX << 16);
     }
     return (int)nloc;
 }
 
-// The cnt (<= RUN) consecutive pairs from q0 of a chunk whose nloc items are
-// in LDS: one binary search for the first, then a walk along the
-// rectangles.  tl: global tile ids, vl: item ids.
+// The cnt (<= RUN) consecutive entries from q0 of a chunk whose nloc items
+// are in LDS: one binary search for the first, then a walk along the
+// strip rectangles.  tl: global strip ids, vl: depth-order positions.
 template <int RUN>
 __device__ __forceinline__ void gen_pairs(const ChunkItems& c, int nloc, int64_t q0, int cnt,
                                           uint32_t (&tl)[RUN], uint32_t (&vl)[RUN]) {
@@ -75,7 +81,7 @@ __device__ __forceinline__ void gen_pairs(const ChunkItems& c, int nloc, int64_t
 #pragma unroll
     for (int e = 0; e < RUN; ++e) {
         if (e < cnt) {
-            if (q0 + e >= next) {   // the next item (every item has >= 1 pair)
+            if (q0 + e >= next) {   // the next item (every item has >= 1 entry)
                 ++lo;
                 wgx = c.wgx[lo];
                 w = (int)(wgx & 0xFFFF);

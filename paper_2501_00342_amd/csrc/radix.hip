@@ -11,9 +11,10 @@
 //               so a partition's stores of one digit are contiguous.
 // The first depth pass drops culled items (depth key 0xFFFFFFFF), so the
 // later passes and everything after them see only the visible items.  The
-// downsweep of the last depth pass also writes, in sorted order, the
-// number of (tile, Gaussian) pairs of each item; the scan below turns
-// those into pair offsets.
+// downsweep of the last depth pass also writes, in sorted order, each
+// item's tile rectangle and its number of (strip, item) entries (tile rows
+// times strip columns of the rectangle); the scan below turns those into
+// entry offsets and also sums the (tile, item) pairs.
 #include "common.hpp"
 #include "pairs.hpp"
 
@@ -30,6 +31,14 @@ __device__ __forceinline__ uint32_t rect_pairs(uint64_t r) {
     const int ty0 = (int)((r >> 32) & 0xFFFF), ty1 = (int)((r >> 48) & 0xFFFF);
     const int w = tx1 - tx0 + 1, h = ty1 - ty0 + 1;
     return (w > 0 && h > 0) ? (uint32_t)(w * h) : 0u;
+}
+
+// (strip, item) entries of a tile rectangle: rows times strip columns
+__device__ __forceinline__ uint32_t rect_entries(uint64_t r) {
+    const int tx0 = (int)(r & 0xFFFF), tx1 = (int)((r >> 16) & 0xFFFF);
+    const int ty0 = (int)((r >> 32) & 0xFFFF), ty1 = (int)((r >> 48) & 0xFFFF);
+    const int w = (tx1 >> kStripShift) - (tx0 >> kStripShift) + 1, h = ty1 - ty0 + 1;
+    return (tx1 >= tx0 && h > 0) ? (uint32_t)(w * h) : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -315,9 +324,9 @@ __device__ __forceinline__ void rank_scatter(uint32_t (&key)[kDownItems], const 
         __builtin_assume(out < (1u << 30));
         if (keys_out) keys_out[out] = (KeyT)k;
         vals_out[out] = v;
-        if (pairs_out) {   // last depth pass: pair count and rectangle in depth order
+        if (pairs_out) {   // last depth pass: entry count and rectangle in depth order
             const uint64_t r = v < (uint64_t)n_rects ? rects[v] : 1ull;   // 1: no pairs
-            pairs_out[out] = rect_pairs(r);
+            pairs_out[out] = rect_entries(r);
             if (rects_out) rects_out[out] = r;
         }
         // last tile pass: a key change between neighbours of this block's run
@@ -462,7 +471,7 @@ k_dup_scatter(Workspace ws, int64_t n, KeyT* __restrict__ keys_out, uint32_t* __
     __shared__ uint32_t s_scan[2][WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t P = ws.header[kHdrPairs];
+    const uint32_t P = ws.header[kHdrEntries];
     const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
     const uint32_t nn = (uint32_t)n;
     const int64_t n_vis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
@@ -530,14 +539,18 @@ k_range_edges(const KeyT* __restrict__ keys, const uint32_t* __restrict__ counts
               const uint32_t* __restrict__ totals, int64_t parts, int cstride,
               const uint32_t* count_ptr, int64_t count_host, uint32_t* __restrict__ ranges,
               int64_t n_tiles) {
-    __shared__ uint32_t s_base;
+    __shared__ uint32_t s_part[256 / 64];
     const int d = blockIdx.y;
-    if (threadIdx.x == 0) {
-        uint32_t b = 0;
-        for (int e = 0; e < d; ++e) b += totals[e];
-        s_base = b;
+    // start of digit d: the totals of the digits below it, summed by the
+    // block (one total per thread, a wave reduction, then the wave sums)
+    {
+        uint32_t t = (int)threadIdx.x < d ? totals[threadIdx.x] : 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = t;
     }
     __syncthreads();
+    const uint32_t s_base = s_part[0] + s_part[1] + s_part[2] + s_part[3];
     const int64_t count = pass_count(count_ptr, count_host);
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p < parts) {
@@ -647,7 +660,7 @@ static void dup_scatter_t(const Workspace& ws, int64_t n, KeyT* keys_out, uint32
     const dim3 g((unsigned)parts), b(kDownThreads);
 #define SGS_DUPSCAT(NB)                                                                        \
     hipLaunchKernelGGL((k_dup_scatter<KeyT, NB>), g, b, 0, s, ws, n, keys_out, vals_out,      \
-                       ws.counts, ws.totals, parts, ranges, ws.n_tiles)
+                       ws.counts, ws.totals, parts, ranges, ws.n_strips)
     switch (bits) {
         case 1: SGS_DUPSCAT(1); break;
         case 2: SGS_DUPSCAT(2); break;
@@ -662,7 +675,7 @@ static void dup_scatter_t(const Workspace& ws, int64_t n, KeyT* keys_out, uint32
     if (ranges) {
         const dim3 eg((unsigned)((parts + 255) / 256), 1u << bits);
         hipLaunchKernelGGL(k_range_edges<KeyT>, eg, dim3(256), 0, s, keys_out, ws.counts, ws.totals,
-                           parts, 2, ws.header + kHdrPairs, pair_capacity, ranges, ws.n_tiles);
+                           parts, 2, ws.header + kHdrEntries, pair_capacity, ranges, ws.n_strips);
     }
 }
 
@@ -677,7 +690,8 @@ void launch_dup_scatter(const Workspace& ws, int64_t n, uint32_t* keys_out, uint
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of the per-item pair counts (in depth order) -> pair offsets
+// exclusive scan of the per-item entry counts (in depth order) -> entry
+// offsets; the (tile, item) pairs of the same items are summed beside it
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s) {
@@ -693,32 +707,43 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s) {
     return r;
 }
 
+// block sums of the entry counts in block_sums[b] and of the pairs of the
+// same items (from their tile rectangles) in block_sums[nb + b]
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* n_ptr, int64_t n_max,
-              uint64_t* __restrict__ block_sums) {
+k_scan_reduce(const uint32_t* __restrict__ in, const uint64_t* __restrict__ rects,
+              const uint32_t* n_ptr, int64_t n_max, uint64_t* __restrict__ block_sums) {
     __shared__ uint64_t s[kScanThreads];
     const int64_t n = pass_count(n_ptr, n_max);
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint64_t run = 0;
+    uint64_t run = 0, pairs = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (i < n) run += in[i];
+        if (i < n) {
+            run += in[i];
+            pairs += rect_pairs(rects[i]);
+        }
     }
     const uint64_t tot = block_sum_u64(run, s);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+    const uint64_t ptot = block_sum_u64(pairs, s);
+    if (threadIdx.x == 0) {
+        block_sums[blockIdx.x] = tot;
+        block_sums[gridDim.x + blockIdx.x] = ptot;
+    }
 }
 
-// one block: exclusive scan of the block sums; P = total, capacity flag
+// one block: exclusive scan of the entry block sums; E = their total, P =
+// the pairs' total, capacity flag when P exceeds the capacity
 __global__ void __launch_bounds__(1024)
 k_scan_sums(uint64_t* __restrict__ block_sums, int64_t nb, uint32_t* header, int64_t capacity,
             uint32_t* pair_offsets) {
     __shared__ uint64_t s[1024];
     const int tid = threadIdx.x;
-    uint64_t carry = 0;
+    uint64_t carry = 0, pairs = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
         const int64_t i = b0 + tid;
         const uint64_t v = i < nb ? block_sums[i] : 0ull;
+        pairs += i < nb ? block_sums[nb + i] : 0ull;
         s[tid] = v;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
@@ -731,10 +756,12 @@ k_scan_sums(uint64_t* __restrict__ block_sums, int64_t nb, uint32_t* header, int
         carry += s[1023];
         __syncthreads();
     }
+    const uint64_t P = block_sum_u64(pairs, s);
     if (tid == 0) {
-        header[kHdrPairs] = (uint32_t)(carry < 0xFFFFFFFFull ? carry : 0xFFFFFFFFull);
-        pair_offsets[header[kHdrVisible]] = header[kHdrPairs];
-        if (carry > (uint64_t)capacity) atomicOr(&header[kHdrStatus], SGS_STATUS_CAPACITY);
+        header[kHdrEntries] = (uint32_t)(carry < 0xFFFFFFFFull ? carry : 0xFFFFFFFFull);
+        header[kHdrPairs] = (uint32_t)(P < 0xFFFFFFFFull ? P : 0xFFFFFFFFull);
+        pair_offsets[header[kHdrVisible]] = header[kHdrEntries];
+        if (P > (uint64_t)capacity) atomicOr(&header[kHdrStatus], SGS_STATUS_CAPACITY);
     }
 }
 
@@ -788,7 +815,7 @@ void launch_scan_pairs(const Workspace& ws, hipStream_t s) {
     if (nb <= 0) return;
     const uint32_t* nv = ws.header + kHdrVisible;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts,
-                       nv, n, ws.scan_sums);
+                       ws.sorted_rects, nv, n, ws.scan_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, ws.scan_sums, nb, ws.header,
                        ws.capacity, ws.pair_offsets);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.pair_counts,

@@ -1,16 +1,23 @@
-// Binning of (tile, depth) pairs: set-up, duplication, tile ranges.
+// Binning of (tile, depth) pairs: set-up, the first level's duplication,
+// tile ranges.
 //
 // The pairs must come out in ascending key order, key = (tile << 32) |
 // bits(float32 depth), ties by Gaussian index (the order a stable sort of
 // index-ordered emission gives).  Instead of a radix sort over the whole
-// 64-bit key, the work is split in two stable radix sorts that give the
-// same order:
+// 64-bit key, three stable steps give the same order:
 //   1. the (camera, Gaussian) items are sorted by their 32-bit depth key
 //      (four 8-bit passes over n_items, values = item index);
-//   2. pairs are emitted item by item in that order (each item's tiles
-//      row-major) and stably partitioned by tile id (ceil(bits/8) passes).
-// A stable partition of a depth-ordered sequence is ordered by (tile,
-// depth, item).  The radix passes live in radix.hip.
+//   2. (strip, item) entries are emitted item by item in that order, one
+//      per tile row and strip column (a strip: at most kStripTiles
+//      consecutive tiles of a row) of the item's tile rectangle, and stably
+//      partitioned by strip id (ceil(bits/8) radix passes);
+//   3. each strip's entries, still in depth order, are expanded into the
+//      pairs of the strip's tiles and written to their final positions
+//      (bin.hip).
+// Strips are numbered row-major within a camera, like the tiles, so tile
+// order is strip order, then column within the strip.  A stable partition
+// of a depth-ordered sequence is ordered by (tile, depth, item).  The radix
+// passes live in radix.hip.
 #include "common.hpp"
 #include "pairs.hpp"
 
@@ -34,20 +41,23 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
 }
 
-// The start of a forward in one launch: every block clears tile ranges;
-// block 0 clears the header, then its thread 0 builds the camera table
-// (after the clear, so a camera error bit survives it).
+// The start of a forward in one launch: every block clears tile and strip
+// ranges; block 0 clears the header, then its thread 0 builds the camera
+// table (after the clear, so a camera error bit survives it).
 __global__ void __launch_bounds__(256)
 k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, int tw, int th,
         float guard) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ws.n_tiles;
          i += (int64_t)gridDim.x * blockDim.x)
         ws.ranges[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ws.n_strips;
+         i += (int64_t)gridDim.x * blockDim.x)
+        ws.strip_ranges[i] = 0u;
     if (blockIdx.x != 0) return;   // uniform
     if (threadIdx.x < kHdrWords) ws.header[threadIdx.x] = 0u;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    int64_t tiles = 0, pix = 0;
+    int64_t tiles = 0, pix = 0, strips = 0;
     bool ok = true;
     for (int c = 0; c < n_cams; ++c) {
         CamTable t;
@@ -61,37 +71,38 @@ k_setup(Workspace ws, const sgs_camera* __restrict__ cams, int n_cams, int tw, i
         t.GX = ok ? (t.W + tw - 1) / tw : 0;
         t.GY = ok ? (t.H + th - 1) / th : 0;
         t.tile_base = (int32_t)tiles;
-        t.pad = 0;
+        t.strip_base = (int32_t)strips;
         t.pix_base = pix;
         t.limx = (double)guard * ((0.5 * t.W) / (double)cams[c].fx);
         t.limy = (double)guard * ((0.5 * t.H) / (double)cams[c].fy);
         ws.cams[c] = t;
         tiles += (int64_t)t.GX * t.GY;
+        strips += (int64_t)t.GY * ((t.GX + kStripTiles - 1) >> kStripShift);
         pix += (int64_t)t.W * t.H;
     }
     // the device cameras must be valid and describe the sizes the host planned for
-    if (!ok || pix != ws.n_pixels || tiles != ws.n_tiles)
+    if (!ok || pix != ws.n_pixels || tiles != ws.n_tiles || strips != ws.n_strips)
         atomicOr(&ws.header[kHdrStatus], SGS_STATUS_CAMERAS);
 }
 
 void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, int tile_w, int tile_h,
                   float guard, hipStream_t s) {
-    int64_t blocks = (2 * ws.n_tiles + 255) / 256;
+    const int64_t most = ws.n_tiles > ws.n_strips ? ws.n_tiles : ws.n_strips;
+    int64_t blocks = (2 * most + 255) / 256;
     blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
     hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(256), 0, s, ws, dev_cams, n_cams, tile_w,
                        tile_h, guard);
 }
 
 // --------------------------------------------------------------------------
-// duplicate (counting): one block per 2048-pair chunk, eight consecutive
-// pairs per thread (balanced: pairs, not Gaussians, are split between
-// threads).  It generates every pair and counts the low 8 bits of its tile
-// id: chunk c's counts go to counts[d * 2 * pair_parts + c] (two chunks per
-// radix partition), the first tile pass's digit histogram; chunks past the
-// pair count get zero rows.  The pairs themselves are generated again by
-// that pass, which scatters them directly (nothing else is written here).
-// (Counting row segments of each item's rectangle instead of single pairs
-// does less work but keeps one thread per item busy, and measured slower.)
+// duplicate (counting): one block per 2048-entry chunk, eight consecutive
+// entries per thread (balanced: entries, not Gaussians, are split between
+// threads).  It generates every (strip, item) entry and counts the low 8
+// bits of its strip id: chunk c's counts go to counts[d * 2 * pair_parts +
+// c] (two chunks per radix partition), the first strip pass's digit
+// histogram; chunks past the entry count get zero rows.  The entries
+// themselves are generated again by that pass, which scatters them
+// directly (nothing else is written here).
 // --------------------------------------------------------------------------
 
 static_assert(2 * kDupChunk == kSortTile, "two duplicate chunks per radix partition");
@@ -106,7 +117,7 @@ k_duplicate(Workspace ws, int64_t n) {
     __shared__ uint32_t s_hist[kRadix];
     const ChunkItems ci = {s_off, s_origin, s_wgx, s_item};
     const int tid = threadIdx.x;
-    const uint32_t P = ws.header[kHdrPairs];
+    const uint32_t P = ws.header[kHdrEntries];
     const int64_t Pc = (int64_t)P < ws.capacity ? (int64_t)P : ws.capacity;
     const uint32_t nn = (uint32_t)n;
     const int64_t n_vis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
@@ -125,7 +136,7 @@ k_duplicate(Workspace ws, int64_t n) {
             continue;   // uniform
         }
         __syncthreads();
-        // thread t walks the kDupRun consecutive pairs from p0 + kDupRun t
+        // thread t walks the kDupRun consecutive entries from p0 + kDupRun t
         const int64_t q0 = p0 + (int64_t)tid * kDupRun;
         if (q0 < p1) {
             uint32_t tl[kDupRun], vl[kDupRun];
@@ -138,7 +149,7 @@ k_duplicate(Workspace ws, int64_t n) {
         __syncthreads();
         ws.counts[tid * row + chunk] = s_hist[tid];
     }
-    // zero rows for the chunks past the pair count
+    // zero rows for the chunks past the entry count
     for (int64_t chunk = n_chunks + blockIdx.x; chunk < row; chunk += gridDim.x)
         ws.counts[tid * row + chunk] = 0;
 }
@@ -178,17 +189,18 @@ void launch_tile_order(const Workspace& ws, int64_t parts, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// sorted 64-bit keys for inspection
+// sorted 64-bit keys for inspection: positions outside every tile range keep
+// all bits set; block t writes the keys of tile t's range
 // --------------------------------------------------------------------------
 
 __global__ void k_read_keys(Workspace ws, int64_t count, uint64_t* keys) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t item = ws.pair_values[i];
-        const uint32_t dk = item < (uint64_t)ws.n_items ? ws.depth_keys[item] : 0xFFFFFFFFu;
-        const uint32_t t = ws.key16 ? (uint32_t)reinterpret_cast<const uint16_t*>(ws.pair_tiles)[i]
-                                    : ws.pair_tiles[i];
-        keys[i] = ((uint64_t)t << 32) | dk;
+    for (int64_t t = blockIdx.x; t < ws.n_tiles; t += gridDim.x) {
+        const uint32_t a = ws.ranges[2 * t], b = ws.ranges[2 * t + 1];
+        for (int64_t i = (int64_t)a + threadIdx.x; i < (int64_t)b && i < count; i += blockDim.x) {
+            const uint32_t item = ws.pair_values[i];
+            const uint32_t dk = item < (uint64_t)ws.n_items ? ws.depth_keys[item] : 0xFFFFFFFFu;
+            keys[i] = ((uint64_t)t << 32) | dk;
+        }
     }
 }
 
@@ -196,7 +208,11 @@ void launch_read_keys(const Workspace& ws, int64_t count, uint64_t* keys, hipStr
     if (count <= 0) return;
     int64_t blocks = (count + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_read_keys, dim3((unsigned)blocks), dim3(256), 0, s, ws, count, keys);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(keys), 0xFFFFFFFFu, 2 * count);
+    if (ws.n_tiles <= 0) return;
+    const int64_t tb = ws.n_tiles < 65536 ? ws.n_tiles : 65536;
+    hipLaunchKernelGGL(k_read_keys, dim3((unsigned)tb), dim3(256), 0, s, ws, count, keys);
 }
 
 }  // namespace sgs

@@ -321,6 +321,14 @@ class Rasterizer:
     def records(self) -> torch.Tensor:
         return self._view(self.layout.records, 16 * self.layout.n_items, torch.float32).view(-1, 16)
 
+    def n_strips(self) -> int:
+        return int(self.layout.n_strips)
+
+    def header(self):
+        """The 16 header words: status bits, pairs, visible items, the two
+        tile-queue counters, first-level entries, second-level chunks."""
+        return self._view(self.layout.header, 16, torch.int32)
+
     def depth_keys(self):
         return self._view(self.layout.depth_keys, self.layout.n_items, torch.int32)
 

@@ -3,7 +3,7 @@
 The roofline fractions the benchmark reports are only as good as these
 per-stage byte counts; each is checked against the traffic of the passes as
 they are built (one 3M-Gaussian frame: 646,587 visible items, 29.6M pairs,
-6,700 tiles).
+6,700 tiles in 134 row strips holding about 4M (strip, item) entries).
 """
 import math
 
@@ -12,6 +12,7 @@ import numpy as np
 import bench
 
 N, NVIS, P, TILES = 3_000_000, 646_587, 29_641_109, 6_700
+STRIPS, E = 134, 4_000_000
 FPG_SG = 51             # 11 geometry floats + SH1 (12) + 4 lobes x 7
 GEOM = 11
 
@@ -23,7 +24,7 @@ def test_geometry_floats():
 def test_preprocess_bytes():
     fc = FPG_SG - GEOM
     want = N * 4 * GEOM + NVIS * 4 * fc + N * 12 + NVIS * 64
-    assert bench.stage_bytes("fwd.preprocess", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == want
+    assert bench.stage_bytes("fwd.preprocess", N, N, NVIS, NVIS, P, TILES, FPG_SG, STRIPS, E, 0) == want
     # every parameter counted: the full record of every Gaussian
     assert bench.stage_bytes_all_params("fwd.preprocess", N, N, NVIS, FPG_SG) == \
         N * 4 * FPG_SG + 4 * N + 64 * NVIS
@@ -37,25 +38,30 @@ def test_depth_sort_bytes_follow_the_passes():
     # last: keys read, (key, item) and each item's rectangle read, then
     # item, pair count and rectangle written
     last = 4 * NVIS + 8 * NVIS + 8 * NVIS + 4 * NVIS + 4 * NVIS + 8 * NVIS
-    assert bench.stage_bytes("fwd.depth_sort", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == \
+    assert bench.stage_bytes("fwd.depth_sort", N, N, NVIS, NVIS, P, TILES, FPG_SG, STRIPS, E, 0) == \
         p0 + mid + last
 
 
 def test_scan_duplicate_and_tile_sort_bytes():
-    assert bench.stage_bytes("fwd.pair_scan", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == 12 * NVIS
-    assert bench.stage_bytes("fwd.duplicate", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == 16 * NVIS
-    # u16 tile keys (6,700 tiles): first pass writes (key, value) = 6 B per
-    # pair, the second reads keys (2), then reads and writes 6 B per pair
-    want = 16 * NVIS + 6 * P + (2 + 12) * P
-    assert bench.stage_bytes("fwd.tile_sort", N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) == want
-    # u32 keys beyond 65,536 tiles, three passes
-    want32 = 16 * NVIS + 8 * P + 2 * (4 + 16) * P
-    assert bench.stage_bytes("fwd.tile_sort", N, N, NVIS, NVIS, P, 100_000, FPG_SG, 3, 0) == want32
+    # entry counts read twice, each item's rectangle once, offsets written
+    assert bench.stage_bytes("fwd.pair_scan", N, N, NVIS, NVIS, P, TILES, FPG_SG, STRIPS, E, 0) == 20 * NVIS
+    assert bench.stage_bytes("fwd.duplicate", N, N, NVIS, NVIS, P, TILES, FPG_SG, STRIPS, E, 0) == 16 * NVIS
+    # 134 strips (one 8-bit pass, u16 strip keys): the pass reads the items
+    # and writes (strip, position) = 6 B per entry; the count reads position
+    # and rectangle (12 B), the scatter position, rectangle and item (16 B)
+    # per entry, and every pair is written once (4 B)
+    want = 16 * NVIS + 6 * E + 12 * E + 16 * E + 4 * P
+    assert bench.stage_bytes("fwd.tile_sort", N, N, NVIS, NVIS, P, TILES, FPG_SG, STRIPS, E, 0) == want
+    # u32 strip keys beyond 65,536 strips and three passes: each later pass
+    # reads the keys, then reads and writes (key, position)
+    want32 = 16 * NVIS + 8 * E + 2 * (4 + 16) * E + 12 * E + 16 * E + 4 * P
+    assert bench.stage_bytes("fwd.tile_sort", N, N, NVIS, NVIS, P, 10 ** 6, FPG_SG, 100_000, E, 0) \
+        == want32
 
 
 def test_blends_have_no_byte_bound():
     for st in ("fwd.blend", "bwd.blend", "fwd.tile_order"):
-        assert bench.stage_bytes(st, N, N, NVIS, NVIS, P, TILES, FPG_SG, 2, 0) is None
+        assert bench.stage_bytes(st, N, N, NVIS, NVIS, P, TILES, FPG_SG, STRIPS, E, 0) is None
 
 
 def test_standard_binning_bytes():
