@@ -9,24 +9,26 @@
 // the entries covering it, in entry order, so writing them in that order
 // gives the order of a stable sort on (tile << 32 | depth) keys.
 //
-// Each strip's entries are cut in chunks of kBinChunk:
+// Each strip's entries are cut in chunks of kBinChunk, each of kBinSubs
+// sub-chunks of kBinSub:
 //   k_bin_chunks   one block: the chunk table (per strip its first chunk and
 //                  chunk count, per chunk its entry range and the strip's
 //                  first tile, width and first column)
-//   k_bin_count    one wave per chunk: how many of the chunk's entries cover
+//   k_bin_count    one wave per sub-chunk: how many of its entries cover
 //                  each tile of the strip (difference array over the tiles)
 //   k_bin_strips   per strip: for each tile, the counts of the strip's
-//                  earlier chunks (exclusive sums over chunks), and each
-//                  tile's total
+//                  earlier sub-chunks (exclusive sums), and each tile's total
 //   k_bin_tiles    one block: exclusive scan of the tile totals over all
 //                  tiles -> first position of each tile, and the ranges
-//   k_bin_scatter  one wave per chunk, lane t holding tile t of the strip:
-//                  for 64 entries at a time, lane t forms the mask of the
-//                  entries covering its tile and appends them, in order, to
-//                  its tile's run, staged in LDS per tile; the staged pairs
-//                  are then stored with consecutive lanes on consecutive
-//                  positions.  A chunk with more pairs than the LDS stage
-//                  stores each pair directly.
+//   k_bin_scatter  one workgroup per chunk, wave w taking sub-chunk w, lane
+//                  t holding tile t of the strip: for 64 entries at a time,
+//                  lane t forms the mask of the entries covering its tile
+//                  and appends them, in order, to its tile's run, staged in
+//                  LDS per tile (the sub-chunk counts place each wave's part
+//                  of the run); the staged pairs are then stored with
+//                  consecutive threads on consecutive positions.  A chunk
+//                  with more pairs than the LDS stage goes through it in
+//                  several windows.
 // Positions at or past the capacity are never written; the ranges are
 // clamped to the capacity (the scan has then set SGS_STATUS_CAPACITY).
 #include "common.hpp"
@@ -34,8 +36,8 @@
 namespace sgs {
 
 static_assert(kStripTiles == 64, "one wave lane per tile of a strip");
-static_assert(kBinChunk % 64 == 0 && kBinChunk / 64 <= 8, "whole entry batches per lane");
-constexpr int kBinBatches = kBinChunk / 64;   // entries per lane of a chunk
+static_assert(kBinSub % 64 == 0 && kBinSub / 64 <= 8, "whole entry batches per lane");
+constexpr int kBinBatches = kBinSub / 64;   // entries per lane of a sub-chunk
 
 // Inclusive scans over the 64 lanes of a wave with DPP moves: shifts by 1,
 // 2, 4 and 8 lanes within each row of 16, then lane 15 of rows 0 and 2 into
@@ -178,34 +180,40 @@ __global__ void __launch_bounds__(64 * kBinWaves)
 k_bin_count(Workspace ws, const uint32_t* __restrict__ entries) {
     __shared__ int s_diff[kBinWaves][kStripTiles + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t nc = ws.header[kHdrChunks];
+    const int64_t nsub = (int64_t)ws.header[kHdrChunks] * kBinSubs;
     const int64_t nvis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
     for (int64_t round = 0;; ++round) {
-        if (round * gridDim.x * kBinWaves >= nc) break;   // uniform over the block
-        const int64_t c = bin_chunk_of(round, nc, kBinWaves, wave);
-        if (c >= nc) continue;   // uniform over the wave
-        const uint4 ci = ws.chunk_info[c];
+        if (round * gridDim.x * kBinWaves >= nsub) break;   // uniform over the block
+        const int64_t r = bin_chunk_of(round, nsub, kBinWaves, wave);
+        if (r >= nsub) continue;   // uniform over the wave
+        const uint4 ci = ws.chunk_info[r / kBinSubs];
         const int sw = (int)(ci.w & 0xFFFF), x0 = (int)(ci.w >> 16);
+        const uint32_t e0 = ci.x + (uint32_t)(r % kBinSubs) * kBinSub;   // this sub-chunk's entries
         s_diff[wave][lane] = 0;
         if (lane == 0) s_diff[wave][kStripTiles] = 0;
-        uint32_t iv[kBinBatches];
+        // loads without branches (clamped indices, validity applied after),
+        // so that they are in flight together
+        const uint32_t last = ci.y > ci.x ? ci.y - 1 : 0u;
+        uint32_t slot[kBinBatches];
 #pragma unroll
         for (int k = 0; k < kBinBatches; ++k) {
-            const uint32_t e = ci.x + (uint32_t)(k * 64 + lane);
-            uint32_t slot = e < ci.y ? entries[e] : 0xFFFFFFFFu;
-            iv[k] = slot;
+            const uint32_t e = e0 + (uint32_t)(k * 64 + lane);
+            slot[k] = entries[e < ci.y ? e : last];
         }
+        bool ok[kBinBatches];
+        uint64_t rect[kBinBatches];
 #pragma unroll
         for (int k = 0; k < kBinBatches; ++k) {
-            const uint32_t slot = iv[k];
-            iv[k] = slot < (uint64_t)nvis ? entry_interval(ws.sorted_rects[slot], x0, sw) : 0xFFFFu;
+            ok[k] = e0 + (uint32_t)(k * 64 + lane) < ci.y && slot[k] < (uint64_t)nvis;
+            rect[k] = ws.sorted_rects[ok[k] ? slot[k] : 0u];
         }
         __builtin_amdgcn_wave_barrier();
         // a wave's LDS operations complete in order: the clears land before
         // the additions, the additions before the reads
 #pragma unroll
         for (int k = 0; k < kBinBatches; ++k) {
-            const int a = (int)(iv[k] & 0xFFFF), w = (int)(iv[k] >> 16);
+            const uint32_t iv = ok[k] ? entry_interval(rect[k], x0, sw) : 0xFFFFu;
+            const int a = (int)(iv & 0xFFFF), w = (int)(iv >> 16);
             if (w > 0) {
                 atomicAdd(&s_diff[wave][a], 1);
                 atomicAdd(&s_diff[wave][a + w], -1);
@@ -213,7 +221,7 @@ k_bin_count(Workspace ws, const uint32_t* __restrict__ entries) {
         }
         __builtin_amdgcn_wave_barrier();
         const uint32_t cnt = wave_incl_scan((uint32_t)s_diff[wave][lane]);
-        ws.chunk_counts[c * kStripTiles + lane] = (uint16_t)cnt;   // 0 past the strip's width
+        ws.chunk_counts[r * kStripTiles + lane] = (uint16_t)cnt;   // 0 past the strip's width
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -229,7 +237,7 @@ __global__ void __launch_bounds__(1024) k_bin_strips(Workspace ws) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t s = blockIdx.x; s < ws.n_strips; s += gridDim.x) {
         const uint4 si = ws.strip_info[s];
-        const int64_t cb = si.x, nch = si.y;
+        const int64_t cb = (int64_t)si.x * kBinSubs, nch = (int64_t)si.y * kBinSubs;   // sub-chunks
         const int sw = (int)(si.w & 0xFFFF);
         const int64_t seg = (nch + WAVES - 1) / WAVES;
         const int64_t k0 = (int64_t)wave * seg < nch ? (int64_t)wave * seg : nch;
@@ -307,125 +315,153 @@ __global__ void __launch_bounds__(1024) k_bin_tiles(Workspace ws) {
 // per chunk: the pairs, staged by tile, then stored
 // ---------------------------------------------------------------------------
 
-static_assert(kBinChunk <= 256 && kStripTiles <= 256, "staged tile and entry index are one byte each");
 static_assert((kBinStage & (kBinStage - 1)) == 0, "the stage index is masked");
 
-// One wave per chunk.  For each batch of 64 entries (lane k holds entry k),
-// an entry covering tiles a .. a + w - 1 sets its bit k in the start mark of
-// tile a and the end mark of tile a + w; lane t (tile t) then ORs the marks
-// of tiles 0 .. t: the entries covering t are those started and not ended,
-// in entry order = bit order.  Lane t walks its set bits and stages their
-// entry indices at its tile's running position.
-__global__ void __launch_bounds__(64)
+// One workgroup per chunk, wave w taking sub-chunk w.  For each batch of 64
+// entries (lane k holds entry k), an entry covering tiles a .. a + w - 1
+// sets its bit k in the start mark of tile a and the end mark of tile a + w;
+// lane t (tile t) then ORs the marks of tiles 0 .. t: the entries covering t
+// are those started and not ended, in entry order = bit order.  Lane t walks
+// its set bits and stages their indices at its tile's running position.
+__global__ void __launch_bounds__(64 * kBinSubs)
 k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* __restrict__ chunk_info) {
-    __shared__ uint32_t s_item[kBinChunk];          // items of the chunk's entries
-    __shared__ uint16_t s_stage[kBinStage];         // tile << 8 | entry index, by tile
-    __shared__ uint64_t s_start[kStripTiles];       // entries starting at each tile
-    __shared__ uint64_t s_end[kStripTiles + 1];     // entries ending before each tile
-    __shared__ int64_t s_gb[kStripTiles];           // position of staged index 0 of each tile's run
-    const int lane = threadIdx.x;
+    static_assert(kStripTiles * kBinChunk <= 65536, "staged tile and entry index fit 16 bits");
+    __shared__ uint32_t s_item[kBinChunk];                  // items of the chunk's entries
+    __shared__ uint16_t s_stage[kBinStage];                 // tile * kBinChunk + entry, by tile
+    __shared__ uint64_t s_start[kBinSubs][kStripTiles];     // entries starting at each tile
+    __shared__ uint64_t s_end[kBinSubs][kStripTiles + 1];   // entries ending before each tile
+    __shared__ int64_t s_gb[kStripTiles];                   // position of staged index 0 of each tile's run
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t nc = ws.header[kHdrChunks];
     const int64_t nvis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
     const int64_t cap = ws.capacity;
-    s_start[lane] = 0ull;
-    s_end[lane] = 0ull;
-    // the chunk's table entry and entries (lane l holds entries l, l + 64,
-    // ...), loaded one chunk ahead: the next chunk's arrive while this one
-    // computes
-    auto load_entries = [&](int64_t cc, uint4& cio, uint32_t (&sl)[kBinBatches]) {
-        cio = chunk_info[cc];
-#pragma unroll
-        for (int k = 0; k < kBinBatches; ++k) {
-            const uint32_t e = cio.x + (uint32_t)(k * 64 + lane);
-            sl[k] = e < cio.y ? entries[e] : 0xFFFFFFFFu;
-        }
-    };
-    int64_t round = 0;
-    int64_t c = bin_chunk_of(0, nc, 1, 0);
-    uint4 ci = make_uint4(0u, 0u, 0u, 0u);
-    uint32_t slot[kBinBatches];
-    if (c < nc) load_entries(c, ci, slot);
-    while (c < nc) {   // uniform
+    s_start[wave][lane] = 0ull;
+    s_end[wave][lane] = 0ull;
+    for (int64_t round = 0;; ++round) {
+        const int64_t c = bin_chunk_of(round, nc, 1, 0);
+        if (c >= nc) break;   // uniform over the block
+        const uint4 ci = chunk_info[c];
         const int sw = (int)(ci.w & 0xFFFF), x0 = (int)(ci.w >> 16);
-        // this lane's tile count, its earlier chunks' count, the tile's
-        // start, and the entries' items and intervals
-        const uint32_t raw = ws.chunk_counts[c * kStripTiles + lane];
-        const uint32_t off = ws.chunk_offsets[c * kStripTiles + lane];
-        const bool live = lane < sw && (int64_t)ci.z + lane < ws.n_tiles;
-        const uint32_t ts = live ? ws.tile_start[ci.z + lane] : 0u;
-        uint32_t item[kBinBatches], iv[kBinBatches];
+        const uint32_t e0 = ci.x + (uint32_t)wave * kBinSub;   // this wave's sub-chunk
+        // loads without branches (clamped indices, validity applied after),
+        // so that they are in flight together: this wave's entries, every
+        // sub-chunk's count of this lane's tile, the chunk's earlier count
+        // and the tile's start
+        const uint32_t last = ci.y > ci.x ? ci.y - 1 : 0u;
+        uint32_t slot[kBinBatches];
 #pragma unroll
         for (int k = 0; k < kBinBatches; ++k) {
-            const bool ok = slot[k] < (uint64_t)nvis;
-            item[k] = ok ? ws.sorted_items[slot[k]] : 0u;
-            iv[k] = ok ? entry_interval(ws.sorted_rects[slot[k]], x0, sw) : 0xFFFFu;
+            const uint32_t e = e0 + (uint32_t)(k * 64 + lane);
+            slot[k] = entries[e < ci.y ? e : last];
         }
-        const int64_t cn = bin_chunk_of(round + 1, nc, 1, 0);
-        uint4 ci_n = ci;
-        uint32_t slot_n[kBinBatches];
-        if (cn < nc) load_entries(cn, ci_n, slot_n);
+        uint32_t raw[kBinSubs];
 #pragma unroll
-        for (int k = 0; k < kBinBatches; ++k) s_item[k * 64 + lane] = item[k];
-        const uint32_t cnt = live ? raw : 0u;
+        for (int q = 0; q < kBinSubs; ++q) raw[q] = ws.chunk_counts[(c * kBinSubs + q) * kStripTiles + lane];
+        const uint32_t off = ws.chunk_offsets[c * kBinSubs * kStripTiles + lane];
+        const bool live = lane < sw && (int64_t)ci.z + lane < ws.n_tiles;
+        const uint32_t ts_l = ws.tile_start[live ? ci.z + lane : 0u];
+        bool ok[kBinBatches];
+        uint32_t item[kBinBatches];
+        uint64_t rect[kBinBatches];
+#pragma unroll
+        for (int k = 0; k < kBinBatches; ++k) {
+            ok[k] = e0 + (uint32_t)(k * 64 + lane) < ci.y && slot[k] < (uint64_t)nvis;
+            const uint32_t sl = ok[k] ? slot[k] : 0u;
+            item[k] = ws.sorted_items[sl];
+            rect[k] = ws.sorted_rects[sl];
+        }
+        // this lane's tile: its pairs in the chunk, its first staged index,
+        // this wave's part of its run, and where the run goes
+        uint32_t cnt = 0, before = 0;
+#pragma unroll
+        for (int q = 0; q < kBinSubs; ++q) {
+            cnt += raw[q];
+            before += q < wave ? raw[q] : 0u;
+        }
+        if (!live) cnt = before = 0;
         const uint32_t incl = wave_incl_scan(cnt);
         const uint32_t lb = incl - cnt;
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-        const int64_t gb = (int64_t)ts + off - lb;   // position = gb + staged index
-        const bool staged = total <= (uint32_t)kBinStage;
-        s_gb[lane] = gb;
-        uint32_t pos = lb;
-        const int ne = (int)(ci.y - ci.x);
+        const int64_t gb = (int64_t)(live ? ts_l : 0u) + off - lb;   // position = gb + staged index
+        if (wave == 0) s_gb[lane] = gb;
+        // the masks of this wave's two batches, kept for the stage windows
+        uint64_t msk[kBinBatches];
 #pragma unroll
         for (int k = 0; k < kBinBatches; ++k) {
-            if (k * 64 >= ne) break;   // uniform
-            const uint32_t a = iv[k] & 0xFFFFu, w = iv[k] >> 16;
+            s_item[wave * kBinSub + k * 64 + lane] = ok[k] ? item[k] : 0u;
+            const uint32_t iv = ok[k] ? entry_interval(rect[k], x0, sw) : 0xFFFFu;
+            const uint32_t a = iv & 0xFFFFu, w = iv >> 16;
             if (w > 0) {
-                atomicOr(&s_start[a], 1ull << lane);
-                atomicOr(&s_end[a + w], 1ull << lane);
+                atomicOr(&s_start[wave][a], 1ull << lane);
+                atomicOr(&s_end[wave][a + w], 1ull << lane);
             }
             __builtin_amdgcn_wave_barrier();
             // a wave's LDS operations complete in order: the marks are set
             // before they are read, and read before they are cleared
-            const uint64_t st = s_start[lane], en = s_end[lane];
-            s_start[lane] = 0ull;
-            s_end[lane] = 0ull;
-            uint64_t m = wave_prefix_or(st) & ~wave_prefix_or(en);
-            if (!live) m = 0ull;
-            if (staged) {
-                // pos stays below the chunk's total; the mask keeps any
-                // count that disagreed with the walk inside the stage
-                const uint32_t tag = ((uint32_t)lane << 8) | (uint32_t)(k * 64);
-                while (m) {
-                    const int j = __builtin_ctzll(m);
-                    m &= m - 1ull;
-                    s_stage[pos & (kBinStage - 1)] = (uint16_t)(tag | (uint32_t)j);
-                    ++pos;
-                }
-            } else {
-                while (m) {
-                    const int j = __builtin_ctzll(m);
-                    m &= m - 1ull;
-                    const int64_t g = gb + pos;
-                    if (g >= 0 && g < cap) ws.pair_values[g] = s_item[k * 64 + j];
-                    ++pos;
-                }
-            }
+            const uint64_t st = s_start[wave][lane], en = s_end[wave][lane];
+            s_start[wave][lane] = 0ull;
+            s_end[wave][lane] = 0ull;
+            const uint64_t m = wave_prefix_or(st) & ~wave_prefix_or(en);
+            msk[k] = live ? m : 0ull;
             __builtin_amdgcn_wave_barrier();
         }
-        if (staged) {
-            // one wave: its LDS writes above complete before these reads
-            for (uint32_t i = lane; i < total; i += 64) {
-                const uint32_t v = s_stage[i];   // total <= kBinStage here
-                const int64_t g = s_gb[v >> 8] + i;
-                if (g >= 0 && g < cap) ws.pair_values[g] = s_item[v & 0xFFu];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        c = cn;
-        ci = ci_n;
+        // the chunk's pairs go through the stage in windows of kBinStage
+        // staged indices (one window unless the chunk holds more pairs)
+        if (total <= (uint32_t)kBinStage) {
+            // one window: each lane walks its set bits, 32 at a time
+            uint32_t p = lb + before;
 #pragma unroll
-        for (int k = 0; k < kBinBatches; ++k) slot[k] = slot_n[k];
-        ++round;
+            for (int k = 0; k < kBinBatches; ++k) {
+                const uint32_t tag = (uint32_t)lane * kBinChunk + (uint32_t)(wave * kBinSub + k * 64);
+                uint32_t lo = (uint32_t)msk[k], hi = (uint32_t)(msk[k] >> 32);
+                // (the mask keeps a count that disagreed with the walk
+                // inside the stage)
+                while (lo) {
+                    s_stage[(p++) & (kBinStage - 1)] = (uint16_t)(tag + (uint32_t)__builtin_ctz(lo));
+                    lo &= lo - 1u;
+                }
+                while (hi) {
+                    s_stage[(p++) & (kBinStage - 1)] = (uint16_t)(tag + 32u + (uint32_t)__builtin_ctz(hi));
+                    hi &= hi - 1u;
+                }
+            }
+            __syncthreads();   // the stage, the items and s_gb are complete
+            for (uint32_t i = tid; i < total; i += 64 * kBinSubs) {
+                const uint32_t v = s_stage[i];
+                const int64_t g = s_gb[v / kBinChunk] + i;
+                if (g >= 0 && g < cap) ws.pair_values[g] = s_item[v % kBinChunk];
+            }
+            __syncthreads();   // stored before the next chunk stages
+            continue;
+        }
+        for (uint32_t w0 = 0; w0 < total; w0 += kBinStage) {
+            const uint32_t w1 = w0 + kBinStage;
+            uint32_t pos = lb + before;
+#pragma unroll
+            for (int k = 0; k < kBinBatches; ++k) {
+                uint64_t m = msk[k];
+                const uint32_t n = (uint32_t)__popcll(m);
+                if (pos < w1 && pos + n > w0) {
+                    const uint32_t tag = (uint32_t)lane * kBinChunk + (uint32_t)(wave * kBinSub + k * 64);
+                    uint32_t p = pos;
+                    while (m) {
+                        const int j = __builtin_ctzll(m);
+                        m &= m - 1ull;
+                        if (p >= w0 && p < w1) s_stage[p - w0] = (uint16_t)(tag + (uint32_t)j);
+                        ++p;
+                    }
+                }
+                pos += n;
+            }
+            __syncthreads();   // the window, the items and s_gb are complete
+            const uint32_t nw = total - w0 < (uint32_t)kBinStage ? total - w0 : (uint32_t)kBinStage;
+            for (uint32_t i = tid; i < nw; i += 64 * kBinSubs) {
+                const uint32_t v = s_stage[i];
+                const int64_t g = s_gb[v / kBinChunk] + w0 + i;
+                if (g >= 0 && g < cap) ws.pair_values[g] = s_item[v % kBinChunk];
+            }
+            __syncthreads();   // the window is stored before the next one is staged
+        }
     }
 }
 
@@ -435,17 +471,17 @@ void launch_bin_tiles(const Workspace& ws, const uint32_t* entry_slots, hipStrea
     // persistent grids no larger than what stays resident (a block that
     // waits for a free slot would run its whole loop after the others)
     const int64_t cus = ws.cus > 0 ? ws.cus : 256;
-    const int64_t cblocks = (ws.chunk_cap + kBinWaves - 1) / kBinWaves;
-    const int64_t cmax = cus * 4;   // 16 waves per CU
+    const int64_t cblocks = (ws.chunk_cap * kBinSubs + kBinWaves - 1) / kBinWaves;
+    const int64_t cmax = cus * 8;   // 32 waves per CU
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)(cblocks < cmax ? cblocks : cmax)),
                        dim3(64 * kBinWaves), 0, s, ws, entry_slots);
     const int64_t sblocks = ws.n_strips < 1024 ? ws.n_strips : 1024;
     hipLaunchKernelGGL(k_bin_strips, dim3((unsigned)sblocks), dim3(1024), 0, s, ws);
     hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, s, ws);
-    const int64_t wmax = cus * 12;   // LDS holds 15 of these one-wave blocks per CU
+    const int64_t wmax = cus * 6;   // LDS holds 6 of these blocks per CU
     const int64_t wblocks = ws.chunk_cap < wmax ? ws.chunk_cap : wmax;
-    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)wblocks), dim3(64), 0, s, ws, entry_slots,
-                       ws.chunk_info);
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)wblocks), dim3(64 * kBinSubs), 0, s, ws,
+                       entry_slots, ws.chunk_info);
 }
 
 }  // namespace sgs

@@ -23,12 +23,15 @@ constexpr int kPersistentBlocks = 1024;              // grid of the persistent k
 constexpr int kDepthPasses = 4;                      // 32-bit depth keys
 // binning of pairs in two levels: items go to row strips of at most
 // kStripTiles tiles (one wave lane per tile), then each strip's entries to
-// its tiles in chunks of kBinChunk entries, one wave per chunk
+// its tiles in chunks of kBinChunk entries: one workgroup per chunk, one
+// wave per sub-chunk of kBinSub entries
 constexpr int kStripShift = 6;
 constexpr int kStripTiles = 1 << kStripShift;
 static_assert(kStripTiles == SGS_STRIP_TILES, "strip width of the ABI");
-constexpr int kBinChunk = 256;                       // entries per chunk (< 65536)
-constexpr int kBinStage = 4096;                      // pairs a chunk stages in LDS (a power of two)
+constexpr int kBinSub = 128;                         // entries per counted sub-chunk
+constexpr int kBinSubs = 4;                          // sub-chunks per chunk
+constexpr int kBinChunk = kBinSub * kBinSubs;        // entries per chunk
+constexpr int kBinStage = 8192;                      // pairs a chunk stages in LDS (a power of two)
 constexpr int kXcds = 8;                             // dies; blocks go to them round-robin
 
 // Renumbers block b of a grid whose first `active` blocks carry work so that
@@ -135,8 +138,8 @@ struct Workspace {
     uint32_t* strip_ranges;      // [start, end) of every strip's entries (first level)
     uint4* strip_info;           // per strip: first chunk, chunks, first tile, width | x0 << 16
     uint4* chunk_info;           // per chunk: first entry, end entry, first tile, width | x0 << 16
-    uint16_t* chunk_counts;      // per chunk: pairs of each of its strip's tiles
-    uint32_t* chunk_offsets;     // per chunk: pairs of the strip's earlier chunks, per tile
+    uint16_t* chunk_counts;      // per sub-chunk: pairs of each of its strip's tiles
+    uint32_t* chunk_offsets;     // per sub-chunk: pairs of the strip's earlier sub-chunks, per tile
     uint32_t* tile_count;        // pairs per tile
     uint32_t* tile_start;        // first pair position of each tile
     uint32_t* tile_keys;         // heavy-first sort key of every tile

@@ -213,8 +213,8 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     pl->tile_count = take((size_t)tiles * 4);
     pl->tile_start = take((size_t)tiles * 4);
     pl->chunk_info = take((size_t)pl->chunk_cap * 16);
-    pl->chunk_counts = take((size_t)pl->chunk_cap * sgs::kStripTiles * 2);
-    pl->chunk_offsets = take((size_t)pl->chunk_cap * sgs::kStripTiles * 4);
+    pl->chunk_counts = take((size_t)pl->chunk_cap * sgs::kBinSubs * sgs::kStripTiles * 2);
+    pl->chunk_offsets = take((size_t)pl->chunk_cap * sgs::kBinSubs * sgs::kStripTiles * 4);
     L.total_bytes = off;
     L.n_items = items;
     L.n_tiles = tiles;

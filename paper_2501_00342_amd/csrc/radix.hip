@@ -105,24 +105,30 @@ k_upsweep(const KeyT* __restrict__ keys, const uint32_t* count_ptr, int64_t coun
 constexpr int kScanRowThreads = 1024;
 constexpr int kScanRowItems = 16;
 
-// block d: exclusive scan of counts[d][0 .. parts) in place; totals[d] = row
-// sum (also added to *kept_out when given).  Each thread owns 16 consecutive
-// entries per round, read and written as four 16-byte words when the row is
-// 16-byte aligned, so a row of up to 16K partitions takes one round; wave
-// scans with lane shuffles, then a scan of the 16 wave totals.
+// block d: exclusive scan of counts[d][0 .. live) in place, where the row
+// holds `parts` entries of `per` items each and live covers the pass's
+// items (count_ptr / count_host); totals[d] = row sum (also added to
+// *kept_out when given).  Entries past live are neither read nor written.
+// Each thread owns 16 consecutive entries per round, read and written as
+// four 16-byte words when the row is 16-byte aligned, so a row of up to 16K
+// partitions takes one round; wave scans with lane shuffles, then a scan of
+// the 16 wave totals.
 __global__ void __launch_bounds__(kScanRowThreads)
 k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__ totals,
-            uint32_t* kept_out) {
+            uint32_t* kept_out, const uint32_t* count_ptr, int64_t count_host, int per) {
     constexpr int WAVES = kScanRowThreads / 64;
     constexpr int IT = kScanRowItems;
     __shared__ uint32_t s_w[WAVES];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t* row = counts + (int64_t)blockIdx.x * parts;
     const bool vec = (reinterpret_cast<uintptr_t>(row) & 15) == 0;
+    const int64_t items = pass_count(count_ptr, count_host);
+    const int64_t live_parts = (items + per - 1) / per;
+    const int64_t live = live_parts < parts ? live_parts : parts;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < parts; b0 += kScanRowThreads * IT) {
+    for (int64_t b0 = 0; b0 < live; b0 += kScanRowThreads * IT) {
         const int64_t i0 = b0 + (int64_t)tid * IT;
-        const bool whole = vec && i0 + IT <= parts;
+        const bool whole = vec && i0 + IT <= live;
         uint32_t v[IT], run = 0;
         if (whole) {
 #pragma unroll
@@ -132,7 +138,7 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < IT; ++k) v[k] = i0 + k < parts ? row[i0 + k] : 0u;
+            for (int k = 0; k < IT; ++k) v[k] = i0 + k < live ? row[i0 + k] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < IT; ++k) run += v[k];
@@ -169,7 +175,7 @@ k_scan_rows(uint32_t* __restrict__ counts, int64_t parts, uint32_t* __restrict__
         } else {
 #pragma unroll
             for (int k = 0; k < IT; ++k)
-                if (i0 + k < parts) row[i0 + k] = v[k];
+                if (i0 + k < live) row[i0 + k] = v[k];
         }
         carry += s_w[WAVES - 1];
         __syncthreads();
@@ -552,11 +558,15 @@ k_range_edges(const KeyT* __restrict__ keys, const uint32_t* __restrict__ counts
     __syncthreads();
     const uint32_t s_base = s_part[0] + s_part[1] + s_part[2] + s_part[3];
     const int64_t count = pass_count(count_ptr, count_host);
+    // the partitions holding the pass's items (the row scans leave the
+    // others untouched)
+    const int64_t lp = (count + kSortTile - 1) / kSortTile;
+    const int64_t live = lp < parts ? lp : parts;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p < parts) {
+    if (p < live) {
         const uint32_t off = counts[((int64_t)d * parts + p) * cstride];
         const uint32_t next =
-            p + 1 < parts ? counts[((int64_t)d * parts + p + 1) * cstride] : totals[d];
+            p + 1 < live ? counts[((int64_t)d * parts + p + 1) * cstride] : totals[d];
         const int64_t at = (int64_t)s_base + off;
         if (next > off && at > 0 && at < count) {
             const uint32_t a = keys[at - 1], b = keys[at];
@@ -602,7 +612,8 @@ static void radix_pass_t(const KeyT* keys_in, const uint32_t* vals_in, KeyT* key
                            counts, parts, drop_culled, bits);
     }
     hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kScanRowThreads), 0, s, counts,
-                       parts * cstride, totals, drop_culled ? kept_out : nullptr);
+                       parts * cstride, totals, drop_culled ? kept_out : nullptr, count_ptr,
+                       count_host, kSortTile / cstride);
     const dim3 g((unsigned)parts);
 #define SGS_DOWNSWEEP(NB)                                                                      \
     downsweep_t<KeyT, NB>(g, s, keys_in, vals_in, keys_out, vals_out, count_ptr, count_host,   \
@@ -656,7 +667,7 @@ static void dup_scatter_t(const Workspace& ws, int64_t n, KeyT* keys_out, uint32
     if (parts <= 0) return;
     const int bits = digit_bits < 1 ? 1 : (digit_bits > kRadixBits ? kRadixBits : digit_bits);
     hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kScanRowThreads), 0, s, ws.counts,
-                       parts * 2, ws.totals, nullptr);
+                       parts * 2, ws.totals, nullptr, ws.header + kHdrEntries, pair_capacity, kDupChunk);
     const dim3 g((unsigned)parts), b(kDownThreads);
 #define SGS_DUPSCAT(NB)                                                                        \
     hipLaunchKernelGGL((k_dup_scatter<KeyT, NB>), g, b, 0, s, ws, n, keys_out, vals_out,      \

@@ -100,7 +100,7 @@ void launch_setup(const Workspace& ws, const sgs_camera* dev_cams, int n_cams, i
 // threads).  It generates every (strip, item) entry and counts the low 8
 // bits of its strip id: chunk c's counts go to counts[d * 2 * pair_parts +
 // c] (two chunks per radix partition), the first strip pass's digit
-// histogram; chunks past the entry count get zero rows.  The entries
+// histogram; chunks past the entry count are left alone.  The entries
 // themselves are generated again by that pass, which scatters them
 // directly (nothing else is written here).
 // --------------------------------------------------------------------------
@@ -149,9 +149,7 @@ k_duplicate(Workspace ws, int64_t n) {
         __syncthreads();
         ws.counts[tid * row + chunk] = s_hist[tid];
     }
-    // zero rows for the chunks past the entry count
-    for (int64_t chunk = n_chunks + blockIdx.x; chunk < row; chunk += gridDim.x)
-        ws.counts[tid * row + chunk] = 0;
+    // (the row scans read only the chunks that hold entries)
 }
 
 void launch_duplicate_counts(const Workspace& ws, int64_t n, hipStream_t s) {
