@@ -332,3 +332,30 @@ def test_blend_work_counters_match_the_oracle_walk(tw, th, ppt):
     for name, g, w in zip(("visited", "evaluated", "blended"), got, want[:3]):
         assert abs(g - w) <= slack, (name, g, w, slack)
     assert want[2] > 0 and want[1] >= want[2]
+
+
+def test_binning_with_two_strip_passes_and_wide_rows():
+    """Binning through two strip passes (more than 256 strips: eight cameras
+    of 12 tile rows, each row of 130 8x8 tiles split into strips of 64, 64
+    and 2 tiles) gives the oracle's sorted keys, values and tile ranges bit
+    for bit, and every camera renders as it does alone."""
+    sc, _ = scenes.small_clustered(6000, 23, 96, 64)
+    cams = scenes.ring_cameras(8, radius=6.0, seed=11, sizes=((1040, 96),))
+    opts = scenes.Options(tile_w=8, tile_h=8)
+    rast, params, out = run_forward(sc, cams, opts)
+    assert rast.n_strips() == 8 * 12 * 3 > 256
+    pres = [F.preprocess(sc, c, opts) for c in cams]
+    keys, vals, ntiles = F.emit_pairs(pres)
+    keys, vals = F.sort_pairs(keys, vals)
+    ranges = F.tile_ranges(keys, ntiles)
+    bits, P = rast.status()
+    assert bits == 0 and P == keys.size
+    assert np.array_equal(rast.sorted_keys(P).cpu().numpy().view(np.uint64), keys)
+    assert np.array_equal(rast.pair_values(P).cpu().numpy().view(np.uint32).astype(np.uint64), vals)
+    rng = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(rng, ranges[:ntiles])
+    for k in (0, 5):
+        img, dep, T, n = camera_numpy(out, cams, k)
+        _, _, single_o = run_forward(sc, [cams[k]], opts)
+        simg, sdep, sT, sn = camera_numpy(single_o, [cams[k]])
+        assert np.array_equal(img, simg) and np.array_equal(n, sn) and np.array_equal(T, sT)
