@@ -215,8 +215,9 @@ typedef struct sgs_layout {
     size_t pair_values;     /* u32 per pair: item = camera * n + g, in blend order
                                (tile ascending, then depth key, then item) */
     size_t ranges;          /* u32[2] per global tile: [start, end), (0,0) if empty */
-    size_t grad2d;          /* f32[10][items]: d/d(u, v, Qa, Qb, Qc, opacity, r, g, b, z);
-                               row 9 only when depth or alpha had a gradient */
+    size_t grad2d;          /* per item a 64-byte record of f32: d/d(u, v, Qa, Qb, Qc,
+                               opacity, r, g, b, z) at floats 0-9 (z only when depth or
+                               alpha had a gradient), floats 10-15 unused */
     int64_t n_items;        /* n_cams * n */
     int64_t n_tiles;        /* total tiles over all cameras */
     int64_t n_pixels;       /* total pixels over all cameras */

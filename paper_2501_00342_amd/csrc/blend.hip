@@ -518,19 +518,20 @@ __device__ __forceinline__ void bwd_tile(const Workspace& ws, const sgs_camera* 
                 // the entry is the same in every lane: its address is scalar
                 const int64_t item =
                     __builtin_amdgcn_readfirstlane(__float_as_uint(e.c.w));
-                float* gi = G + item;
+                float* gi = G + item * kG2;
                 // lane 15 of row r adds channel ch (u, Qa, v, Qb for rows
                 // 0-3), lane 14 channel 4 + ch (Qc, r, sigma, g) and, in the
                 // rows with ch < NV - 8, lane 13 channel 8 + ch (b, z) -- NV
-                // lanes of one atomic instruction (channel order of grad2d:
-                // u, v, Qa, Qb, Qc, sigma, r, g, b, z)
+                // lanes of one atomic instruction, all on the item's 64-byte
+                // gradient record (channel order: u, v, Qa, Qb, Qc, sigma,
+                // r, g, b, z)
                 const int r = lane >> 4, sel = 15 - (lane & 15);
                 const int ch = 2 * (r & 1) + (r >> 1);
                 if (sel < 2 || (sel == 2 && ch < NV - 8)) {
                     const float c0 = r == 0 ? g_u : (r == 1 ? -0.5f * s3 : (r == 2 ? g_v : -s4));
                     const float c1 = r == 0 ? -0.5f * s5 : x[1];
                     const int chan = sel == 0 ? ch : (sel == 1 ? 4 + ch : 8 + ch);
-                    unsafeAtomicAdd(gi + chan * M, sel == 0 ? c0 : (sel == 1 ? c1 : x[2]));
+                    unsafeAtomicAdd(gi + chan, sel == 0 ? c0 : (sel == 1 ? c1 : x[2]));
                 }
             }
         }

@@ -47,6 +47,11 @@ __device__ __forceinline__ int64_t xcd_part(uint32_t b, int64_t active) {
     return (int64_t)x * q + (x < r ? x : r) + i;
 }
 
+// per-item 2D gradient record of the backward: d/d(u, v, Qa, Qb, Qc,
+// opacity, r, g, b, z) at floats 0-9 of a 64-byte record (one cache line, so
+// that a wave's nine gradient atomics for a splat land on one line)
+constexpr int kG2 = 16;
+
 // header words (u32) at workspace offset 0
 enum Header : int {
     kHdrStatus = 0,

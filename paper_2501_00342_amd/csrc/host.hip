@@ -199,7 +199,7 @@ int plan(const sgs_gaussians* g, const sgs_camera* cams, int32_t n_cams, const s
     L.ranges = take((size_t)tiles * 8);
     pl->tile_keys = take((size_t)tiles * 4);
     pl->tile_order = take((size_t)tiles * 4);
-    L.grad2d = take((size_t)items * 10 * 4);
+    L.grad2d = take((size_t)items * sgs::kG2 * 4);
     pl->gx_colour = take((size_t)n * 3 * 4);
     pl->counts = take((size_t)pl->max_parts * sgs::kRadix * 4);
     pl->totals = take((size_t)sgs::kRadix * 4);
@@ -609,8 +609,8 @@ int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const s
     Marker mk{timing_slot(g_timing.bwd, g_timing.bwd_used), s};
     const bool dg = grad_depth || grad_alpha;
     mk.mark(0);
-    // row 9 (dL/dz) only when depth or alpha carry a gradient
-    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, (dg ? 10 : 9) * ws.n_items, s);
+    // every item's whole 64-byte gradient record (whole lines)
+    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, sgs::kG2 * ws.n_items, s);
     if (pl.queue) sgs::launch_fill_u32(ws.header + sgs::kHdrQueueBwd, 0u, 1, s);
     mk.mark(1);
     sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, grad_depth, grad_alpha,

@@ -106,10 +106,13 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
             const uint64_t tr = PF && ci == 0 ? rect0 : ws.tile_rects[item];
             const bool vis = active && (int)((tr >> 16) & 0xFFFF) >= (int)(tr & 0xFFFF);
             // with registers to spare, issued before the gather's wait
-            float grgb[3];
+            // (only a visible item's gradient record is read)
+            float grgb[3] = {0.0f, 0.0f, 0.0f};
             if constexpr (PF) {
+                if (vis) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[(6 + c) * M + item];
+                    for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[item * kG2 + 6 + c];
+                }
             }
             const int got = gather_colour<3 * NC, CT>(p, gc, vis && slot < 0, used, crec, s_g[wave], &slot);
             used += got;
@@ -117,7 +120,7 @@ k_colour_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Workspac
             if (!vis) continue;
             if constexpr (!PF) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[(6 + c) * M + item];
+                for (int c = 0; c < 3; ++c) grgb[c] = ws.grad2d[item * kG2 + 6 + c];
             }
             const char* r = reinterpret_cast<const char*>(crec) + slot * RS * ColourElem<CT>::bytes;
             float d[3], dist;
@@ -192,12 +195,15 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
     const double dil = o.dilation;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // inputs of this thread's next Gaussian, loaded while the current one
-    // computes: geometry, the colour part of the mean's gradient, and the
-    // first camera's rectangle and 2D gradients (u, v, Qa, Qb, Qc, sigma)
+    // computes: geometry, the colour part of the mean's gradient, the first
+    // camera's rectangle and, when that camera sees it, its 2D gradients
+    // (u, v, Qa, Qb, Qc, sigma, z).  The rectangles are loaded one Gaussian
+    // further ahead, so that the gradient record is fetched only for a
+    // visible item without waiting for its rectangle.
     struct In {
         float X[3], ls[3], q[4], logit, gxc[3];
         uint64_t rect0;
-        float g0[6];
+        float g0[7];
     };
     auto load = [&](int64_t g, In& in) {
 #pragma unroll
@@ -209,16 +215,36 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
 #pragma unroll
         for (int c = 0; c < 4; ++c) in.q[c] = p.quats[c * n + g];
         in.logit = p.opacity_logits[g];
-        in.rect0 = ws.tile_rects[g];
+    };
+    auto load_g2 = [&](int64_t g, uint64_t rect, In& in) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) in.g0[c] = ws.grad2d[c * M + g];
+        for (int c = 0; c < 7; ++c) in.g0[c] = 0.0f;
+        in.rect0 = rect;
+        if ((int)((rect >> 16) & 0xFFFF) >= (int)(rect & 0xFFFF)) {   // visible
+            const float* r0 = ws.grad2d + g * kG2;
+            const float4 a = *reinterpret_cast<const float4*>(r0);
+            const float2 b = *reinterpret_cast<const float2*>(r0 + 4);
+            in.g0[0] = a.x; in.g0[1] = a.y; in.g0[2] = a.z; in.g0[3] = a.w;
+            in.g0[4] = b.x; in.g0[5] = b.y;
+            in.g0[6] = depth_grad ? r0[9] : 0.0f;
+        }
     };
     In cur;
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < n) load(g, cur);
+    uint64_t rect_n = 1ull;   // the rectangle of this thread's next Gaussian (1: no pairs)
+    if (g < n) {
+        load(g, cur);
+        load_g2(g, ws.tile_rects[g], cur);
+        if (g + stride < n) rect_n = ws.tile_rects[g + stride];
+    }
     for (; g < n; g += stride) {
         In nxt;
-        if (g + stride < n) load(g + stride, nxt);
+        if (g + stride < n) {
+            load(g + stride, nxt);
+            load_g2(g + stride, rect_n, nxt);
+        }
+        if (g + 2 * stride < n) rect_n = ws.tile_rects[g + 2 * stride];
+        const float* g0 = cur.g0;
         double gX[3] = {0.0, 0.0, 0.0}, gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
         double glogit = 0.0;
         const double X[3] = {cur.X[0], cur.X[1], cur.X[2]};
@@ -239,13 +265,14 @@ k_geom_bwd(Params p, const sgs_camera* __restrict__ cams, int n_cams, Opts o, Wo
             any = true;
             const sgs_camera& cam = cams[ci];
             const CamTable ct = ws.cams[ci];
-            float g2d[6];
+            float g2d[7];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) g2d[c] = ci == 0 ? cur.g0[c] : ws.grad2d[c * M + item];
+            for (int c = 0; c < 6; ++c) g2d[c] = ci == 0 ? g0[c] : ws.grad2d[item * kG2 + c];
+            g2d[6] = ci == 0 ? g0[6] : (depth_grad ? ws.grad2d[item * kG2 + 9] : 0.0f);
             const double gu = g2d[0], gv = g2d[1];
             // depth z = x_cam[2] carries dL/dz from the blend when depth or
             // alpha had an upstream gradient
-            const double gzd = depth_grad ? (double)ws.grad2d[9 * M + item] : 0.0;
+            const double gzd = depth_grad ? (double)g2d[6] : 0.0;
             const double gQa = g2d[2], gQb = g2d[3];
             const double gQc = g2d[4];
             glogit += (double)g2d[5] * sig * (1.0 - sig);

@@ -344,7 +344,8 @@ class Rasterizer:
     def grad2d(self):
         """(10, items): d/d(u, v, Qa, Qb, Qc, opacity, r, g, b, z) of the last
         backward (row 9 only after one with a depth or alpha gradient)."""
-        return self._view(self.layout.grad2d, 10 * self.layout.n_items, torch.float32).view(10, -1)
+        rec = self._view(self.layout.grad2d, 16 * self.layout.n_items, torch.float32).view(-1, 16)
+        return rec[:, :10].t()
 
     def sorted_keys(self, count) -> torch.Tensor:
         keys = torch.empty(count, dtype=torch.int64, device=self.device)
