@@ -217,7 +217,8 @@ typedef struct sgs_layout {
     size_t ranges;          /* u32[2] per global tile: [start, end), (0,0) if empty */
     size_t grad2d;          /* per item a 64-byte record of f32: d/d(u, v, Qa, Qb, Qc,
                                opacity, r, g, b, z) at floats 0-9 (z only when depth or
-                               alpha had a gradient), floats 10-15 unused */
+                               alpha had a gradient), floats 10-15 unused; written for
+                               the items the forward kept visible, others unspecified */
     int64_t n_items;        /* n_cams * n */
     int64_t n_tiles;        /* total tiles over all cameras */
     int64_t n_pixels;       /* total pixels over all cameras */

@@ -609,8 +609,9 @@ int render_backward(const sgs_gaussians* g, const sgs_camera* host_cams, const s
     Marker mk{timing_slot(g_timing.bwd, g_timing.bwd_used), s};
     const bool dg = grad_depth || grad_alpha;
     mk.mark(0);
-    // every item's whole 64-byte gradient record (whole lines)
-    sgs::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.grad2d), 0u, sgs::kG2 * ws.n_items, s);
+    // the 64-byte gradient records of the visible items (whole lines); no
+    // kernel writes or reads another item's record
+    sgs::launch_clear_grad2d(ws, s);
     if (pl.queue) sgs::launch_fill_u32(ws.header + sgs::kHdrQueueBwd, 0u, 1, s);
     mk.mark(1);
     sgs::launch_blend_bwd(ws, dev_cams, n_cams, pl.o, *fwd, grad_image, grad_depth, grad_alpha,

@@ -345,7 +345,9 @@ class Rasterizer:
         """(10, items): d/d(u, v, Qa, Qb, Qc, opacity, r, g, b, z) of the last
         backward (row 9 only after one with a depth or alpha gradient)."""
         rec = self._view(self.layout.grad2d, 16 * self.layout.n_items, torch.float32).view(-1, 16)
-        return rec[:, :10].t()
+        # records exist for the visible items only (depth key not all ones)
+        vis = (self.depth_keys() != -1).unsqueeze(1)
+        return torch.where(vis, rec[:, :10], torch.zeros_like(rec[:, :10])).t()
 
     def sorted_keys(self, count) -> torch.Tensor:
         keys = torch.empty(count, dtype=torch.int64, device=self.device)
