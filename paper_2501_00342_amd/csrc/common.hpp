@@ -249,7 +249,7 @@ void launch_l1(const Workspace& ws, int n_cams, const float* image, const float*
                float* grad, double* loss, hipStream_t s);
 void launch_read_keys(const Workspace& ws, int64_t count, uint64_t* keys, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
-// zeroes the 2D gradient records of the visible items (depth order list)
+// zeroes the 2D gradient records of the visible items
 void launch_clear_grad2d(const Workspace& ws, hipStream_t s);
 
 }  // namespace sgs

@@ -35,24 +35,25 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
 }
 
 // zeroes the 2D gradient record of every visible item (the backward blend
-// adds only into those, and the backward preprocess reads only those)
+// adds only into those, and the backward preprocess reads only those), from
+// the depth-order list: four consecutive threads clear the four 16-byte
+// quarters of one record, so each record is one whole-line store
 __global__ void __launch_bounds__(256) k_clear_grad2d(Workspace ws) {
+    constexpr int Q = kG2 / 4;   // 16-byte quarters per record
     const int64_t nv = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
     const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t item = ws.sorted_items[i];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nv * Q;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t item = ws.sorted_items[t / Q];
         if (item >= (uint64_t)ws.n_items) continue;
-        float4* r = reinterpret_cast<float4*>(ws.grad2d + (int64_t)item * kG2);
-#pragma unroll
-        for (int q = 0; q < kG2 / 4; ++q) r[q] = z;
+        reinterpret_cast<float4*>(ws.grad2d)[(int64_t)item * Q + (t % Q)] = z;
     }
 }
 
 void launch_clear_grad2d(const Workspace& ws, hipStream_t s) {
     if (ws.n_items <= 0) return;
-    int64_t blocks = (ws.n_items + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    int64_t blocks = (ws.n_items * (kG2 / 4) + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, ws);
 }
 
