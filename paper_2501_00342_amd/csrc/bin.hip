@@ -317,6 +317,40 @@ __global__ void __launch_bounds__(1024) k_bin_tiles(Workspace ws) {
 
 static_assert((kBinStage & (kBinStage - 1)) == 0, "the stage index is masked");
 
+// The store of a staged window of n pairs whose first staged index is w0:
+// thread tid takes staged indices tid + 256 j, four at a time so that their
+// LDS reads are in flight together.  Staged value v = tile * kBinChunk +
+// entry goes to s_gb[tile] + w0 + index (32-bit positions; one at or past
+// the capacity, or below zero, is not written).
+__device__ __forceinline__ void store_stage(uint32_t* __restrict__ out, const uint16_t* s_stage,
+                                            const int32_t* s_gb, const uint32_t* s_item, uint32_t n,
+                                            uint32_t w0, uint32_t cap) {
+    constexpr uint32_t T = 64 * kBinSubs, U = 4;
+    char* const ob = reinterpret_cast<char*>(out);
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += T * U) {
+        uint32_t v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * T;
+            v[u] = s_stage[i < n ? i : i0];
+        }
+        int32_t gb[U];
+        uint32_t it[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            gb[u] = s_gb[v[u] / kBinChunk];
+            it[u] = s_item[v[u] % kBinChunk];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * T;
+            const uint32_t g = (uint32_t)(gb[u] + (int32_t)(w0 + i));
+            // (a byte offset below 2^32: g < cap < 2^30)
+            if (i < n && g < cap) *reinterpret_cast<uint32_t*>(ob + 4u * g) = it[u];
+        }
+    }
+}
+
 // One workgroup per chunk, wave w taking sub-chunk w.  For each batch of 64
 // entries (lane k holds entry k), an entry covering tiles a .. a + w - 1
 // sets its bit k in the start mark of tile a and the end mark of tile a + w;
@@ -330,11 +364,11 @@ k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* _
     __shared__ uint16_t s_stage[kBinStage];                 // tile * kBinChunk + entry, by tile
     __shared__ uint64_t s_start[kBinSubs][kStripTiles];     // entries starting at each tile
     __shared__ uint64_t s_end[kBinSubs][kStripTiles + 1];   // entries ending before each tile
-    __shared__ int64_t s_gb[kStripTiles];                   // position of staged index 0 of each tile's run
+    __shared__ int32_t s_gb[kStripTiles];                   // position of staged index 0 of each tile's run
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t nc = ws.header[kHdrChunks];
     const int64_t nvis = ws.header[kHdrVisible] < ws.n_items ? ws.header[kHdrVisible] : ws.n_items;
-    const int64_t cap = ws.capacity;
+    const uint32_t cap = (uint32_t)ws.capacity;   // below 2^30
     s_start[wave][lane] = 0ull;
     s_end[wave][lane] = 0ull;
     for (int64_t round = 0;; ++round) {
@@ -382,7 +416,11 @@ k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* _
         const uint32_t incl = wave_incl_scan(cnt);
         const uint32_t lb = incl - cnt;
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-        const int64_t gb = (int64_t)(live ? ts_l : 0u) + off - lb;   // position = gb + staged index
+        // position = gb + staged index, in 32 bits: a run that starts at or
+        // past the capacity (< 2^30) gets gb = 2^30, so none of its
+        // positions (staged indices < 2^15) is below the capacity
+        const int64_t gb64 = (int64_t)(live ? ts_l : 0u) + off - lb;
+        const int32_t gb = (int32_t)(gb64 < (int64_t(1) << 30) ? gb64 : (int64_t(1) << 30));
         if (wave == 0) s_gb[lane] = gb;
         // the masks of this wave's two batches, kept for the stage windows
         uint64_t msk[kBinBatches];
@@ -408,29 +446,32 @@ k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* _
         // the chunk's pairs go through the stage in windows of kBinStage
         // staged indices (one window unless the chunk holds more pairs)
         if (total <= (uint32_t)kBinStage) {
-            // one window: each lane walks its set bits, 32 at a time
-            uint32_t p = lb + before;
+            // one window: each lane walks its set bits, 32 at a time, with
+            // the stage addressed in bytes (the mask keeps a count that
+            // disagreed with the walk inside the stage)
+            char* const stage = reinterpret_cast<char*>(s_stage);
+            uint32_t pb = 2u * (lb + before);
 #pragma unroll
             for (int k = 0; k < kBinBatches; ++k) {
+                // a multiple of 64: the entry index is or-ed into the low bits
                 const uint32_t tag = (uint32_t)lane * kBinChunk + (uint32_t)(wave * kBinSub + k * 64);
                 uint32_t lo = (uint32_t)msk[k], hi = (uint32_t)(msk[k] >> 32);
-                // (the mask keeps a count that disagreed with the walk
-                // inside the stage)
                 while (lo) {
-                    s_stage[(p++) & (kBinStage - 1)] = (uint16_t)(tag + (uint32_t)__builtin_ctz(lo));
+                    *reinterpret_cast<uint16_t*>(stage + (pb & (2u * kBinStage - 2u))) =
+                        (uint16_t)(tag | (uint32_t)__builtin_ctz(lo));
+                    pb += 2u;
                     lo &= lo - 1u;
                 }
+                const uint32_t tag_hi = tag | 32u;
                 while (hi) {
-                    s_stage[(p++) & (kBinStage - 1)] = (uint16_t)(tag + 32u + (uint32_t)__builtin_ctz(hi));
+                    *reinterpret_cast<uint16_t*>(stage + (pb & (2u * kBinStage - 2u))) =
+                        (uint16_t)(tag_hi | (uint32_t)__builtin_ctz(hi));
+                    pb += 2u;
                     hi &= hi - 1u;
                 }
             }
             __syncthreads();   // the stage, the items and s_gb are complete
-            for (uint32_t i = tid; i < total; i += 64 * kBinSubs) {
-                const uint32_t v = s_stage[i];
-                const int64_t g = s_gb[v / kBinChunk] + i;
-                if (g >= 0 && g < cap) ws.pair_values[g] = s_item[v % kBinChunk];
-            }
+            store_stage(ws.pair_values, s_stage, s_gb, s_item, total, 0u, cap);
             __syncthreads();   // stored before the next chunk stages
             continue;
         }
@@ -455,11 +496,7 @@ k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* _
             }
             __syncthreads();   // the window, the items and s_gb are complete
             const uint32_t nw = total - w0 < (uint32_t)kBinStage ? total - w0 : (uint32_t)kBinStage;
-            for (uint32_t i = tid; i < nw; i += 64 * kBinSubs) {
-                const uint32_t v = s_stage[i];
-                const int64_t g = s_gb[v / kBinChunk] + w0 + i;
-                if (g >= 0 && g < cap) ws.pair_values[g] = s_item[v % kBinChunk];
-            }
+            store_stage(ws.pair_values, s_stage, s_gb, s_item, nw, w0, cap);
             __syncthreads();   // the window is stored before the next one is staged
         }
     }
