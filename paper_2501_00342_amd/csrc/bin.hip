@@ -477,18 +477,21 @@ k_bin_scatter(Workspace ws, const uint32_t* __restrict__ entries, const uint4* _
         }
         for (uint32_t w0 = 0; w0 < total; w0 += kBinStage) {
             const uint32_t w1 = w0 + kBinStage;
+            // each half mask whose run overlaps the window is walked up to
+            // the window's end; the others are only counted
             uint32_t pos = lb + before;
 #pragma unroll
-            for (int k = 0; k < kBinBatches; ++k) {
-                uint64_t m = msk[k];
-                const uint32_t n = (uint32_t)__popcll(m);
+            for (int h = 0; h < 2 * kBinBatches; ++h) {
+                uint32_t m = (h & 1) ? (uint32_t)(msk[h >> 1] >> 32) : (uint32_t)msk[h >> 1];
+                const uint32_t n = (uint32_t)__popc(m);
                 if (pos < w1 && pos + n > w0) {
-                    const uint32_t tag = (uint32_t)lane * kBinChunk + (uint32_t)(wave * kBinSub + k * 64);
+                    const uint32_t tag =
+                        (uint32_t)lane * kBinChunk + (uint32_t)(wave * kBinSub + (h >> 1) * 64 + (h & 1) * 32);
                     uint32_t p = pos;
-                    while (m) {
-                        const int j = __builtin_ctzll(m);
-                        m &= m - 1ull;
-                        if (p >= w0 && p < w1) s_stage[p - w0] = (uint16_t)(tag + (uint32_t)j);
+                    while (m && p < w1) {
+                        // (below w0 the difference wraps past the stage)
+                        if (p - w0 < (uint32_t)kBinStage) s_stage[p - w0] = (uint16_t)(tag | (uint32_t)__builtin_ctz(m));
+                        m &= m - 1u;
                         ++p;
                     }
                 }
@@ -515,7 +518,7 @@ void launch_bin_tiles(const Workspace& ws, const uint32_t* entry_slots, hipStrea
     const int64_t sblocks = ws.n_strips < 1024 ? ws.n_strips : 1024;
     hipLaunchKernelGGL(k_bin_strips, dim3((unsigned)sblocks), dim3(1024), 0, s, ws);
     hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, s, ws);
-    const int64_t wmax = cus * 6;   // LDS holds 6 of these blocks per CU
+    const int64_t wmax = cus * 7;   // LDS holds 7 of these blocks (22.5 KB each) per CU
     const int64_t wblocks = ws.chunk_cap < wmax ? ws.chunk_cap : wmax;
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)wblocks), dim3(64 * kBinSubs), 0, s, ws,
                        entry_slots, ws.chunk_info);
