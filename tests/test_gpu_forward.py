@@ -1,4 +1,5 @@
 """Forward parity of the HIP path against the FP64 oracle (GPU)."""
+import dataclasses
 import math
 
 import numpy as np
@@ -359,3 +360,29 @@ def test_binning_with_two_strip_passes_and_wide_rows():
         _, _, single_o = run_forward(sc, [cams[k]], opts)
         simg, sdep, sT, sn = camera_numpy(single_o, [cams[k]])
         assert np.array_equal(img, simg) and np.array_equal(n, sn) and np.array_equal(T, sT)
+
+
+@pytest.mark.gpu
+def test_binning_chunks_past_the_stage():
+    """Large splats (log-scales raised by log 8, so that most span a good
+    part of a 130-tile row) give more than 8,192 pairs per 512-entry chunk
+    on average, so some chunk passes through the scatter's 8,192-pair LDS
+    stage in several windows.  Keys, values and tile ranges still equal the
+    oracle's bit for bit."""
+    sc, cam = scenes.small_clustered(20000, 29, 1040, 96)
+    sc = dataclasses.replace(sc, log_scales=(sc.log_scales + np.float32(math.log(8.0))).astype(np.float32))
+    opts = scenes.Options(tile_w=8, tile_h=8)
+    rast, params, out = run_forward(sc, [cam], opts)
+    bits, P = rast.status()
+    assert bits == 0
+    n_chunks = int(rast.header().cpu().numpy()[6])
+    assert n_chunks > 0 and P > 8192 * n_chunks   # so the largest chunk holds more than 8,192
+    pre = F.preprocess(sc, cam, opts)
+    keys, vals, ntiles = F.emit_pairs([pre])
+    keys, vals = F.sort_pairs(keys, vals)
+    ranges = F.tile_ranges(keys, ntiles)
+    assert P == keys.size
+    assert np.array_equal(rast.sorted_keys(P).cpu().numpy().view(np.uint64), keys)
+    assert np.array_equal(rast.pair_values(P).cpu().numpy().view(np.uint32).astype(np.uint64), vals)
+    rng = rast.ranges().cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(rng, ranges[:ntiles])
