@@ -242,8 +242,20 @@ __global__ void __launch_bounds__(1024) k_bin_strips(Workspace ws) {
         const int64_t seg = (nch + WAVES - 1) / WAVES;
         const int64_t k0 = (int64_t)wave * seg < nch ? (int64_t)wave * seg : nch;
         const int64_t k1 = k0 + seg < nch ? k0 + seg : nch;
+        // eight sub-chunks' counts in flight at a time (indices clamped to
+        // the wave's run, so the loads carry no branches)
+        constexpr int U = 8;
         uint32_t sum = 0;
-        for (int64_t k = k0; k < k1; ++k) sum += ws.chunk_counts[(cb + k) * kStripTiles + lane];
+        for (int64_t k = k0; k < k1; k += U) {
+            uint32_t v[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t kk = k + j < k1 ? k + j : k1 - 1;
+                v[j] = ws.chunk_counts[(cb + kk) * kStripTiles + lane];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) sum += k + j < k1 ? v[j] : 0u;
+        }
         __syncthreads();   // the previous strip is done with s_seg
         s_seg[wave][lane] = sum;
         __syncthreads();
@@ -254,11 +266,20 @@ __global__ void __launch_bounds__(1024) k_bin_strips(Workspace ws) {
             run += w < wave ? v : 0u;
             total += v;
         }
-        for (int64_t k = k0; k < k1; ++k) {
-            const int64_t i = (cb + k) * kStripTiles + lane;
-            const uint32_t v = ws.chunk_counts[i];
-            ws.chunk_offsets[i] = run;
-            run += v;
+        for (int64_t k = k0; k < k1; k += U) {
+            uint32_t v[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t kk = k + j < k1 ? k + j : k1 - 1;
+                v[j] = ws.chunk_counts[(cb + kk) * kStripTiles + lane];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (k + j < k1) {
+                    ws.chunk_offsets[(cb + k + j) * kStripTiles + lane] = run;
+                    run += v[j];
+                }
+            }
         }
         if (wave == 0 && lane < sw && (int64_t)si.z + lane < ws.n_tiles) ws.tile_count[si.z + lane] = total;
     }
