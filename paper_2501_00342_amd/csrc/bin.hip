@@ -291,24 +291,35 @@ __global__ void __launch_bounds__(1024) k_bin_strips(Workspace ws) {
 
 __global__ void __launch_bounds__(1024) k_bin_tiles(Workspace ws) {
     constexpr int WAVES = 1024 / 64;
-    constexpr int IT = 16;
+    constexpr int IT = 8;
+    constexpr int N = 1024 * IT;   // tiles per round
+    // the round's counts, then its starts (saturated to 32 bits); entry N
+    // holds the start after the round
+    __shared__ uint32_t s_v[N + 1];
     __shared__ uint64_t s_w[WAVES];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t T = ws.n_tiles;
     const uint64_t cap = (uint64_t)ws.capacity;
+    auto sat = [](uint64_t x) { return (uint32_t)(x < 0xFFFFFFFFull ? x : 0xFFFFFFFFull); };
     uint64_t carry = 0;
-    for (int64_t b0 = 0; b0 < T; b0 += 1024 * IT) {
-        const int64_t i0 = b0 + (int64_t)tid * IT;
+    for (int64_t b0 = 0; b0 < T; b0 += N) {
+        // coalesced loads, then each thread takes IT consecutive tiles
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int64_t i = b0 + (int64_t)k * 1024 + tid;
+            s_v[k * 1024 + tid] = i < T ? ws.tile_count[i] : 0u;
+        }
+        __syncthreads();
         uint32_t v[IT];
         uint64_t run = 0;
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            v[k] = i0 + k < T ? ws.tile_count[i0 + k] : 0u;
+            v[k] = s_v[tid * IT + k];
             run += v[k];
         }
         const uint64_t incl = wave_incl_scan64(run);
         if (lane == 63) s_w[wave] = incl;
-        __syncthreads();
+        __syncthreads();   // the counts are read and the wave totals written
         uint64_t before = 0, all = 0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
@@ -318,17 +329,27 @@ __global__ void __launch_bounds__(1024) k_bin_tiles(Workspace ws) {
         uint64_t st = carry + before + incl - run;
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            const int64_t i = i0 + k;
+            s_v[tid * IT + k] = sat(st);
+            st += v[k];
+        }
+        if (tid == 0) s_v[N] = sat(carry + all);
+        __syncthreads();
+        // coalesced stores: a tile's range ends where the next tile starts
+        // (clamped to the capacity; a saturated start lies past it)
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int j = k * 1024 + tid;
+            const int64_t i = b0 + j;
             if (i < T) {
-                ws.tile_start[i] = (uint32_t)(st < 0xFFFFFFFFull ? st : 0xFFFFFFFFull);
-                const uint64_t a = st < cap ? st : cap, e = st + v[k] < cap ? st + v[k] : cap;
+                const uint32_t a32 = s_v[j], e32 = s_v[j + 1];
+                ws.tile_start[i] = a32;
+                const uint64_t a = a32 < cap ? a32 : cap, e = e32 < cap ? e32 : cap;
                 ws.ranges[2 * i] = a < e ? (uint32_t)a : 0u;
                 ws.ranges[2 * i + 1] = a < e ? (uint32_t)e : 0u;
             }
-            st += v[k];
         }
         carry += all;
-        __syncthreads();   // s_w is read before the next round writes it
+        __syncthreads();   // s_v and s_w are read before the next round writes them
     }
 }
 
